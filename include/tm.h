@@ -1,0 +1,222 @@
+/*
+ * tm.h - C ABI of the MI355X (gfx950) edge-orientation template matcher.
+ *
+ * The method is that of Le & Lin, "GPU-accelerated image alignment for object
+ * detection in industrial applications" (arXiv 2112.05576), Sec. II: a model
+ * image and a search image go through edge extraction and an image pyramid;
+ * every pose (x, y, theta) of the top level is scored with the similarity
+ * measure of Eq. (1) under the rigid projection of Eq. (2), each model point
+ * taking its best vote over a neighbouring window (size 3 in the paper); the
+ * best poses are then refined level by level down to the full image.
+ *
+ * Conventions for every call:
+ *  - Device pointers ("_dev") are HIP device memory of the current device.
+ *    Host pointers are plain host memory.  No call takes ownership of a
+ *    caller buffer.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Work is enqueued on it and every call returns without waiting for the
+ *    device, except tm_build_model (it waits once for the point counts) and
+ *    the first call that has to grow an internal buffer (it waits before
+ *    freeing the old one).  Inputs must stay valid until the stream has
+ *    passed the call.
+ *  - Every call returns a tm_status.  On failure nothing has been enqueued
+ *    (validation happens first) and tm_last_error() describes the problem in
+ *    the calling thread.  A failed HIP runtime call returns TM_EDEVICE.
+ *  - A model may be used by any number of streams at once as long as they use
+ *    the same angle grid (its rotated-point table is cached per grid).  A
+ *    pyramid carries the scratch space of tm_detect / tm_refine, so one
+ *    pyramid is used by one stream at a time.
+ *
+ * Image layout: uint8, row-major, `pitch` bytes between rows (pitch >= width).
+ * Coordinates: x to the right, y down; the model's reference point is its
+ * pixel (width/2, height/2) (integer division) at every pyramid level, and a
+ * pose (x, y) places that point at search pixel (x, y) of the pose's level.
+ */
+#ifndef TM_H
+#define TM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TM_OK = 0,
+    TM_EINVAL = -1,    /* invalid argument (message says which)              */
+    TM_ENOMEM = -2,    /* device or host allocation failed                   */
+    TM_EDEVICE = -3,   /* a HIP runtime call failed                          */
+    TM_ECAPACITY = -4  /* a result did not fit the caller's capacity        */
+} tm_status;
+
+typedef enum { TM_FP32 = 0, TM_FP16 = 1 } tm_precision;
+
+#define TM_MAX_LEVELS 8
+
+/* Pyramid and edge parameters (Sec. II para. 2: edge detection threshold,
+ * number of pyramid levels).  A pixel is an edge iff gx^2 + gy^2 >
+ * floor(edge_thresh^2), gx and gy being the integer 3x3 Sobel responses
+ * (zero on the one-pixel image frame); level l+1 is the 2x2 rounded mean of
+ * level l, floor(w/2) x floor(h/2).  `precision` selects how the search
+ * pyramid stores unit gradient directions (FP32, or FP16 with FP32
+ * accumulation); models ignore it. */
+typedef struct {
+    int32_t levels;       /* 1 .. TM_MAX_LEVELS                       */
+    float edge_thresh;    /* >= 0, on the scale of the integer Sobel  */
+    int32_t precision;    /* tm_precision                             */
+} tm_pyr_params;
+
+/* Search parameters (Sec. II para. 2: step sizes in x, y and theta, the
+ * neighbouring-search size) plus the multi-instance selection settings.
+ * Angles: level l of an L-level search uses step theta_step_top_deg /
+ * 2^(L-1-l) and angles theta_min_deg + k * step.  A range of 360 degrees or
+ * more wraps (ceil(360/step) angles); a smaller range holds both end points
+ * (floor(range/step + 1e-9) + 1 angles) and clamps.  The top level is
+ * searched exhaustively on the grid x = i*step_x, y = j*step_y; each lower
+ * level re-scores the 27 poses (2x+a, 2y+b, 2k+c), a, b, c in {-1, 0, 1}. */
+typedef struct {
+    int32_t step_x, step_y;       /* >= 1 pixels of the top level            */
+    double theta_min_deg;
+    double theta_range_deg;       /* > 0                                      */
+    double theta_step_top_deg;    /* > 0, the angle step of the top level     */
+    int32_t neighbourhood;        /* odd window side >= 1; the paper uses 3   */
+    float min_score;              /* S_w floor for candidates and matches     */
+    float nms_min_dist;           /* level-0 pixels; <= 0: half the model radius */
+    int32_t max_candidates;       /* 1 .. 1024, kept after the top level      */
+    int32_t max_matches;          /* >= 1, returned by tm_detect              */
+} tm_search_params;
+
+/* A pose with its scores.  (x, y) is in pixels of `level`; k indexes the
+ * level's angle grid and theta_deg = theta_min + k * step is given for
+ * convenience.  score_w is Eq. (1) with the neighbourhood vote, score_1 the
+ * same with the centre tap only. */
+typedef struct {
+    int32_t x, y;
+    int32_t k;
+    int32_t level;
+    float theta_deg;
+    float score_w;
+    float score_1;
+    int32_t reserved;
+} tm_pose;
+
+/* An arbitrary pose to score: integer translation, any angle. */
+typedef struct {
+    int32_t x, y;
+    double theta_deg;
+} tm_eval_pose;
+
+typedef struct tm_model_s tm_model;
+typedef struct tm_pyramid_s tm_pyramid;
+
+/* Edge points of a model image on every pyramid level (Sec. II para. 2; the
+ * points are the t_i of Eq. (2), row-major, relative to the reference pixel).
+ * Waits on `stream` once to learn the point counts.  TM_EINVAL if the image
+ * is smaller than 2^(levels-1) * 3 pixels a side or if a level has no edge
+ * point.  The image is not retained. */
+tm_status tm_build_model(const uint8_t* img_dev, int32_t width, int32_t height, int32_t pitch,
+                         const tm_pyr_params* params, void* stream, tm_model** out);
+
+/* Grey-level pyramid of a search image and its unit-gradient-direction field
+ * on every level ((0, 0) off the edge set).  Allocates the pyramid; the image
+ * is copied, not retained.  TM_EINVAL if the image is smaller than
+ * 2^(levels-1) * 3 pixels a side. */
+tm_status tm_build_pyramid(const uint8_t* img_dev, int32_t width, int32_t height, int32_t pitch,
+                           const tm_pyr_params* params, void* stream, tm_pyramid** out);
+
+/* Rebuild an existing pyramid from a new image of the same size; allocates
+ * nothing. */
+tm_status tm_update_pyramid(tm_pyramid* pyr, const uint8_t* img_dev, int32_t pitch, void* stream);
+
+/* Eq. (1) at n arbitrary poses of one level: scores_dev[2i] = S_w,
+ * scores_dev[2i+1] = S_1 for poses_dev[i].  `neighbourhood` is the odd window
+ * side (3 in the paper).  Model points whose window falls outside the image
+ * vote 0; the sum is divided by the model's point count at that level. */
+tm_status tm_score_poses(const tm_model* model, const tm_pyramid* pyr, int32_t level,
+                         int32_t neighbourhood, const tm_eval_pose* poses_dev, int32_t n,
+                         float* scores_dev, void* stream);
+
+/* Exhaustive search of one level (Sec. II para. 3, Fig. 2): for every
+ * translation of the step grid, the best angle of the level's grid by the key
+ * (S_w desc, S_1 desc, k asc).  Outputs are [gh][gw] arrays with
+ * gw = ceil(w_level/step_x), gh = ceil(h_level/step_y). */
+tm_status tm_score_map(const tm_model* model, tm_pyramid* pyr, int32_t level,
+                       const tm_search_params* params, float* sw_dev, float* s1_dev, int32_t* k_dev,
+                       void* stream);
+
+/* Candidate selection on a score map of `level` (layout as tm_score_map):
+ * grid points with S_w >= min_score whose key (S_w desc, S_1 desc, x asc,
+ * y asc) beats all 8 grid neighbours, sorted by the key, thinned greedily so
+ * that accepted poses are >= dmin apart in level-0 pixels (distance scaled by
+ * 2^level), at most `capacity`.  Writes the poses and their count (device
+ * int).  Used inside tm_detect; exported so that it can be run on a given
+ * map. */
+tm_status tm_select(const float* sw_dev, const float* s1_dev, const int32_t* k_dev, int32_t gw, int32_t gh,
+                    int32_t step_x, int32_t step_y, int32_t level, float min_score, float dmin,
+                    tm_pose* out_dev, int32_t capacity, int32_t* n_out_dev, void* stream);
+
+/* Full detection (Sec. II): exhaustive search of the top level, candidate
+ * selection (at most max_candidates), refinement down to level 0, then the
+ * final selection: candidates with S_w >= min_score, key order, greedy
+ * suppression within nms_min_dist, at most min(max_matches, capacity).
+ * Poses are written to out_dev at level 0 and their count to *n_out_dev. */
+tm_status tm_detect(const tm_model* model, tm_pyramid* pyr, const tm_search_params* params,
+                    tm_pose* out_dev, int32_t capacity, int32_t* n_out_dev, void* stream);
+
+/* Coarse-to-fine refinement of n poses (each at its own `level`, a grid
+ * index k of that level) down to level 0; poses are replaced in place by the
+ * best of the 27-pose neighbourhood at each level below theirs.  No
+ * selection is applied. */
+tm_status tm_refine(const tm_model* model, tm_pyramid* pyr, const tm_search_params* params,
+                    tm_pose* poses_dev, int32_t n, void* stream);
+
+/* --- inspection (tests, tools) ------------------------------------------ */
+
+/* Level geometry of a model: size of the level image and point count. */
+tm_status tm_model_level_info(const tm_model* model, int32_t level, int32_t* width, int32_t* height,
+                              int32_t* n_points);
+
+/* Copy a model level's points to device buffers: t_dev[2i..2i+1] = t_i
+ * (int32), g_dev[2i..2i+1] = the integer Sobel gradient at the point. */
+tm_status tm_model_points(const tm_model* model, int32_t level, int32_t* t_dev, int32_t* g_dev,
+                          void* stream);
+
+/* Rotated model table of a level for angles theta_min + k * step, k < K:
+ * q_dev[(k*n + i)*2 ..] = round(R t_i) (int32 pairs), r_dev[...] = R d_i
+ * (float pairs), with the rounding rule floor(v + 0.5 + 1e-9) in FP64. */
+tm_status tm_model_table(const tm_model* model, int32_t level, double theta_min, double step, int32_t K,
+                         int32_t* q_dev, float* r_dev, void* stream);
+
+/* Level geometry and device storage of a pyramid: the uint8 image (row-major,
+ * pitch = width) and the direction field (pairs of float, or of half for
+ * TM_FP16, row-major).  The pointers stay owned by the pyramid. */
+tm_status tm_pyramid_level(const tm_pyramid* pyr, int32_t level, int32_t* width, int32_t* height,
+                           const uint8_t** img_dev, const void** field_dev, int32_t* precision);
+
+/* Copy a pyramid level into caller device buffers (either may be NULL):
+ * img_dev gets width*height bytes, field_dev width*height pairs (float, or
+ * half for TM_FP16). */
+tm_status tm_pyramid_read(const tm_pyramid* pyr, int32_t level, uint8_t* img_dev, void* field_dev, void* stream);
+
+/* Stage timing.  While enabled, tm_detect and tm_score_map record a pair of
+ * HIP events around the exhaustive-search kernel on the call's stream.
+ * tm_timing_read waits for the recorded events, returns the summed kernel
+ * time in milliseconds and the number of launches, and clears the record. */
+tm_status tm_timing_enable(int32_t on);
+tm_status tm_timing_read(double* dense_ms, int32_t* launches);
+
+void tm_model_free(tm_model* model);
+void tm_pyramid_free(tm_pyramid* pyr);
+
+/* Description of the last failure in the calling thread ("" if none). */
+const char* tm_last_error(void);
+
+/* Library version string. */
+const char* tm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TM_H */

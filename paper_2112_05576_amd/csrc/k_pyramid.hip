@@ -1,0 +1,269 @@
+// Edge extraction and image pyramid (Sec. II para. 2): uint8 levels by 2x2
+// rounded means, integer Sobel gradients, magnitude threshold and unit
+// gradient directions per level; model edge points in row-major order.
+#include "tm_device.h"
+
+namespace tmk {
+
+namespace {
+
+struct LevelsArg {
+    uint8_t* img[kMaxLevels];
+    int w[kMaxLevels];
+    int h[kMaxLevels];
+};
+
+// One workgroup takes a 64x64 block of level `base` and produces the matching
+// cells of levels base+1 .. top (at most 6 more levels: 32x32 down to 1x1).
+// Every output pixel depends only on its own 2^k x 2^k block, so blocks are
+// independent.  Level `base` is read from `src` (pitched); when base == 0 the
+// block is also copied into level 0.
+__global__ __launch_bounds__(256) void k_pyr_build(const uint8_t* __restrict__ src, int src_pitch, LevelsArg lv,
+                                                    int base, int top, int copy_base)
+{
+    __shared__ uint8_t cells[16 * 16];
+    const int t = threadIdx.x;
+    const int cx = t & 15, cy = t >> 4;
+    const int W = lv.w[base], H = lv.h[base];
+    const int x0 = blockIdx.x * 64 + cx * 4;
+    const int y0 = blockIdx.y * 64 + cy * 4;
+    int v[4][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            int x = x0 + i, y = y0 + j;
+            v[j][i] = (x < W && y < H) ? (int)src[(size_t)y * src_pitch + x] : 0;
+        }
+    }
+    if (copy_base) {
+        uint8_t* dst = lv.img[base];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (x0 + i < W && y0 + j < H) dst[(size_t)(y0 + j) * W + x0 + i] = (uint8_t)v[j][i];
+    }
+    if (top <= base) return;
+    // level base+1: a 2x2 patch per thread
+    int l1[2][2];
+    {
+        const int l = base + 1, W1 = lv.w[l], H1 = lv.h[l];
+        const int bx = blockIdx.x * 32 + cx * 2, by = blockIdx.y * 32 + cy * 2;
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                int s = v[2 * j][2 * i] + v[2 * j][2 * i + 1] + v[2 * j + 1][2 * i] + v[2 * j + 1][2 * i + 1];
+                l1[j][i] = (s + 2) >> 2;
+                if (bx + i < W1 && by + j < H1) lv.img[l][(size_t)(by + j) * W1 + bx + i] = (uint8_t)l1[j][i];
+            }
+    }
+    if (top <= base + 1) return;
+    // level base+2: one pixel per thread, kept in LDS for the levels above
+    {
+        const int l = base + 2, W2 = lv.w[l], H2 = lv.h[l];
+        int s = l1[0][0] + l1[0][1] + l1[1][0] + l1[1][1];
+        int p = (s + 2) >> 2;
+        int x = blockIdx.x * 16 + cx, y = blockIdx.y * 16 + cy;
+        if (x < W2 && y < H2) lv.img[l][(size_t)y * W2 + x] = (uint8_t)p;
+        cells[cy * 16 + cx] = (uint8_t)p;
+    }
+    int side = 16;
+    for (int l = base + 3; l <= top && l <= base + 6; ++l) {
+        __syncthreads();
+        const int ns = side / 2;
+        int p = 0;
+        const bool act = t < ns * ns;
+        const int ix = t % ns, iy = t / ns;
+        if (act) {
+            int s = cells[(2 * iy) * side + 2 * ix] + cells[(2 * iy) * side + 2 * ix + 1] +
+                    cells[(2 * iy + 1) * side + 2 * ix] + cells[(2 * iy + 1) * side + 2 * ix + 1];
+            p = (s + 2) >> 2;
+            const int Wl = lv.w[l], Hl = lv.h[l];
+            int x = blockIdx.x * ns + ix, y = blockIdx.y * ns + iy;
+            if (x < Wl && y < Hl) lv.img[l][(size_t)y * Wl + x] = (uint8_t)p;
+        }
+        __syncthreads();
+        if (act) cells[iy * ns + ix] = (uint8_t)p;
+        side = ns;
+    }
+}
+
+struct FieldsArg {
+    const uint8_t* img[kMaxLevels];
+    void* field[kMaxLevels];
+    int w[kMaxLevels];
+    int h[kMaxLevels];
+    int block0[kMaxLevels + 1];  // first workgroup of each level
+    int L;
+};
+
+__device__ __forceinline__ void sobel_at(const uint8_t* __restrict__ img, int W, int H, int x, int y, int* gx,
+                                         int* gy)
+{
+    if (x < 1 || y < 1 || x > W - 2 || y > H - 2) {
+        *gx = 0;
+        *gy = 0;
+        return;
+    }
+    const uint8_t* r0 = img + (size_t)(y - 1) * W + x;
+    const uint8_t* r1 = r0 + W;
+    const uint8_t* r2 = r1 + W;
+    int a = r0[-1], b = r0[0], c = r0[1];
+    int d = r1[-1], f = r1[1];
+    int g = r2[-1], h = r2[0], i = r2[1];
+    *gx = (c + 2 * f + i) - (a + 2 * d + g);
+    *gy = (g + 2 * h + i) - (a + 2 * b + c);
+}
+
+// Unit gradient direction of every pixel of every level: (gx, gy)/|g| formed
+// in FP64 and rounded once to the storage precision where gx^2 + gy^2 > T2,
+// (0, 0) elsewhere.  Each thread covers 4 consecutive pixels of a row.
+__global__ __launch_bounds__(256) void k_sobel_fields(FieldsArg a, long long T2, int precision)
+{
+    int l = 0;
+    while (l + 1 < a.L && (int)blockIdx.x >= a.block0[l + 1]) ++l;
+    const int W = a.w[l], H = a.h[l];
+    const int qw = (W + 3) / 4;
+    const int idx = ((int)blockIdx.x - a.block0[l]) * 256 + (int)threadIdx.x;
+    const int y = idx / qw, x0 = (idx % qw) * 4;
+    if (y >= H) return;
+    const uint8_t* img = a.img[l];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int x = x0 + i;
+        if (x >= W) break;
+        int gx, gy;
+        sobel_at(img, W, H, x, y, &gx, &gy);
+        const long long m2 = (long long)gx * gx + (long long)gy * gy;
+        double dx = 0.0, dy = 0.0;
+        if (m2 > T2) {
+            double m = sqrt((double)m2);
+            dx = (double)gx / m;
+            dy = (double)gy / m;
+        }
+        const size_t o = (size_t)y * W + x;
+        if (precision == TM_FP16) {
+            reinterpret_cast<__half2*>(a.field[l])[o] = __floats2half2_rn((float)dx, (float)dy);
+        } else {
+            reinterpret_cast<float2*>(a.field[l])[o] = make_float2((float)dx, (float)dy);
+        }
+    }
+}
+
+struct PointsArg {
+    const uint8_t* img[kMaxLevels];
+    ModelPoint* pts[kMaxLevels];
+    int w[kMaxLevels];
+    int h[kMaxLevels];
+    int* counts;
+};
+
+// One workgroup per model level: thread t scans a contiguous run of pixels,
+// counts its edge pixels, an exclusive scan gives each run its output offset,
+// and a second pass writes the points, so the list is in row-major order.
+__global__ __launch_bounds__(1024) void k_model_points(PointsArg a, long long T2)
+{
+    __shared__ int scan[1024];
+    const int l = blockIdx.x;
+    const int W = a.w[l], H = a.h[l];
+    const int N = W * H;
+    const int per = (N + 1023) / 1024;
+    const int p0 = min(N, (int)threadIdx.x * per), p1 = min(N, p0 + per);
+    const uint8_t* img = a.img[l];
+    int cnt = 0;
+    for (int p = p0; p < p1; ++p) {
+        int gx, gy;
+        sobel_at(img, W, H, p % W, p / W, &gx, &gy);
+        cnt += ((long long)gx * gx + (long long)gy * gy > T2) ? 1 : 0;
+    }
+    scan[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // Hillis-Steele inclusive scan
+        int v = threadIdx.x >= (unsigned)off ? scan[threadIdx.x - off] : 0;
+        __syncthreads();
+        scan[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int o = scan[threadIdx.x] - cnt;
+    const int cx = W / 2, cy = H / 2;
+    for (int p = p0; p < p1; ++p) {
+        int x = p % W, y = p / W, gx, gy;
+        sobel_at(img, W, H, x, y, &gx, &gy);
+        if ((long long)gx * gx + (long long)gy * gy > T2) {
+            ModelPoint mp;
+            mp.tx = (int16_t)(x - cx);
+            mp.ty = (int16_t)(y - cy);
+            mp.gx = (int16_t)gx;
+            mp.gy = (int16_t)gy;
+            a.pts[l][o++] = mp;
+        }
+    }
+    if (threadIdx.x == 1023) a.counts[l] = scan[1023];
+}
+
+}  // namespace
+
+hipError_t launch_pyr_build(const uint8_t* src, int src_pitch, const PyrLevel* lv, int L, hipStream_t s)
+{
+    LevelsArg a = {};
+    for (int l = 0; l < L; ++l) {
+        a.img[l] = lv[l].img;
+        a.w[l] = lv[l].w;
+        a.h[l] = lv[l].h;
+    }
+    // first pass reads the caller's image; later passes (more than 7 levels)
+    // restart from the last level produced
+    int base = 0;
+    const uint8_t* in = src;
+    int pitch = src_pitch;
+    int copy = 1;
+    while (true) {
+        int top = min(L - 1, base + 6);
+        dim3 grid((a.w[base] + 63) / 64, (a.h[base] + 63) / 64);
+        hipLaunchKernelGGL(k_pyr_build, grid, dim3(256), 0, s, in, pitch, a, base, top, copy);
+        if (top >= L - 1) break;
+        base = top;
+        in = lv[base].img;
+        pitch = lv[base].w;
+        copy = 0;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sobel_fields(const PyrLevel* lv, int L, long long T2, int precision, hipStream_t s)
+{
+    FieldsArg a = {};
+    a.L = L;
+    int blocks = 0;
+    for (int l = 0; l < L; ++l) {
+        a.img[l] = lv[l].img;
+        a.field[l] = lv[l].field;
+        a.w[l] = lv[l].w;
+        a.h[l] = lv[l].h;
+        a.block0[l] = blocks;
+        long long quads = (long long)((lv[l].w + 3) / 4) * lv[l].h;
+        blocks += (int)((quads + 255) / 256);
+    }
+    a.block0[L] = blocks;
+    hipLaunchKernelGGL(k_sobel_fields, dim3(blocks), dim3(256), 0, s, a, T2, precision);
+    return hipGetLastError();
+}
+
+hipError_t launch_model_points(const PyrLevel* lv, int L, long long T2, ModelPoint* const* pts, int* counts,
+                               hipStream_t s)
+{
+    PointsArg a = {};
+    for (int l = 0; l < L; ++l) {
+        a.img[l] = lv[l].img;
+        a.pts[l] = pts[l];
+        a.w[l] = lv[l].w;
+        a.h[l] = lv[l].h;
+    }
+    a.counts = counts;
+    hipLaunchKernelGGL(k_model_points, dim3(L), dim3(1024), 0, s, a, T2);
+    return hipGetLastError();
+}
+
+}  // namespace tmk

@@ -1,0 +1,92 @@
+// Device-side helpers shared by the kernels: degree sine/cosine, the rigid
+// projection of one model point (Eq. 2), field loads and the selection key.
+#pragma once
+
+#include "tm_internal.h"
+
+namespace tmk {
+
+// cos and sin of an angle in degrees with an exact reduction to the first
+// quadrant, so that every multiple of 90 degrees yields exact 0 and +-1 and a
+// quarter turn of the angle is an exact swap/negation of the pair.
+__device__ __forceinline__ void sincos_deg(double deg, double* c, double* s)
+{
+#pragma clang fp contract(off)
+    double r = fmod(deg, 360.0);
+    if (r < 0.0) r += 360.0;
+    if (r >= 360.0) r -= 360.0;
+    int q = (int)floor(r / 90.0);
+    q = q > 3 ? 3 : q;
+    double phi = r - 90.0 * (double)q;
+    double rad = phi * (M_PI / 180.0);
+    double c0 = cos(rad), s0 = sin(rad);
+    if (q == 0) { *c = c0;  *s = s0; }
+    else if (q == 1) { *c = -s0; *s = c0; }
+    else if (q == 2) { *c = -c0; *s = -s0; }
+    else { *c = s0; *s = -c0; }
+}
+
+// Eq. (2) for one model point without the translation: integer position
+// offset q = floor(R t + 0.5 + 1e-9) (FP64, products rounded separately) and
+// rotated unit direction r = R d, d = g / |g| formed in FP64.
+__device__ __forceinline__ void project_point(const ModelPoint& p, double c, double s, int* qx, int* qy,
+                                              double* rx, double* ry)
+{
+#pragma clang fp contract(off)
+    double tx = (double)p.tx, ty = (double)p.ty;
+    double vx = c * tx - s * ty;
+    double vy = s * tx + c * ty;
+    *qx = (int)floor(vx + 0.5 + 1e-9);
+    *qy = (int)floor(vy + 0.5 + 1e-9);
+    double gx = (double)p.gx, gy = (double)p.gy;
+    double m = sqrt(gx * gx + gy * gy);
+    double dx = gx / m, dy = gy / m;
+    *rx = c * dx - s * dy;
+    *ry = s * dx + c * dy;
+}
+
+__device__ __forceinline__ double level_theta(double theta_min, double step, int k)
+{
+#pragma clang fp contract(off)
+    return theta_min + (double)k * step;
+}
+
+// Angle index on a level grid: wrap for a full circle, clamp otherwise.
+__device__ __forceinline__ int angle_index(int k, int K, int full)
+{
+    if (full) {
+        int m = k % K;
+        return m < 0 ? m + K : m;
+    }
+    return k < 0 ? 0 : (k > K - 1 ? K - 1 : k);
+}
+
+// Dot of a rotated model direction with the field at (x, y); 0 outside the
+// image (and at non-edge pixels, whose stored direction is (0, 0)).
+__device__ __forceinline__ float field_dot(const void* field, int precision, int W, int H, int x, int y, float rx,
+                                           float ry)
+{
+    if (x < 0 || y < 0 || x >= W || y >= H) return 0.0f;
+    size_t o = (size_t)y * W + x;
+    if (precision == TM_FP16) {
+        __half2 g = reinterpret_cast<const __half2*>(field)[o];
+        float2 f = __half22float2(g);
+        return rx * f.x + ry * f.y;
+    }
+    float2 g = reinterpret_cast<const float2*>(field)[o];
+    return rx * g.x + ry * g.y;
+}
+
+// The selection key: S_w desc, S_1 desc, then position x asc, y asc, then
+// angle index asc.  true iff (aw, a1, ax, ay, ak) ranks strictly before b.
+__device__ __forceinline__ bool key_better(float aw, float a1, int ax, int ay, int ak, float bw, float b1, int bx,
+                                           int by, int bk)
+{
+    if (aw != bw) return aw > bw;
+    if (a1 != b1) return a1 > b1;
+    if (ax != bx) return ax < bx;
+    if (ay != by) return ay < by;
+    return ak < bk;
+}
+
+}  // namespace tmk

@@ -1,0 +1,319 @@
+"""Python binding of the C ABI in include/tm.h (argument marshalling only).
+
+Every computation runs in the HIP library ``lib/libtm.so``; torch supplies
+device memory and the current stream.  Importing works without the library;
+the first call that needs it raises ``TMError`` if it has not been built
+(``python -m paper_2112_05576_amd.build``).  There is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libtm.so")
+
+TM_OK, TM_EINVAL, TM_ENOMEM, TM_EDEVICE, TM_ECAPACITY = 0, -1, -2, -3, -4
+TM_FP32, TM_FP16 = 0, 1
+MAX_LEVELS = 8
+
+
+class TMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"tm status {status}: {msg}")
+        self.status = status
+
+
+class PyrParamsC(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("edge_thresh", ctypes.c_float), ("precision", ctypes.c_int32)]
+
+
+class SearchParamsC(ctypes.Structure):
+    _fields_ = [("step_x", ctypes.c_int32), ("step_y", ctypes.c_int32), ("theta_min_deg", ctypes.c_double),
+                ("theta_range_deg", ctypes.c_double), ("theta_step_top_deg", ctypes.c_double),
+                ("neighbourhood", ctypes.c_int32), ("min_score", ctypes.c_float), ("nms_min_dist", ctypes.c_float),
+                ("max_candidates", ctypes.c_int32), ("max_matches", ctypes.c_int32)]
+
+
+# tm_pose: x, y, k, level (int32), theta_deg, score_w, score_1 (float32), reserved
+POSE_WORDS = 8
+POSE_DTYPE = np.dtype([("x", "<i4"), ("y", "<i4"), ("k", "<i4"), ("level", "<i4"), ("theta", "<f4"),
+                       ("sw", "<f4"), ("s1", "<f4"), ("reserved", "<i4")])
+EVAL_DTYPE = np.dtype([("x", "<i4"), ("y", "<i4"), ("theta", "<f8")])
+
+_lib = None
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+
+
+def lib():
+    """The loaded C library; raises TMError if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise TMError(TM_EDEVICE, f"HIP library not built: {LIB_PATH} (run paper_2112_05576_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "tm_build_model": [_vp, _i32, _i32, _i32, ctypes.POINTER(PyrParamsC), _vp, ctypes.POINTER(_vp)],
+            "tm_build_pyramid": [_vp, _i32, _i32, _i32, ctypes.POINTER(PyrParamsC), _vp, ctypes.POINTER(_vp)],
+            "tm_update_pyramid": [_vp, _vp, _i32, _vp],
+            "tm_score_poses": [_vp, _vp, _i32, _i32, _vp, _i32, _vp, _vp],
+            "tm_score_map": [_vp, _vp, _i32, ctypes.POINTER(SearchParamsC), _vp, _vp, _vp, _vp],
+            "tm_select": [_vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, ctypes.c_float, ctypes.c_float, _vp, _i32,
+                          _vp, _vp],
+            "tm_detect": [_vp, _vp, ctypes.POINTER(SearchParamsC), _vp, _i32, _vp, _vp],
+            "tm_refine": [_vp, _vp, ctypes.POINTER(SearchParamsC), _vp, _i32, _vp],
+            "tm_model_level_info": [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
+            "tm_model_points": [_vp, _i32, _vp, _vp, _vp],
+            "tm_model_table": [_vp, _i32, ctypes.c_double, ctypes.c_double, _i32, _vp, _vp, _vp],
+            "tm_pyramid_level": [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_vp),
+                                 ctypes.POINTER(_vp), ctypes.POINTER(_i32)],
+            "tm_pyramid_read": [_vp, _i32, _vp, _vp, _vp],
+            "tm_timing_enable": [_i32],
+            "tm_timing_read": [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32)],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.tm_model_free.argtypes = [_vp]
+        L.tm_model_free.restype = None
+        L.tm_pyramid_free.argtypes = [_vp]
+        L.tm_pyramid_free.restype = None
+        L.tm_last_error.restype = ctypes.c_char_p
+        L.tm_version.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != TM_OK:
+        raise TMError(st, lib().tm_last_error().decode())
+
+
+def _stream(stream=None) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _dev_u8(img) -> torch.Tensor:
+    if isinstance(img, np.ndarray):
+        img = torch.from_numpy(np.ascontiguousarray(img, dtype=np.uint8))
+    if img.dtype != torch.uint8 or img.dim() != 2:
+        raise TMError(TM_EINVAL, "image must be a 2-D uint8 array")
+    if not img.is_cuda:
+        img = img.cuda()
+    if img.stride(1) != 1:
+        img = img.contiguous()
+    return img
+
+
+@dataclass
+class SearchParams:
+    """Search settings (see tm_search_params in include/tm.h)."""
+    step_x: int = 1
+    step_y: int = 1
+    theta_min: float = 0.0
+    theta_range: float = 360.0
+    theta_step_top: float = 1.0
+    neighbourhood: int = 3
+    min_score: float = 0.5
+    nms_min_dist: float = 0.0
+    max_candidates: int = 32
+    max_matches: int = 8
+
+    def c(self) -> SearchParamsC:
+        return SearchParamsC(self.step_x, self.step_y, self.theta_min, self.theta_range, self.theta_step_top,
+                             self.neighbourhood, self.min_score, self.nms_min_dist, self.max_candidates,
+                             self.max_matches)
+
+
+class Model:
+    """Edge-point model of a template image on every pyramid level."""
+
+    def __init__(self, img, levels: int, edge_thresh: float, stream=None):
+        img = _dev_u8(img)
+        self._h = _vp()
+        p = PyrParamsC(levels, edge_thresh, TM_FP32)
+        H, W = img.shape
+        _check(lib().tm_build_model(_vp(img.data_ptr()), W, H, img.stride(0), ctypes.byref(p),
+                                    _vp(_stream(stream)), ctypes.byref(self._h)))
+        self.levels = levels
+
+    @property
+    def handle(self):
+        return self._h
+
+    def level_info(self, level: int):
+        w, h, n = _i32(), _i32(), _i32()
+        _check(lib().tm_model_level_info(self._h, level, ctypes.byref(w), ctypes.byref(h), ctypes.byref(n)))
+        return w.value, h.value, n.value
+
+    def points(self, level: int, stream=None):
+        n = self.level_info(level)[2]
+        t = torch.empty((n, 2), dtype=torch.int32, device="cuda")
+        g = torch.empty((n, 2), dtype=torch.int32, device="cuda")
+        _check(lib().tm_model_points(self._h, level, _vp(t.data_ptr()), _vp(g.data_ptr()), _vp(_stream(stream))))
+        return t, g
+
+    def table(self, level: int, theta_min: float, step: float, K: int, stream=None):
+        n = self.level_info(level)[2]
+        q = torch.empty((K, n, 2), dtype=torch.int32, device="cuda")
+        r = torch.empty((K, n, 2), dtype=torch.float32, device="cuda")
+        _check(lib().tm_model_table(self._h, level, theta_min, step, K, _vp(q.data_ptr()), _vp(r.data_ptr()),
+                                    _vp(_stream(stream))))
+        return q, r
+
+    def free(self):
+        if self._h:
+            lib().tm_model_free(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Pyramid:
+    """Grey-level pyramid and unit-direction field of a search image."""
+
+    def __init__(self, img, levels: int, edge_thresh: float, precision: int = TM_FP32, stream=None):
+        img = _dev_u8(img)
+        self._h = _vp()
+        p = PyrParamsC(levels, edge_thresh, precision)
+        H, W = img.shape
+        _check(lib().tm_build_pyramid(_vp(img.data_ptr()), W, H, img.stride(0), ctypes.byref(p),
+                                      _vp(_stream(stream)), ctypes.byref(self._h)))
+        self.levels = levels
+        self.precision = precision
+        self.shape = (H, W)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def update(self, img, stream=None):
+        img = _dev_u8(img)
+        _check(lib().tm_update_pyramid(self._h, _vp(img.data_ptr()), img.stride(0), _vp(_stream(stream))))
+
+    def level_shape(self, level: int):
+        w, h, prec = _i32(), _i32(), _i32()
+        a, b = _vp(), _vp()
+        _check(lib().tm_pyramid_level(self._h, level, ctypes.byref(w), ctypes.byref(h), ctypes.byref(a),
+                                      ctypes.byref(b), ctypes.byref(prec)))
+        return h.value, w.value
+
+    def read(self, level: int, stream=None):
+        """(uint8 image, direction field as float32 (H, W, 2)) of a level."""
+        H, W = self.level_shape(level)
+        img = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+        dt = torch.float16 if self.precision == TM_FP16 else torch.float32
+        fld = torch.empty((H, W, 2), dtype=dt, device="cuda")
+        _check(lib().tm_pyramid_read(self._h, level, _vp(img.data_ptr()), _vp(fld.data_ptr()),
+                                     _vp(_stream(stream))))
+        return img, fld
+
+    def free(self):
+        if self._h:
+            lib().tm_pyramid_free(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def poses_to_numpy(t: torch.Tensor, n: int | None = None) -> np.ndarray:
+    a = t.detach().cpu().numpy().view(POSE_DTYPE).reshape(-1)
+    return a if n is None else a[:n]
+
+
+def score_poses(model: Model, pyr: Pyramid, level: int, x, y, theta, neighbourhood: int = 3, stream=None):
+    """S_w and S_1 (float32 tensor (n, 2)) of integer translations x, y and angles theta (degrees)."""
+    ep = np.zeros(len(x), EVAL_DTYPE)
+    ep["x"] = np.asarray(x, np.int32)
+    ep["y"] = np.asarray(y, np.int32)
+    ep["theta"] = np.asarray(theta, np.float64)
+    dev = torch.from_numpy(ep.view(np.uint8)).cuda()
+    out = torch.empty((len(ep), 2), dtype=torch.float32, device="cuda")
+    _check(lib().tm_score_poses(model.handle, pyr.handle, level, neighbourhood, _vp(dev.data_ptr()), len(ep),
+                                _vp(out.data_ptr()), _vp(_stream(stream))))
+    return out
+
+
+def score_map(model: Model, pyr: Pyramid, level: int, sp: SearchParams, stream=None):
+    """Best (S_w, S_1, k) per translation of the level's step grid."""
+    H, W = pyr.level_shape(level)
+    gh, gw = (H + sp.step_y - 1) // sp.step_y, (W + sp.step_x - 1) // sp.step_x
+    sw = torch.empty((gh, gw), dtype=torch.float32, device="cuda")
+    s1 = torch.empty((gh, gw), dtype=torch.float32, device="cuda")
+    k = torch.empty((gh, gw), dtype=torch.int32, device="cuda")
+    c = sp.c()
+    _check(lib().tm_score_map(model.handle, pyr.handle, level, ctypes.byref(c), _vp(sw.data_ptr()),
+                              _vp(s1.data_ptr()), _vp(k.data_ptr()), _vp(_stream(stream))))
+    return sw, s1, k
+
+
+def select(sw: torch.Tensor, s1: torch.Tensor, k: torch.Tensor, sx: int, sy: int, level: int, min_score: float,
+           dmin: float, capacity: int, stream=None):
+    """Candidate selection on a map; returns (poses int32 tensor (capacity, 8), count tensor)."""
+    sw, s1, k = sw.contiguous(), s1.contiguous(), k.contiguous().to(torch.int32)
+    gh, gw = sw.shape
+    out = torch.empty((capacity, POSE_WORDS), dtype=torch.int32, device="cuda")
+    n = torch.zeros(1, dtype=torch.int32, device="cuda")
+    _check(lib().tm_select(_vp(sw.data_ptr()), _vp(s1.data_ptr()), _vp(k.data_ptr()), gw, gh, sx, sy, level,
+                           min_score, dmin, _vp(out.data_ptr()), capacity, _vp(n.data_ptr()), _vp(_stream(stream))))
+    return out, n
+
+
+def detect_async(model: Model, pyr: Pyramid, sp: SearchParams, out: torch.Tensor, n_out: torch.Tensor,
+                 stream=None):
+    """Enqueue a detection writing into caller buffers (no synchronisation)."""
+    c = sp.c()
+    _check(lib().tm_detect(model.handle, pyr.handle, ctypes.byref(c), _vp(out.data_ptr()), out.shape[0],
+                           _vp(n_out.data_ptr()), _vp(_stream(stream))))
+
+
+def detect(model: Model, pyr: Pyramid, sp: SearchParams, capacity: int | None = None, stream=None) -> np.ndarray:
+    """Detections at level 0 as a numpy structured array (POSE_DTYPE)."""
+    cap = capacity or sp.max_matches
+    out = torch.empty((cap, POSE_WORDS), dtype=torch.int32, device="cuda")
+    n = torch.zeros(1, dtype=torch.int32, device="cuda")
+    detect_async(model, pyr, sp, out, n, stream)
+    m = int(n.item())
+    return poses_to_numpy(out, m)
+
+
+def refine(model: Model, pyr: Pyramid, sp: SearchParams, poses: np.ndarray, stream=None) -> np.ndarray:
+    """Refine poses (POSE_DTYPE, each at its level) down to level 0."""
+    a = np.ascontiguousarray(poses, dtype=POSE_DTYPE)
+    dev = torch.from_numpy(a.view(np.int32).reshape(-1, POSE_WORDS).copy()).cuda()
+    c = sp.c()
+    _check(lib().tm_refine(model.handle, pyr.handle, ctypes.byref(c), _vp(dev.data_ptr()), len(a),
+                           _vp(_stream(stream))))
+    return poses_to_numpy(dev)
+
+
+def timing_enable(on: bool = True):
+    """Record HIP events around every exhaustive-search kernel launch."""
+    _check(lib().tm_timing_enable(1 if on else 0))
+
+
+def timing_read():
+    """(total ms, launches) of the search kernels recorded since the last read."""
+    ms, n = ctypes.c_double(), _i32()
+    _check(lib().tm_timing_read(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
+def version() -> str:
+    return lib().tm_version().decode()

@@ -1,0 +1,358 @@
+"""GPU (HIP library, through the C ABI) against the FP64 oracle on the same
+seeded inputs.
+
+Bars: bit-exact uint8 pyramid levels, edge masks, model points and rotated
+position offsets; directions within FP32 rounding; scores within 1e-5
+absolute (FP32 path); the chosen angle / pose equal to the oracle's or, where
+several are correct, one whose oracle key lies within 1e-5 of the oracle's
+best (a tie at FP32 resolution)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2112_05576_amd as P
+
+    P.lib()  # raises if the HIP library is missing
+    return P
+
+
+def _P():
+    import paper_2112_05576_amd as P
+
+    return P
+
+
+def _scene_img(H, W, seed):
+    rng = np.random.default_rng(seed)
+    sh = synth.make_model_shape("polygon", 96, rng)
+    sc = synth.render_scene(rng, W, H, sh, 96, 1 if min(H, W) > 110 else 0, 6.0, 0.2, (0.7, 1.4), (-20, 20),
+                            clutter=20)
+    return sc.image
+
+
+# ------------------------------------------------------------ pyramid, edges
+@pytest.mark.parametrize("H,W,L,tau,pad", [(128, 128, 1, 30.0, 0), (480, 640, 4, 80.0, 0), (211, 333, 3, 45.5, 13),
+                                           (2048, 2048, 5, 80.0, 0), (24, 40, 4, 20.0, 5)])
+def test_pyramid_and_edges(H, W, L, tau, pad):
+    P = _P()
+    case(f"pyramid {W}x{H} L={L} tau={tau} pad={pad}")
+    img = _scene_img(H, W, 7000 + H + W)
+    big = np.zeros((H, W + pad), np.uint8)
+    big[:, :W] = img
+    dev = torch.from_numpy(big).cuda()[:, :W]
+    pyr = P.Pyramid(dev, L, tau)
+    ref_levels = O.pyramid(img, L)
+    for l in range(L):
+        gi, gf = pyr.read(l)
+        gi = gi.cpu().numpy()
+        gf = gf.cpu().numpy().astype(np.float64)
+        assert np.array_equal(gi, ref_levels[l]), f"level {l} pixels"
+        of = O.edge_field(ref_levels[l], tau)
+        assert np.array_equal(np.any(gf != 0, -1), np.any(of != 0, -1)), f"level {l} edge mask"
+        assert np.abs(gf - of).max() <= 6e-8, f"level {l} directions"
+
+
+def test_pyramid_update_reuses_storage():
+    P = _P()
+    case("pyramid update")
+    a = _scene_img(96, 128, 1)
+    b = _scene_img(96, 128, 2)
+    pyr = P.Pyramid(a, 3, 40.0)
+    pyr.update(torch.from_numpy(b).cuda())
+    for l, lv in enumerate(O.pyramid(b, 3)):
+        assert np.array_equal(pyr.read(l)[0].cpu().numpy(), lv)
+
+
+# ------------------------------------------------------------ model, tables
+@pytest.mark.parametrize("ci", [1, 2, 3])
+def test_model_points_and_tables(ci):
+    P = _P()
+    sc = synth.scene_for_config(ci)
+    cfg = sc.config
+    L = cfg["levels"]
+    case(f"model C{ci} L={L}")
+    gm = P.Model(sc.model, L, cfg["tau_m"])
+    om = O.build_model(sc.model, O.PyrParams(L, cfg["tau_m"]))
+    for l in range(L):
+        t, g = gm.points(l)
+        t = t.cpu().numpy()
+        g = g.cpu().numpy().astype(np.float64)
+        assert np.array_equal(t, om.levels[l].t), f"level {l} t"
+        d = g / np.hypot(g[:, 0], g[:, 1])[:, None]
+        assert np.abs(d - om.levels[l].d).max() <= 1e-15
+    sp = O.SearchParams(theta_step_top=cfg["theta_step_top"], theta_range=cfg["theta_range"])
+    for l in sorted({L - 1, 0}):
+        st = O.level_step(sp, L, l)
+        K = O.level_count(sp, st)
+        q, r = gm.table(l, 0.0, st, K)
+        q = q.cpu().numpy()
+        r = r.cpu().numpy().astype(np.float64)
+        ks = range(K) if l == L - 1 else np.random.default_rng(3).choice(K, 40, replace=False)
+        ml = om.levels[l]
+        for k in ks:
+            oq, orr = O.rotate(ml.t, ml.d, O.theta(0.0, st, int(k)))
+            assert np.array_equal(q[k], oq), f"level {l} angle {k} q"
+            assert np.abs(r[k] - orr).max() <= 6e-8
+
+
+# ------------------------------------------------------------ scores
+@pytest.mark.parametrize("ci,level,win", [(1, 0, 3), (1, 0, 1), (1, 0, 5), (2, 2, 3), (2, 0, 3), (3, 4, 3)])
+def test_score_poses(ci, level, win):
+    P = _P()
+    sc = synth.scene_for_config(ci)
+    cfg = sc.config
+    L = cfg["levels"]
+    case(f"score_poses C{ci} level={level} win={win}")
+    gm = P.Model(sc.model, L, cfg["tau_m"])
+    pyr = P.Pyramid(sc.image, L, cfg["tau_s"])
+    om = O.build_model(sc.model, O.PyrParams(L, cfg["tau_m"]))
+    g = O.field_pyramid(sc.image, L, cfg["tau_s"])[level]
+    H, W, _ = g.shape
+    rng = np.random.default_rng(11 + level)
+    n = 300
+    xs = rng.integers(-12, W + 12, n)
+    ys = rng.integers(-12, H + 12, n)
+    th = rng.uniform(-400.0, 400.0, n)
+    th[:8] = [0.0, 90.0, 180.0, 270.0, 30.0, 45.0, 60.0, -90.0]
+    for i, it in enumerate(sc.instances[:3]):  # poses on the instances score high
+        s = 2.0 ** -level
+        xs[8 + i], ys[8 + i], th[8 + i] = int(round(it.x * s)), int(round(it.y * s)), it.theta
+    got = P.score_poses(gm, pyr, level, xs, ys, th, win).cpu().numpy().astype(np.float64)
+    ml = om.levels[level]
+    ref = np.array([O.score(g, ml.t, ml.d, int(xs[i]), int(ys[i]), float(th[i]), win) for i in range(n)])
+    err = np.abs(got - ref).max()
+    print(f"max |err| = {err:.3g}, max score {ref[:, 0].max():.3f}")
+    assert err <= TOL
+
+
+def _check_map(gm_map, om_map, g, ml, theta_min, step, sx, sy, win):
+    """S_w, S_1 within TOL everywhere; the angle equal or an oracle tie."""
+    sw, s1, k = [t.cpu().numpy() for t in gm_map]
+    mw, m1, mk = om_map
+    assert sw.shape == mw.shape
+    ew, e1 = np.abs(sw - mw).max(), np.abs(s1 - m1).max()
+    print(f"map {sw.shape}: max |dS_w| {ew:.3g} |dS_1| {e1:.3g}")
+    assert ew <= TOL and e1 <= TOL
+    diff = np.argwhere(k != mk)
+    for (j, i) in diff:
+        a = O.score(g, ml.t, ml.d, int(i * sx), int(j * sy), O.theta(theta_min, step, int(k[j, i])), win)
+        assert abs(a[0] - mw[j, i]) <= TOL and abs(a[1] - m1[j, i]) <= TOL, (i, j, k[j, i], mk[j, i])
+    print(f"angle differs at {len(diff)} of {k.size} translations (all ties)")
+
+
+@pytest.mark.parametrize("ci,step_top", [(1, 5.0), (2, 1.0), (3, 8.0)])
+def test_score_map_top_level(ci, step_top):
+    P = _P()
+    sc = synth.scene_for_config(ci)
+    cfg = sc.config
+    L = cfg["levels"]
+    top = L - 1
+    case(f"score_map C{ci} top level {top}")
+    gm = P.Model(sc.model, L, cfg["tau_m"])
+    pyr = P.Pyramid(sc.image, L, cfg["tau_s"])
+    sp = P.SearchParams(theta_step_top=step_top)
+    got = P.score_map(gm, pyr, top, sp)
+    om = O.build_model(sc.model, O.PyrParams(L, cfg["tau_m"]))
+    g = O.field_pyramid(sc.image, L, cfg["tau_s"])[top]
+    ml = om.levels[top]
+    K = int(np.ceil(360.0 / step_top))
+    ref = O.top_map(g, ml.t, ml.d, 0.0, step_top, K)
+    _check_map(got, ref, g, ml, 0.0, step_top, 1, 1, 3)
+
+
+@pytest.mark.parametrize("H,W,sx,sy,win,rng_deg", [(61, 67, 1, 1, 3, 360.0), (64, 60, 2, 3, 3, 360.0),
+                                                   (50, 53, 1, 1, 5, 90.0), (45, 47, 3, 3, 1, 360.0),
+                                                   (40, 201, 1, 1, 3, 360.0)])
+def test_score_map_shapes_and_paths(H, W, sx, sy, win, rng_deg):
+    """Ragged tile tails, the generic path (steps > 1, other windows), a
+    partial angle range."""
+    P = _P()
+    case(f"score_map {W}x{H} step=({sx},{sy}) win={win} range={rng_deg}")
+    rng = np.random.default_rng(900 + H)
+    shape = synth.make_model_shape("blocks", 24, rng)
+    model = synth.render_model(shape, 24)
+    sc = synth.render_scene(rng, W, H, shape, 24, 1, 5.0, clutter=6)
+    gm = P.Model(model, 1, 30.0)
+    pyr = P.Pyramid(sc.image, 1, 30.0)
+    step = 7.5
+    sp = P.SearchParams(step_x=sx, step_y=sy, neighbourhood=win, theta_step_top=step, theta_min=-20.0,
+                        theta_range=rng_deg)
+    got = P.score_map(gm, pyr, 0, sp)
+    om = O.build_model(model, O.PyrParams(1, 30.0))
+    g = O.edge_field(sc.image, 30.0)
+    ml = om.levels[0]
+    osp = O.SearchParams(theta_step_top=step, theta_range=rng_deg)
+    K = O.level_count(osp, step)
+    ref = O.top_map(g, ml.t, ml.d, -20.0, step, K, sx, sy, win)
+    _check_map(got, ref, g, ml, -20.0, step, sx, sy, win)
+
+
+# ------------------------------------------------------------ selection
+def test_select_golden_cases():
+    import json
+    import os
+
+    P = _P()
+    cases = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "select_cases.json")))
+    for c in cases["select"]:
+        case(f"select {c['name']}")
+        sw = torch.tensor(c["mw"], dtype=torch.float32).cuda()
+        s1 = torch.tensor(c["m1"], dtype=torch.float32).cuda()
+        k = torch.tensor(c["mk"], dtype=torch.int32).cuda()
+        out, n = P.select(sw, s1, k, c["sx"], c["sy"], c["level"], c["min_score"], c["dmin"], c["max_out"])
+        got = P.poses_to_numpy(out, int(n.item()))
+        assert len(got) == len(c["expect"]), c["name"]
+        for g, e in zip(got, c["expect"]):
+            assert (g["x"], g["y"], g["k"]) == tuple(e[:3]), c["name"]
+            assert g["sw"] == np.float32(e[3]) and g["s1"] == np.float32(e[4])
+
+
+@pytest.mark.parametrize("seed,dmin,cap", [(0, 12.0, 32), (1, 0.0, 1024), (2, 40.0, 5)])
+def test_select_on_oracle_maps(seed, dmin, cap):
+    """The same FP32 map into both selections: identical candidate lists."""
+    P = _P()
+    case(f"select on C2 map seed={seed} dmin={dmin} cap={cap}")
+    sc = synth.scene_for_config(2, seed)
+    cfg = sc.config
+    om = O.build_model(sc.model, O.PyrParams(4, cfg["tau_m"]))
+    g = O.field_pyramid(sc.image, 4, cfg["tau_s"])[3]
+    ml = om.levels[3]
+    mw, m1, mk = O.top_map(g, ml.t, ml.d, 0.0, 4.0, 90)
+    mw32, m132 = mw.astype(np.float32), m1.astype(np.float32)
+    ref = O.select(mw32.astype(np.float64), m132.astype(np.float64), mk, 1, 1, 3, 0.3, dmin, cap)
+    out, n = P.select(torch.from_numpy(mw32).cuda(), torch.from_numpy(m132).cuda(),
+                      torch.from_numpy(mk).cuda(), 1, 1, 3, 0.3, dmin, cap)
+    got = P.poses_to_numpy(out, int(n.item()))
+    print(f"{len(ref)} candidates")
+    assert len(got) == len(ref) and len(ref) > 0
+    assert np.array_equal(got["x"], ref.x) and np.array_equal(got["y"], ref.y) and np.array_equal(got["k"], ref.k)
+    assert np.array_equal(got["sw"], ref.sw.astype(np.float32))
+
+
+def test_select_large_candidate_count():
+    """More local maxima than the in-LDS sort holds: the global-memory path."""
+    P = _P()
+    case("select with > 2048 local maxima")
+    rng = np.random.default_rng(5)
+    gh, gw = 160, 200
+    mw = rng.random((gh, gw)).astype(np.float32)
+    m1 = rng.random((gh, gw)).astype(np.float32)
+    mk = rng.integers(0, 50, (gh, gw)).astype(np.int32)
+    ref = O.select(mw.astype(np.float64), m1.astype(np.float64), mk, 2, 2, 1, 0.0, 3.0, 1024)
+    out, n = P.select(torch.from_numpy(mw).cuda(), torch.from_numpy(m1).cuda(), torch.from_numpy(mk).cuda(), 2, 2,
+                      1, 0.0, 3.0, 1024)
+    got = P.poses_to_numpy(out, int(n.item()))
+    assert len(got) == len(ref)
+    assert np.array_equal(got["x"], ref.x) and np.array_equal(got["y"], ref.y) and np.array_equal(got["k"], ref.k)
+
+
+# ------------------------------------------------------------ refine, detect
+def _oracle_key(fields, om, sp, L, x, y, k, level=0):
+    st = O.level_step(sp, L, level)
+    ml = om.levels[level]
+    return O.score(fields[level], ml.t, ml.d, int(x), int(y), O.theta(sp.theta_min, st, int(k)), sp.neighbourhood)
+
+
+def _match_detections(got, ref, fields, om, osp, L):
+    assert len(got) == len(ref), (len(got), len(ref))
+    ties = 0
+    for g, r in zip(got, ref):
+        if (int(g["x"]), int(g["y"]), int(g["k"])) == (r.x, r.y, r.k):
+            assert abs(g["sw"] - r.sw) <= TOL and abs(g["s1"] - r.s1) <= TOL
+            continue
+        a = _oracle_key(fields, om, osp, L, g["x"], g["y"], g["k"])
+        assert abs(a[0] - r.sw) <= TOL and abs(a[1] - r.s1) <= TOL, (g, r)
+        ties += 1
+    return ties
+
+
+@pytest.mark.parametrize("ci,index", [(1, 0), (1, 1), (2, 0), (2, 1), (3, 0)])
+def test_detect_matches_oracle(ci, index):
+    P = _P()
+    sc = synth.scene_for_config(ci, index)
+    cfg = sc.config
+    L = cfg["levels"]
+    case(f"detect C{ci} image {index}")
+    osp = O.SearchParams(theta_step_top=cfg["theta_step_top"], theta_range=360.0)
+    tr = O.detect(sc.image, sc.model, O.PyrParams(L, cfg["tau_s"]), O.PyrParams(L, cfg["tau_m"]), osp)
+    gm = P.Model(sc.model, L, cfg["tau_m"])
+    pyr = P.Pyramid(sc.image, L, cfg["tau_s"])
+    got = P.detect(gm, pyr, P.SearchParams(theta_step_top=cfg["theta_step_top"]))
+    ties = _match_detections(got, tr.detections, tr.fields, tr.model, osp, L)
+    print(f"{len(got)} detections, {ties} ties; truth {[(round(i.x), round(i.y), round(i.theta)) for i in sc.instances]}")
+
+
+@pytest.mark.parametrize("quarter", [0, 1, 2, 3])
+def test_detect_pasted_model_exact(quarter):
+    P = _P()
+    case(f"detect pasted model quarter={quarter}")
+    rng = np.random.default_rng(20211200 + 500 + quarter)
+    model = synth.render_model(synth.make_model_shape("blocks", 32, rng), 32)
+    img = synth.paste_rot90(model, 128, 112, 63, 48, quarter)
+    gm = P.Model(model, 3, 30.0)
+    pyr = P.Pyramid(img, 3, 30.0)
+    got = P.detect(gm, pyr, P.SearchParams(theta_step_top=10.0, max_matches=1))
+    assert len(got) == 1
+    d = got[0]
+    assert (d["x"], d["y"], d["theta"]) == (63, 48, 90.0 * quarter)
+    assert abs(d["sw"] - 1) <= TOL and abs(d["s1"] - 1) <= TOL
+
+
+def test_refine_matches_oracle():
+    P = _P()
+    case("refine C2 oracle candidates")
+    sc = synth.scene_for_config(2, 2)
+    cfg = sc.config
+    L = 4
+    osp = O.SearchParams(theta_step_top=1.0)
+    tr = O.detect(sc.image, sc.model, O.PyrParams(L, cfg["tau_s"]), O.PyrParams(L, cfg["tau_m"]), osp)
+    cand = tr.candidates
+    poses = np.zeros(len(cand), P.POSE_DTYPE)
+    poses["x"], poses["y"], poses["k"], poses["level"] = cand.x, cand.y, cand.k, L - 1
+    poses["sw"], poses["s1"] = cand.sw, cand.s1
+    gm = P.Model(sc.model, L, cfg["tau_m"])
+    pyr = P.Pyramid(sc.image, L, cfg["tau_s"])
+    got = P.refine(gm, pyr, P.SearchParams(theta_step_top=1.0), poses)
+    ref = tr.refined[-1]
+    ties = 0
+    for i in range(len(cand)):
+        g = got[i]
+        if (g["x"], g["y"], g["k"]) == (ref.x[i], ref.y[i], ref.k[i]):
+            assert abs(g["sw"] - ref.sw[i]) <= TOL and abs(g["s1"] - ref.s1[i]) <= TOL
+            continue
+        a = _oracle_key(tr.fields, tr.model, osp, L, g["x"], g["y"], g["k"])
+        assert abs(a[0] - ref.sw[i]) <= TOL and abs(a[1] - ref.s1[i]) <= TOL, (i, g, ref.rows()[i])
+        ties += 1
+    print(f"{len(cand)} candidates refined, {ties} ties")
+
+
+def test_detect_is_deterministic():
+    P = _P()
+    case("determinism")
+    sc = synth.scene_for_config(2, 3)
+    cfg = sc.config
+    gm = P.Model(sc.model, 4, cfg["tau_m"])
+    pyr = P.Pyramid(sc.image, 4, cfg["tau_s"])
+    sp = P.SearchParams()
+    a = P.detect(gm, pyr, sp)
+    m1 = [t.clone() for t in P.score_map(gm, pyr, 3, sp)]
+    for _ in range(3):
+        assert np.array_equal(P.detect(gm, pyr, sp), a)
+        m2 = P.score_map(gm, pyr, 3, sp)
+        assert all(torch.equal(x, y) for x, y in zip(m1, m2))
