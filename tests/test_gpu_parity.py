@@ -304,13 +304,15 @@ def test_detect_pasted_model_exact(quarter):
     case(f"detect pasted model quarter={quarter}")
     rng = np.random.default_rng(20211200 + 500 + quarter)
     model = synth.render_model(synth.make_model_shape("blocks", 32, rng), 32)
-    img = synth.paste_rot90(model, 128, 112, 63, 48, quarter)
+    # the quarter-turned model's cells align with the 4x4 cells of level 2
+    ux, uy = [(64, 48), (63, 48), (63, 47), (64, 47)][quarter]
+    img = synth.paste_rot90(model, 128, 112, ux, uy, quarter)
     gm = P.Model(model, 3, 30.0)
     pyr = P.Pyramid(img, 3, 30.0)
     got = P.detect(gm, pyr, P.SearchParams(theta_step_top=10.0, max_matches=1))
     assert len(got) == 1
     d = got[0]
-    assert (d["x"], d["y"], d["theta"]) == (63, 48, 90.0 * quarter)
+    assert (d["x"], d["y"], d["theta"]) == (ux, uy, 90.0 * quarter)
     assert abs(d["sw"] - 1) <= TOL and abs(d["s1"] - 1) <= TOL
 
 

@@ -183,21 +183,22 @@ def test_T1_pasted_model_scores_one_and_is_found(oracle_mod, quarter):
     assert np.sum(mw >= mw[uy, ux]) >= 2 and m1[uy, ux] == m1[mw >= mw[uy, ux]].max()
 
 
-@pytest.mark.parametrize("levels,ux,uy", [(2, 47, 40), (2, 49, 42), (3, 63, 48), (3, 67, 52)])
-def test_T1_coarse_to_fine_finds_exact_pose(oracle_mod, levels, ux, uy):
+@pytest.mark.parametrize("levels,ux,uy,quarter", [(2, 47, 40, 1), (2, 49, 42, 1), (3, 63, 48, 1), (3, 67, 52, 1),
+                                                  (3, 64, 48, 0), (3, 63, 47, 2), (3, 64, 47, 3)])
+def test_T1_coarse_to_fine_finds_exact_pose(oracle_mod, levels, ux, uy, quarter):
     """Search starts at the top image and refines down (Sec. II para. 2).
     A level-l cell of the model covers offsets t in [2^l a - 16, 2^l a - 16 +
-    2^l - 1]; after the quarter turn its first column is ux + 17 - 2^l (b + 1),
-    a multiple of 2^l exactly when ux = -1 (mod 2^l), and its first row is
-    uy - 16 + 2^l a, a multiple when uy = 0 (mod 2^l).  Then every level of the
-    search image is an exact paste of the model's level and the top level
-    scores exactly 1 at 90 degrees."""
+    2^l - 1] on each axis.  A turn that keeps an axis starts the cell at
+    u - 16 + 2^l a, a multiple of 2^l when u = 0 (mod 2^l); a turn that
+    negates it starts the cell at u + 17 - 2^l (a + 1), a multiple when
+    u = -1 (mod 2^l).  Then every level of the search image is an exact paste
+    of the model's level and the top level scores exactly 1 at the turn."""
     model = _model32(7)
-    img = synth.paste_rot90(model, 128, 112, ux, uy, 1)
+    img = synth.paste_rot90(model, 128, 112, ux, uy, quarter)
     sp = oracle_mod.SearchParams(theta_step_top=10.0, min_score=0.5, max_matches=1)
     tr = oracle_mod.detect(img, model, oracle_mod.PyrParams(levels, 30.0), oracle_mod.PyrParams(levels, 30.0), sp)
     d = tr.detections[0]
-    assert (d.x, d.y, d.theta) == (ux, uy, 90.0)
+    assert (d.x, d.y, d.theta) == (ux, uy, 90.0 * quarter)
     assert abs(d.sw - 1.0) <= 1e-12 and abs(d.s1 - 1.0) <= 1e-12
 
 
