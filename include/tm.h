@@ -164,11 +164,12 @@ tm_status tm_select(const float* sw_dev, const float* s1_dev, const int32_t* k_d
 tm_status tm_detect(const tm_model* model, tm_pyramid* pyr, const tm_search_params* params,
                     tm_pose* out_dev, int32_t capacity, int32_t* n_out_dev, void* stream);
 
-/* Coarse-to-fine refinement of n poses (each at its own `level`, a grid
- * index k of that level) down to level 0; poses are replaced in place by the
- * best of the 27-pose neighbourhood at each level below theirs.  No
- * selection is applied. */
-tm_status tm_refine(const tm_model* model, tm_pyramid* pyr, const tm_search_params* params,
+/* Coarse-to-fine refinement of n poses of level `from_level` (x, y, k on
+ * that level's grid) down to level 0, in place: at each level below, the pose
+ * is replaced by the best (by the selection key) of the 27 poses
+ * (2x+a, 2y+b, 2k+c), a, b, c in {-1, 0, 1}, inside the level image.  Poses
+ * must lie inside their level.  No selection is applied. */
+tm_status tm_refine(const tm_model* model, tm_pyramid* pyr, const tm_search_params* params, int32_t from_level,
                     tm_pose* poses_dev, int32_t n, void* stream);
 
 /* --- inspection (tests, tools) ------------------------------------------ */

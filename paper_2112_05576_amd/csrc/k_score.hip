@@ -14,6 +14,8 @@
 // point order per lane, in blocks of 32 (bounding FP32 error by about
 // 2^-24 (32 + n/32) per score).  Each workgroup covers a chunk of angles and
 // writes its best angle per translation; a second kernel reduces the chunks.
+#include <stdlib.h>
+
 #include "tm_device.h"
 
 namespace tmk {
@@ -50,7 +52,7 @@ struct FastArgs {
 };
 
 template <int G, int R, int LC>
-__global__ __launch_bounds__(256) void k_dense_fast(FastArgs a)
+__global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     float2* tile = reinterpret_cast<float2*>(smem);
@@ -190,7 +192,8 @@ struct GenericArgs {
 };
 
 // Any step and window: one thread per grid translation, taps read from
-// global memory with bounds checks.
+// global memory (clamped addresses, no branches).
+template <int PREC>
 __global__ __launch_bounds__(256) void k_dense_generic(GenericArgs a)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -213,10 +216,11 @@ __global__ __launch_bounds__(256) void k_dense_generic(GenericArgs a)
                 const int px = x + e.qx, py = y + e.qy;
                 float best = -INFINITY;
                 for (int dy = -h; dy <= h; ++dy)
+#pragma unroll 3
                     for (int dx = -h; dx <= h; ++dx)
-                        best = fmaxf(best, field_dot(a.field, a.precision, a.W, a.H, px + dx, py + dy, e.rx, e.ry));
+                        best = fmaxf(best, field_dot<PREC>(a.field, a.W, a.H, px + dx, py + dy, e.rx, e.ry));
                 pw += best;
-                p1 += field_dot(a.field, a.precision, a.W, a.H, px, py, e.rx, e.ry);
+                p1 += field_dot<PREC>(a.field, a.W, a.H, px, py, e.rx, e.ry);
             }
             tw += pw;
             t1 += p1;
@@ -234,33 +238,78 @@ __global__ __launch_bounds__(256) void k_dense_generic(GenericArgs a)
     a.pk[o] = bk;
 }
 
-// Best angle per translation over the C chunk partials, in key order.
+// Best angle per translation over the C chunk partials, in key order.  A
+// workgroup takes 32 translations; 8 threads share one translation, each
+// scanning every 8th chunk with its loads issued ahead of the comparisons,
+// then the 8 partial bests are merged through LDS.  The key is a total order,
+// so the result does not depend on the split.
+constexpr int kRedLanes = 8;
+constexpr int kRedPos = 32;
+
 __global__ __launch_bounds__(256) void k_reduce_chunks(const float* __restrict__ pw, const float* __restrict__ p1,
                                                         const int32_t* __restrict__ pk, int C, int np,
                                                         float* __restrict__ ow, float* __restrict__ o1,
                                                         int32_t* __restrict__ ok)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
-    float w0 = pw[p], s0 = p1[p];
-    int k = pk[p];
-    for (int c = 1; c < C; ++c) {
-        const size_t q = (size_t)c * np + p;
-        if (key_better(pw[q], p1[q], 0, 0, pk[q], w0, s0, 0, 0, k)) {
-            w0 = pw[q];
-            s0 = p1[q];
-            k = pk[q];
+    __shared__ float sw_[kRedPos][kRedLanes], s1_[kRedPos][kRedLanes];
+    __shared__ int sk_[kRedPos][kRedLanes];
+    const int lane = threadIdx.x % kRedLanes, slot = threadIdx.x / kRedLanes;
+    const int p = blockIdx.x * kRedPos + slot;
+    float w0 = -INFINITY, s0 = -INFINITY;
+    int k = 0x7fffffff;
+    if (p < np) {
+        int c = lane;
+        for (; c + 3 * kRedLanes < C; c += 4 * kRedLanes) {
+            float w[4], s[4];
+            int kk[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const size_t q = (size_t)(c + u * kRedLanes) * np + p;
+                w[u] = pw[q];
+                s[u] = p1[q];
+                kk[u] = pk[q];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (key_better(w[u], s[u], 0, 0, kk[u], w0, s0, 0, 0, k)) {
+                    w0 = w[u];
+                    s0 = s[u];
+                    k = kk[u];
+                }
+        }
+        for (; c < C; c += kRedLanes) {
+            const size_t q = (size_t)c * np + p;
+            const float w = pw[q], s = p1[q];
+            const int kk = pk[q];
+            if (key_better(w, s, 0, 0, kk, w0, s0, 0, 0, k)) {
+                w0 = w;
+                s0 = s;
+                k = kk;
+            }
         }
     }
-    ow[p] = w0;
-    o1[p] = s0;
-    ok[p] = k;
+    sw_[slot][lane] = w0;
+    s1_[slot][lane] = s0;
+    sk_[slot][lane] = k;
+    __syncthreads();
+    if (lane == 0 && p < np) {
+        for (int u = 1; u < kRedLanes; ++u)
+            if (key_better(sw_[slot][u], s1_[slot][u], 0, 0, sk_[slot][u], w0, s0, 0, 0, k)) {
+                w0 = sw_[slot][u];
+                s0 = s1_[slot][u];
+                k = sk_[slot][u];
+            }
+        ow[p] = w0;
+        o1[p] = s0;
+        ok[p] = k;
+    }
 }
 
 // One wave per pose: lanes take points i = lane, lane + 64, ...; each point's
 // rotation is formed in FP64, its window read from global memory; per-lane
 // sums are combined by a fixed butterfly.
-__global__ __launch_bounds__(256) void k_sparse(const void* __restrict__ field, int W, int H, int precision,
+template <int PREC>
+__global__ __launch_bounds__(256) void k_sparse(const void* __restrict__ field, int W, int H,
                                                  const ModelPoint* __restrict__ pts, int n, int win,
                                                  const tm_eval_pose* __restrict__ poses, int np,
                                                  float* __restrict__ scores)
@@ -281,10 +330,11 @@ __global__ __launch_bounds__(256) void k_sparse(const void* __restrict__ field, 
         const int px = ps.x + qx, py = ps.y + qy;
         float best = -INFINITY;
         for (int dy = -h; dy <= h; ++dy)
+#pragma unroll 3
             for (int dx = -h; dx <= h; ++dx)
-                best = fmaxf(best, field_dot(field, precision, W, H, px + dx, py + dy, fx, fy));
+                best = fmaxf(best, field_dot<PREC>(field, W, H, px + dx, py + dy, fx, fy));
         sw += best;
-        s1 += field_dot(field, precision, W, H, px, py, fx, fy);
+        s1 += field_dot<PREC>(field, W, H, px, py, fx, fy);
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -310,6 +360,17 @@ struct Plan {
 
 constexpr int kLC[] = {64, 96, 128, 192, 256};
 
+// Launch-shape knobs of the search kernel: waves stacked in y per workgroup,
+// waves splitting the angle chunk, and angles per wave.  Defaults can be
+// overridden by TM_DENSE_WY / TM_DENSE_WA / TM_DENSE_APW (tuning runs).
+int knob(const char* name, int dflt, int lo, int hi)
+{
+    const char* v = getenv(name);
+    if (!v || !*v) return dflt;
+    int x = atoi(v);
+    return x < lo ? lo : (x > hi ? hi : x);
+}
+
 Plan make_plan(const DenseGeom& g)
 {
     Plan p = {};
@@ -318,8 +379,9 @@ Plan make_plan(const DenseGeom& g)
     if (p.fast) {
         p.G = 32;
         p.R = 8;
-        p.WY = 1;
-        p.WA = 4;
+        p.WY = knob("TM_DENSE_WY", 1, 1, 4);
+        p.WA = knob("TM_DENSE_WA", 4, 1, 16);
+        if (p.WY * p.WA > 16) p.WA = 16 / p.WY;
         const int TW = p.G - 2, TH = p.WY * (64 / p.G) * p.R;
         p.LC = 0;
         for (int lc : kLC)
@@ -341,6 +403,7 @@ Plan make_plan(const DenseGeom& g)
         const long long units = (long long)p.tiles_x * p.tiles_y * g.K;
         long long per_wave = units / 4096;
         if (per_wave < 1) per_wave = 1;
+        per_wave = knob("TM_DENSE_APW", (int)per_wave, 1, 1 << 20);
         p.A = (int)(per_wave * p.WA);
         p.C = (g.K + p.A - 1) / p.A;
     } else {
@@ -443,7 +506,10 @@ hipError_t launch_dense(const DenseGeom& g, void* ws, float* ow, float* o1, int3
         a.p1 = p1;
         a.pk = pk;
         dim3 grid((g.gw * g.gh + 255) / 256, p.C);
-        hipLaunchKernelGGL(k_dense_generic, grid, dim3(256), 0, s, a);
+        if (g.precision == TM_FP16)
+            hipLaunchKernelGGL(k_dense_generic<TM_FP16>, grid, dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL(k_dense_generic<TM_FP32>, grid, dim3(256), 0, s, a);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
@@ -451,7 +517,8 @@ hipError_t launch_dense(const DenseGeom& g, void* ws, float* ow, float* o1, int3
         e = hipEventRecord(ev1, s);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, s, pw, p1, pk, p.C,
+    hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((np + kRedPos - 1) / kRedPos)), dim3(kRedPos * kRedLanes), 0,
+                       s, pw, p1, pk, p.C,
                        (int)np, ow, o1, ok);
     return hipGetLastError();
 }
@@ -460,8 +527,12 @@ hipError_t launch_sparse(const void* field, int W, int H, int precision, const M
                          const tm_eval_pose* poses, int np, float* scores, hipStream_t s)
 {
     if (np == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sparse, dim3((np + 3) / 4), dim3(256), 0, s, field, W, H, precision, pts, n, win, poses, np,
-                       scores);
+    if (precision == TM_FP16)
+        hipLaunchKernelGGL(k_sparse<TM_FP16>, dim3((np + 3) / 4), dim3(256), 0, s, field, W, H, pts, n, win, poses,
+                           np, scores);
+    else
+        hipLaunchKernelGGL(k_sparse<TM_FP32>, dim3((np + 3) / 4), dim3(256), 0, s, field, W, H, pts, n, win, poses,
+                           np, scores);
     return hipGetLastError();
 }
 

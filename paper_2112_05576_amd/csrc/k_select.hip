@@ -23,111 +23,157 @@ __device__ __forceinline__ bool kb(const Keys& a, int i, int j)
     return key_better(a.sw[i], a.s1[i], a.x[i], a.y[i], a.k[i], a.sw[j], a.s1[j], a.x[j], a.y[j], a.k[j]);
 }
 
-__device__ __forceinline__ void kswap(const Keys& a, int i, int j)
+__device__ __forceinline__ void kcopy(const Keys& dst, int i, const Keys& src, int j)
 {
-    float t;
-    int u;
-    t = a.sw[i]; a.sw[i] = a.sw[j]; a.sw[j] = t;
-    t = a.s1[i]; a.s1[i] = a.s1[j]; a.s1[j] = t;
-    u = a.x[i]; a.x[i] = a.x[j]; a.x[j] = u;
-    u = a.y[i]; a.y[i] = a.y[j]; a.y[j] = u;
-    u = a.k[i]; a.k[i] = a.k[j]; a.k[j] = u;
+    dst.sw[i] = src.sw[j];
+    dst.s1[i] = src.s1[j];
+    dst.x[i] = src.x[j];
+    dst.y[i] = src.y[j];
+    dst.k[i] = src.k[j];
 }
 
-// Bitonic sort of P (a power of two) entries, best key first.  Every thread
-// of the block takes part; the arrays may live in LDS or global memory.
-__device__ void sort_best_first(const Keys& a, int P)
+constexpr int kBuckets = 1024;
+
+// S_w in [-1, 1] to a bucket, best first.  The map is monotone (1 - s is
+// rounded monotonically, the scaling by 512 is exact), so a better S_w never
+// lands in a later bucket and sorting each bucket by the full key sorts all.
+__device__ __forceinline__ int score_bucket(float sw)
 {
-    for (int size = 2; size <= P; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = threadIdx.x; i < P / 2; i += blockDim.x) {
-                const int lo = 2 * i - (i & (stride - 1));
-                const int hi = lo + stride;
-                const bool up = (lo & size) == 0;
-                if (up ? kb(a, hi, lo) : kb(a, lo, hi)) kswap(a, lo, hi);
-            }
-            __syncthreads();
-        }
+    const int b = (int)((1.0f - sw) * 512.0f);
+    return b < 0 ? 0 : (b > kBuckets - 1 ? kBuckets - 1 : b);
+}
+
+// Exclusive prefix sum over the block (1024 threads, one value each).
+__device__ int block_exclusive_scan(int v, int* wsum)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(x, o, 64);
+        if (lane >= o) x += t;
     }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    if (w == 0) {
+        int t = lane < 16 ? wsum[lane] : 0;
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            const int u = __shfl_up(t, o, 64);
+            if (lane >= o) t += u;
+        }
+        if (lane < 16) wsum[lane] = t;
+    }
+    __syncthreads();
+    const int r = x - v + (w > 0 ? wsum[w - 1] : 0);
+    __syncthreads();
+    return r;
 }
 
-__device__ __forceinline__ void set_sentinel(const Keys& a, int i)
+// Sort in[0..N) best first into out[0..N) (1024 threads): bucket by S_w, then
+// each element's position inside its bucket is its rank by the full key
+// among the bucket's members.  Positions are distinct, so ranks are too.
+// cnt, off: kBuckets ints (LDS); idx: N ints; wsum: 16 ints.
+__device__ void bucket_sort(const Keys& in, const Keys& out, int N, int* cnt, int* off, int* idx, int* wsum)
 {
-    a.sw[i] = -INFINITY;
-    a.s1[i] = -INFINITY;
-    a.x[i] = 0x7fffffff;
-    a.y[i] = 0x7fffffff;
-    a.k[i] = 0x7fffffff;
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < N; i += blockDim.x) atomicAdd(&cnt[score_bucket(in.sw[i])], 1);
+    __syncthreads();
+    const int c = cnt[threadIdx.x];
+    off[threadIdx.x] = block_exclusive_scan(c, wsum);
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const int b = score_bucket(in.sw[i]);
+        idx[off[b] + atomicAdd(&cnt[b], 1)] = i;
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < N; s += blockDim.x) {
+        const int i = idx[s];
+        const int b = score_bucket(in.sw[i]);
+        const int b0 = off[b], b1 = b0 + cnt[b];
+        int rank = 0;
+        for (int t = b0; t < b1; ++t) rank += kb(in, idx[t], i) ? 1 : 0;
+        kcopy(out, b0 + rank, in, i);
+    }
+    __syncthreads();
 }
 
-__device__ __forceinline__ int next_pow2(int v)
+__device__ __forceinline__ bool too_close(int x, int y, int ax, int ay, int level, double dmin2)
 {
-    int p = 1;
-    while (p < v) p <<= 1;
-    return p;
+    const long long dx = (long long)x - ax, dy = (long long)y - ay;
+    const long long d2 = (dx * dx + dy * dy) << (2 * level);
+    return (double)d2 < dmin2;
 }
 
 // Greedy suppression over `a` sorted best first (N entries), run by wave 0:
 // a pose is accepted iff its squared distance (scaled by 4^level) to every
 // accepted pose is >= dmin2.  The distance test is exact: integer squared
-// distance and a squared float, both exact in FP64.
+// distance and a squared float, both exact in FP64.  The wave takes 64
+// candidates at a time: each lane tests its candidate against the poses
+// accepted so far, then the survivors are accepted in key order, each one
+// removing the later lanes it is too close to.
 __device__ int greedy_wave0(const Keys& a, int N, int level, double dmin2, int cap, int* ax, int* ay, int* aidx)
 {
     const int lane = threadIdx.x & 63;
     int acc = 0;
-    for (int c = 0; c < N && acc < cap; ++c) {
-        const int x = a.x[c], y = a.y[c];
-        bool sup = false;
-        for (int q = lane; q < acc; q += 64) {
-            const long long dx = (long long)x - ax[q], dy = (long long)y - ay[q];
-            const long long d2 = (dx * dx + dy * dy) << (2 * level);
-            sup |= (double)d2 < dmin2;
-        }
-        if (__ballot(sup) == 0ull) {
+    for (int c0 = 0; c0 < N && acc < cap; c0 += 64) {
+        const int c = c0 + lane;
+        const bool valid = c < N;
+        const int x = valid ? a.x[c] : 0, y = valid ? a.y[c] : 0;
+        bool sup = !valid;
+        for (int q = 0; q < acc; ++q) sup = sup || too_close(x, y, ax[q], ay[q], level, dmin2);
+        unsigned long long live = __ballot(!sup);
+        while (live != 0ull && acc < cap) {
+            const int j = __builtin_ctzll(live);
+            const int xj = __shfl(x, j, 64), yj = __shfl(y, j, 64);
             if (lane == 0) {
-                ax[acc] = x;
-                ay[acc] = y;
-                aidx[acc] = c;
+                ax[acc] = xj;
+                ay[acc] = yj;
+                aidx[acc] = c0 + j;
             }
-            __threadfence_block();
             ++acc;
+            live &= ~__ballot(too_close(x, y, xj, yj, level, dmin2));
+            live &= (j == 63) ? 0ull : ~((2ull << j) - 1ull);
         }
+        __threadfence_block();
     }
     return acc;
 }
 
-constexpr int kSelCap = 2048;   // candidates sorted in LDS by k_select
+constexpr int kSelCap = 1024;   // candidates sorted into LDS by k_select (more go through global scratch)
 constexpr int kFinCap = 1024;   // candidates handled by k_final
 
 __global__ __launch_bounds__(1024) void k_select(const float* __restrict__ mw, const float* __restrict__ m1,
                                                   const int32_t* __restrict__ mk, int gw, int gh, int sx, int sy,
                                                   int level, float min_score, double dmin2, double theta_min,
                                                   double step_level, tm_pose* __restrict__ out, int cap,
-                                                  int32_t* __restrict__ n_out, Keys g)
+                                                  int32_t* __restrict__ n_out, Keys g, Keys gs, int* gidx)
 {
     __shared__ float l_sw[kSelCap], l_s1[kSelCap];
     __shared__ int l_x[kSelCap], l_y[kSelCap], l_k[kSelCap];
     __shared__ int acc_x[kFinCap], acc_y[kFinCap], acc_i[kFinCap];
+    __shared__ int cnt[kBuckets], off[kBuckets], wsum[16];
     __shared__ int count, n_acc;
     if (threadIdx.x == 0) count = 0;
     __syncthreads();
     const int np = gw * gh;
     for (int p = threadIdx.x; p < np; p += blockDim.x) {
-        const float w = mw[p];
-        if (!(w >= min_score)) continue;
         const int j = p / gw, i = p - j * gw;
-        const float s = m1[p];
-        bool is_max = true;
-        for (int b = -1; b <= 1 && is_max; ++b) {
+        const float w = mw[p], s = m1[p];
+        bool is_max = w >= min_score;
+        // all 8 neighbours are loaded at clamped addresses, then compared
+#pragma unroll
+        for (int b = -1; b <= 1; ++b) {
+#pragma unroll
             for (int a = -1; a <= 1; ++a) {
                 if (a == 0 && b == 0) continue;
                 const int ii = i + a, jj = j + b;
-                if (ii < 0 || ii >= gw || jj < 0 || jj >= gh) continue;
-                const int q = jj * gw + ii;
-                if (!key_better(w, s, i, j, 0, mw[q], m1[q], ii, jj, 0)) {
-                    is_max = false;
-                    break;
-                }
+                const bool in = (unsigned)ii < (unsigned)gw && (unsigned)jj < (unsigned)gh;
+                const int q = min(max(jj, 0), gh - 1) * gw + min(max(ii, 0), gw - 1);
+                const float nw = mw[q], n1 = m1[q];
+                is_max = is_max && (!in || key_better(w, s, i, j, 0, nw, n1, ii, jj, 0));
             }
         }
         if (is_max) {
@@ -141,27 +187,14 @@ __global__ __launch_bounds__(1024) void k_select(const float* __restrict__ mw, c
     }
     __syncthreads();
     const int N = count;
-    const int P = next_pow2(N > 0 ? N : 1);
     Keys a;
-    if (P <= kSelCap) {
+    if (N <= kSelCap) {
         a = Keys{l_sw, l_s1, l_x, l_y, l_k};
-        for (int i = threadIdx.x; i < P; i += blockDim.x) {
-            if (i < N) {
-                l_sw[i] = g.sw[i];
-                l_s1[i] = g.s1[i];
-                l_x[i] = g.x[i];
-                l_y[i] = g.y[i];
-                l_k[i] = g.k[i];
-            } else {
-                set_sentinel(a, i);
-            }
-        }
+        bucket_sort(g, a, N, cnt, off, acc_i, wsum);  // acc_i doubles as the index buffer
     } else {
-        a = g;
-        for (int i = N + threadIdx.x; i < P; i += blockDim.x) set_sentinel(a, i);
+        a = gs;
+        bucket_sort(g, a, N, cnt, off, gidx, wsum);
     }
-    __syncthreads();
-    sort_best_first(a, P);
     const int capc = cap < kFinCap ? cap : kFinCap;
     if (threadIdx.x < 64) {
         const int m = greedy_wave0(a, N, level, dmin2, capc, acc_x, acc_y, acc_i);
@@ -185,13 +218,17 @@ __global__ __launch_bounds__(1024) void k_select(const float* __restrict__ mw, c
     if (threadIdx.x == 0) *n_out = m;
 }
 
+// Final selection of the refined level-0 poses: score floor, key order (rank
+// by counting, the list is short), greedy suppression, at most cap.
 __global__ __launch_bounds__(256) void k_final(const tm_pose* __restrict__ cand, const int32_t* __restrict__ n_cand,
                                                 int max_cand, float min_score, double dmin2, double theta_min,
                                                 double step0, tm_pose* __restrict__ out, int cap,
                                                 int32_t* __restrict__ n_out)
 {
+    __shared__ float u_sw[kFinCap], u_s1[kFinCap];
+    __shared__ int u_x[kFinCap], u_y[kFinCap], u_k[kFinCap];
     __shared__ float l_sw[kFinCap], l_s1[kFinCap];
-    __shared__ int l_x[kFinCap], l_y[kFinCap], l_k[kFinCap], l_src[kFinCap];
+    __shared__ int l_x[kFinCap], l_y[kFinCap], l_k[kFinCap];
     __shared__ int acc_x[kFinCap], acc_y[kFinCap], acc_i[kFinCap];
     __shared__ int count, n_acc;
     if (threadIdx.x == 0) count = 0;
@@ -203,20 +240,23 @@ __global__ __launch_bounds__(256) void k_final(const tm_pose* __restrict__ cand,
         const tm_pose c = cand[i];
         if (!(c.score_w >= min_score)) continue;
         const int idx = atomicAdd(&count, 1);
-        l_sw[idx] = c.score_w;
-        l_s1[idx] = c.score_1;
-        l_x[idx] = c.x;
-        l_y[idx] = c.y;
-        l_k[idx] = c.k;
-        l_src[idx] = i;
+        u_sw[idx] = c.score_w;
+        u_s1[idx] = c.score_1;
+        u_x[idx] = c.x;
+        u_y[idx] = c.y;
+        u_k[idx] = c.k;
     }
     __syncthreads();
     const int N = count;
-    const int P = next_pow2(N > 0 ? N : 1);
+    Keys u{u_sw, u_s1, u_x, u_y, u_k};
     Keys a{l_sw, l_s1, l_x, l_y, l_k};
-    for (int i = N + threadIdx.x; i < P; i += blockDim.x) set_sentinel(a, i);
+    // duplicates (equal keys) keep their relative order by arrival index
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        int rank = 0;
+        for (int j = 0; j < N; ++j) rank += (kb(u, j, i) || (j < i && !kb(u, i, j))) ? 1 : 0;
+        kcopy(a, rank, u, i);
+    }
     __syncthreads();
-    sort_best_first(a, P);
     if (threadIdx.x < 64) {
         const int m = greedy_wave0(a, N, 0, dmin2, cap < kFinCap ? cap : kFinCap, acc_x, acc_y, acc_i);
         if (threadIdx.x == 0) n_acc = m;
@@ -243,27 +283,29 @@ __global__ __launch_bounds__(256) void k_final(const tm_pose* __restrict__ cand,
 
 size_t select_workspace_bytes(int gw, int gh)
 {
-    size_t np = (size_t)gw * gh;
-    size_t P = 1;
-    while (P < np) P <<= 1;
-    return P * 20 + 256;
+    const size_t np = (size_t)gw * gh;
+    return np * (2 * 20 + 4) + 256;
 }
 
 hipError_t launch_select(const float* sw, const float* s1, const int32_t* k, int gw, int gh, int sx, int sy,
                          int level, float min_score, double dmin2, double theta_min, double step_level,
                          tm_pose* out, int capacity, int32_t* n_out, void* scratch, hipStream_t s)
 {
-    size_t np = (size_t)gw * gh;
-    size_t P = 1;
-    while (P < np) P <<= 1;
-    Keys g;
+    const size_t np = (size_t)gw * gh;
+    Keys g, gs;
     g.sw = reinterpret_cast<float*>(scratch);
-    g.s1 = g.sw + P;
-    g.x = reinterpret_cast<int*>(g.s1 + P);
-    g.y = g.x + P;
-    g.k = g.y + P;
+    g.s1 = g.sw + np;
+    g.x = reinterpret_cast<int*>(g.s1 + np);
+    g.y = g.x + np;
+    g.k = g.y + np;
+    gs.sw = reinterpret_cast<float*>(g.k + np);
+    gs.s1 = gs.sw + np;
+    gs.x = reinterpret_cast<int*>(gs.s1 + np);
+    gs.y = gs.x + np;
+    gs.k = gs.y + np;
+    int* gidx = gs.k + np;
     hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, sw, s1, k, gw, gh, sx, sy, level, min_score, dmin2,
-                       theta_min, step_level, out, capacity, n_out, g);
+                       theta_min, step_level, out, capacity, n_out, g, gs, gidx);
     return hipGetLastError();
 }
 

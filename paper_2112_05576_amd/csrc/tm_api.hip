@@ -253,12 +253,12 @@ tmk::DenseGeom dense_geom(const tm_model* m, const tm_pyramid* p, int level, con
     return g;
 }
 
-// scratch layout of detect: [dense partials][map w|1|k][select keys][cands][count]
+// scratch layout of detect: [dense partials][map w|1|k][select keys][cands][count][refine]
 struct DetectLayout {
-    size_t dense, map, sel, cand, total;
+    size_t dense, map, sel, cand, refine, total;
 };
 
-DetectLayout detect_layout(const tmk::DenseGeom& g, int max_cand)
+DetectLayout detect_layout(const tmk::DenseGeom& g, int max_cand, size_t refine_bytes)
 {
     DetectLayout d;
     const size_t np = (size_t)g.gw * g.gh;
@@ -270,6 +270,8 @@ DetectLayout detect_layout(const tmk::DenseGeom& g, int max_cand)
     off += align_up(tmk::select_workspace_bytes(g.gw, g.gh), 256);
     d.cand = off;
     off += align_up((size_t)max_cand * sizeof(tm_pose) + 256, 256);
+    d.refine = off;
+    off += align_up(refine_bytes, 256);
     d.total = off;
     return d;
 }
@@ -605,7 +607,8 @@ TM_EXPORT tm_status tm_detect(const tm_model* m, tm_pyramid* p, const tm_search_
     st = get_table(m, top, sp->theta_min_deg, g.step[top], g.K[top], s, &tab);
     if (st != TM_OK) return st;
     tmk::DenseGeom dg = dense_geom(m, p, top, sp, tab, g.K[top]);
-    DetectLayout lay = detect_layout(dg, sp->max_candidates);
+    tmk::RefineArgs ra = refine_args(m, p, sp, g);
+    DetectLayout lay = detect_layout(dg, sp->max_candidates, tmk::refine_workspace_bytes(ra, sp->max_candidates));
     st = ensure_ws(p, lay.total, s);
     if (st != TM_OK) return st;
     uint8_t* base = reinterpret_cast<uint8_t*>(p->ws.ptr);
@@ -623,10 +626,7 @@ TM_EXPORT tm_status tm_detect(const tm_model* m, tm_pyramid* p, const tm_search_
     HIP_TRY(tmk::launch_dense(dg, base + lay.dense, mw, m1, mk, s, ev0, ev1));
     HIP_TRY(tmk::launch_select(mw, m1, mk, dg.gw, dg.gh, sp->step_x, sp->step_y, top, sp->min_score, dmin2,
                               sp->theta_min_deg, g.step[top], cand, sp->max_candidates, ncand, base + lay.sel, s));
-    if (p->L > 1) {
-        tmk::RefineArgs ra = refine_args(m, p, sp, g);
-        HIP_TRY(tmk::launch_refine(ra, cand, sp->max_candidates, ncand, s));
-    }
+    if (p->L > 1) HIP_TRY(tmk::launch_refine(ra, cand, sp->max_candidates, ncand, top, base + lay.refine, s));
     const int cap = std::min(capacity, sp->max_matches);
     HIP_TRY(tmk::launch_final(cand, ncand, sp->max_candidates, sp->min_score, dmin2, sp->theta_min_deg, g.step[0],
                              out, cap, n_out, s));
@@ -659,8 +659,8 @@ TM_EXPORT tm_status tm_timing_read(double* ms, int32_t* launches)
     return TM_OK;
 }
 
-TM_EXPORT tm_status tm_refine(const tm_model* m, tm_pyramid* p, const tm_search_params* sp, tm_pose* poses,
-                              int32_t n, void* stream)
+TM_EXPORT tm_status tm_refine(const tm_model* m, tm_pyramid* p, const tm_search_params* sp, int32_t from_level,
+                              tm_pose* poses, int32_t n, void* stream)
 {
     tm_status st = check_pair(m, p, "tm_refine");
     if (st != TM_OK) return st;
@@ -672,7 +672,10 @@ TM_EXPORT tm_status tm_refine(const tm_model* m, tm_pyramid* p, const tm_search_
     Grid g;
     st = make_grid(sp, p->L, &g);
     if (st != TM_OK) return st;
+    if (from_level < 0 || from_level >= p->L) return fail(TM_EINVAL, "tm_refine: bad from_level %d", from_level);
     tmk::RefineArgs ra = refine_args(m, p, sp, g);
-    HIP_TRY(tmk::launch_refine(ra, poses, n, nullptr, S(stream)));
+    st = ensure_ws(p, tmk::refine_workspace_bytes(ra, n), S(stream));
+    if (st != TM_OK) return st;
+    HIP_TRY(tmk::launch_refine(ra, poses, n, nullptr, from_level, p->ws.ptr, S(stream)));
     return TM_OK;
 }

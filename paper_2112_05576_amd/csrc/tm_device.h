@@ -61,20 +61,29 @@ __device__ __forceinline__ int angle_index(int k, int K, int full)
     return k < 0 ? 0 : (k > K - 1 ? K - 1 : k);
 }
 
-// Dot of a rotated model direction with the field at (x, y); 0 outside the
-// image (and at non-edge pixels, whose stored direction is (0, 0)).
-__device__ __forceinline__ float field_dot(const void* field, int precision, int W, int H, int x, int y, float rx,
-                                           float ry)
+// Direction field element as float2, for FP32 or FP16 storage.
+template <int PREC>
+__device__ __forceinline__ float2 field_load(const void* field, size_t o)
 {
-    if (x < 0 || y < 0 || x >= W || y >= H) return 0.0f;
-    size_t o = (size_t)y * W + x;
-    if (precision == TM_FP16) {
-        __half2 g = reinterpret_cast<const __half2*>(field)[o];
-        float2 f = __half22float2(g);
-        return rx * f.x + ry * f.y;
+    if constexpr (PREC == TM_FP16) {
+        return __half22float2(reinterpret_cast<const __half2*>(field)[o]);
+    } else {
+        return reinterpret_cast<const float2*>(field)[o];
     }
-    float2 g = reinterpret_cast<const float2*>(field)[o];
-    return rx * g.x + ry * g.y;
+}
+
+// Dot of a rotated model direction with the field at (x, y); 0 outside the
+// image (and at non-edge pixels, whose stored direction is (0, 0)).  The
+// address is clamped and the result selected, without a branch, so that the
+// loads of many taps are in flight together.
+template <int PREC>
+__device__ __forceinline__ float field_dot(const void* field, int W, int H, int x, int y, float rx, float ry)
+{
+    const bool in = (unsigned)x < (unsigned)W && (unsigned)y < (unsigned)H;
+    const int xc = min(max(x, 0), W - 1), yc = min(max(y, 0), H - 1);
+    const float2 g = field_load<PREC>(field, (size_t)yc * W + xc);
+    const float v = rx * g.x + ry * g.y;
+    return in ? v : 0.0f;
 }
 
 // The selection key: S_w desc, S_1 desc, then position x asc, y asc, then

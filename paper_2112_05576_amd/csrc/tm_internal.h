@@ -142,8 +142,11 @@ struct RefineArgs {
     double theta_min;
 };
 
-// Refine poses[i] (for i < *n_dev if n_dev, else i < n) from its level to 0.
-hipError_t launch_refine(const RefineArgs& a, tm_pose* poses, int n, const int32_t* n_dev, hipStream_t s);
+// Refine poses[i] (i < *n_dev if n_dev, else i < n), all of level from_level,
+// down to level 0, in place.  ws: refine_workspace_bytes(a, n) bytes.
+size_t refine_workspace_bytes(const RefineArgs& a, int n);
+hipError_t launch_refine(const RefineArgs& a, tm_pose* poses, int n, const int32_t* n_dev, int from_level, void* ws,
+                         hipStream_t s);
 
 // Final selection: S_w floor, key sort, greedy NMS at level 0, <= capacity.
 hipError_t launch_final(const tm_pose* cand, const int32_t* n_cand, int max_cand, float min_score, double dmin2,

@@ -66,7 +66,7 @@ def lib():
             "tm_select": [_vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, ctypes.c_float, ctypes.c_float, _vp, _i32,
                           _vp, _vp],
             "tm_detect": [_vp, _vp, ctypes.POINTER(SearchParamsC), _vp, _i32, _vp, _vp],
-            "tm_refine": [_vp, _vp, ctypes.POINTER(SearchParamsC), _vp, _i32, _vp],
+            "tm_refine": [_vp, _vp, ctypes.POINTER(SearchParamsC), _i32, _vp, _i32, _vp],
             "tm_model_level_info": [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
             "tm_model_points": [_vp, _i32, _vp, _vp, _vp],
             "tm_model_table": [_vp, _i32, ctypes.c_double, ctypes.c_double, _i32, _vp, _vp, _vp],
@@ -293,12 +293,13 @@ def detect(model: Model, pyr: Pyramid, sp: SearchParams, capacity: int | None = 
     return poses_to_numpy(out, m)
 
 
-def refine(model: Model, pyr: Pyramid, sp: SearchParams, poses: np.ndarray, stream=None) -> np.ndarray:
-    """Refine poses (POSE_DTYPE, each at its level) down to level 0."""
+def refine(model: Model, pyr: Pyramid, sp: SearchParams, poses: np.ndarray, from_level: int,
+           stream=None) -> np.ndarray:
+    """Refine poses (POSE_DTYPE) of level `from_level` down to level 0."""
     a = np.ascontiguousarray(poses, dtype=POSE_DTYPE)
     dev = torch.from_numpy(a.view(np.int32).reshape(-1, POSE_WORDS).copy()).cuda()
     c = sp.c()
-    _check(lib().tm_refine(model.handle, pyr.handle, ctypes.byref(c), _vp(dev.data_ptr()), len(a),
+    _check(lib().tm_refine(model.handle, pyr.handle, ctypes.byref(c), from_level, _vp(dev.data_ptr()), len(a),
                            _vp(_stream(stream))))
     return poses_to_numpy(dev)
 

@@ -68,7 +68,7 @@ def test_invalid_arguments_fail_before_the_device(L):
     assert L.tm_select(None, None, None, 4, 4, 1, 1, 0, 0.5, 1.0, None, 8, None, None) == tm.TM_EINVAL
     assert L.tm_select(fake, fake, fake, 4, 4, 1, 1, 0, 0.5, 1.0, fake, 0, fake, None) == tm.TM_EINVAL
     assert L.tm_select(fake, fake, fake, 4, 4, 0, 1, 0, 0.5, 1.0, fake, 8, fake, None) == tm.TM_EINVAL
-    assert L.tm_refine(None, None, ctypes.byref(sp), fake, 1, None) == tm.TM_EINVAL
+    assert L.tm_refine(None, None, ctypes.byref(sp), 3, fake, 1, None) == tm.TM_EINVAL
     assert L.tm_score_poses(None, None, 0, 3, fake, 1, fake, None) == tm.TM_EINVAL
     assert L.tm_model_level_info(None, 0, None, None, None) == tm.TM_EINVAL
     assert L.tm_pyramid_read(None, 0, None, None, None) == tm.TM_EINVAL

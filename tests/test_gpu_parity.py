@@ -330,7 +330,7 @@ def test_refine_matches_oracle():
     poses["sw"], poses["s1"] = cand.sw, cand.s1
     gm = P.Model(sc.model, L, cfg["tau_m"])
     pyr = P.Pyramid(sc.image, L, cfg["tau_s"])
-    got = P.refine(gm, pyr, P.SearchParams(theta_step_top=1.0), poses)
+    got = P.refine(gm, pyr, P.SearchParams(theta_step_top=1.0), poses, L - 1)
     ref = tr.refined[-1]
     ties = 0
     for i in range(len(cand)):
