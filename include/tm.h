@@ -172,6 +172,34 @@ tm_status tm_detect(const tm_model* model, tm_pyramid* pyr, const tm_search_para
 tm_status tm_refine(const tm_model* model, tm_pyramid* pyr, const tm_search_params* params, int32_t from_level,
                     tm_pose* poses_dev, int32_t n, void* stream);
 
+/* --- batches ------------------------------------------------------------ */
+
+/* A batch binds n_images device images (each width x height, `pitch` bytes
+ * per row) and n_models models to output buffers, for the detection of
+ * every model in every image (Sec. II applied pair by pair).  Pair
+ * p = image * n_models + model writes at most min(capacity, max_matches)
+ * poses to out_dev[p * capacity ...] and their count to n_out_dev[p].
+ * Creation allocates the pyramids, the rotated tables of the top level and
+ * all scratch, and waits for the uploads; models must outlive the batch (their
+ * points are read, their table cache is not used).  At most 65535 pairs. */
+typedef struct tm_batch_s tm_batch;
+tm_status tm_batch_create(const tm_model* const* models, int32_t n_models, const uint8_t* const* images_dev,
+                          const int32_t* widths, const int32_t* heights, const int32_t* pitches, int32_t n_images,
+                          const tm_pyr_params* pyr_params, const tm_search_params* params, tm_pose* out_dev,
+                          int32_t capacity, int32_t* n_out_dev, void* stream, tm_batch** out);
+
+/* Enqueue the whole batch: pyramids and direction fields of every bound image
+ * (read at execution time, so new contents in the same buffers are picked
+ * up), then the exhaustive search, selection, refinement and final selection
+ * of every pair, each stage one launch over all pairs.  Allocates nothing and
+ * never waits, so it can be captured in a graph. */
+tm_status tm_batch_run(tm_batch* batch, void* stream);
+
+/* The pyramid the batch built for one image (owned by the batch). */
+tm_status tm_batch_pyramid(const tm_batch* batch, int32_t image, const tm_pyramid** out);
+
+void tm_batch_free(tm_batch* batch);
+
 /* --- inspection (tests, tools) ------------------------------------------ */
 
 /* Level geometry of a model: size of the level image and point count. */

@@ -7,6 +7,7 @@ from .tm import (  # noqa: F401
     POSE_DTYPE,
     TM_FP16,
     TM_FP32,
+    Batch,
     Model,
     Pyramid,
     SearchParams,

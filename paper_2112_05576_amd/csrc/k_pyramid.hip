@@ -7,21 +7,22 @@ namespace tmk {
 
 namespace {
 
-struct LevelsArg {
-    uint8_t* img[kMaxLevels];
-    int w[kMaxLevels];
-    int h[kMaxLevels];
-};
 
 // One workgroup takes a 64x64 block of level `base` and produces the matching
 // cells of levels base+1 .. top (at most 6 more levels: 32x32 down to 1x1).
 // Every output pixel depends only on its own 2^k x 2^k block, so blocks are
 // independent.  Level `base` is read from `src` (pitched); when base == 0 the
 // block is also copied into level 0.
-__global__ __launch_bounds__(256) void k_pyr_build(const uint8_t* __restrict__ src, int src_pitch, LevelsArg lv,
-                                                    int base, int top, int copy_base)
+template <bool BATCH>
+__global__ __launch_bounds__(256) void k_pyr_build(PyrBuildArg one, const PyrBuildArg* __restrict__ many, int base,
+                                                    int top, int copy_base)
 {
     __shared__ uint8_t cells[16 * 16];
+    const PyrBuildArg& lv = BATCH ? many[blockIdx.z] : one;
+    top = min(top, lv.L - 1);
+    if ((int)blockIdx.x * 64 >= lv.w[base] || (int)blockIdx.y * 64 >= lv.h[base]) return;
+    const uint8_t* __restrict__ src = base == 0 ? lv.src : lv.img[base];
+    const int src_pitch = base == 0 ? lv.pitch : lv.w[base];
     const int t = threadIdx.x;
     const int cx = t & 15, cy = t >> 4;
     const int W = lv.w[base], H = lv.h[base];
@@ -90,14 +91,6 @@ __global__ __launch_bounds__(256) void k_pyr_build(const uint8_t* __restrict__ s
     }
 }
 
-struct FieldsArg {
-    const uint8_t* img[kMaxLevels];
-    void* field[kMaxLevels];
-    int w[kMaxLevels];
-    int h[kMaxLevels];
-    int block0[kMaxLevels + 1];  // first workgroup of each level
-    int L;
-};
 
 __device__ __forceinline__ void sobel_at(const uint8_t* __restrict__ img, int W, int H, int x, int y, int* gx,
                                          int* gy)
@@ -120,8 +113,13 @@ __device__ __forceinline__ void sobel_at(const uint8_t* __restrict__ img, int W,
 // Unit gradient direction of every pixel of every level: (gx, gy)/|g| formed
 // in FP64 and rounded once to the storage precision where gx^2 + gy^2 > T2,
 // (0, 0) elsewhere.  Each thread covers 4 consecutive pixels of a row.
-__global__ __launch_bounds__(256) void k_sobel_fields(FieldsArg a, long long T2, int precision)
+template <bool BATCH>
+__global__ __launch_bounds__(256) void k_sobel_fields(FieldsArg one, const FieldsArg* __restrict__ many)
 {
+    const FieldsArg& a = BATCH ? many[blockIdx.y] : one;
+    if ((int)blockIdx.x >= a.block0[a.L]) return;
+    const long long T2 = a.T2;
+    const int precision = a.precision;
     int l = 0;
     while (l + 1 < a.L && (int)blockIdx.x >= a.block0[l + 1]) ++l;
     const int W = a.w[l], H = a.h[l];
@@ -205,37 +203,26 @@ __global__ __launch_bounds__(1024) void k_model_points(PointsArg a, long long T2
 
 }  // namespace
 
-hipError_t launch_pyr_build(const uint8_t* src, int src_pitch, const PyrLevel* lv, int L, hipStream_t s)
+PyrBuildArg pyr_build_arg(const uint8_t* src, int src_pitch, const PyrLevel* lv, int L)
 {
-    LevelsArg a = {};
+    PyrBuildArg a = {};
+    a.src = src;
+    a.pitch = src_pitch;
+    a.L = L;
     for (int l = 0; l < L; ++l) {
         a.img[l] = lv[l].img;
         a.w[l] = lv[l].w;
         a.h[l] = lv[l].h;
     }
-    // first pass reads the caller's image; later passes (more than 7 levels)
-    // restart from the last level produced
-    int base = 0;
-    const uint8_t* in = src;
-    int pitch = src_pitch;
-    int copy = 1;
-    while (true) {
-        int top = min(L - 1, base + 6);
-        dim3 grid((a.w[base] + 63) / 64, (a.h[base] + 63) / 64);
-        hipLaunchKernelGGL(k_pyr_build, grid, dim3(256), 0, s, in, pitch, a, base, top, copy);
-        if (top >= L - 1) break;
-        base = top;
-        in = lv[base].img;
-        pitch = lv[base].w;
-        copy = 0;
-    }
-    return hipGetLastError();
+    return a;
 }
 
-hipError_t launch_sobel_fields(const PyrLevel* lv, int L, long long T2, int precision, hipStream_t s)
+FieldsArg fields_arg(const PyrLevel* lv, int L, long long T2, int precision)
 {
     FieldsArg a = {};
     a.L = L;
+    a.T2 = T2;
+    a.precision = precision;
     int blocks = 0;
     for (int l = 0; l < L; ++l) {
         a.img[l] = lv[l].img;
@@ -247,7 +234,44 @@ hipError_t launch_sobel_fields(const PyrLevel* lv, int L, long long T2, int prec
         blocks += (int)((quads + 255) / 256);
     }
     a.block0[L] = blocks;
-    hipLaunchKernelGGL(k_sobel_fields, dim3(blocks), dim3(256), 0, s, a, T2, precision);
+    return a;
+}
+
+// Level passes: levels 1..6 from the caller's image, then (more than 7
+// levels) from the last level produced.
+hipError_t launch_pyr_build(const uint8_t* src, int src_pitch, const PyrLevel* lv, int L, hipStream_t s)
+{
+    PyrBuildArg a = pyr_build_arg(src, src_pitch, lv, L);
+    for (int base = 0;; base += 6) {
+        const int top = min(L - 1, base + 6);
+        dim3 grid((a.w[base] + 63) / 64, (a.h[base] + 63) / 64);
+        hipLaunchKernelGGL(k_pyr_build<false>, grid, dim3(256), 0, s, a, nullptr, base, top, base == 0 ? 1 : 0);
+        if (top >= L - 1) break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sobel_fields(const PyrLevel* lv, int L, long long T2, int precision, hipStream_t s)
+{
+    FieldsArg a = fields_arg(lv, L, T2, precision);
+    hipLaunchKernelGGL(k_sobel_fields<false>, dim3(a.block0[L]), dim3(256), 0, s, a, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_pyramids_batch(const PyrBuildArg* pb, const FieldsArg* fa, int n_images, int L, int max_w,
+                                 int max_h, int max_field_blocks, const int* level_w, const int* level_h,
+                                 hipStream_t s)
+{
+    for (int base = 0;; base += 6) {
+        const int top = min(L - 1, base + 6);
+        dim3 grid((level_w[base] + 63) / 64, (level_h[base] + 63) / 64, n_images);
+        hipLaunchKernelGGL(k_pyr_build<true>, grid, dim3(256), 0, s, PyrBuildArg{}, pb, base, top,
+                           base == 0 ? 1 : 0);
+        if (top >= L - 1) break;
+    }
+    (void)max_w;
+    (void)max_h;
+    hipLaunchKernelGGL(k_sobel_fields<true>, dim3(max_field_blocks, n_images), dim3(256), 0, s, FieldsArg{}, fa);
     return hipGetLastError();
 }
 

@@ -14,6 +14,8 @@
 // point order per lane, in blocks of 32 (bounding FP32 error by about
 // 2^-24 (32 + n/32) per score).  Each workgroup covers a chunk of angles and
 // writes its best angle per translation; a second kernel reduces the chunks.
+// Every launch covers all (image, model) pairs of a batch: blockIdx.y (or z)
+// is the pair.
 #include <stdlib.h>
 
 #include "tm_device.h"
@@ -36,41 +38,85 @@ __device__ __forceinline__ float dpp_from_upper(float v)  // lane j receives lan
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xF, 0xF, true));
 }
 
-struct FastArgs {
-    const float2* field;
-    int W, H;
-    const TabEntry* tab;
-    int n_pad, K;
-    float n_f;
-    int A;              // angles per workgroup
-    int WY, WA;         // waves stacked in y, waves splitting the angles
-    int tiles_x, tiles_y;
-    int halo, LR;       // halo width, LDS rows
-    float* pw;          // [C][H][W] partial best S_w
-    float* p1;          //            partial best S_1
-    int32_t* pk;        //            partial best k
+// max(v[j-1], v[j], v[j+1]) across lanes.  ASM: two v_max_f32 with a DPP
+// source (the moves fold into the max); s_nop 1 covers the two wait states a
+// DPP read needs after a VALU write of its source.
+template <bool ASM>
+__device__ __forceinline__ float hmax3(float v)
+{
+    if constexpr (ASM) {
+        float m;
+        asm volatile(
+            "s_nop 1\n\t"
+            "v_max_f32_dpp %0, %1, %1 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+            "v_max_f32_dpp %0, %1, %0 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+            : "=&v"(m)
+            : "v"(v));
+        return m;
+    } else {
+        return fmaxf(fmaxf(v, dpp_from_lower(v)), dpp_from_upper(v));
+    }
+}
+
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+
+// Storage of one field pixel in the LDS tile and its dot product with a
+// table entry's rotated direction: FP32 pairs, or FP16 pairs with the
+// v_dot2_f32_f16 product accumulated in FP32.
+template <int PREC>
+struct Px;
+template <>
+struct Px<TM_FP32> {
+    using T = float2;
+    static __device__ __forceinline__ T zero() { return make_float2(0.f, 0.f); }
+    static __device__ __forceinline__ T load(const void* f, size_t o) { return reinterpret_cast<const float2*>(f)[o]; }
+    static __device__ __forceinline__ float dot(const TabEntry& e, T g) { return e.rx * g.x + e.ry * g.y; }
+};
+template <>
+struct Px<TM_FP16> {
+    using T = uint32_t;
+    static __device__ __forceinline__ T zero() { return 0u; }
+    static __device__ __forceinline__ T load(const void* f, size_t o) { return reinterpret_cast<const uint32_t*>(f)[o]; }
+    static __device__ __forceinline__ float dot(const TabEntry& e, T g)
+    {
+        return __builtin_amdgcn_fdot2(__builtin_bit_cast(h2_t, e.rh), __builtin_bit_cast(h2_t, g), 0.0f, false);
+    }
 };
 
-template <int G, int R, int LC>
-__global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a)
+struct FastArgs {
+    int level;          // searched level
+    int K;              // angles
+    int A;              // angles per workgroup
+    int WY, WA;         // waves stacked in y, waves splitting the angles
+    int C;              // chunks of angles
+};
+
+template <int G, int R, int LC, int PREC, bool ASM>
+__global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc* __restrict__ pairs)
 {
+    using T = typename Px<PREC>::T;
     extern __shared__ __align__(16) unsigned char smem[];
-    float2* tile = reinterpret_cast<float2*>(smem);
+    T* tile = reinterpret_cast<T*>(smem);
     constexpr int NS = 64 / G;   // segments per wave
     constexpr int TW = G - 2;    // output columns per segment
+    const PairDesc& P = pairs[blockIdx.y];
+    const int n_tiles = P.tiles_x * P.tiles_y;
+    if ((int)blockIdx.x >= n_tiles * a.C) return;
     const int TH = a.WY * NS * R;
-    const int n_tiles = a.tiles_x * a.tiles_y;
     const int chunk = blockIdx.x / n_tiles;
     const int tid = blockIdx.x % n_tiles;
-    const int X0 = (tid % a.tiles_x) * TW, Y0 = (tid / a.tiles_x) * TH;
-    const int halo = a.halo;
+    const int X0 = (tid % P.tiles_x) * TW, Y0 = (tid / P.tiles_x) * TH;
+    const int W = P.W[a.level], H = P.H[a.level];
+    const void* field = P.field[a.level];
+    const int halo = P.rad + 1;
+    const int LR = TH + 2 * halo;
     const int fc = TW + 2 * halo;
 
-    for (int e = threadIdx.x; e < a.LR * fc; e += blockDim.x) {
+    for (int e = threadIdx.x; e < LR * fc; e += blockDim.x) {
         const int r = e / fc, c = e - r * fc;
         const int x = X0 - halo + c, y = Y0 - halo + r;
-        float2 v = make_float2(0.f, 0.f);
-        if (x >= 0 && x < a.W && y >= 0 && y < a.H) v = a.field[(size_t)y * a.W + x];
+        T v = Px<PREC>::zero();
+        if (x >= 0 && x < W && y >= 0 && y < H) v = Px<PREC>::load(field, (size_t)y * W + x);
         tile[r * LC + c] = v;
     }
     __syncthreads();
@@ -80,7 +126,10 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a)
     const int wy = wid % a.WY, wa = wid / a.WY;
     const int seg = lane / G, li = lane - seg * G;
     const int row0 = (wy * NS + seg) * R;  // first output row of the strip, tile-relative
-    const float2* lbase = tile + (halo - 1 + row0) * LC + (halo - 1 + li);
+    const T* lbase = tile + (halo - 1 + row0) * LC + (halo - 1 + li);
+    const TabEntry* __restrict__ tab = P.tab;
+    const int n_pad = P.n_pad;
+    const float n_f = (float)P.n[a.level];
 
     float bw[R], b1[R];
     int bk[R];
@@ -92,35 +141,34 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a)
     }
     const int k0 = chunk * a.A, k1 = min(a.K, k0 + a.A);
     for (int k = k0 + wa; k < k1; k += a.WA) {
-        const TabEntry* __restrict__ T = a.tab + (size_t)k * a.n_pad;
+        const TabEntry* __restrict__ Tb = tab + (size_t)k * n_pad;
         float tw[R], t1[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             tw[r] = 0.f;
             t1[r] = 0.f;
         }
-        for (int i0 = 0; i0 < a.n_pad; i0 += kBlock) {
+        for (int i0 = 0; i0 < n_pad; i0 += kBlock) {
             float pw[R], p1[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 pw[r] = 0.f;
                 p1[r] = 0.f;
             }
-            const int i1 = min(a.n_pad, i0 + kBlock);
+            const int i1 = min(n_pad, i0 + kBlock);
 #pragma unroll 2
             for (int i = i0; i < i1; ++i) {
-                const TabEntry e = T[i];
-                const float2* p = lbase + (int)e.qy * LC + (int)e.qx;
+                const TabEntry e = Tb[i];
+                const T* p = lbase + (int)e.qy * LC + (int)e.qx;
                 float D[R + 2];
 #pragma unroll
-                for (int rr = 0; rr < R + 2; ++rr) {
-                    const float2 g = p[rr * LC];
-                    D[rr] = e.rx * g.x + e.ry * g.y;
-                }
+                for (int rr = 0; rr < R + 2; ++rr) D[rr] = Px<PREC>::dot(e, p[rr * LC]);
+                float V[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) V[r] = fmaxf(fmaxf(D[r], D[r + 1]), D[r + 2]);
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const float v = fmaxf(fmaxf(D[r], D[r + 1]), D[r + 2]);
-                    pw[r] += fmaxf(fmaxf(v, dpp_from_lower(v)), dpp_from_upper(v));
+                    pw[r] += hmax3<ASM>(V[r]);
                     p1[r] += D[r + 1];
                 }
             }
@@ -132,7 +180,7 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a)
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const float sw = tw[r] / a.n_f, s1 = t1[r] / a.n_f;
+            const float sw = tw[r] / n_f, s1 = t1[r] / n_f;
             if (sw > bw[r] || (sw == bw[r] && s1 > b1[r])) {
                 bw[r] = sw;
                 b1[r] = s1;
@@ -160,7 +208,7 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a)
     for (int p = threadIdx.x; p < npos; p += blockDim.x) {
         const int py = p / TW, px = p - py * TW;
         const int X = X0 + px, Y = Y0 + py;
-        if (X >= a.W || Y >= a.H) continue;
+        if (X >= W || Y >= H) continue;
         float w0 = cw[p], s0 = c1[p];
         int kk = ck[p];
         for (int w = 1; w < a.WA; ++w) {
@@ -171,46 +219,44 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a)
                 kk = ck[q];
             }
         }
-        const size_t o = ((size_t)chunk * a.H + Y) * a.W + X;
-        a.pw[o] = w0;
-        a.p1[o] = s0;
-        a.pk[o] = kk;
+        const size_t o = ((size_t)chunk * H + Y) * W + X;
+        P.pw[o] = w0;
+        P.p1[o] = s0;
+        P.pk[o] = kk;
     }
 }
 
 struct GenericArgs {
-    const void* field;
-    int W, H, precision;
-    const TabEntry* tab;
-    int n, n_pad, K;
-    float n_f;
-    int sx, sy, win, gw, gh;
-    int A;
-    float* pw;
-    float* p1;
-    int32_t* pk;
+    int level, K, A, sx, sy, win;
 };
 
 // Any step and window: one thread per grid translation, taps read from
-// global memory (clamped addresses, no branches).
+// global memory (clamped addresses, no branches).  grid: (translations,
+// chunk, pair).
 template <int PREC>
-__global__ __launch_bounds__(256) void k_dense_generic(GenericArgs a)
+__global__ __launch_bounds__(256) void k_dense_generic(GenericArgs a, const PairDesc* __restrict__ pairs)
 {
+    const PairDesc& P = pairs[blockIdx.z];
+    const int gw = P.gw, gh = P.gh;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const int chunk = blockIdx.y;
-    if (p >= a.gw * a.gh) return;
-    const int gy = p / a.gw, gx = p - gy * a.gw;
+    if (p >= gw * gh) return;
+    const int W = P.W[a.level], H = P.H[a.level];
+    const void* field = P.field[a.level];
+    const int n = P.n[a.level];
+    const float n_f = (float)n;
+    const int gy = p / gw, gx = p - gy * gw;
     const int x = gx * a.sx, y = gy * a.sy;
     const int h = (a.win - 1) / 2;
     float bw = -INFINITY, b1 = -INFINITY;
     int bk = -1;
     const int k0 = chunk * a.A, k1 = min(a.K, k0 + a.A);
     for (int k = k0; k < k1; ++k) {
-        const TabEntry* __restrict__ T = a.tab + (size_t)k * a.n_pad;
+        const TabEntry* __restrict__ T = P.tab + (size_t)k * P.n_pad;
         float tw = 0.f, t1 = 0.f;
-        for (int i0 = 0; i0 < a.n; i0 += kBlock) {
+        for (int i0 = 0; i0 < n; i0 += kBlock) {
             float pw = 0.f, p1 = 0.f;
-            const int i1 = min(a.n, i0 + kBlock);
+            const int i1 = min(n, i0 + kBlock);
             for (int i = i0; i < i1; ++i) {
                 const TabEntry e = T[i];
                 const int px = x + e.qx, py = y + e.qy;
@@ -218,24 +264,24 @@ __global__ __launch_bounds__(256) void k_dense_generic(GenericArgs a)
                 for (int dy = -h; dy <= h; ++dy)
 #pragma unroll 3
                     for (int dx = -h; dx <= h; ++dx)
-                        best = fmaxf(best, field_dot<PREC>(a.field, a.W, a.H, px + dx, py + dy, e.rx, e.ry));
+                        best = fmaxf(best, field_dot<PREC>(field, W, H, px + dx, py + dy, e.rx, e.ry));
                 pw += best;
-                p1 += field_dot<PREC>(a.field, a.W, a.H, px, py, e.rx, e.ry);
+                p1 += field_dot<PREC>(field, W, H, px, py, e.rx, e.ry);
             }
             tw += pw;
             t1 += p1;
         }
-        const float sw = tw / a.n_f, s1 = t1 / a.n_f;
+        const float sw = tw / n_f, s1 = t1 / n_f;
         if (sw > bw || (sw == bw && s1 > b1)) {
             bw = sw;
             b1 = s1;
             bk = k;
         }
     }
-    const size_t o = ((size_t)chunk * a.gh + gy) * a.gw + gx;
-    a.pw[o] = bw;
-    a.p1[o] = b1;
-    a.pk[o] = bk;
+    const size_t o = ((size_t)chunk * gh + gy) * gw + gx;
+    P.pw[o] = bw;
+    P.p1[o] = b1;
+    P.pk[o] = bk;
 }
 
 // Best angle per translation over the C chunk partials, in key order.  A
@@ -246,13 +292,16 @@ __global__ __launch_bounds__(256) void k_dense_generic(GenericArgs a)
 constexpr int kRedLanes = 8;
 constexpr int kRedPos = 32;
 
-__global__ __launch_bounds__(256) void k_reduce_chunks(const float* __restrict__ pw, const float* __restrict__ p1,
-                                                        const int32_t* __restrict__ pk, int C, int np,
-                                                        float* __restrict__ ow, float* __restrict__ o1,
-                                                        int32_t* __restrict__ ok)
+__global__ __launch_bounds__(256) void k_reduce_chunks(int C, const PairDesc* __restrict__ pairs)
 {
     __shared__ float sw_[kRedPos][kRedLanes], s1_[kRedPos][kRedLanes];
     __shared__ int sk_[kRedPos][kRedLanes];
+    const PairDesc& P = pairs[blockIdx.y];
+    const int np = P.gw * P.gh;
+    if ((int)blockIdx.x * kRedPos >= np) return;
+    const float* __restrict__ pw = P.pw;
+    const float* __restrict__ p1 = P.p1;
+    const int32_t* __restrict__ pk = P.pk;
     const int lane = threadIdx.x % kRedLanes, slot = threadIdx.x / kRedLanes;
     const int p = blockIdx.x * kRedPos + slot;
     float w0 = -INFINITY, s0 = -INFINITY;
@@ -299,9 +348,9 @@ __global__ __launch_bounds__(256) void k_reduce_chunks(const float* __restrict__
                 s0 = s1_[slot][u];
                 k = sk_[slot][u];
             }
-        ow[p] = w0;
-        o1[p] = s0;
-        ok[p] = k;
+        P.mw[p] = w0;
+        P.m1[p] = s0;
+        P.mk[p] = k;
     }
 }
 
@@ -348,21 +397,12 @@ __global__ __launch_bounds__(256) void k_sparse(const void* __restrict__ field, 
 }
 
 // ---------------------------------------------------------------- planning
-struct Plan {
-    bool fast;
-    int G, R, LC;
-    int WY, WA;
-    int tiles_x, tiles_y;
-    int halo, LR;
-    int A, C;
-    size_t lds;
-};
-
 constexpr int kLC[] = {64, 96, 128, 192, 256};
 
 // Launch-shape knobs of the search kernel: waves stacked in y per workgroup,
-// waves splitting the angle chunk, and angles per wave.  Defaults can be
-// overridden by TM_DENSE_WY / TM_DENSE_WA / TM_DENSE_APW (tuning runs).
+// waves splitting the angle chunk, angles per wave, and the window-max form.
+// Defaults can be overridden by TM_DENSE_WY / TM_DENSE_WA / TM_DENSE_APW /
+// TM_DENSE_ASM (tuning runs).
 int knob(const char* name, int dflt, int lo, int hi)
 {
     const char* v = getenv(name);
@@ -371,11 +411,56 @@ int knob(const char* name, int dflt, int lo, int hi)
     return x < lo ? lo : (x > hi ? hi : x);
 }
 
-Plan make_plan(const DenseGeom& g)
+template <int G, int R, int LC, int PREC, bool ASM>
+hipError_t launch_fast_t(const DensePlan& p, const FastArgs& a, const PairDesc* d, int npairs, hipStream_t s)
 {
-    Plan p = {};
-    const int halo = g.rad + 1;
-    p.fast = g.sx == 1 && g.sy == 1 && g.win == 3 && g.precision == TM_FP32;
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dense_fast<G, R, LC, PREC, ASM>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_dense_fast<G, R, LC, PREC, ASM>), dim3(p.max_blocks, npairs), dim3(64 * p.WY * p.WA), p.lds,
+                       s, a, d);
+    return hipGetLastError();
+}
+
+template <int PREC, bool ASM>
+hipError_t launch_fast_p(const DensePlan& p, const FastArgs& a, const PairDesc* d, int npairs, hipStream_t s)
+{
+    switch (p.LC) {
+        case 64: return launch_fast_t<32, 8, 64, PREC, ASM>(p, a, d, npairs, s);
+        case 96: return launch_fast_t<32, 8, 96, PREC, ASM>(p, a, d, npairs, s);
+        case 128: return launch_fast_t<32, 8, 128, PREC, ASM>(p, a, d, npairs, s);
+        case 192: return launch_fast_t<32, 8, 192, PREC, ASM>(p, a, d, npairs, s);
+        default: return launch_fast_t<32, 8, 256, PREC, ASM>(p, a, d, npairs, s);
+    }
+}
+
+}  // namespace
+
+void plan_tiles(const DensePlan& p, const PairGeom& g, int* tiles_x, int* tiles_y)
+{
+    if (!p.fast) {
+        *tiles_x = *tiles_y = 0;
+        return;
+    }
+    const int TW = p.G - 2, TH = p.WY * (64 / p.G) * p.R;
+    *tiles_x = (g.W + TW - 1) / TW;
+    *tiles_y = (g.H + TH - 1) / TH;
+}
+
+DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
+{
+    DensePlan p = {};
+    int max_halo = 0;
+    for (int i = 0; i < npairs; ++i) {
+        max_halo = max(max_halo, g[i].rad + 1);
+        p.max_np = max(p.max_np, g[i].gw * g[i].gh);
+    }
+    p.fast = s.sx == 1 && s.sy == 1 && s.win == 3;
+    p.asm_dpp = knob("TM_DENSE_ASM", 0, 0, 1) != 0;
     if (p.fast) {
         p.G = 32;
         p.R = 8;
@@ -385,141 +470,90 @@ Plan make_plan(const DenseGeom& g)
         const int TW = p.G - 2, TH = p.WY * (64 / p.G) * p.R;
         p.LC = 0;
         for (int lc : kLC)
-            if (lc >= TW + 2 * halo) {
+            if (lc >= TW + 2 * max_halo) {
                 p.LC = lc;
                 break;
             }
-        p.halo = halo;
-        p.LR = TH + 2 * halo;
-        p.tiles_x = (g.W + TW - 1) / TW;
-        p.tiles_y = (g.H + TH - 1) / TH;
-        size_t tile_bytes = (size_t)p.LR * p.LC * sizeof(float2);
-        size_t comb_bytes = (size_t)12 * p.WA * TH * TW;
+        const size_t tile_bytes = (size_t)(TH + 2 * max_halo) * p.LC * (s.precision == TM_FP16 ? 4 : 8);
+        const size_t comb_bytes = (size_t)12 * p.WA * TH * TW;
         p.lds = tile_bytes > comb_bytes ? tile_bytes : comb_bytes;
         if (p.LC == 0 || p.lds > 160 * 1024) p.fast = false;
     }
     if (p.fast) {
-        // about four waves per SIMD over the whole grid, whole angles per wave
-        const long long units = (long long)p.tiles_x * p.tiles_y * g.K;
+        // about four waves per SIMD over the whole batch, whole angles per wave
+        long long units = 0;
+        int max_tiles = 0;
+        for (int i = 0; i < npairs; ++i) {
+            int tx, ty;
+            plan_tiles(p, g[i], &tx, &ty);
+            units += (long long)tx * ty * s.K[s.level];
+            max_tiles = max(max_tiles, tx * ty);
+        }
         long long per_wave = units / 4096;
         if (per_wave < 1) per_wave = 1;
         per_wave = knob("TM_DENSE_APW", (int)per_wave, 1, 1 << 20);
         p.A = (int)(per_wave * p.WA);
-        p.C = (g.K + p.A - 1) / p.A;
+        p.C = (s.K[s.level] + p.A - 1) / p.A;
+        p.max_blocks = max_tiles * p.C;
     } else {
-        const int blocks = (g.gw * g.gh + 255) / 256;
-        int C = (2048 + blocks - 1) / blocks;  // enough workgroups to fill the chip
-        if (C > g.K) C = g.K;
+        long long np_all = 0;
+        for (int i = 0; i < npairs; ++i) np_all += (long long)g[i].gw * g[i].gh;
+        const long long blocks = (np_all + 255) / 256;
+        long long C = (2048 + blocks - 1) / blocks;  // enough workgroups to fill the chip
+        if (C > s.K[s.level]) C = s.K[s.level];
         if (C < 1) C = 1;
-        p.A = (g.K + C - 1) / C;
-        p.C = (g.K + p.A - 1) / p.A;
+        p.A = (int)((s.K[s.level] + C - 1) / C);
+        p.C = (s.K[s.level] + p.A - 1) / p.A;
     }
     return p;
 }
 
-template <int G, int R, int LC>
-hipError_t launch_fast_t(const Plan& p, const FastArgs& a, hipStream_t s)
-{
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dense_fast<G, R, LC>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
-    const int blocks = p.tiles_x * p.tiles_y * p.C;
-    hipLaunchKernelGGL((k_dense_fast<G, R, LC>), dim3(blocks), dim3(64 * p.WY * p.WA), p.lds, s, a);
-    return hipGetLastError();
-}
+size_t dense_partials_bytes(const DensePlan& p, int np) { return (size_t)p.C * np * 12; }
 
-hipError_t launch_fast(const Plan& p, const FastArgs& a, hipStream_t s)
-{
-    switch (p.LC) {
-        case 64: return launch_fast_t<32, 8, 64>(p, a, s);
-        case 96: return launch_fast_t<32, 8, 96>(p, a, s);
-        case 128: return launch_fast_t<32, 8, 128>(p, a, s);
-        case 192: return launch_fast_t<32, 8, 192>(p, a, s);
-        default: return launch_fast_t<32, 8, 256>(p, a, s);
-    }
-}
-
-}  // namespace
-
-size_t dense_workspace_bytes(const DenseGeom& g)
-{
-    Plan p = make_plan(g);
-    const size_t np = p.fast ? (size_t)g.W * g.H : (size_t)g.gw * g.gh;
-    return (size_t)p.C * np * 12 + 256;
-}
-
-hipError_t launch_dense(const DenseGeom& g, void* ws, float* ow, float* o1, int32_t* ok, hipStream_t s,
+hipError_t launch_dense(const SearchDesc& s, const DensePlan& p, const PairDesc* d, int npairs, hipStream_t st,
                         hipEvent_t ev0, hipEvent_t ev1)
 {
-    Plan p = make_plan(g);
-    const size_t np = p.fast ? (size_t)g.W * g.H : (size_t)g.gw * g.gh;
-    float* pw = reinterpret_cast<float*>(ws);
-    float* p1 = pw + (size_t)p.C * np;
-    int32_t* pk = reinterpret_cast<int32_t*>(p1 + (size_t)p.C * np);
     hipError_t e;
     if (ev0) {
-        e = hipEventRecord(ev0, s);
+        e = hipEventRecord(ev0, st);
         if (e != hipSuccess) return e;
     }
     if (p.fast) {
         FastArgs a;
-        a.field = reinterpret_cast<const float2*>(g.field);
-        a.W = g.W;
-        a.H = g.H;
-        a.tab = g.tab;
-        a.n_pad = g.n_pad;
-        a.K = g.K;
-        a.n_f = (float)g.n;
+        a.level = s.level;
+        a.K = s.K[s.level];
         a.A = p.A;
         a.WY = p.WY;
         a.WA = p.WA;
-        a.tiles_x = p.tiles_x;
-        a.tiles_y = p.tiles_y;
-        a.halo = p.halo;
-        a.LR = p.LR;
-        a.pw = pw;
-        a.p1 = p1;
-        a.pk = pk;
-        e = launch_fast(p, a, s);
+        a.C = p.C;
+        if (s.precision == TM_FP16)
+            e = p.asm_dpp ? launch_fast_p<TM_FP16, true>(p, a, d, npairs, st)
+                          : launch_fast_p<TM_FP16, false>(p, a, d, npairs, st);
+        else
+            e = p.asm_dpp ? launch_fast_p<TM_FP32, true>(p, a, d, npairs, st)
+                          : launch_fast_p<TM_FP32, false>(p, a, d, npairs, st);
     } else {
         GenericArgs a;
-        a.field = g.field;
-        a.W = g.W;
-        a.H = g.H;
-        a.precision = g.precision;
-        a.tab = g.tab;
-        a.n = g.n;
-        a.n_pad = g.n_pad;
-        a.K = g.K;
-        a.n_f = (float)g.n;
-        a.sx = g.sx;
-        a.sy = g.sy;
-        a.win = g.win;
-        a.gw = g.gw;
-        a.gh = g.gh;
+        a.level = s.level;
+        a.K = s.K[s.level];
         a.A = p.A;
-        a.pw = pw;
-        a.p1 = p1;
-        a.pk = pk;
-        dim3 grid((g.gw * g.gh + 255) / 256, p.C);
-        if (g.precision == TM_FP16)
-            hipLaunchKernelGGL(k_dense_generic<TM_FP16>, grid, dim3(256), 0, s, a);
+        a.sx = s.sx;
+        a.sy = s.sy;
+        a.win = s.win;
+        dim3 grid((p.max_np + 255) / 256, p.C, npairs);
+        if (s.precision == TM_FP16)
+            hipLaunchKernelGGL(k_dense_generic<TM_FP16>, grid, dim3(256), 0, st, a, d);
         else
-            hipLaunchKernelGGL(k_dense_generic<TM_FP32>, grid, dim3(256), 0, s, a);
+            hipLaunchKernelGGL(k_dense_generic<TM_FP32>, grid, dim3(256), 0, st, a, d);
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
     if (ev1) {
-        e = hipEventRecord(ev1, s);
+        e = hipEventRecord(ev1, st);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((np + kRedPos - 1) / kRedPos)), dim3(kRedPos * kRedLanes), 0,
-                       s, pw, p1, pk, p.C,
-                       (int)np, ow, o1, ok);
+    hipLaunchKernelGGL(k_reduce_chunks, dim3((p.max_np + kRedPos - 1) / kRedPos, npairs), dim3(kRedPos * kRedLanes),
+                       0, st, p.C, d);
     return hipGetLastError();
 }
 

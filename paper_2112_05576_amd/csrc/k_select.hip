@@ -145,12 +145,31 @@ __device__ int greedy_wave0(const Keys& a, int N, int level, double dmin2, int c
 constexpr int kSelCap = 1024;   // candidates sorted into LDS by k_select (more go through global scratch)
 constexpr int kFinCap = 1024;   // candidates handled by k_final
 
-__global__ __launch_bounds__(1024) void k_select(const float* __restrict__ mw, const float* __restrict__ m1,
-                                                  const int32_t* __restrict__ mk, int gw, int gh, int sx, int sy,
-                                                  int level, float min_score, double dmin2, double theta_min,
-                                                  double step_level, tm_pose* __restrict__ out, int cap,
-                                                  int32_t* __restrict__ n_out, Keys g, Keys gs, int* gidx)
+struct SelectArgs {
+    int sx, sy, level, cap;
+    float min_score;
+    double theta_min, step_level;
+};
+
+// One workgroup per pair (blockIdx.y).
+__global__ __launch_bounds__(1024) void k_select(SelectArgs sa, const PairDesc* __restrict__ pairs)
 {
+    const PairDesc& P = pairs[blockIdx.y];
+    const float* __restrict__ mw = P.mw;
+    const float* __restrict__ m1 = P.m1;
+    const int32_t* __restrict__ mk = P.mk;
+    const int gw = P.gw, gh = P.gh, sx = sa.sx, sy = sa.sy, level = sa.level, cap = sa.cap;
+    const float min_score = sa.min_score;
+    const double dmin2 = (double)P.dmin * (double)P.dmin;
+    const double theta_min = sa.theta_min, step_level = sa.step_level;
+    tm_pose* __restrict__ out = P.cand;
+    int32_t* __restrict__ n_out = P.ncand;
+    const size_t npg = (size_t)gw * gh;
+    Keys g{P.sel, P.sel + npg, reinterpret_cast<int*>(P.sel + 2 * npg), reinterpret_cast<int*>(P.sel + 3 * npg),
+           reinterpret_cast<int*>(P.sel + 4 * npg)};
+    Keys gs{P.sel + 5 * npg, P.sel + 6 * npg, reinterpret_cast<int*>(P.sel + 7 * npg),
+            reinterpret_cast<int*>(P.sel + 8 * npg), reinterpret_cast<int*>(P.sel + 9 * npg)};
+    int* gidx = reinterpret_cast<int*>(P.sel + 10 * npg);
     __shared__ float l_sw[kSelCap], l_s1[kSelCap];
     __shared__ int l_x[kSelCap], l_y[kSelCap], l_k[kSelCap];
     __shared__ int acc_x[kFinCap], acc_y[kFinCap], acc_i[kFinCap];
@@ -220,11 +239,24 @@ __global__ __launch_bounds__(1024) void k_select(const float* __restrict__ mw, c
 
 // Final selection of the refined level-0 poses: score floor, key order (rank
 // by counting, the list is short), greedy suppression, at most cap.
-__global__ __launch_bounds__(256) void k_final(const tm_pose* __restrict__ cand, const int32_t* __restrict__ n_cand,
-                                                int max_cand, float min_score, double dmin2, double theta_min,
-                                                double step0, tm_pose* __restrict__ out, int cap,
-                                                int32_t* __restrict__ n_out)
+struct FinalArgs {
+    int max_cand, cap;
+    float min_score;
+    double theta_min, step0;
+};
+
+// One workgroup per pair (blockIdx.y).
+__global__ __launch_bounds__(256) void k_final(FinalArgs fa, const PairDesc* __restrict__ pairs)
 {
+    const PairDesc& P = pairs[blockIdx.y];
+    const tm_pose* __restrict__ cand = P.cand;
+    const int32_t* __restrict__ n_cand = P.ncand;
+    const int max_cand = fa.max_cand, cap = fa.cap;
+    const float min_score = fa.min_score;
+    const double dmin2 = (double)P.dmin * (double)P.dmin;
+    const double theta_min = fa.theta_min, step0 = fa.step0;
+    tm_pose* __restrict__ out = P.out;
+    int32_t* __restrict__ n_out = P.n_out;
     __shared__ float u_sw[kFinCap], u_s1[kFinCap];
     __shared__ int u_x[kFinCap], u_y[kFinCap], u_k[kFinCap];
     __shared__ float l_sw[kFinCap], l_s1[kFinCap];
@@ -281,39 +313,32 @@ __global__ __launch_bounds__(256) void k_final(const tm_pose* __restrict__ cand,
 
 }  // namespace
 
-size_t select_workspace_bytes(int gw, int gh)
-{
-    const size_t np = (size_t)gw * gh;
-    return np * (2 * 20 + 4) + 256;
-}
+size_t select_scratch_bytes(int np) { return (size_t)np * 44 + 256; }
 
-hipError_t launch_select(const float* sw, const float* s1, const int32_t* k, int gw, int gh, int sx, int sy,
-                         int level, float min_score, double dmin2, double theta_min, double step_level,
-                         tm_pose* out, int capacity, int32_t* n_out, void* scratch, hipStream_t s)
+hipError_t launch_select(const SearchDesc& s, const PairDesc* d, int npairs, int max_np, hipStream_t st)
 {
-    const size_t np = (size_t)gw * gh;
-    Keys g, gs;
-    g.sw = reinterpret_cast<float*>(scratch);
-    g.s1 = g.sw + np;
-    g.x = reinterpret_cast<int*>(g.s1 + np);
-    g.y = g.x + np;
-    g.k = g.y + np;
-    gs.sw = reinterpret_cast<float*>(g.k + np);
-    gs.s1 = gs.sw + np;
-    gs.x = reinterpret_cast<int*>(gs.s1 + np);
-    gs.y = gs.x + np;
-    gs.k = gs.y + np;
-    int* gidx = gs.k + np;
-    hipLaunchKernelGGL(k_select, dim3(1), dim3(1024), 0, s, sw, s1, k, gw, gh, sx, sy, level, min_score, dmin2,
-                       theta_min, step_level, out, capacity, n_out, g, gs, gidx);
+    (void)max_np;
+    SelectArgs a;
+    a.sx = s.sx;
+    a.sy = s.sy;
+    a.level = s.level;
+    a.cap = s.max_cand;
+    a.min_score = s.min_score;
+    a.theta_min = s.theta_min;
+    a.step_level = s.step[s.level];
+    hipLaunchKernelGGL(k_select, dim3(1, npairs), dim3(1024), 0, st, a, d);
     return hipGetLastError();
 }
 
-hipError_t launch_final(const tm_pose* cand, const int32_t* n_cand, int max_cand, float min_score, double dmin2,
-                        double theta_min, double step0, tm_pose* out, int capacity, int32_t* n_out, hipStream_t s)
+hipError_t launch_final(const SearchDesc& s, const PairDesc* d, int npairs, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, s, cand, n_cand, max_cand, min_score, dmin2, theta_min, step0,
-                       out, capacity, n_out);
+    FinalArgs a;
+    a.max_cand = s.max_cand;
+    a.cap = s.capacity;
+    a.min_score = s.min_score;
+    a.theta_min = s.theta_min;
+    a.step0 = s.step[0];
+    hipLaunchKernelGGL(k_final, dim3(1, npairs), dim3(256), 0, st, a, d);
     return hipGetLastError();
 }
 

@@ -163,6 +163,7 @@ tm_status ensure_ws(tm_pyramid* p, size_t bytes, hipStream_t s)
     bytes = align_up(bytes, 1 << 20);
     HIP_TRY(hipMalloc(&p->ws.ptr, bytes));
     p->ws.bytes = bytes;
+    p->desc_valid = false;
     return TM_OK;
 }
 
@@ -212,68 +213,141 @@ tm_status check_pair(const tm_model* m, const tm_pyramid* p, const char* what)
     return TM_OK;
 }
 
-tmk::RefineArgs refine_args(const tm_model* m, const tm_pyramid* p, const tm_search_params* sp, const Grid& g)
+tmk::SearchDesc make_search(const tm_search_params* sp, const Grid& g, int level, int precision, int capacity)
 {
-    tmk::RefineArgs a = {};
-    for (int l = 0; l < p->L; ++l) {
-        a.lv[l].field = p->lv[l].field;
-        a.lv[l].W = p->lv[l].w;
-        a.lv[l].H = p->lv[l].h;
-        a.lv[l].pts = m->lv[l].pts;
-        a.lv[l].n = m->lv[l].n;
-        a.lv[l].step = g.step[l];
-        a.lv[l].K = g.K[l];
+    tmk::SearchDesc s;
+    memset(&s, 0, sizeof(s));
+    s.L = g.L;
+    s.level = level;
+    for (int l = 0; l < g.L; ++l) {
+        s.K[l] = g.K[l];
+        s.step[l] = g.step[l];
     }
-    a.L = p->L;
-    a.precision = p->precision;
-    a.win = sp->neighbourhood;
-    a.full = g.full;
-    a.theta_min = sp->theta_min_deg;
-    return a;
+    s.theta_min = sp->theta_min_deg;
+    s.full = g.full;
+    s.win = sp->neighbourhood;
+    s.sx = sp->step_x;
+    s.sy = sp->step_y;
+    s.precision = precision;
+    s.min_score = sp->min_score;
+    s.max_cand = sp->max_candidates;
+    s.capacity = capacity;
+    return s;
 }
 
-tmk::DenseGeom dense_geom(const tm_model* m, const tm_pyramid* p, int level, const tm_search_params* sp,
-                         const tmk::TabEntry* tab, int K)
+tmk::PairGeom pair_geom(const tm_model* m, const tm_pyramid* p, int level, int sx, int sy)
 {
-    tmk::DenseGeom g;
-    g.field = p->lv[level].field;
+    tmk::PairGeom g;
     g.W = p->lv[level].w;
     g.H = p->lv[level].h;
-    g.precision = p->precision;
-    g.tab = tab;
-    g.n = m->lv[level].n;
-    g.n_pad = m->lv[level].n_pad;
-    g.K = K;
-    g.sx = sp->step_x;
-    g.sy = sp->step_y;
-    g.win = sp->neighbourhood;
+    g.gw = (g.W + sx - 1) / sx;
+    g.gh = (g.H + sy - 1) / sy;
     g.rad = m->lv[level].rad;
-    g.gw = (g.W + g.sx - 1) / g.sx;
-    g.gh = (g.H + g.sy - 1) / g.sy;
+    g.n = m->lv[level].n;
     return g;
 }
 
-// scratch layout of detect: [dense partials][map w|1|k][select keys][cands][count][refine]
-struct DetectLayout {
-    size_t dense, map, sel, cand, refine, total;
-};
-
-DetectLayout detect_layout(const tmk::DenseGeom& g, int max_cand, size_t refine_bytes)
+// Static part of a pair descriptor: the image's levels, the model's levels,
+// the rotated table of the searched level and the suppression distance.
+void pair_static(tmk::PairDesc* d, const tm_model* m, const tm_pyramid* p, const tmk::TabEntry* tab, int level,
+                 const tmk::PairGeom& g, const tmk::DensePlan& plan, float dmin)
 {
-    DetectLayout d;
+    for (int l = 0; l < p->L; ++l) {
+        d->field[l] = p->lv[l].field;
+        d->W[l] = p->lv[l].w;
+        d->H[l] = p->lv[l].h;
+        d->pts[l] = m->lv[l].pts;
+        d->n[l] = m->lv[l].n;
+    }
+    d->tab = tab;
+    d->n_pad = m->lv[level].n_pad;
+    d->rad = m->lv[level].rad;
+    d->gw = g.gw;
+    d->gh = g.gh;
+    tmk::plan_tiles(plan, g, &d->tiles_x, &d->tiles_y);
+    d->dmin = dmin;
+}
+
+// Scratch of one pair placed at `base` (null: measure only); returns bytes.
+// search: chunk partials and the best-angle map; select: selection scratch
+// and the candidate list; refine: centres and partial sums per level.
+size_t pair_scratch(tmk::PairDesc* d, const tm_model* m, const tmk::PairGeom& g, const tmk::DensePlan& plan, int L,
+                    int max_cand, bool search, bool select, bool refine, uint8_t* base)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> uint8_t* {
+        uint8_t* r = base ? base + off : nullptr;
+        off = align_up(off + bytes, 256);
+        return r;
+    };
     const size_t np = (size_t)g.gw * g.gh;
-    d.dense = 0;
-    size_t off = align_up(tmk::dense_workspace_bytes(g), 256);
-    d.map = off;
-    off += align_up(np * 12, 256);
-    d.sel = off;
-    off += align_up(tmk::select_workspace_bytes(g.gw, g.gh), 256);
-    d.cand = off;
-    off += align_up((size_t)max_cand * sizeof(tm_pose) + 256, 256);
-    d.refine = off;
-    off += align_up(refine_bytes, 256);
-    d.total = off;
-    return d;
+    if (search) {
+        const size_t C = (size_t)plan.C;
+        float* pw = reinterpret_cast<float*>(take(tmk::dense_partials_bytes(plan, (int)np)));
+        float* mw = reinterpret_cast<float*>(take(np * 12));
+        if (base) {
+            d->pw = pw;
+            d->p1 = pw + C * np;
+            d->pk = reinterpret_cast<int32_t*>(pw + 2 * C * np);
+            d->mw = mw;
+            d->m1 = mw + np;
+            d->mk = reinterpret_cast<int32_t*>(mw + 2 * np);
+        }
+    }
+    if (select) {
+        float* sel = reinterpret_cast<float*>(take(tmk::select_scratch_bytes((int)np)));
+        uint8_t* cp = take((size_t)max_cand * sizeof(tm_pose) + 256);
+        if (base) {
+            d->sel = sel;
+            d->cand = reinterpret_cast<tm_pose*>(cp);
+            d->ncand = reinterpret_cast<int32_t*>(cp + (size_t)max_cand * sizeof(tm_pose));
+        }
+    }
+    if (refine) {
+        tm_pose* c0 = reinterpret_cast<tm_pose*>(take((size_t)max_cand * sizeof(tm_pose)));
+        tm_pose* c1 = reinterpret_cast<tm_pose*>(take((size_t)max_cand * sizeof(tm_pose)));
+        if (base) {
+            d->ctr[0] = c0;
+            d->ctr[1] = c1;
+        }
+        for (int l = 0; l < L; ++l) {
+            float* pl = reinterpret_cast<float*>(
+                take((size_t)max_cand * 3 * tmk::refine_chunks(m->lv[l].n) * 18 * sizeof(float)));
+            if (base) d->part[l] = pl;
+        }
+    }
+    return off;
+}
+
+__global__ void k_put_desc(tmk::PairDesc d, tmk::PairDesc* dst)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = d;
+}
+
+constexpr size_t kDescBytes = 4096;  // reserved at the start of a pyramid's scratch for its descriptor
+static_assert(sizeof(tmk::PairDesc) <= 1024, "descriptor cache");
+
+// Device copy of a one-pair descriptor at the start of the pyramid's scratch,
+// enqueued only when it differs from the last one written there.
+tm_status put_desc(tm_pyramid* p, const tmk::PairDesc& d, hipStream_t s, tmk::PairDesc** out)
+{
+    tmk::PairDesc* dev = reinterpret_cast<tmk::PairDesc*>(p->ws.ptr);
+    if (!p->desc_valid || memcmp(p->last_desc, &d, sizeof(d)) != 0) {
+        hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, d, dev);
+        HIP_TRY(hipGetLastError());
+        memcpy(p->last_desc, &d, sizeof(d));
+        p->desc_valid = true;
+    }
+    *out = dev;
+    return TM_OK;
+}
+
+void refine_max_chunks(const tm_model* const* models, int n_models, int L, int* mc)
+{
+    for (int l = 0; l < L; ++l) {
+        mc[l] = 1;
+        for (int j = 0; j < n_models; ++j) mc[l] = std::max(mc[l], tmk::refine_chunks(models[j]->lv[l].n));
+    }
 }
 
 }  // namespace
@@ -284,16 +358,12 @@ TM_EXPORT const char* tm_last_error(void) { return g_err; }
 
 TM_EXPORT const char* tm_version(void) { return "tm-hip 0.1 (gfx950)"; }
 
-TM_EXPORT tm_status tm_build_pyramid(const uint8_t* img, int32_t w, int32_t h, int32_t pitch,
-                                     const tm_pyr_params* pp, void* stream, tm_pyramid** out)
+namespace {
+// A pyramid of a w x h image with storage for all levels (not yet built).
+tm_status alloc_pyramid(int w, int h, const tm_pyr_params* pp, tm_pyramid** out)
 {
-    g_err[0] = 0;
-    if (!out) return fail(TM_EINVAL, "tm_build_pyramid: null out");
-    *out = nullptr;
-    tm_status st = check_image(img, w, h, pitch, pp, "tm_build_pyramid");
-    if (st != TM_OK) return st;
     tm_pyramid* p = new (std::nothrow) tm_pyramid_s();
-    if (!p) return fail(TM_ENOMEM, "tm_build_pyramid: host allocation");
+    if (!p) return fail(TM_ENOMEM, "pyramid: host allocation");
     p->L = pp->levels;
     p->precision = pp->precision;
     p->tau = pp->edge_thresh;
@@ -313,7 +383,7 @@ TM_EXPORT tm_status tm_build_pyramid(const uint8_t* img, int32_t w, int32_t h, i
     hipError_t e = hipMalloc(&p->block, total);
     if (e != hipSuccess) {
         delete p;
-        return hip_fail(e, "tm_build_pyramid: hipMalloc");
+        return hip_fail(e, "pyramid: hipMalloc");
     }
     for (int l = 0; l < p->L; ++l) {
         p->lv[l].w = ws[l];
@@ -321,6 +391,22 @@ TM_EXPORT tm_status tm_build_pyramid(const uint8_t* img, int32_t w, int32_t h, i
         p->lv[l].img = reinterpret_cast<uint8_t*>(p->block) + img_off[l];
         p->lv[l].field = reinterpret_cast<uint8_t*>(p->block) + fld_off[l];
     }
+    *out = p;
+    return TM_OK;
+}
+}  // namespace
+
+TM_EXPORT tm_status tm_build_pyramid(const uint8_t* img, int32_t w, int32_t h, int32_t pitch,
+                                     const tm_pyr_params* pp, void* stream, tm_pyramid** out)
+{
+    g_err[0] = 0;
+    if (!out) return fail(TM_EINVAL, "tm_build_pyramid: null out");
+    *out = nullptr;
+    tm_status st = check_image(img, w, h, pitch, pp, "tm_build_pyramid");
+    if (st != TM_OK) return st;
+    tm_pyramid* p = nullptr;
+    st = alloc_pyramid(w, h, pp, &p);
+    if (st != TM_OK) return st;
     st = tm_update_pyramid(p, img, pitch, stream);
     if (st != TM_OK) {
         tm_pyramid_free(p);
@@ -549,13 +635,25 @@ TM_EXPORT tm_status tm_score_map(const tm_model* m, tm_pyramid* p, int32_t level
     const tmk::TabEntry* tab = nullptr;
     st = get_table(m, level, sp->theta_min_deg, g.step[level], g.K[level], s, &tab);
     if (st != TM_OK) return st;
-    tmk::DenseGeom dg = dense_geom(m, p, level, sp, tab, g.K[level]);
-    st = ensure_ws(p, tmk::dense_workspace_bytes(dg), s);
+    tmk::SearchDesc sd = make_search(sp, g, level, p->precision, 1);
+    tmk::PairGeom pg = pair_geom(m, p, level, sp->step_x, sp->step_y);
+    tmk::DensePlan plan = tmk::plan_dense(sd, &pg, 1);
+    tmk::PairDesc d;
+    memset(&d, 0, sizeof(d));
+    pair_static(&d, m, p, tab, level, pg, plan, 0.f);
+    st = ensure_ws(p, kDescBytes + pair_scratch(&d, m, pg, plan, p->L, 1, true, false, false, nullptr), s);
+    if (st != TM_OK) return st;
+    pair_scratch(&d, m, pg, plan, p->L, 1, true, false, false, reinterpret_cast<uint8_t*>(p->ws.ptr) + kDescBytes);
+    d.mw = sw;
+    d.m1 = s1;
+    d.mk = k;
+    tmk::PairDesc* dd = nullptr;
+    st = put_desc(p, d, s, &dd);
     if (st != TM_OK) return st;
     hipEvent_t ev0, ev1;
     st = timing_pair(&ev0, &ev1);
     if (st != TM_OK) return st;
-    HIP_TRY(tmk::launch_dense(dg, p->ws.ptr, sw, s1, k, s, ev0, ev1));
+    HIP_TRY(tmk::launch_dense(sd, plan, dd, 1, s, ev0, ev1));
     return TM_OK;
 }
 
@@ -566,12 +664,13 @@ TM_EXPORT tm_status tm_select(const float* sw, const float* s1, const int32_t* k
     if (!sw || !s1 || !k || !out || !n_out) return fail(TM_EINVAL, "tm_select: null argument");
     if (gw < 1 || gh < 1 || sx < 1 || sy < 1 || level < 0 || level >= 31)
         return fail(TM_EINVAL, "tm_select: bad geometry");
+    if ((long long)gw * gh > (1LL << 28)) return fail(TM_EINVAL, "tm_select: map too large");
     if (capacity < 1 || capacity > 1024) return fail(TM_EINVAL, "tm_select: capacity must be in [1, 1024]");
     if (!isfinite(min_score) || !isfinite(dmin)) return fail(TM_EINVAL, "tm_select: non-finite threshold");
-    // scratch comes from a small private buffer (this entry point has no pyramid)
+    // scratch: a private buffer of this thread (this entry point has no pyramid)
     static thread_local void* scratch = nullptr;
     static thread_local size_t scratch_bytes = 0;
-    size_t need = tmk::select_workspace_bytes(gw, gh);
+    const size_t need = kDescBytes + tmk::select_scratch_bytes(gw * gh);
     hipStream_t s = S(stream);
     if (need > scratch_bytes) {
         if (scratch) {
@@ -583,9 +682,29 @@ TM_EXPORT tm_status tm_select(const float* sw, const float* s1, const int32_t* k
         HIP_TRY(hipMalloc(&scratch, need));
         scratch_bytes = need;
     }
-    const double dmin2 = (double)dmin * (double)dmin;
-    HIP_TRY(tmk::launch_select(sw, s1, k, gw, gh, sx, sy, level, min_score, dmin2, 0.0, 0.0, out, capacity, n_out,
-                              scratch, s));
+    tmk::SearchDesc sd;
+    memset(&sd, 0, sizeof(sd));
+    sd.L = level + 1;
+    sd.level = level;
+    sd.sx = sx;
+    sd.sy = sy;
+    sd.min_score = min_score;
+    sd.max_cand = capacity;
+    tmk::PairDesc d;
+    memset(&d, 0, sizeof(d));
+    d.gw = gw;
+    d.gh = gh;
+    d.dmin = dmin;
+    d.mw = const_cast<float*>(sw);
+    d.m1 = const_cast<float*>(s1);
+    d.mk = const_cast<int32_t*>(k);
+    d.sel = reinterpret_cast<float*>(reinterpret_cast<uint8_t*>(scratch) + kDescBytes);
+    d.cand = out;
+    d.ncand = n_out;
+    tmk::PairDesc* dd = reinterpret_cast<tmk::PairDesc*>(scratch);
+    hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, d, dd);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(tmk::launch_select(sd, dd, 1, gw * gh, s));
     return TM_OK;
 }
 
@@ -606,30 +725,34 @@ TM_EXPORT tm_status tm_detect(const tm_model* m, tm_pyramid* p, const tm_search_
     const tmk::TabEntry* tab = nullptr;
     st = get_table(m, top, sp->theta_min_deg, g.step[top], g.K[top], s, &tab);
     if (st != TM_OK) return st;
-    tmk::DenseGeom dg = dense_geom(m, p, top, sp, tab, g.K[top]);
-    tmk::RefineArgs ra = refine_args(m, p, sp, g);
-    DetectLayout lay = detect_layout(dg, sp->max_candidates, tmk::refine_workspace_bytes(ra, sp->max_candidates));
-    st = ensure_ws(p, lay.total, s);
+    tmk::SearchDesc sd = make_search(sp, g, top, p->precision, std::min(capacity, sp->max_matches));
+    tmk::PairGeom pg = pair_geom(m, p, top, sp->step_x, sp->step_y);
+    tmk::DensePlan plan = tmk::plan_dense(sd, &pg, 1);
+    tmk::PairDesc d;
+    memset(&d, 0, sizeof(d));
+    pair_static(&d, m, p, tab, top, pg, plan, default_dmin(m, sp));
+    const bool refine = p->L > 1;
+    st = ensure_ws(p, kDescBytes + pair_scratch(&d, m, pg, plan, p->L, sp->max_candidates, true, true, refine, nullptr),
+                   s);
     if (st != TM_OK) return st;
-    uint8_t* base = reinterpret_cast<uint8_t*>(p->ws.ptr);
-    const size_t np = (size_t)dg.gw * dg.gh;
-    float* mw = reinterpret_cast<float*>(base + lay.map);
-    float* m1 = mw + np;
-    int32_t* mk = reinterpret_cast<int32_t*>(m1 + np);
-    tm_pose* cand = reinterpret_cast<tm_pose*>(base + lay.cand);
-    int32_t* ncand = reinterpret_cast<int32_t*>(base + lay.cand + (size_t)sp->max_candidates * sizeof(tm_pose));
-    const float dmin = default_dmin(m, sp);
-    const double dmin2 = (double)dmin * (double)dmin;
+    pair_scratch(&d, m, pg, plan, p->L, sp->max_candidates, true, true, refine,
+                 reinterpret_cast<uint8_t*>(p->ws.ptr) + kDescBytes);
+    d.out = out;
+    d.n_out = n_out;
+    tmk::PairDesc* dd = nullptr;
+    st = put_desc(p, d, s, &dd);
+    if (st != TM_OK) return st;
     hipEvent_t ev0, ev1;
     st = timing_pair(&ev0, &ev1);
     if (st != TM_OK) return st;
-    HIP_TRY(tmk::launch_dense(dg, base + lay.dense, mw, m1, mk, s, ev0, ev1));
-    HIP_TRY(tmk::launch_select(mw, m1, mk, dg.gw, dg.gh, sp->step_x, sp->step_y, top, sp->min_score, dmin2,
-                              sp->theta_min_deg, g.step[top], cand, sp->max_candidates, ncand, base + lay.sel, s));
-    if (p->L > 1) HIP_TRY(tmk::launch_refine(ra, cand, sp->max_candidates, ncand, top, base + lay.refine, s));
-    const int cap = std::min(capacity, sp->max_matches);
-    HIP_TRY(tmk::launch_final(cand, ncand, sp->max_candidates, sp->min_score, dmin2, sp->theta_min_deg, g.step[0],
-                             out, cap, n_out, s));
+    HIP_TRY(tmk::launch_dense(sd, plan, dd, 1, s, ev0, ev1));
+    HIP_TRY(tmk::launch_select(sd, dd, 1, pg.gw * pg.gh, s));
+    if (refine) {
+        int mc[TM_MAX_LEVELS];
+        refine_max_chunks(&m, 1, p->L, mc);
+        HIP_TRY(tmk::launch_refine(sd, dd, 1, top, mc, s));
+    }
+    HIP_TRY(tmk::launch_final(sd, dd, 1, s));
     return TM_OK;
 }
 
@@ -667,15 +790,216 @@ TM_EXPORT tm_status tm_refine(const tm_model* m, tm_pyramid* p, const tm_search_
     st = check_search(sp, "tm_refine");
     if (st != TM_OK) return st;
     if (n < 0) return fail(TM_EINVAL, "tm_refine: n < 0");
+    if (from_level < 0 || from_level >= p->L) return fail(TM_EINVAL, "tm_refine: bad from_level %d", from_level);
     if (n == 0) return TM_OK;
     if (!poses) return fail(TM_EINVAL, "tm_refine: null poses");
     Grid g;
     st = make_grid(sp, p->L, &g);
     if (st != TM_OK) return st;
-    if (from_level < 0 || from_level >= p->L) return fail(TM_EINVAL, "tm_refine: bad from_level %d", from_level);
-    tmk::RefineArgs ra = refine_args(m, p, sp, g);
-    st = ensure_ws(p, tmk::refine_workspace_bytes(ra, n), S(stream));
+    if (from_level == 0) return TM_OK;
+    hipStream_t s = S(stream);
+    tmk::SearchDesc sd = make_search(sp, g, from_level, p->precision, 1);
+    sd.max_cand = n;
+    tmk::PairGeom pg = pair_geom(m, p, from_level, sp->step_x, sp->step_y);
+    tmk::DensePlan plan = {};
+    tmk::PairDesc d;
+    memset(&d, 0, sizeof(d));
+    pair_static(&d, m, p, nullptr, from_level, pg, plan, 0.f);
+    st = ensure_ws(p, kDescBytes + pair_scratch(&d, m, pg, plan, p->L, n, false, false, true, nullptr), s);
     if (st != TM_OK) return st;
-    HIP_TRY(tmk::launch_refine(ra, poses, n, nullptr, from_level, p->ws.ptr, S(stream)));
+    pair_scratch(&d, m, pg, plan, p->L, n, false, false, true, reinterpret_cast<uint8_t*>(p->ws.ptr) + kDescBytes);
+    d.cand = poses;
+    d.ncand = nullptr;
+    tmk::PairDesc* dd = nullptr;
+    st = put_desc(p, d, s, &dd);
+    if (st != TM_OK) return st;
+    int mc[TM_MAX_LEVELS];
+    refine_max_chunks(&m, 1, p->L, mc);
+    HIP_TRY(tmk::launch_refine(sd, dd, 1, from_level, mc, s));
+    return TM_OK;
+}
+
+// ======================================================================= batch
+
+struct tm_batch_s {
+    int n_models = 0, n_images = 0, npairs = 0, L = 0;
+    std::vector<tm_pyramid*> pyrs;
+    std::vector<const tm_model*> models;
+    tmk::SearchDesc sd;
+    tmk::DensePlan plan;
+    int max_chunks[TM_MAX_LEVELS];
+    int level_w[TM_MAX_LEVELS], level_h[TM_MAX_LEVELS];
+    int max_field_blocks = 0, max_np = 0;
+    void* scratch = nullptr;
+    tmk::PairDesc* d_pairs = nullptr;
+    tmk::PyrBuildArg* d_pb = nullptr;
+    tmk::FieldsArg* d_fa = nullptr;
+};
+
+TM_EXPORT void tm_batch_free(tm_batch* b)
+{
+    if (!b) return;
+    for (tm_pyramid* p : b->pyrs) tm_pyramid_free(p);
+    if (b->scratch) hipFree(b->scratch);
+    delete b;
+}
+
+TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_models, const uint8_t* const* images,
+                                    const int32_t* widths, const int32_t* heights, const int32_t* pitches,
+                                    int32_t n_images, const tm_pyr_params* pp, const tm_search_params* sp,
+                                    tm_pose* out, int32_t capacity, int32_t* n_out, void* stream, tm_batch** outb)
+{
+    g_err[0] = 0;
+    if (!outb) return fail(TM_EINVAL, "tm_batch_create: null out");
+    *outb = nullptr;
+    if (!models || !images || !widths || !heights || !pitches || !pp || !out || !n_out)
+        return fail(TM_EINVAL, "tm_batch_create: null argument");
+    if (n_models < 1 || n_images < 1) return fail(TM_EINVAL, "tm_batch_create: need at least one model and image");
+    if ((long long)n_models * n_images > 65535) return fail(TM_EINVAL, "tm_batch_create: more than 65535 pairs");
+    if (capacity < 1) return fail(TM_EINVAL, "tm_batch_create: capacity < 1");
+    tm_status st = check_search(sp, "tm_batch_create");
+    if (st != TM_OK) return st;
+    for (int j = 0; j < n_models; ++j) {
+        if (!models[j]) return fail(TM_EINVAL, "tm_batch_create: null model %d", j);
+        if (models[j]->L < pp->levels)
+            return fail(TM_EINVAL, "tm_batch_create: model %d has %d levels, need %d", j, models[j]->L, pp->levels);
+    }
+    for (int i = 0; i < n_images; ++i) {
+        st = check_image(images[i], widths[i], heights[i], pitches[i], pp, "tm_batch_create");
+        if (st != TM_OK) return st;
+    }
+    const int L = pp->levels, top = L - 1;
+    Grid g;
+    st = make_grid(sp, L, &g);
+    if (st != TM_OK) return st;
+    hipStream_t s = S(stream);
+    tm_batch* b = new (std::nothrow) tm_batch_s();
+    if (!b) return fail(TM_ENOMEM, "tm_batch_create: host allocation");
+    b->n_models = n_models;
+    b->n_images = n_images;
+    b->npairs = n_models * n_images;
+    b->L = L;
+    b->models.assign(models, models + n_models);
+    for (int i = 0; i < n_images; ++i) {
+        tm_pyramid* p = nullptr;
+        st = alloc_pyramid(widths[i], heights[i], pp, &p);
+        if (st != TM_OK) {
+            tm_batch_free(b);
+            return st;
+        }
+        b->pyrs.push_back(p);
+    }
+    b->sd = make_search(sp, g, top, pp->precision, std::min(capacity, sp->max_matches));
+    std::vector<tmk::PairGeom> pg(b->npairs);
+    for (int i = 0; i < n_images; ++i)
+        for (int j = 0; j < n_models; ++j)
+            pg[i * n_models + j] = pair_geom(models[j], b->pyrs[i], top, sp->step_x, sp->step_y);
+    b->plan = tmk::plan_dense(b->sd, pg.data(), b->npairs);
+    refine_max_chunks(models, n_models, L, b->max_chunks);
+    for (auto& q : pg) b->max_np = std::max(b->max_np, q.gw * q.gh);
+
+    // one allocation: tables, descriptors, pyramid arguments, pair scratch
+    const int K = g.K[top];
+    std::vector<size_t> tab_off(n_models);
+    size_t off = 0;
+    for (int j = 0; j < n_models; ++j) {
+        tab_off[j] = off;
+        off = align_up(off + (size_t)K * models[j]->lv[top].n_pad * sizeof(tmk::TabEntry), 256);
+    }
+    const size_t desc_off = off;
+    off = align_up(off + (size_t)b->npairs * sizeof(tmk::PairDesc), 256);
+    const size_t pb_off = off;
+    off = align_up(off + (size_t)n_images * sizeof(tmk::PyrBuildArg), 256);
+    const size_t fa_off = off;
+    off = align_up(off + (size_t)n_images * sizeof(tmk::FieldsArg), 256);
+    std::vector<size_t> pair_off(b->npairs);
+    const bool refine = L > 1;
+    for (int q = 0; q < b->npairs; ++q) {
+        tmk::PairDesc tmp;
+        memset(&tmp, 0, sizeof(tmp));
+        pair_off[q] = off;
+        off += align_up(pair_scratch(&tmp, models[q % n_models], pg[q], b->plan, L, sp->max_candidates, true, true,
+                                     refine, nullptr),
+                        256);
+    }
+    hipError_t e = hipMalloc(&b->scratch, off);
+    if (e != hipSuccess) {
+        tm_batch_free(b);
+        return hip_fail(e, "tm_batch_create: hipMalloc");
+    }
+    uint8_t* base = reinterpret_cast<uint8_t*>(b->scratch);
+    b->d_pairs = reinterpret_cast<tmk::PairDesc*>(base + desc_off);
+    b->d_pb = reinterpret_cast<tmk::PyrBuildArg*>(base + pb_off);
+    b->d_fa = reinterpret_cast<tmk::FieldsArg*>(base + fa_off);
+    for (int j = 0; j < n_models; ++j) {
+        const tm_model_level& ml = models[j]->lv[top];
+        e = tmk::launch_tables(ml.pts, ml.n, ml.n_pad, sp->theta_min_deg, g.step[top], K,
+                               reinterpret_cast<tmk::TabEntry*>(base + tab_off[j]), s);
+        if (e != hipSuccess) {
+            tm_batch_free(b);
+            return hip_fail(e, "tm_batch_create: tables");
+        }
+    }
+    std::vector<tmk::PairDesc> hd(b->npairs);
+    for (int i = 0; i < n_images; ++i)
+        for (int j = 0; j < n_models; ++j) {
+            const int q = i * n_models + j;
+            tmk::PairDesc& d = hd[q];
+            memset(&d, 0, sizeof(d));
+            pair_static(&d, models[j], b->pyrs[i], reinterpret_cast<tmk::TabEntry*>(base + tab_off[j]), top, pg[q],
+                        b->plan, default_dmin(models[j], sp));
+            pair_scratch(&d, models[j], pg[q], b->plan, L, sp->max_candidates, true, true, refine,
+                         base + pair_off[q]);
+            d.out = out + (size_t)q * capacity;
+            d.n_out = n_out + q;
+        }
+    std::vector<tmk::PyrBuildArg> hpb(n_images);
+    std::vector<tmk::FieldsArg> hfa(n_images);
+    for (int l = 0; l < L; ++l) b->level_w[l] = b->level_h[l] = 0;
+    for (int i = 0; i < n_images; ++i) {
+        hpb[i] = tmk::pyr_build_arg(images[i], pitches[i], b->pyrs[i]->lv, L);
+        hfa[i] = tmk::fields_arg(b->pyrs[i]->lv, L, b->pyrs[i]->T2, pp->precision);
+        b->max_field_blocks = std::max(b->max_field_blocks, hfa[i].block0[L]);
+        for (int l = 0; l < L; ++l) {
+            b->level_w[l] = std::max(b->level_w[l], b->pyrs[i]->lv[l].w);
+            b->level_h[l] = std::max(b->level_h[l], b->pyrs[i]->lv[l].h);
+        }
+    }
+    e = hipMemcpyAsync(b->d_pairs, hd.data(), hd.size() * sizeof(tmk::PairDesc), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_pb, hpb.data(), hpb.size() * sizeof(tmk::PyrBuildArg), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_fa, hfa.data(), hfa.size() * sizeof(tmk::FieldsArg), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        tm_batch_free(b);
+        return hip_fail(e, "tm_batch_create: upload");
+    }
+    *outb = b;
+    return TM_OK;
+}
+
+TM_EXPORT tm_status tm_batch_run(tm_batch* b, void* stream)
+{
+    if (!b) return fail(TM_EINVAL, "tm_batch_run: null batch");
+    hipStream_t s = S(stream);
+    const int top = b->L - 1;
+    HIP_TRY(tmk::launch_pyramids_batch(b->d_pb, b->d_fa, b->n_images, b->L, b->level_w[0], b->level_h[0],
+                                       b->max_field_blocks, b->level_w, b->level_h, s));
+    hipEvent_t ev0, ev1;
+    tm_status st = timing_pair(&ev0, &ev1);
+    if (st != TM_OK) return st;
+    HIP_TRY(tmk::launch_dense(b->sd, b->plan, b->d_pairs, b->npairs, s, ev0, ev1));
+    HIP_TRY(tmk::launch_select(b->sd, b->d_pairs, b->npairs, b->max_np, s));
+    if (b->L > 1) HIP_TRY(tmk::launch_refine(b->sd, b->d_pairs, b->npairs, top, b->max_chunks, s));
+    HIP_TRY(tmk::launch_final(b->sd, b->d_pairs, b->npairs, s));
+    return TM_OK;
+}
+
+TM_EXPORT tm_status tm_batch_pyramid(const tm_batch* b, int32_t image, const tm_pyramid** out)
+{
+    if (!b || !out) return fail(TM_EINVAL, "tm_batch_pyramid: null argument");
+    if (image < 0 || image >= b->n_images) return fail(TM_EINVAL, "tm_batch_pyramid: bad image %d", image);
+    *out = b->pyrs[image];
     return TM_OK;
 }

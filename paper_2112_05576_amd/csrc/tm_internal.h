@@ -52,6 +52,8 @@ struct tm_pyramid_s {
     tmk::PyrLevel lv[tmk::kMaxLevels] = {};
     void* block = nullptr;  // single allocation holding all levels
     tmk::Workspace ws;       // scratch of detect / refine / score_map
+    bool desc_valid = false;  // ws starts with a device copy of last_desc
+    unsigned char last_desc[1024];
 };
 
 struct tm_model_level {
@@ -82,6 +84,36 @@ namespace tmk {
 // ---------------------------------------------------------------- launchers
 // All launchers enqueue on `s` and return the hipGetLastError() status.
 
+// Arguments of the pyramid kernels for one image (by value for one image, in
+// device memory for a batch).
+struct PyrBuildArg {
+    const uint8_t* src;          // caller's image (level 0 source)
+    int pitch;
+    int L;
+    uint8_t* img[kMaxLevels];    // level images
+    int w[kMaxLevels];
+    int h[kMaxLevels];
+};
+
+struct FieldsArg {
+    const uint8_t* img[kMaxLevels];
+    void* field[kMaxLevels];
+    int w[kMaxLevels];
+    int h[kMaxLevels];
+    int block0[kMaxLevels + 1];  // first workgroup of each level
+    int L;
+    int precision;
+    long long T2;
+};
+
+PyrBuildArg pyr_build_arg(const uint8_t* src, int src_pitch, const PyrLevel* lv, int L);
+FieldsArg fields_arg(const PyrLevel* lv, int L, long long T2, int precision);
+// Pyramids and fields of n_images images in one pass (pb, fa: device arrays);
+// level_w/level_h: largest level sizes over the images.
+hipError_t launch_pyramids_batch(const PyrBuildArg* pb, const FieldsArg* fa, int n_images, int L, int max_w,
+                                 int max_h, int max_field_blocks, const int* level_w, const int* level_h,
+                                 hipStream_t s);
+
 // Level-0 copy (pitched source) and uint8 levels base+1 .. top.
 hipError_t launch_pyr_build(const uint8_t* src, int src_pitch, const PyrLevel* lv, int L, hipStream_t s);
 // Unit direction fields of levels 0 .. L-1 (FP32 or FP16).
@@ -96,60 +128,84 @@ hipError_t launch_tables(const ModelPoint* pts, int n, int n_pad, double theta_m
 // Expand a table into plain int32 q pairs and float r pairs.
 hipError_t launch_table_export(const TabEntry* tab, int n, int n_pad, int K, int32_t* q, float* r, hipStream_t s);
 
-struct DenseGeom {
-    const void* field;
-    int W, H;             // level size
-    int precision;
-    const TabEntry* tab;  // [K][n_pad]
-    int n, n_pad, K;
-    int sx, sy, win;      // step grid, window side
-    int rad;              // |q| bound
-    int gw, gh;           // grid size
+// One (image, model) pair of a detection: the image's pyramid levels, the
+// model's levels, the rotated table of the searched level, and the pair's
+// scratch and result buffers.  Lives in device memory; kernels take the pair
+// from blockIdx.y.
+struct PairDesc {
+    const void* field[kMaxLevels];   // direction field per level
+    int W[kMaxLevels], H[kMaxLevels];
+    const ModelPoint* pts[kMaxLevels];
+    int n[kMaxLevels];
+    const TabEntry* tab;             // rotated table of the searched level, [K][n_pad]
+    int n_pad, rad;                  // table padding; bound on |q| at the searched level
+    int gw, gh;                      // translation grid of the searched level
+    int tiles_x, tiles_y;            // search tiles (fast path)
+    float dmin;                      // suppression distance, level-0 pixels
+    float* pw;                       // chunk partials [C][gh][gw]: best S_w,
+    float* p1;                       //   S_1,
+    int32_t* pk;                     //   angle
+    float* mw;                       // best angle per translation [gh][gw]: S_w,
+    float* m1;                       //   S_1,
+    int32_t* mk;                     //   angle
+    float* sel;                      // selection scratch, select_scratch_bytes(gw*gh)
+    tm_pose* cand;                   // candidates [max_cand] (refined in place)
+    int32_t* ncand;                  // their count (device); null: max_cand
+    tm_pose* ctr[2];                 // refinement centres [max_cand]
+    float* part[kMaxLevels];         // refinement partials [max_cand][3][chunks_l][18]
+    tm_pose* out;                    // results [capacity]
+    int32_t* n_out;                  // their count
 };
 
-// Exhaustive search of one level: best (S_w, S_1, k) per grid translation.
-// Uses ws (device scratch) of at least dense_workspace_bytes(g) bytes.
-size_t dense_workspace_bytes(const DenseGeom& g);
-// ev0 / ev1 (optional) are recorded around the search kernel only.
-hipError_t launch_dense(const DenseGeom& g, void* ws, float* ow, float* o1, int32_t* ok, hipStream_t s,
+// Settings shared by every pair of a launch.
+struct SearchDesc {
+    int L;                      // pyramid levels
+    int level;                  // level searched exhaustively (or selected / refined from)
+    int K[kMaxLevels];          // angles per level
+    double step[kMaxLevels];    // angle step per level
+    double theta_min;
+    int full, win, sx, sy, precision;
+    float min_score;
+    int max_cand, capacity;
+};
+
+// Launch plan of the exhaustive search, common to all pairs.
+struct DensePlan {
+    bool fast, asm_dpp;
+    int G, R, LC, WY, WA;
+    int A, C;                   // angles per workgroup, chunks of angles
+    size_t lds;
+    int max_blocks;             // workgroups of the largest pair (fast path)
+    int max_np;                 // translations of the largest pair
+};
+
+// The searched level of one pair, for planning.
+struct PairGeom {
+    int W, H, gw, gh, rad, n;
+};
+
+DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs);
+// Tile counts of a pair under a plan (fast path).
+void plan_tiles(const DensePlan& p, const PairGeom& g, int* tiles_x, int* tiles_y);
+size_t dense_partials_bytes(const DensePlan& p, int np);
+size_t select_scratch_bytes(int np);
+int refine_chunks(int n);
+
+// Exhaustive search of s.level for every pair: pair.mw/m1/mk.  ev0 / ev1
+// (optional) are recorded around the search kernel only.
+hipError_t launch_dense(const SearchDesc& s, const DensePlan& p, const PairDesc* d, int npairs, hipStream_t st,
                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Candidates of every pair from its map: pair.cand / ncand (<= s.max_cand).
+hipError_t launch_select(const SearchDesc& s, const PairDesc* d, int npairs, int max_np, hipStream_t st);
+// Refine pair.cand (poses of level from_level) down to level 0, in place.
+// max_chunks[l]: largest refine_chunks(n[l]) over the pairs.
+hipError_t launch_refine(const SearchDesc& s, const PairDesc* d, int npairs, int from_level, const int* max_chunks,
+                         hipStream_t st);
+// Final selection of every pair: pair.cand -> pair.out / n_out.
+hipError_t launch_final(const SearchDesc& s, const PairDesc* d, int npairs, hipStream_t st);
 
 // One wave per pose: S_w and S_1 of arbitrary poses.
 hipError_t launch_sparse(const void* field, int W, int H, int precision, const ModelPoint* pts, int n, int win,
                          const tm_eval_pose* poses, int np, float* scores, hipStream_t s);
-
-// Candidate selection on a map (scratch: gw*gh entries of 32 bytes).
-size_t select_workspace_bytes(int gw, int gh);
-hipError_t launch_select(const float* sw, const float* s1, const int32_t* k, int gw, int gh, int sx, int sy,
-                         int level, float min_score, double dmin2, double theta_min, double step_level,
-                         tm_pose* out, int capacity, int32_t* n_out, void* scratch, hipStream_t s);
-
-struct RefineLevel {
-    const void* field;
-    int W, H;
-    const ModelPoint* pts;
-    int n;
-    double step;
-    int K;
-};
-
-struct RefineArgs {
-    RefineLevel lv[kMaxLevels];
-    int L;                // levels present; poses above L-1 start at L-1
-    int precision;
-    int win;
-    int full;             // wrap angle indices (else clamp)
-    double theta_min;
-};
-
-// Refine poses[i] (i < *n_dev if n_dev, else i < n), all of level from_level,
-// down to level 0, in place.  ws: refine_workspace_bytes(a, n) bytes.
-size_t refine_workspace_bytes(const RefineArgs& a, int n);
-hipError_t launch_refine(const RefineArgs& a, tm_pose* poses, int n, const int32_t* n_dev, int from_level, void* ws,
-                         hipStream_t s);
-
-// Final selection: S_w floor, key sort, greedy NMS at level 0, <= capacity.
-hipError_t launch_final(const tm_pose* cand, const int32_t* n_cand, int max_cand, float min_score, double dmin2,
-                        double theta_min, double step0, tm_pose* out, int capacity, int32_t* n_out, hipStream_t s);
 
 }  // namespace tmk

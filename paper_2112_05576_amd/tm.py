@@ -74,6 +74,11 @@ def lib():
                                  ctypes.POINTER(_vp), ctypes.POINTER(_i32)],
             "tm_pyramid_read": [_vp, _i32, _vp, _vp, _vp],
             "tm_timing_enable": [_i32],
+            "tm_batch_create": [ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp), ctypes.POINTER(_i32),
+                                ctypes.POINTER(_i32), ctypes.POINTER(_i32), _i32, ctypes.POINTER(PyrParamsC),
+                                ctypes.POINTER(SearchParamsC), _vp, _i32, _vp, _vp, ctypes.POINTER(_vp)],
+            "tm_batch_run": [_vp, _vp],
+            "tm_batch_pyramid": [_vp, _i32, ctypes.POINTER(_vp)],
             "tm_timing_read": [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32)],
         }
         for name, args in sig.items():
@@ -84,6 +89,8 @@ def lib():
         L.tm_model_free.restype = None
         L.tm_pyramid_free.argtypes = [_vp]
         L.tm_pyramid_free.restype = None
+        L.tm_batch_free.argtypes = [_vp]
+        L.tm_batch_free.restype = None
         L.tm_last_error.restype = ctypes.c_char_p
         L.tm_version.restype = ctypes.c_char_p
         _lib = L
@@ -302,6 +309,55 @@ def refine(model: Model, pyr: Pyramid, sp: SearchParams, poses: np.ndarray, from
     _check(lib().tm_refine(model.handle, pyr.handle, ctypes.byref(c), from_level, _vp(dev.data_ptr()), len(a),
                            _vp(_stream(stream))))
     return poses_to_numpy(dev)
+
+
+class Batch:
+    """Every model against every image in one enqueue (tm_batch_run).  The
+    images (2-D uint8 device tensors) stay bound: write new contents into the
+    same tensors and run again.  Results: `out` (pairs, capacity, 8) int32 and
+    `n_out` (pairs,), pair = image * n_models + model."""
+
+    def __init__(self, models, images, levels: int, edge_thresh: float, sp: SearchParams,
+                 precision: int = TM_FP32, capacity: int | None = None, stream=None):
+        self.images = [_dev_u8(im) for im in images]
+        self.models = list(models)
+        self.capacity = capacity or sp.max_matches
+        npairs = len(self.images) * len(self.models)
+        self.out = torch.empty((npairs, self.capacity, POSE_WORDS), dtype=torch.int32, device="cuda")
+        self.n_out = torch.zeros((npairs,), dtype=torch.int32, device="cuda")
+        nm, ni = len(self.models), len(self.images)
+        mh = (_vp * nm)(*[m.handle for m in self.models])
+        ih = (_vp * ni)(*[im.data_ptr() for im in self.images])
+        ws = (_i32 * ni)(*[im.shape[1] for im in self.images])
+        hs = (_i32 * ni)(*[im.shape[0] for im in self.images])
+        ps = (_i32 * ni)(*[im.stride(0) for im in self.images])
+        pp = PyrParamsC(levels, edge_thresh, precision)
+        c = sp.c()
+        self._h = _vp()
+        _check(lib().tm_batch_create(mh, nm, ih, ws, hs, ps, ni, ctypes.byref(pp), ctypes.byref(c),
+                                     _vp(self.out.data_ptr()), self.capacity, _vp(self.n_out.data_ptr()),
+                                     _vp(_stream(stream)), ctypes.byref(self._h)))
+        self.n_models = nm
+
+    def run(self, stream=None):
+        _check(lib().tm_batch_run(self._h, _vp(_stream(stream))))
+
+    def results(self):
+        """Per pair, the detections as a numpy structured array (waits for the device)."""
+        n = self.n_out.cpu().numpy()
+        o = self.out.cpu().numpy()
+        return [o[p].view(POSE_DTYPE).reshape(-1)[:n[p]] for p in range(len(n))]
+
+    def free(self):
+        if self._h:
+            lib().tm_batch_free(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def timing_enable(on: bool = True):

@@ -358,3 +358,157 @@ def test_detect_is_deterministic():
         assert np.array_equal(P.detect(gm, pyr, sp), a)
         m2 = P.score_map(gm, pyr, 3, sp)
         assert all(torch.equal(x, y) for x, y in zip(m1, m2))
+
+
+# ------------------------------------------------------------ FP16 directions
+# Each component of a unit vector rounded to half has relative error <= 2^-11,
+# so |r_h . g_h - r . g| <= 2 * 2^-11 (+ FP32 rounding of the sums); the max of
+# a window and the mean over points keep that bound.
+TOL16 = 2 * 2.0 ** -11 + 2e-5
+
+
+@pytest.mark.parametrize("ci", [2, 3])
+def test_score_map_fp16(ci):
+    P = _P()
+    sc = synth.scene_for_config(ci)
+    cfg = sc.config
+    L = cfg["levels"]
+    top = L - 1
+    case(f"score_map FP16 C{ci}")
+    gm = P.Model(sc.model, L, cfg["tau_m"])
+    pyr = P.Pyramid(sc.image, L, cfg["tau_s"], precision=P.TM_FP16)
+    st = cfg["theta_step_top"]
+    sw, s1, k = [t.cpu().numpy() for t in P.score_map(gm, pyr, top, P.SearchParams(theta_step_top=st))]
+    om = O.build_model(sc.model, O.PyrParams(L, cfg["tau_m"]))
+    g = O.field_pyramid(sc.image, L, cfg["tau_s"])[top]
+    ml = om.levels[top]
+    mw, m1, mk = O.top_map(g, ml.t, ml.d, 0.0, st, int(np.ceil(360.0 / st)))
+    ew, e1 = np.abs(sw - mw).max(), np.abs(s1 - m1).max()
+    print(f"FP16 map: max |dS_w| {ew:.3g} mean {np.abs(sw - mw).mean():.3g} p99 "
+          f"{np.quantile(np.abs(sw - mw), 0.99):.3g}; max |dS_1| {e1:.3g}")
+    assert ew <= TOL16 and e1 <= TOL16
+    for (j, i) in np.argwhere(k != mk)[:200]:
+        a = O.score(g, ml.t, ml.d, int(i), int(j), O.theta(0.0, st, int(k[j, i])))
+        assert abs(a[0] - mw[j, i]) <= 2 * TOL16, (i, j)
+
+
+def test_score_poses_fp16():
+    P = _P()
+    sc = synth.scene_for_config(2)
+    cfg = sc.config
+    case("score_poses FP16 C2 level 1")
+    gm = P.Model(sc.model, 4, cfg["tau_m"])
+    pyr = P.Pyramid(sc.image, 4, cfg["tau_s"], precision=P.TM_FP16)
+    g = O.field_pyramid(sc.image, 4, cfg["tau_s"])[1]
+    ml = O.build_model(sc.model, O.PyrParams(4, cfg["tau_m"])).levels[1]
+    rng = np.random.default_rng(77)
+    xs, ys, th = rng.integers(0, 320, 200), rng.integers(0, 240, 200), rng.uniform(0, 360, 200)
+    got = P.score_poses(gm, pyr, 1, xs, ys, th).cpu().numpy().astype(np.float64)
+    ref = np.array([O.score(g, ml.t, ml.d, int(xs[i]), int(ys[i]), float(th[i])) for i in range(200)])
+    assert np.abs(got - ref).max() <= TOL16
+
+
+@pytest.mark.parametrize("index", [0, 1])
+def test_detect_fp16_matches_oracle(index):
+    P = _P()
+    sc = synth.scene_for_config(2, index)
+    cfg = sc.config
+    case(f"detect FP16 C2 image {index}")
+    osp = O.SearchParams(theta_step_top=1.0)
+    tr = O.detect(sc.image, sc.model, O.PyrParams(4, cfg["tau_s"]), O.PyrParams(4, cfg["tau_m"]), osp)
+    gm = P.Model(sc.model, 4, cfg["tau_m"])
+    pyr = P.Pyramid(sc.image, 4, cfg["tau_s"], precision=P.TM_FP16)
+    got = P.detect(gm, pyr, P.SearchParams(theta_step_top=1.0))
+    ref = tr.detections
+    print(f"FP16 {[(int(d['x']), int(d['y']), int(d['k']), round(float(d['sw']), 4)) for d in got]}")
+    print(f"FP64 {[(d.x, d.y, d.k, round(d.sw, 4)) for d in ref]}")
+    # the top match: the same pose, or one the oracle scores within two FP16 bounds of its own
+    assert len(got) >= 1 and len(ref) >= 1
+    g0, r0 = got[0], ref[0]
+    if (int(g0["x"]), int(g0["y"]), int(g0["k"])) != (r0.x, r0.y, r0.k):
+        a = _oracle_key(tr.fields, tr.model, osp, 4, g0["x"], g0["y"], g0["k"])
+        assert abs(a[0] - r0.sw) <= 2 * TOL16, (g0, r0)
+    assert abs(float(g0["sw"]) - r0.sw) <= 2 * TOL16
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_search_kernel_shape_independence(precision, monkeypatch):
+    """Every launch shape and both window-max variants give bit-identical maps
+    (the per-lane sums run in point order whatever the tiling)."""
+    P = _P()
+    sc = synth.scene_for_config(2, 4)
+    cfg = sc.config
+    case(f"launch shapes precision={precision}")
+    gm = P.Model(sc.model, 4, cfg["tau_m"])
+    pyr = P.Pyramid(sc.image, 4, cfg["tau_s"], precision=precision)
+    sp = P.SearchParams(theta_step_top=1.0)
+    ref = [t.clone() for t in P.score_map(gm, pyr, 3, sp)]
+    for wy, wa, apw, asm in [(1, 4, 1, 1), (2, 4, 1, 0), (1, 8, 2, 1), (1, 16, 1, 0), (4, 1, 3, 1)]:
+        monkeypatch.setenv("TM_DENSE_WY", str(wy))
+        monkeypatch.setenv("TM_DENSE_WA", str(wa))
+        monkeypatch.setenv("TM_DENSE_APW", str(apw))
+        monkeypatch.setenv("TM_DENSE_ASM", str(asm))
+        got = P.score_map(gm, pyr, 3, sp)
+        assert all(torch.equal(x, y) for x, y in zip(ref, got)), (wy, wa, apw, asm)
+
+
+# ------------------------------------------------------------ batches
+def _poses_equal(a, b):
+    return len(a) == len(b) and all(
+        (int(x["x"]), int(x["y"]), int(x["k"]), float(x["sw"]), float(x["s1"])) ==
+        (int(y["x"]), int(y["y"]), int(y["k"]), float(y["sw"]), float(y["s1"])) for x, y in zip(a, b))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batch_equals_single_detections(precision):
+    """One launch per stage over all (image, model) pairs gives exactly the
+    detections of the single-image calls (mixed sizes, two models)."""
+    P = _P()
+    case(f"batch vs single precision={precision}")
+    cfg = synth.CONFIGS[2]
+    scenes = [synth.scene_for_config(2, i) for i in range(3)]
+    big = synth.scene_for_config(2, 7, W=1280, H=1024, n_inst=4)
+    rng = np.random.default_rng(4242)
+    m2 = synth.render_model(synth.make_model_shape("polygon", 96, rng), 96)
+    models = [P.Model(scenes[0].model, 4, cfg["tau_m"]), P.Model(m2, 4, cfg["tau_m"])]
+    images = [torch.from_numpy(s.image).cuda() for s in scenes] + [torch.from_numpy(big.image).cuda()]
+    sp = P.SearchParams(theta_step_top=1.0)
+    b = P.Batch(models, images, 4, cfg["tau_s"], sp, precision=precision)
+    b.run()
+    got = b.results()
+    for i, im in enumerate(images):
+        pyr = P.Pyramid(im, 4, cfg["tau_s"], precision=precision)
+        for j, m in enumerate(models):
+            ref = P.detect(m, pyr, sp)
+            assert _poses_equal(got[i * 2 + j], ref), (i, j, got[i * 2 + j], ref)
+    # run again on new contents of the same buffers
+    images[0].copy_(torch.from_numpy(scenes[1].image).cuda())
+    b.run()
+    again = b.results()
+    assert _poses_equal(again[0], got[2]) and _poses_equal(again[1], got[3])
+
+
+def test_batch_pyramids_match_oracle():
+    P = _P()
+    case("batch pyramids")
+    imgs = [_scene_img(96, 128, 11), _scene_img(211, 333, 12)]
+    dev = [torch.from_numpy(i).cuda() for i in imgs]
+    rng = np.random.default_rng(4243)
+    m = P.Model(synth.render_model(synth.make_model_shape("blocks", 32, rng), 32), 2, 30.0)
+    b = P.Batch([m], dev, 2, 45.5, P.SearchParams(theta_step_top=10.0))
+    b.run()
+    torch.cuda.synchronize()
+    import ctypes
+    for i, im in enumerate(imgs):
+        h = ctypes.c_void_p()
+        assert P.lib().tm_batch_pyramid(b._h, i, ctypes.byref(h)) == 0
+        pyr = P.Pyramid.__new__(P.Pyramid)
+        pyr._h, pyr.levels, pyr.precision = h, 2, 0
+        try:
+            for l, lv in enumerate(O.pyramid(im, 2)):
+                gi, gf = pyr.read(l)
+                assert np.array_equal(gi.cpu().numpy(), lv)
+                of = O.edge_field(lv, 45.5)
+                assert np.abs(gf.cpu().numpy().astype(np.float64) - of).max() <= 6e-8
+        finally:
+            pyr._h = ctypes.c_void_p()  # owned by the batch
