@@ -107,6 +107,13 @@ typedef struct {
     double theta_deg;
 } tm_eval_pose;
 
+/* A pose with continuous translation (pixels of its level) and angle, and
+ * the (image, model) pair of a batch it belongs to (ignored outside one). */
+typedef struct {
+    float x, y, theta_deg;
+    int32_t pair;
+} tm_cont_pose;
+
 typedef struct tm_model_s tm_model;
 typedef struct tm_pyramid_s tm_pyramid;
 
@@ -171,6 +178,32 @@ tm_status tm_detect(const tm_model* model, tm_pyramid* pyr, const tm_search_para
  * must lie inside their level.  No selection is applied. */
 tm_status tm_refine(const tm_model* model, tm_pyramid* pyr, const tm_search_params* params, int32_t from_level,
                     tm_pose* poses_dev, int32_t n, void* stream);
+
+/* --- continuous score (differentiable; an extension beside Eq. (1)) ---- */
+
+/* S_c = (1/n) sum_i r_i . B(R(theta) t_i + u): the model's rotated
+ * directions against the bilinearly interpolated direction field of `level`
+ * (zero off the edge set and outside the image), no window, no rounding.
+ * scores_dev[i] for poses_dev[i]; FP32. */
+tm_status tm_cont_score(const tm_model* model, tm_pyramid* pyr, int32_t level, const tm_cont_pose* poses_dev,
+                        int32_t n, float* scores_dev, void* stream);
+
+/* Backward of tm_cont_score: grad_poses_dev[3i..3i+2] = grad_scores_dev[i] *
+ * dS_c/d(x, y, theta_deg) of pose i (grad_scores_dev NULL: ones).  The
+ * derivative is that of the bilinear patch (pixel cell) containing each
+ * projected point. */
+tm_status tm_cont_score_backward(const tm_model* model, tm_pyramid* pyr, int32_t level,
+                                 const tm_cont_pose* poses_dev, int32_t n, const float* grad_scores_dev,
+                                 float* grad_poses_dev, void* stream);
+
+/* Line search in FP64: for each pose i, S_c evaluated in double precision at
+ * pose + alphas[j] * dirs_dev[3i..3i+2] rounded to the FP32 pose record,
+ * j < n_alphas (host array, 1 to 16 finite values); the pose moves to the
+ * best (ties: the earlier step) and scores_dev[i] (may be NULL) receives
+ * that score.  Uses the pyramid's scratch (8 bytes per evaluation). */
+tm_status tm_cont_line_search(const tm_model* model, tm_pyramid* pyr, int32_t level, tm_cont_pose* poses_dev,
+                              const float* dirs_dev, int32_t n, const double* alphas, int32_t n_alphas,
+                              float* scores_dev, void* stream);
 
 /* --- batches ------------------------------------------------------------ */
 

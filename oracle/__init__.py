@@ -84,6 +84,9 @@ def lib():
         L.orc_final.argtypes = [ctypes.c_int, _i32p, _i32p, _i32p, _f64p, _f64p, ctypes.c_double,
                                 ctypes.c_float, ctypes.c_int]
         L.orc_final.restype = ctypes.c_int
+        L.orc_cont_score.argtypes = [_f64p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, _f64p, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double), _f64p]
+        L.orc_cont_score.restype = None
         _lib = L
     return _lib
 
@@ -260,6 +263,17 @@ def top_map(g: np.ndarray, t, d, theta_min: float, step: float, K: int, sx: int 
                       int(sx), int(sy), int(win), mw, m1, mk,
                       int(nthreads if nthreads else default_threads()))
     return mw, m1, mk
+
+
+def cont_score(g: np.ndarray, t, d, ux: float, uy: float, theta_deg: float):
+    """O12: continuous (bilinear) score and its gradient (d/dux, d/duy, d/dtheta_deg)."""
+    H, W, _ = g.shape
+    S = ctypes.c_double()
+    grad = np.empty(3, np.float64)
+    lib().orc_cont_score(np.ascontiguousarray(g), W, H, len(t), np.ascontiguousarray(t, np.int32),
+                         np.ascontiguousarray(d, np.float64), float(ux), float(uy), float(theta_deg),
+                         ctypes.byref(S), grad)
+    return S.value, grad
 
 
 # ------------------------------------------------------------- O9 .. O11

@@ -460,3 +460,70 @@ ORC_API int orc_final(int nc, int32_t* cx, int32_t* cy, int32_t* ck, double* cw,
     free(c);
     return m;
 }
+
+/* ----------------------------------------------------------------- O12 */
+/* Continuous score (an extension beside Eq. (1)): the mean over the model's
+ * points of r_i . B(R(theta) t_i + u), B the bilinear interpolation of the
+ * unit-direction field (0 off the edge set and outside the image), with no
+ * window and no rounding of positions; theta in degrees.  Also its gradient
+ * with respect to (u_x, u_y, theta_deg): per point,
+ *   d/du   = J_B(p)^T r,
+ *   d/dth  = (pi/180) [ (R' d) . B(p) + r . (J_B(p) R' t) ],
+ * R' = dR/dtheta_rad, J_B the 2x2 Jacobian of B in the cell containing p
+ * (cells are [x0, x0+1) x [y0, y0+1), x0 = floor(p_x)). */
+static void orc_field_at(const double* g, int W, int H, int x, int y, double* vx, double* vy)
+{
+    if (x < 0 || x >= W || y < 0 || y >= H) {
+        *vx = 0.0;
+        *vy = 0.0;
+        return;
+    }
+    size_t o = (size_t)y * W + x;
+    *vx = g[2 * o];
+    *vy = g[2 * o + 1];
+}
+
+ORC_API void orc_cont_score(const double* g, int W, int H, int n, const int32_t* t, const double* d,
+                            double ux, double uy, double theta_deg, double* S, double* grad)
+{
+    double c, s;
+    orc_sincos_deg(theta_deg, &c, &s);
+    const double k = M_PI / 180.0;
+    double sum = 0.0, gx = 0.0, gy = 0.0, gt = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double tx = (double)t[2 * i], ty = (double)t[2 * i + 1];
+        double dx = d[2 * i], dy = d[2 * i + 1];
+        double px = c * tx - s * ty + ux;
+        double py = s * tx + c * ty + uy;
+        double rx = c * dx - s * dy, ry = s * dx + c * dy;
+        double x0 = floor(px), y0 = floor(py);
+        double fx = px - x0, fy = py - y0;
+        int ix = (int)x0, iy = (int)y0;
+        double a00x, a00y, a10x, a10y, a01x, a01y, a11x, a11y;
+        orc_field_at(g, W, H, ix, iy, &a00x, &a00y);
+        orc_field_at(g, W, H, ix + 1, iy, &a10x, &a10y);
+        orc_field_at(g, W, H, ix, iy + 1, &a01x, &a01y);
+        orc_field_at(g, W, H, ix + 1, iy + 1, &a11x, &a11y);
+        double bx = (1 - fx) * (1 - fy) * a00x + fx * (1 - fy) * a10x + (1 - fx) * fy * a01x + fx * fy * a11x;
+        double by = (1 - fx) * (1 - fy) * a00y + fx * (1 - fy) * a10y + (1 - fx) * fy * a01y + fx * fy * a11y;
+        /* Jacobian columns: dB/dpx, dB/dpy */
+        double bxx = (1 - fy) * (a10x - a00x) + fy * (a11x - a01x);
+        double byx = (1 - fy) * (a10y - a00y) + fy * (a11y - a01y);
+        double bxy = (1 - fx) * (a01x - a00x) + fx * (a11x - a10x);
+        double byy = (1 - fx) * (a01y - a00y) + fx * (a11y - a10y);
+        double v = rx * bx + ry * by;
+        double dpx = rx * bxx + ry * byx; /* r . dB/dpx */
+        double dpy = rx * bxy + ry * byy; /* r . dB/dpy */
+        /* R' t and R' d (derivative with respect to theta in radians) */
+        double rtx = -s * tx - c * ty, rty = c * tx - s * ty;
+        double rdx = -s * dx - c * dy, rdy = c * dx - s * dy;
+        sum += v;
+        gx += dpx;
+        gy += dpy;
+        gt += (rdx * bx + rdy * by) + (rtx * dpx + rty * dpy);
+    }
+    *S = sum / (double)n;
+    grad[0] = gx / (double)n;
+    grad[1] = gy / (double)n;
+    grad[2] = k * gt / (double)n;
+}

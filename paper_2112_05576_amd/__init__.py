@@ -8,6 +8,11 @@ from .tm import (  # noqa: F401
     TM_FP16,
     TM_FP32,
     Batch,
+    ContinuousScore,
+    cont_line_search,
+    cont_score,
+    cont_score_backward,
+    refine_continuous,
     Model,
     Pyramid,
     SearchParams,

@@ -819,6 +819,78 @@ TM_EXPORT tm_status tm_refine(const tm_model* m, tm_pyramid* p, const tm_search_
     return TM_OK;
 }
 
+// ======================================================================= continuous
+
+namespace {
+// Descriptor of one (model, pyramid) pair for the continuous score, at the
+// start of the pyramid's scratch; extra bytes follow it.
+tm_status cont_prepare(const tm_model* m, tm_pyramid* p, int level, size_t extra, hipStream_t s,
+                       tmk::PairDesc** dd, const char* what)
+{
+    tm_status st = check_pair(m, p, what);
+    if (st != TM_OK) return st;
+    if (level < 0 || level >= p->L) return fail(TM_EINVAL, "%s: bad level %d", what, level);
+    st = ensure_ws(p, kDescBytes + extra, s);
+    if (st != TM_OK) return st;
+    tmk::PairDesc d;
+    memset(&d, 0, sizeof(d));
+    for (int l = 0; l < p->L; ++l) {
+        d.field[l] = p->lv[l].field;
+        d.W[l] = p->lv[l].w;
+        d.H[l] = p->lv[l].h;
+        d.pts[l] = m->lv[l].pts;
+        d.n[l] = m->lv[l].n;
+    }
+    return put_desc(p, d, s, dd);
+}
+}  // namespace
+
+TM_EXPORT tm_status tm_cont_score(const tm_model* m, tm_pyramid* p, int32_t level, const tm_cont_pose* poses,
+                                  int32_t n, float* scores, void* stream)
+{
+    if (n < 0) return fail(TM_EINVAL, "tm_cont_score: n < 0");
+    if (n > 0 && (!poses || !scores)) return fail(TM_EINVAL, "tm_cont_score: null buffer");
+    tmk::PairDesc* dd = nullptr;
+    tm_status st = cont_prepare(m, p, level, 0, S(stream), &dd, "tm_cont_score");
+    if (st != TM_OK) return st;
+    HIP_TRY(tmk::launch_cont(dd, 0, level, p->precision, poses, n, nullptr, scores, false, S(stream)));
+    return TM_OK;
+}
+
+TM_EXPORT tm_status tm_cont_score_backward(const tm_model* m, tm_pyramid* p, int32_t level,
+                                           const tm_cont_pose* poses, int32_t n, const float* gin, float* gout,
+                                           void* stream)
+{
+    if (n < 0) return fail(TM_EINVAL, "tm_cont_score_backward: n < 0");
+    if (n > 0 && (!poses || !gout)) return fail(TM_EINVAL, "tm_cont_score_backward: null buffer");
+    tmk::PairDesc* dd = nullptr;
+    tm_status st = cont_prepare(m, p, level, 0, S(stream), &dd, "tm_cont_score_backward");
+    if (st != TM_OK) return st;
+    HIP_TRY(tmk::launch_cont(dd, 0, level, p->precision, poses, n, gin, gout, true, S(stream)));
+    return TM_OK;
+}
+
+TM_EXPORT tm_status tm_cont_line_search(const tm_model* m, tm_pyramid* p, int32_t level, tm_cont_pose* poses,
+                                        const float* dirs, int32_t n, const double* alphas, int32_t n_alphas,
+                                        float* scores, void* stream)
+{
+    if (n < 0) return fail(TM_EINVAL, "tm_cont_line_search: n < 0");
+    if (n > 0 && (!poses || !dirs)) return fail(TM_EINVAL, "tm_cont_line_search: null buffer");
+    if (!alphas || n_alphas < 1 || n_alphas > 16)
+        return fail(TM_EINVAL, "tm_cont_line_search: need 1..16 step lengths");
+    for (int j = 0; j < n_alphas; ++j)
+        if (!isfinite(alphas[j])) return fail(TM_EINVAL, "tm_cont_line_search: non-finite step length");
+    if ((long long)n * n_alphas > (1LL << 30)) return fail(TM_EINVAL, "tm_cont_line_search: too many evaluations");
+    tmk::PairDesc* dd = nullptr;
+    tm_status st = cont_prepare(m, p, level, tmk::line_search_scratch_bytes(n, n_alphas), S(stream), &dd,
+                                "tm_cont_line_search");
+    if (st != TM_OK) return st;
+    double* scratch = reinterpret_cast<double*>(reinterpret_cast<uint8_t*>(p->ws.ptr) + kDescBytes);
+    HIP_TRY(tmk::launch_line_search(dd, 0, level, p->precision, poses, dirs, n, alphas, n_alphas, scores, scratch,
+                                    S(stream)));
+    return TM_OK;
+}
+
 // ======================================================================= batch
 
 struct tm_batch_s {

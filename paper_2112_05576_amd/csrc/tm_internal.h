@@ -204,6 +204,15 @@ hipError_t launch_refine(const SearchDesc& s, const PairDesc* d, int npairs, int
 // Final selection of every pair: pair.cand -> pair.out / n_out.
 hipError_t launch_final(const SearchDesc& s, const PairDesc* d, int npairs, hipStream_t st);
 
+// Continuous score (forward) or its backward of n poses; d: descriptor array
+// (batched: pose.pair selects, else descriptor 0).
+hipError_t launch_cont(const PairDesc* d, int batched, int level, int precision, const tm_cont_pose* poses, int n,
+                       const float* gin, float* out, bool backward, hipStream_t s);
+size_t line_search_scratch_bytes(int n, int n_alpha);
+hipError_t launch_line_search(const PairDesc* d, int batched, int level, int precision, tm_cont_pose* poses,
+                              const float* dirs, int n, const double* alphas, int n_alpha, float* scores,
+                              double* scratch, hipStream_t s);
+
 // One wave per pose: S_w and S_1 of arbitrary poses.
 hipError_t launch_sparse(const void* field, int W, int H, int precision, const ModelPoint* pts, int n, int win,
                          const tm_eval_pose* poses, int np, float* scores, hipStream_t s);

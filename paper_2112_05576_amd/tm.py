@@ -78,6 +78,10 @@ def lib():
                                 ctypes.POINTER(_i32), ctypes.POINTER(_i32), _i32, ctypes.POINTER(PyrParamsC),
                                 ctypes.POINTER(SearchParamsC), _vp, _i32, _vp, _vp, ctypes.POINTER(_vp)],
             "tm_batch_run": [_vp, _vp],
+            "tm_cont_score": [_vp, _vp, _i32, _vp, _i32, _vp, _vp],
+            "tm_cont_score_backward": [_vp, _vp, _i32, _vp, _i32, _vp, _vp, _vp],
+            "tm_cont_line_search": [_vp, _vp, _i32, _vp, _vp, _i32, ctypes.POINTER(ctypes.c_double), _i32, _vp,
+                                    _vp],
             "tm_batch_pyramid": [_vp, _i32, ctypes.POINTER(_vp)],
             "tm_timing_read": [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32)],
         }
@@ -358,6 +362,90 @@ class Batch:
             self.free()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- continuous score
+CONT_DTYPE = np.dtype([("x", "<f4"), ("y", "<f4"), ("theta", "<f4"), ("pair", "<i4")])
+
+
+def _cont_poses(poses: torch.Tensor) -> torch.Tensor:
+    """(n, 3) float32 (x, y, theta_deg) -> device tm_cont_pose records (n, 4) float32 view."""
+    p = poses.detach().to(device="cuda", dtype=torch.float32).reshape(-1, 3)
+    rec = torch.zeros((p.shape[0], 4), dtype=torch.float32, device="cuda")
+    rec[:, :3] = p
+    return rec.contiguous()
+
+
+def cont_score(model: Model, pyr: Pyramid, level: int, poses: torch.Tensor, stream=None) -> torch.Tensor:
+    """Continuous score of (n, 3) poses (x, y, theta_deg) at `level`."""
+    rec = _cont_poses(poses)
+    out = torch.empty(rec.shape[0], dtype=torch.float32, device="cuda")
+    _check(lib().tm_cont_score(model.handle, pyr.handle, level, _vp(rec.data_ptr()), rec.shape[0],
+                               _vp(out.data_ptr()), _vp(_stream(stream))))
+    return out
+
+
+def cont_score_backward(model: Model, pyr: Pyramid, level: int, poses: torch.Tensor,
+                        grad_scores: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """grad_scores[i] * dS/d(x, y, theta_deg) of each pose, (n, 3)."""
+    rec = _cont_poses(poses)
+    out = torch.empty((rec.shape[0], 3), dtype=torch.float32, device="cuda")
+    g = None if grad_scores is None else grad_scores.detach().to(device="cuda", dtype=torch.float32).contiguous()
+    _check(lib().tm_cont_score_backward(model.handle, pyr.handle, level, _vp(rec.data_ptr()), rec.shape[0],
+                                        _vp(g.data_ptr()) if g is not None else None, _vp(out.data_ptr()),
+                                        _vp(_stream(stream))))
+    return out
+
+
+def cont_line_search(model: Model, pyr: Pyramid, level: int, poses: torch.Tensor, dirs: torch.Tensor, alphas,
+                     stream=None):
+    """Move each pose to the best of pose + alpha_j dir (scores in FP64); returns (poses, scores)."""
+    rec = _cont_poses(poses)
+    d = dirs.detach().to(device="cuda", dtype=torch.float32).reshape(-1, 3).contiguous()
+    a = (ctypes.c_double * len(alphas))(*[float(v) for v in alphas])
+    sc = torch.empty(rec.shape[0], dtype=torch.float32, device="cuda")
+    _check(lib().tm_cont_line_search(model.handle, pyr.handle, level, _vp(rec.data_ptr()), _vp(d.data_ptr()),
+                                     rec.shape[0], a, len(alphas), _vp(sc.data_ptr()), _vp(_stream(stream))))
+    return rec[:, :3].clone(), sc
+
+
+class ContinuousScore(torch.autograd.Function):
+    """S_c(poses) with the hand-written backward kernel: forward
+    tm_cont_score, backward tm_cont_score_backward."""
+
+    @staticmethod
+    def forward(ctx, poses, model, pyr, level):
+        ctx.save_for_backward(poses)
+        ctx.model, ctx.pyr, ctx.level = model, pyr, level
+        return cont_score(model, pyr, level, poses)
+
+    @staticmethod
+    def backward(ctx, grad):
+        (poses,) = ctx.saved_tensors
+        return cont_score_backward(ctx.model, ctx.pyr, ctx.level, poses, grad), None, None, None
+
+
+def refine_continuous(model: Model, pyr: Pyramid, poses: torch.Tensor, steps: int = 8, level: int = 0,
+                      step_xy: float = 0.5, step_theta: float = 0.5, decay: float = 0.6):
+    """Sub-pixel / sub-degree refinement of (n, 3) poses (x, y, theta_deg) by
+    gradient ascent on S_c.  Each step takes the gradient (backward kernel),
+    scales its translation part to length step_xy and its angle part to
+    +-step_theta degrees, and moves each pose to the best of the step lengths
+    {0, 1/8, 1/4, 1/2, 1, 2} along it, scored in FP64; so no pose's score goes
+    down.  Step lengths shrink by `decay` per step.  Returns (poses, scores),
+    the scores those of the FP64 line search (FP32-rounded)."""
+    p = poses.detach().to(device="cuda", dtype=torch.float32).reshape(-1, 3).clone()
+    alphas = [0.0, 0.125, 0.25, 0.5, 1.0, 2.0]
+    sxy, sth = step_xy, step_theta
+    sc = None
+    for _ in range(max(1, steps)):
+        g = cont_score_backward(model, pyr, level, p)
+        d = torch.cat([sxy * g[:, :2] / g[:, :2].norm(dim=1, keepdim=True).clamp_min(1e-20),
+                       (sth * torch.sign(g[:, 2]))[:, None]], dim=1)
+        p, sc = cont_line_search(model, pyr, level, p, d, alphas)
+        sxy *= decay
+        sth *= decay
+    return p, sc
 
 
 def timing_enable(on: bool = True):

@@ -336,6 +336,68 @@ def test_T8_translation_equivariance(oracle_mod):
         assert oracle_mod.score(g1, ml.t, ml.d, x, y, th) == oracle_mod.score(g2, ml.t, ml.d, x + b, y + a, th)
 
 
+# ---------------------------------------------------------------- O12
+def test_continuous_score_equals_centre_score_on_the_grid(oracle_mod):
+    """At integer translations and quarter turns every projected point is a
+    pixel, so bilinear interpolation returns the pixel and S_c equals S_1."""
+    rng = _rng(60)
+    img = rng.integers(0, 256, (60, 64), dtype=np.uint8)
+    ml = oracle_mod.build_model(_model32(8), oracle_mod.PyrParams(1, 30.0)).levels[0]
+    g = oracle_mod.edge_field(img, 40.0)
+    for (x, y, th) in [(20, 30, 0.0), (31, 17, 90.0), (40, 41, 180.0), (3, 58, 270.0), (-5, 10, -90.0)]:
+        sc, _ = oracle_mod.cont_score(g, ml.t, ml.d, x, y, th)
+        assert sc == oracle_mod.score(g, ml.t, ml.d, x, y, th)[1]
+
+
+def test_continuous_score_constant_field_closed_form(oracle_mod):
+    """On a constant unit field f the interpolated direction is f wherever all
+    four neighbours are inside, so S_c = mean(R(theta) d_i) . f, and its
+    gradient in translation is zero."""
+    ml = oracle_mod.build_model(_model32(9), oracle_mod.PyrParams(1, 30.0)).levels[0]
+    f = np.array([0.6, 0.8])
+    g = np.broadcast_to(f, (90, 90, 2)).copy()
+    for (x, y, th) in [(45.3, 44.7, 12.5), (40.9, 50.2, 200.0)]:
+        sc, grad = oracle_mod.cont_score(g, ml.t, ml.d, x, y, th)
+        c, s = np.cos(np.deg2rad(th)), np.sin(np.deg2rad(th))
+        r = ml.d @ np.array([[c, -s], [s, c]]).T
+        assert abs(sc - (r @ f).mean()) <= 1e-14
+        assert abs(grad[0]) <= 1e-14 and abs(grad[1]) <= 1e-14
+        # d/dtheta of mean(R d) . f in degrees
+        dr = ml.d @ np.array([[-s, -c], [c, -s]]).T
+        assert abs(grad[2] - np.pi / 180 * (dr @ f).mean()) <= 1e-14
+
+
+def test_continuous_gradient_matches_central_differences(oracle_mod):
+    """Away from pixel-cell boundaries the score is smooth: central
+    differences (h = 1e-3 px / degree) agree with the analytic gradient."""
+    model = _model32(10)
+    img = synth.paste_rot90(model, 90, 90, 45, 44, 0)
+    img = np.clip(img.astype(np.int64) + _rng(61).integers(-3, 4, img.shape), 0, 255).astype(np.uint8)
+    ml = oracle_mod.build_model(model, oracle_mod.PyrParams(1, 30.0)).levels[0]
+    g = oracle_mod.edge_field(img, 30.0)
+    rng = _rng(62)
+    h = 1e-3
+    checked = 0
+    for _ in range(400):
+        x, y, th = 45 + rng.uniform(-1.5, 1.5), 44 + rng.uniform(-1.5, 1.5), rng.uniform(-3, 3)
+        c, s = np.cos(np.deg2rad(th)), np.sin(np.deg2rad(th))
+        p = ml.t @ np.array([[c, -s], [s, c]]).T + [x, y]
+        f = p - np.floor(p)
+        if np.min(np.minimum(f, 1 - f)) < 4 * h:
+            continue  # a point would cross a cell boundary inside the stencil
+        _, grad = oracle_mod.cont_score(g, ml.t, ml.d, x, y, th)
+        fd = []
+        for e in np.eye(3):
+            sp_, _ = oracle_mod.cont_score(g, ml.t, ml.d, x + h * e[0], y + h * e[1], th + h * e[2])
+            sm_, _ = oracle_mod.cont_score(g, ml.t, ml.d, x - h * e[0], y - h * e[1], th - h * e[2])
+            fd.append((sp_ - sm_) / (2 * h))
+        assert np.allclose(grad, fd, atol=1e-8, rtol=1e-6), (grad, fd)
+        checked += 1
+        if checked >= 5:
+            break
+    assert checked >= 3
+
+
 # ---------------------------------------------------------------- O10
 def test_refine_picks_best_of_27_by_bruteforce(oracle_mod):
     rng = _rng(50)
