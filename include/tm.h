@@ -214,7 +214,10 @@ tm_status tm_cont_line_search(const tm_model* model, tm_pyramid* pyr, int32_t le
  * poses to out_dev[p * capacity ...] and their count to n_out_dev[p].
  * Creation allocates the pyramids, the rotated tables of the top level and
  * all scratch, and waits for the uploads; models must outlive the batch (their
- * points are read, their table cache is not used).  At most 65535 pairs. */
+ * points are read, their table cache is not used).  At most 65535 pairs.
+ * The exhaustive search runs over a work list fixed here: each pair's
+ * blocks, heaviest models first, dealt to the eight XCDs in equal-cost
+ * contiguous runs, so that uneven pairs do not leave a tail. */
 typedef struct tm_batch_s tm_batch;
 tm_status tm_batch_create(const tm_model* const* models, int32_t n_models, const uint8_t* const* images_dev,
                           const int32_t* widths, const int32_t* heights, const int32_t* pitches, int32_t n_images,
@@ -227,6 +230,26 @@ tm_status tm_batch_create(const tm_model* const* models, int32_t n_models, const
  * of every pair, each stage one launch over all pairs.  Allocates nothing and
  * never waits, so it can be captured in a graph. */
 tm_status tm_batch_run(tm_batch* batch, void* stream);
+
+/* As tm_batch_run, as one graph launch: the first call captures the batch's
+ * launches into a HIP graph (on a private stream, without running them) and
+ * keeps it with the batch; every call then launches that graph on `stream`.
+ * Search-kernel timing (tm_timing_enable) does not apply to graph launches. */
+tm_status tm_batch_run_graph(tm_batch* batch, void* stream);
+
+/* The continuous score, its backward and the FP64 line search (as
+ * tm_cont_score, tm_cont_score_backward and tm_cont_line_search) over the
+ * pairs of a batch, against the fields its last run built: pose.pair names
+ * the pair (image * n_models + model); a pose naming no pair of the batch
+ * gets NaN results (the line search leaves it where it is).  The line search
+ * keeps its scratch with the batch (allocated, or grown, on first need). */
+tm_status tm_batch_cont_score(tm_batch* batch, int32_t level, const tm_cont_pose* poses_dev, int32_t n,
+                              float* scores_dev, void* stream);
+tm_status tm_batch_cont_score_backward(tm_batch* batch, int32_t level, const tm_cont_pose* poses_dev, int32_t n,
+                                       const float* grad_scores_dev, float* grad_poses_dev, void* stream);
+tm_status tm_batch_cont_line_search(tm_batch* batch, int32_t level, tm_cont_pose* poses_dev, const float* dirs_dev,
+                                    int32_t n, const double* alphas, int32_t n_alphas, float* scores_dev,
+                                    void* stream);
 
 /* The pyramid the batch built for one image (owned by the batch). */
 tm_status tm_batch_pyramid(const tm_batch* batch, int32_t image, const tm_pyramid** out);

@@ -24,6 +24,7 @@ struct ContArgs {
     int level;
     int n;            // poses
     int batched;      // pose.pair selects the descriptor (else descriptor 0)
+    int npairs;       // descriptors; a pose naming another pair gets NaN results
     int n_alpha;      // line search: step lengths
     double alpha[kMaxAlphas];
 };
@@ -62,7 +63,17 @@ __global__ __launch_bounds__(256) void k_cont(ContArgs a, const PairDesc* __rest
     const int j = MODE == 2 ? w % a.n_alpha : 0;
     if (pi >= a.n) return;
     const tm_cont_pose ps = poses[pi];
-    const PairDesc& P = pairs[a.batched ? ps.pair : 0];
+    const int pr = a.batched ? ps.pair : 0;
+    if ((unsigned)pr >= (unsigned)a.npairs) {
+        if (lane == 0) {
+            const float nan = __builtin_nanf("");
+            if (MODE == 0) out[pi] = nan;
+            if (MODE == 1) out[3 * pi] = out[3 * pi + 1] = out[3 * pi + 2] = nan;
+            if (MODE == 2) out64[w] = __builtin_nan("");
+        }
+        return;
+    }
+    const PairDesc& P = pairs[pr];
     double x = ps.x, y = ps.y, th = ps.theta_deg;
     if (MODE == 2) {
         const tm_cont_pose m = moved(ps, a.alpha[j], dirs + 3 * pi);
@@ -147,6 +158,11 @@ __global__ __launch_bounds__(256) void k_line_pick(ContArgs a, const double* __r
 {
     const int pi = blockIdx.x * blockDim.x + threadIdx.x;
     if (pi >= a.n) return;
+    const int pr = a.batched ? poses[pi].pair : 0;
+    if ((unsigned)pr >= (unsigned)a.npairs) {  // pose left as it is
+        if (scores) scores[pi] = __builtin_nanf("");
+        return;
+    }
     int best = 0;
     double bs = s64[(size_t)pi * a.n_alpha];
     for (int j = 1; j < a.n_alpha; ++j) {
@@ -160,23 +176,24 @@ __global__ __launch_bounds__(256) void k_line_pick(ContArgs a, const double* __r
     if (scores) scores[pi] = (float)bs;
 }
 
-ContArgs cont_args(int level, int n, int batched)
+ContArgs cont_args(int level, int n, int batched, int npairs)
 {
     ContArgs a = {};
     a.level = level;
     a.n = n;
     a.batched = batched;
+    a.npairs = batched ? npairs : 1;
     a.n_alpha = 1;
     return a;
 }
 
 }  // namespace
 
-hipError_t launch_cont(const PairDesc* d, int batched, int level, int precision, const tm_cont_pose* poses, int n,
-                       const float* gin, float* out, bool backward, hipStream_t s)
+hipError_t launch_cont(const PairDesc* d, int batched, int npairs, int level, int precision, const tm_cont_pose* poses,
+                       int n, const float* gin, float* out, bool backward, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    ContArgs a = cont_args(level, n, batched);
+    ContArgs a = cont_args(level, n, batched, npairs);
     dim3 grid((n + 3) / 4);
     if (backward) {
         if (precision == TM_FP16)
@@ -196,12 +213,12 @@ hipError_t launch_cont(const PairDesc* d, int batched, int level, int precision,
 
 size_t line_search_scratch_bytes(int n, int n_alpha) { return (size_t)n * n_alpha * sizeof(double) + 256; }
 
-hipError_t launch_line_search(const PairDesc* d, int batched, int level, int precision, tm_cont_pose* poses,
-                              const float* dirs, int n, const double* alphas, int n_alpha, float* scores,
-                              double* scratch, hipStream_t s)
+hipError_t launch_line_search(const PairDesc* d, int batched, int npairs, int level, int precision,
+                              tm_cont_pose* poses, const float* dirs, int n, const double* alphas, int n_alpha,
+                              float* scores, double* scratch, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
-    ContArgs a = cont_args(level, n, batched);
+    ContArgs a = cont_args(level, n, batched, npairs);
     a.n_alpha = n_alpha;
     for (int j = 0; j < n_alpha; ++j) a.alpha[j] = alphas[j];
     dim3 grid((unsigned)(((long long)n * n_alpha + 3) / 4));

@@ -18,6 +18,8 @@
 // is the pair.
 #include <stdlib.h>
 
+#include <algorithm>
+
 #include "tm_device.h"
 
 namespace tmk {
@@ -89,6 +91,7 @@ struct FastArgs {
     int A;              // angles per workgroup
     int WY, WA;         // waves stacked in y, waves splitting the angles
     int C;              // chunks of angles
+    const int2* work;   // optional work list: block b runs (pair, block) work[b]; pair < 0: nothing
 };
 
 template <int G, int R, int LC, int PREC, bool ASM>
@@ -99,12 +102,19 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc*
     T* tile = reinterpret_cast<T*>(smem);
     constexpr int NS = 64 / G;   // segments per wave
     constexpr int TW = G - 2;    // output columns per segment
-    const PairDesc& P = pairs[blockIdx.y];
+    int pr = blockIdx.y, bx = blockIdx.x;
+    if (a.work) {
+        const int2 wv = a.work[blockIdx.x];
+        pr = wv.x;
+        bx = wv.y;
+        if (pr < 0) return;
+    }
+    const PairDesc& P = pairs[pr];
     const int n_tiles = P.tiles_x * P.tiles_y;
-    if ((int)blockIdx.x >= n_tiles * a.C) return;
+    if (bx >= n_tiles * a.C) return;
     const int TH = a.WY * NS * R;
-    const int chunk = blockIdx.x / n_tiles;
-    const int tid = blockIdx.x % n_tiles;
+    const int chunk = bx / n_tiles;
+    const int tid = bx % n_tiles;
     const int X0 = (tid % P.tiles_x) * TW, Y0 = (tid / P.tiles_x) * TH;
     const int W = P.W[a.level], H = P.H[a.level];
     const void* field = P.field[a.level];
@@ -411,6 +421,8 @@ int knob(const char* name, int dflt, int lo, int hi)
     return x < lo ? lo : (x > hi ? hi : x);
 }
 
+// d == nullptr: only raise the kernel's LDS limit (done once, before any
+// launch, so that no attribute call happens while a stream is captured).
 template <int G, int R, int LC, int PREC, bool ASM>
 hipError_t launch_fast_t(const DensePlan& p, const FastArgs& a, const PairDesc* d, int npairs, hipStream_t s)
 {
@@ -421,8 +433,9 @@ hipError_t launch_fast_t(const DensePlan& p, const FastArgs& a, const PairDesc* 
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((k_dense_fast<G, R, LC, PREC, ASM>), dim3(p.max_blocks, npairs), dim3(64 * p.WY * p.WA), p.lds,
-                       s, a, d);
+    if (!d) return hipSuccess;
+    const dim3 grid = a.work ? dim3(p.n_work) : dim3(p.max_blocks, npairs);
+    hipLaunchKernelGGL((k_dense_fast<G, R, LC, PREC, ASM>), grid, dim3(64 * p.WY * p.WA), p.lds, s, a, d);
     return hipGetLastError();
 }
 
@@ -508,7 +521,72 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
     return p;
 }
 
+bool build_work(const DensePlan& p, const PairGeom* g, int npairs, std::vector<int2>& out)
+{
+    out.clear();
+    if (!p.fast || !knob("TM_DENSE_WORKLIST", 1, 0, 1)) return true;
+    constexpr int kXcd = 8;
+    struct Run {
+        int pair, blocks;
+        double cost;  // per block: its points (the taps scale with n) plus the tile staging
+    };
+    std::vector<Run> runs;
+    double total = 0;
+    for (int i = 0; i < npairs; ++i) {
+        int tx, ty;
+        plan_tiles(p, g[i], &tx, &ty);
+        const Run r{i, tx * ty * p.C, (double)g[i].n + 8.0};
+        runs.push_back(r);
+        total += r.cost * r.blocks;
+    }
+    std::stable_sort(runs.begin(), runs.end(), [](const Run& a, const Run& b) { return a.cost > b.cost; });
+    // Fill the bins in turn, heaviest blocks first, each to an equal share of
+    // the cost; a pair's blocks stay contiguous (split over at most a few bins).
+    std::vector<std::vector<int2>> bin(kXcd);
+    const double share = total / kXcd;
+    int b = 0;
+    double load = 0;
+    for (const Run& r : runs)
+        for (int k = 0; k < r.blocks; ++k) {
+            if (load >= share && b < kXcd - 1) {
+                ++b;
+                load = 0;
+            }
+            bin[b].push_back(make_int2(r.pair, k));
+            load += r.cost;
+        }
+    size_t longest = 0;
+    for (auto& v : bin) longest = std::max(longest, v.size());
+    // Workgroup w is dispatched to XCD w % 8: interleave the bins.
+    out.assign(longest * kXcd, make_int2(-1, 0));
+    for (int x = 0; x < kXcd; ++x)
+        for (size_t j = 0; j < bin[x].size(); ++j) out[j * kXcd + x] = bin[x][j];
+    // every block of every pair exactly once
+    std::vector<int> first(npairs + 1, 0);
+    for (const Run& r : runs) first[r.pair + 1] = r.blocks;
+    for (int i = 0; i < npairs; ++i) first[i + 1] += first[i];
+    std::vector<unsigned char> seen(first[npairs], 0);
+    for (const int2& w : out) {
+        if (w.x < 0) continue;
+        if (w.x >= npairs || w.y < 0 || w.y >= first[w.x + 1] - first[w.x] || seen[first[w.x] + w.y]++) return false;
+    }
+    for (unsigned char c : seen)
+        if (!c) return false;
+    return true;
+}
+
 size_t dense_partials_bytes(const DensePlan& p, int np) { return (size_t)p.C * np * 12; }
+
+hipError_t prepare_dense(const SearchDesc& s, const DensePlan& p)
+{
+    if (!p.fast) return hipSuccess;
+    FastArgs a = {};
+    if (s.precision == TM_FP16)
+        return p.asm_dpp ? launch_fast_p<TM_FP16, true>(p, a, nullptr, 0, nullptr)
+                         : launch_fast_p<TM_FP16, false>(p, a, nullptr, 0, nullptr);
+    return p.asm_dpp ? launch_fast_p<TM_FP32, true>(p, a, nullptr, 0, nullptr)
+                     : launch_fast_p<TM_FP32, false>(p, a, nullptr, 0, nullptr);
+}
 
 hipError_t launch_dense(const SearchDesc& s, const DensePlan& p, const PairDesc* d, int npairs, hipStream_t st,
                         hipEvent_t ev0, hipEvent_t ev1)
@@ -526,6 +604,7 @@ hipError_t launch_dense(const SearchDesc& s, const DensePlan& p, const PairDesc*
         a.WY = p.WY;
         a.WA = p.WA;
         a.C = p.C;
+        a.work = p.work;
         if (s.precision == TM_FP16)
             e = p.asm_dpp ? launch_fast_p<TM_FP16, true>(p, a, d, npairs, st)
                           : launch_fast_p<TM_FP16, false>(p, a, d, npairs, st);

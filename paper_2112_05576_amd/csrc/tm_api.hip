@@ -853,7 +853,7 @@ TM_EXPORT tm_status tm_cont_score(const tm_model* m, tm_pyramid* p, int32_t leve
     tmk::PairDesc* dd = nullptr;
     tm_status st = cont_prepare(m, p, level, 0, S(stream), &dd, "tm_cont_score");
     if (st != TM_OK) return st;
-    HIP_TRY(tmk::launch_cont(dd, 0, level, p->precision, poses, n, nullptr, scores, false, S(stream)));
+    HIP_TRY(tmk::launch_cont(dd, 0, 1, level, p->precision, poses, n, nullptr, scores, false, S(stream)));
     return TM_OK;
 }
 
@@ -866,7 +866,7 @@ TM_EXPORT tm_status tm_cont_score_backward(const tm_model* m, tm_pyramid* p, int
     tmk::PairDesc* dd = nullptr;
     tm_status st = cont_prepare(m, p, level, 0, S(stream), &dd, "tm_cont_score_backward");
     if (st != TM_OK) return st;
-    HIP_TRY(tmk::launch_cont(dd, 0, level, p->precision, poses, n, gin, gout, true, S(stream)));
+    HIP_TRY(tmk::launch_cont(dd, 0, 1, level, p->precision, poses, n, gin, gout, true, S(stream)));
     return TM_OK;
 }
 
@@ -886,7 +886,7 @@ TM_EXPORT tm_status tm_cont_line_search(const tm_model* m, tm_pyramid* p, int32_
                                 "tm_cont_line_search");
     if (st != TM_OK) return st;
     double* scratch = reinterpret_cast<double*>(reinterpret_cast<uint8_t*>(p->ws.ptr) + kDescBytes);
-    HIP_TRY(tmk::launch_line_search(dd, 0, level, p->precision, poses, dirs, n, alphas, n_alphas, scores, scratch,
+    HIP_TRY(tmk::launch_line_search(dd, 0, 1, level, p->precision, poses, dirs, n, alphas, n_alphas, scores, scratch,
                                     S(stream)));
     return TM_OK;
 }
@@ -906,11 +906,16 @@ struct tm_batch_s {
     tmk::PairDesc* d_pairs = nullptr;
     tmk::PyrBuildArg* d_pb = nullptr;
     tmk::FieldsArg* d_fa = nullptr;
+    hipGraphExec_t graph = nullptr;  // captured tm_batch_run, made by the first tm_batch_run_graph
+    void* ls_buf = nullptr;          // line-search scratch of the continuous score
+    size_t ls_bytes = 0;
 };
 
 TM_EXPORT void tm_batch_free(tm_batch* b)
 {
     if (!b) return;
+    if (b->graph) hipGraphExecDestroy(b->graph);
+    if (b->ls_buf) hipFree(b->ls_buf);
     for (tm_pyramid* p : b->pyrs) tm_pyramid_free(p);
     if (b->scratch) hipFree(b->scratch);
     delete b;
@@ -967,6 +972,11 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
         for (int j = 0; j < n_models; ++j)
             pg[i * n_models + j] = pair_geom(models[j], b->pyrs[i], top, sp->step_x, sp->step_y);
     b->plan = tmk::plan_dense(b->sd, pg.data(), b->npairs);
+    std::vector<int2> work;
+    if (!tmk::build_work(b->plan, pg.data(), b->npairs, work)) {
+        tm_batch_free(b);
+        return fail(TM_EDEVICE, "tm_batch_create: internal error in the search work list");
+    }
     refine_max_chunks(models, n_models, L, b->max_chunks);
     for (auto& q : pg) b->max_np = std::max(b->max_np, q.gw * q.gh);
 
@@ -984,6 +994,8 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
     off = align_up(off + (size_t)n_images * sizeof(tmk::PyrBuildArg), 256);
     const size_t fa_off = off;
     off = align_up(off + (size_t)n_images * sizeof(tmk::FieldsArg), 256);
+    const size_t work_off = off;
+    off = align_up(off + work.size() * sizeof(int2), 256);
     std::vector<size_t> pair_off(b->npairs);
     const bool refine = L > 1;
     for (int q = 0; q < b->npairs; ++q) {
@@ -1042,6 +1054,11 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
         e = hipMemcpyAsync(b->d_pb, hpb.data(), hpb.size() * sizeof(tmk::PyrBuildArg), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_fa, hfa.data(), hfa.size() * sizeof(tmk::FieldsArg), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !work.empty()) {
+        b->plan.work = reinterpret_cast<const int2*>(base + work_off);
+        b->plan.n_work = (int)work.size();
+        e = hipMemcpyAsync(base + work_off, work.data(), work.size() * sizeof(int2), hipMemcpyHostToDevice, s);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         tm_batch_free(b);
@@ -1051,20 +1068,116 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
     return TM_OK;
 }
 
-TM_EXPORT tm_status tm_batch_run(tm_batch* b, void* stream)
+namespace {
+tm_status batch_enqueue(tm_batch* b, hipStream_t s, bool timed)
 {
-    if (!b) return fail(TM_EINVAL, "tm_batch_run: null batch");
-    hipStream_t s = S(stream);
     const int top = b->L - 1;
     HIP_TRY(tmk::launch_pyramids_batch(b->d_pb, b->d_fa, b->n_images, b->L, b->level_w[0], b->level_h[0],
                                        b->max_field_blocks, b->level_w, b->level_h, s));
-    hipEvent_t ev0, ev1;
-    tm_status st = timing_pair(&ev0, &ev1);
-    if (st != TM_OK) return st;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (timed) {
+        tm_status st = timing_pair(&ev0, &ev1);
+        if (st != TM_OK) return st;
+    }
     HIP_TRY(tmk::launch_dense(b->sd, b->plan, b->d_pairs, b->npairs, s, ev0, ev1));
     HIP_TRY(tmk::launch_select(b->sd, b->d_pairs, b->npairs, b->max_np, s));
     if (b->L > 1) HIP_TRY(tmk::launch_refine(b->sd, b->d_pairs, b->npairs, top, b->max_chunks, s));
     HIP_TRY(tmk::launch_final(b->sd, b->d_pairs, b->npairs, s));
+    return TM_OK;
+}
+}  // namespace
+
+TM_EXPORT tm_status tm_batch_run(tm_batch* b, void* stream)
+{
+    if (!b) return fail(TM_EINVAL, "tm_batch_run: null batch");
+    return batch_enqueue(b, S(stream), true);
+}
+
+TM_EXPORT tm_status tm_batch_run_graph(tm_batch* b, void* stream)
+{
+    if (!b) return fail(TM_EINVAL, "tm_batch_run_graph: null batch");
+    if (!b->graph) {
+        // Capture on a private stream: nothing runs, the launches become nodes.
+        HIP_TRY(tmk::prepare_dense(b->sd, b->plan));
+        hipStream_t cs = nullptr;
+        HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        tm_status st = TM_OK;
+        if (e == hipSuccess) {
+            st = batch_enqueue(b, cs, false);
+            hipGraph_t g = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(cs, &g);
+            if (st == TM_OK && e2 != hipSuccess) st = hip_fail(e2, "tm_batch_run_graph: end capture");
+            if (st == TM_OK) {
+                e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+                if (e != hipSuccess) {
+                    b->graph = nullptr;
+                    st = hip_fail(e, "tm_batch_run_graph: instantiate");
+                }
+            }
+            if (g) hipGraphDestroy(g);
+        } else {
+            st = hip_fail(e, "tm_batch_run_graph: begin capture");
+        }
+        hipStreamDestroy(cs);
+        if (st != TM_OK) return st;
+    }
+    HIP_TRY(hipGraphLaunch(b->graph, S(stream)));
+    return TM_OK;
+}
+
+namespace {
+tm_status batch_cont_check(const tm_batch* b, int level, int n, const void* poses, const void* out, const char* what)
+{
+    if (!b) return fail(TM_EINVAL, "%s: null batch", what);
+    if (level < 0 || level >= b->L) return fail(TM_EINVAL, "%s: bad level %d", what, level);
+    if (n < 0) return fail(TM_EINVAL, "%s: n < 0", what);
+    if (n > 0 && (!poses || !out)) return fail(TM_EINVAL, "%s: null buffer", what);
+    return TM_OK;
+}
+}  // namespace
+
+TM_EXPORT tm_status tm_batch_cont_score(tm_batch* b, int32_t level, const tm_cont_pose* poses, int32_t n,
+                                        float* scores, void* stream)
+{
+    tm_status st = batch_cont_check(b, level, n, poses, scores, "tm_batch_cont_score");
+    if (st != TM_OK) return st;
+    HIP_TRY(tmk::launch_cont(b->d_pairs, 1, b->npairs, level, b->sd.precision, poses, n, nullptr, scores, false,
+                             S(stream)));
+    return TM_OK;
+}
+
+TM_EXPORT tm_status tm_batch_cont_score_backward(tm_batch* b, int32_t level, const tm_cont_pose* poses, int32_t n,
+                                                 const float* gin, float* gout, void* stream)
+{
+    tm_status st = batch_cont_check(b, level, n, poses, gout, "tm_batch_cont_score_backward");
+    if (st != TM_OK) return st;
+    HIP_TRY(tmk::launch_cont(b->d_pairs, 1, b->npairs, level, b->sd.precision, poses, n, gin, gout, true, S(stream)));
+    return TM_OK;
+}
+
+TM_EXPORT tm_status tm_batch_cont_line_search(tm_batch* b, int32_t level, tm_cont_pose* poses, const float* dirs,
+                                              int32_t n, const double* alphas, int32_t n_alphas, float* scores,
+                                              void* stream)
+{
+    tm_status st = batch_cont_check(b, level, n, poses, dirs, "tm_batch_cont_line_search");
+    if (st != TM_OK) return st;
+    if (!alphas || n_alphas < 1 || n_alphas > 16)
+        return fail(TM_EINVAL, "tm_batch_cont_line_search: need 1..16 step lengths");
+    for (int j = 0; j < n_alphas; ++j)
+        if (!isfinite(alphas[j])) return fail(TM_EINVAL, "tm_batch_cont_line_search: non-finite step length");
+    if ((long long)n * n_alphas > (1LL << 30))
+        return fail(TM_EINVAL, "tm_batch_cont_line_search: too many evaluations");
+    const size_t need = tmk::line_search_scratch_bytes(n, n_alphas);
+    if (need > b->ls_bytes) {
+        if (b->ls_buf) HIP_TRY(hipFree(b->ls_buf));  // waits for earlier users
+        b->ls_buf = nullptr;
+        b->ls_bytes = 0;
+        HIP_TRY(hipMalloc(&b->ls_buf, need));
+        b->ls_bytes = need;
+    }
+    HIP_TRY(tmk::launch_line_search(b->d_pairs, 1, b->npairs, level, b->sd.precision, poses, dirs, n, alphas,
+                                    n_alphas, scores, reinterpret_cast<double*>(b->ls_buf), S(stream)));
     return TM_OK;
 }
 

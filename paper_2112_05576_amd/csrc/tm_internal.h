@@ -7,6 +7,8 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/tm.h"
 
 namespace tmk {
@@ -177,6 +179,8 @@ struct DensePlan {
     size_t lds;
     int max_blocks;             // workgroups of the largest pair (fast path)
     int max_np;                 // translations of the largest pair
+    const int2* work = nullptr; // optional device work list (fast path, build_work)
+    int n_work = 0;
 };
 
 // The searched level of one pair, for planning.
@@ -188,9 +192,18 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs);
 // Tile counts of a pair under a plan (fast path).
 void plan_tiles(const DensePlan& p, const PairGeom& g, int* tiles_x, int* tiles_y);
 size_t dense_partials_bytes(const DensePlan& p, int np);
+// Work list of the fast search over many pairs: the blocks binned onto the
+// eight XCDs to equal cost, heaviest first (longest processing time), pairs
+// kept contiguous within a bin for L2 reuse of their tables; entry b is run
+// by workgroup b, (-1, 0) entries pad the bins to equal length.  Empty when
+// the plan is not the fast path; false if the list failed its own check
+// (every block of every pair exactly once).
+bool build_work(const DensePlan& p, const PairGeom* g, int npairs, std::vector<int2>& out);
 size_t select_scratch_bytes(int np);
 int refine_chunks(int n);
 
+// Kernel attributes of the plan's search kernel (call before capturing it).
+hipError_t prepare_dense(const SearchDesc& s, const DensePlan& p);
 // Exhaustive search of s.level for every pair: pair.mw/m1/mk.  ev0 / ev1
 // (optional) are recorded around the search kernel only.
 hipError_t launch_dense(const SearchDesc& s, const DensePlan& p, const PairDesc* d, int npairs, hipStream_t st,
@@ -205,13 +218,13 @@ hipError_t launch_refine(const SearchDesc& s, const PairDesc* d, int npairs, int
 hipError_t launch_final(const SearchDesc& s, const PairDesc* d, int npairs, hipStream_t st);
 
 // Continuous score (forward) or its backward of n poses; d: descriptor array
-// (batched: pose.pair selects, else descriptor 0).
-hipError_t launch_cont(const PairDesc* d, int batched, int level, int precision, const tm_cont_pose* poses, int n,
-                       const float* gin, float* out, bool backward, hipStream_t s);
+// of npairs entries (batched: pose.pair selects, else descriptor 0).
+hipError_t launch_cont(const PairDesc* d, int batched, int npairs, int level, int precision, const tm_cont_pose* poses,
+                       int n, const float* gin, float* out, bool backward, hipStream_t s);
 size_t line_search_scratch_bytes(int n, int n_alpha);
-hipError_t launch_line_search(const PairDesc* d, int batched, int level, int precision, tm_cont_pose* poses,
-                              const float* dirs, int n, const double* alphas, int n_alpha, float* scores,
-                              double* scratch, hipStream_t s);
+hipError_t launch_line_search(const PairDesc* d, int batched, int npairs, int level, int precision,
+                              tm_cont_pose* poses, const float* dirs, int n, const double* alphas, int n_alpha,
+                              float* scores, double* scratch, hipStream_t s);
 
 // One wave per pose: S_w and S_1 of arbitrary poses.
 hipError_t launch_sparse(const void* field, int W, int H, int precision, const ModelPoint* pts, int n, int win,

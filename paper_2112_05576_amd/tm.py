@@ -78,6 +78,10 @@ def lib():
                                 ctypes.POINTER(_i32), ctypes.POINTER(_i32), _i32, ctypes.POINTER(PyrParamsC),
                                 ctypes.POINTER(SearchParamsC), _vp, _i32, _vp, _vp, ctypes.POINTER(_vp)],
             "tm_batch_run": [_vp, _vp],
+            "tm_batch_run_graph": [_vp, _vp],
+            "tm_batch_cont_score": [_vp, _i32, _vp, _i32, _vp, _vp],
+            "tm_batch_cont_score_backward": [_vp, _i32, _vp, _i32, _vp, _vp, _vp],
+            "tm_batch_cont_line_search": [_vp, _i32, _vp, _vp, _i32, ctypes.POINTER(ctypes.c_double), _i32, _vp, _vp],
             "tm_cont_score": [_vp, _vp, _i32, _vp, _i32, _vp, _vp],
             "tm_cont_score_backward": [_vp, _vp, _i32, _vp, _i32, _vp, _vp, _vp],
             "tm_cont_line_search": [_vp, _vp, _i32, _vp, _vp, _i32, ctypes.POINTER(ctypes.c_double), _i32, _vp,
@@ -343,8 +347,30 @@ class Batch:
                                      _vp(_stream(stream)), ctypes.byref(self._h)))
         self.n_models = nm
 
-    def run(self, stream=None):
-        _check(lib().tm_batch_run(self._h, _vp(_stream(stream))))
+    def run(self, stream=None, graph: bool = False):
+        """Enqueue the batch; graph=True launches it as one captured HIP graph."""
+        f = lib().tm_batch_run_graph if graph else lib().tm_batch_run
+        _check(f(self._h, _vp(_stream(stream))))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def cont_score(self, level: int, poses: torch.Tensor, pairs, stream=None) -> torch.Tensor:
+        """S_c of (n, 3) poses on pairs[i] (image * n_models + model)."""
+        return _score(_ContBatch(self), level, _cont_poses(poses, pairs), stream)
+
+    def cont_score_backward(self, level: int, poses: torch.Tensor, pairs, grad_scores=None, stream=None):
+        return _backward(_ContBatch(self), level, _cont_poses(poses, pairs), grad_scores, stream)
+
+    def cont_line_search(self, level: int, poses: torch.Tensor, pairs, dirs: torch.Tensor, alphas, stream=None):
+        rec, sc = _line_search(_ContBatch(self), level, _cont_poses(poses, pairs), dirs, alphas, stream)
+        return rec[:, :3].clone(), sc
+
+    def refine_continuous(self, poses: torch.Tensor, pairs, steps: int = 8, level: int = 0, step_xy: float = 0.5,
+                          step_theta: float = 0.5, decay: float = 0.6):
+        """refine_continuous over the batch's pairs (see the module function)."""
+        return _ascend(_ContBatch(self), _cont_poses(poses, pairs), steps, level, step_xy, step_theta, decay)
 
     def results(self):
         """Per pair, the detections as a numpy structured array (waits for the device)."""
@@ -365,64 +391,135 @@ class Batch:
 
 
 # ---------------------------------------------------------------- continuous score
-CONT_DTYPE = np.dtype([("x", "<f4"), ("y", "<f4"), ("theta", "<f4"), ("pair", "<i4")])
-
-
-def _cont_poses(poses: torch.Tensor) -> torch.Tensor:
-    """(n, 3) float32 (x, y, theta_deg) -> device tm_cont_pose records (n, 4) float32 view."""
+def _cont_poses(poses: torch.Tensor, pairs=None) -> torch.Tensor:
+    """(n, 3) (x, y, theta_deg) [+ (n,) pair indices] -> device tm_cont_pose
+    records, as an (n, 4) float32 tensor whose last column holds the int32
+    pair bits."""
     p = poses.detach().to(device="cuda", dtype=torch.float32).reshape(-1, 3)
     rec = torch.zeros((p.shape[0], 4), dtype=torch.float32, device="cuda")
     rec[:, :3] = p
+    if pairs is not None:
+        pr = torch.as_tensor(pairs, dtype=torch.int32).to("cuda").reshape(-1)
+        if pr.shape[0] != p.shape[0]:
+            raise TMError(TM_EINVAL, "one pair index per pose")
+        rec.view(torch.int32)[:, 3] = pr
     return rec.contiguous()
+
+
+def _alphas(alphas):
+    return (ctypes.c_double * len(alphas))(*[float(v) for v in alphas]), len(alphas)
+
+
+class _ContSingle:
+    """Continuous-score calls on one (model, pyramid) pair."""
+
+    def __init__(self, model: Model, pyr: Pyramid):
+        self.model, self.pyr = model, pyr
+
+    def score(self, level, rec, out, st):
+        _check(lib().tm_cont_score(self.model.handle, self.pyr.handle, level, _vp(rec.data_ptr()), rec.shape[0],
+                                   _vp(out.data_ptr()), _vp(st)))
+
+    def backward(self, level, rec, gin, gout, st):
+        _check(lib().tm_cont_score_backward(self.model.handle, self.pyr.handle, level, _vp(rec.data_ptr()),
+                                            rec.shape[0], gin, _vp(gout.data_ptr()), _vp(st)))
+
+    def line_search(self, level, rec, dirs, alphas, sc, st):
+        a, na = _alphas(alphas)
+        _check(lib().tm_cont_line_search(self.model.handle, self.pyr.handle, level, _vp(rec.data_ptr()),
+                                         _vp(dirs.data_ptr()), rec.shape[0], a, na, _vp(sc.data_ptr()), _vp(st)))
+
+
+class _ContBatch:
+    """Continuous-score calls over the pairs of a batch."""
+
+    def __init__(self, batch):
+        self.batch = batch
+
+    def score(self, level, rec, out, st):
+        _check(lib().tm_batch_cont_score(self.batch.handle, level, _vp(rec.data_ptr()), rec.shape[0],
+                                         _vp(out.data_ptr()), _vp(st)))
+
+    def backward(self, level, rec, gin, gout, st):
+        _check(lib().tm_batch_cont_score_backward(self.batch.handle, level, _vp(rec.data_ptr()), rec.shape[0], gin,
+                                                  _vp(gout.data_ptr()), _vp(st)))
+
+    def line_search(self, level, rec, dirs, alphas, sc, st):
+        a, na = _alphas(alphas)
+        _check(lib().tm_batch_cont_line_search(self.batch.handle, level, _vp(rec.data_ptr()), _vp(dirs.data_ptr()),
+                                               rec.shape[0], a, na, _vp(sc.data_ptr()), _vp(st)))
+
+
+def _score(t, level, rec, stream=None):
+    out = torch.empty(rec.shape[0], dtype=torch.float32, device="cuda")
+    t.score(level, rec, out, _stream(stream))
+    return out
+
+
+def _backward(t, level, rec, grad_scores=None, stream=None):
+    out = torch.empty((rec.shape[0], 3), dtype=torch.float32, device="cuda")
+    g = None if grad_scores is None else grad_scores.detach().to(device="cuda", dtype=torch.float32).contiguous()
+    t.backward(level, rec, _vp(g.data_ptr()) if g is not None else None, out, _stream(stream))
+    return out
+
+
+def _line_search(t, level, rec, dirs, alphas, stream=None):
+    rec = rec.clone()
+    d = dirs.detach().to(device="cuda", dtype=torch.float32).reshape(-1, 3).contiguous()
+    sc = torch.empty(rec.shape[0], dtype=torch.float32, device="cuda")
+    t.line_search(level, rec, d, alphas, sc, _stream(stream))
+    return rec, sc
+
+
+def _ascend(t, rec, steps, level, step_xy, step_theta, decay):
+    alphas = [0.0, 0.125, 0.25, 0.5, 1.0, 2.0]
+    sxy, sth = step_xy, step_theta
+    sc = None
+    for _ in range(max(1, steps)):
+        g = _backward(t, level, rec)
+        d = torch.cat([sxy * g[:, :2] / g[:, :2].norm(dim=1, keepdim=True).clamp_min(1e-20),
+                       (sth * torch.sign(g[:, 2]))[:, None]], dim=1)
+        rec, sc = _line_search(t, level, rec, d, alphas)
+        sxy *= decay
+        sth *= decay
+    return rec[:, :3].clone(), sc
 
 
 def cont_score(model: Model, pyr: Pyramid, level: int, poses: torch.Tensor, stream=None) -> torch.Tensor:
     """Continuous score of (n, 3) poses (x, y, theta_deg) at `level`."""
-    rec = _cont_poses(poses)
-    out = torch.empty(rec.shape[0], dtype=torch.float32, device="cuda")
-    _check(lib().tm_cont_score(model.handle, pyr.handle, level, _vp(rec.data_ptr()), rec.shape[0],
-                               _vp(out.data_ptr()), _vp(_stream(stream))))
-    return out
+    return _score(_ContSingle(model, pyr), level, _cont_poses(poses), stream)
 
 
 def cont_score_backward(model: Model, pyr: Pyramid, level: int, poses: torch.Tensor,
                         grad_scores: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """grad_scores[i] * dS/d(x, y, theta_deg) of each pose, (n, 3)."""
-    rec = _cont_poses(poses)
-    out = torch.empty((rec.shape[0], 3), dtype=torch.float32, device="cuda")
-    g = None if grad_scores is None else grad_scores.detach().to(device="cuda", dtype=torch.float32).contiguous()
-    _check(lib().tm_cont_score_backward(model.handle, pyr.handle, level, _vp(rec.data_ptr()), rec.shape[0],
-                                        _vp(g.data_ptr()) if g is not None else None, _vp(out.data_ptr()),
-                                        _vp(_stream(stream))))
-    return out
+    return _backward(_ContSingle(model, pyr), level, _cont_poses(poses), grad_scores, stream)
 
 
 def cont_line_search(model: Model, pyr: Pyramid, level: int, poses: torch.Tensor, dirs: torch.Tensor, alphas,
                      stream=None):
     """Move each pose to the best of pose + alpha_j dir (scores in FP64); returns (poses, scores)."""
-    rec = _cont_poses(poses)
-    d = dirs.detach().to(device="cuda", dtype=torch.float32).reshape(-1, 3).contiguous()
-    a = (ctypes.c_double * len(alphas))(*[float(v) for v in alphas])
-    sc = torch.empty(rec.shape[0], dtype=torch.float32, device="cuda")
-    _check(lib().tm_cont_line_search(model.handle, pyr.handle, level, _vp(rec.data_ptr()), _vp(d.data_ptr()),
-                                     rec.shape[0], a, len(alphas), _vp(sc.data_ptr()), _vp(_stream(stream))))
+    rec, sc = _line_search(_ContSingle(model, pyr), level, _cont_poses(poses), dirs, alphas, stream)
     return rec[:, :3].clone(), sc
 
 
 class ContinuousScore(torch.autograd.Function):
-    """S_c(poses) with the hand-written backward kernel: forward
-    tm_cont_score, backward tm_cont_score_backward."""
+    """S_c of (n, 3) poses with the hand-written backward kernel.  Call as
+    ContinuousScore.apply(poses, model, pyramid, level), or with a Batch in
+    place of the model and the (n,) pair indices in place of the pyramid."""
 
     @staticmethod
-    def forward(ctx, poses, model, pyr, level):
-        ctx.save_for_backward(poses)
-        ctx.model, ctx.pyr, ctx.level = model, pyr, level
-        return cont_score(model, pyr, level, poses)
+    def forward(ctx, poses, model_or_batch, pyr_or_pairs, level):
+        if isinstance(model_or_batch, Batch):
+            t, rec = _ContBatch(model_or_batch), _cont_poses(poses, pyr_or_pairs)
+        else:
+            t, rec = _ContSingle(model_or_batch, pyr_or_pairs), _cont_poses(poses)
+        ctx.t, ctx.rec, ctx.level = t, rec, level
+        return _score(t, level, rec)
 
     @staticmethod
     def backward(ctx, grad):
-        (poses,) = ctx.saved_tensors
-        return cont_score_backward(ctx.model, ctx.pyr, ctx.level, poses, grad), None, None, None
+        return _backward(ctx.t, ctx.level, ctx.rec, grad), None, None, None
 
 
 def refine_continuous(model: Model, pyr: Pyramid, poses: torch.Tensor, steps: int = 8, level: int = 0,
@@ -434,18 +531,7 @@ def refine_continuous(model: Model, pyr: Pyramid, poses: torch.Tensor, steps: in
     {0, 1/8, 1/4, 1/2, 1, 2} along it, scored in FP64; so no pose's score goes
     down.  Step lengths shrink by `decay` per step.  Returns (poses, scores),
     the scores those of the FP64 line search (FP32-rounded)."""
-    p = poses.detach().to(device="cuda", dtype=torch.float32).reshape(-1, 3).clone()
-    alphas = [0.0, 0.125, 0.25, 0.5, 1.0, 2.0]
-    sxy, sth = step_xy, step_theta
-    sc = None
-    for _ in range(max(1, steps)):
-        g = cont_score_backward(model, pyr, level, p)
-        d = torch.cat([sxy * g[:, :2] / g[:, :2].norm(dim=1, keepdim=True).clamp_min(1e-20),
-                       (sth * torch.sign(g[:, 2]))[:, None]], dim=1)
-        p, sc = cont_line_search(model, pyr, level, p, d, alphas)
-        sxy *= decay
-        sth *= decay
-    return p, sc
+    return _ascend(_ContSingle(model, pyr), _cont_poses(poses), steps, level, step_xy, step_theta, decay)
 
 
 def timing_enable(on: bool = True):

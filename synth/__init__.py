@@ -8,7 +8,14 @@ detector's arithmetic; both the oracle tests and the GPU path consume its
 images.
 """
 from .workloads import (  # noqa: F401
+    C4,
+    C4_MODELS,
+    C4_SIZES,
     CONFIGS,
+    BatchScene,
+    c4_image,
+    c4_model,
+    c5_poses,
     Instance,
     Scene,
     make_model_shape,

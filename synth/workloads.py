@@ -77,9 +77,10 @@ class Shape:
         return m
 
 
-def make_model_shape(kind: str, size: int, rng: np.random.Generator) -> Shape:
+def make_model_shape(kind: str, size: int, rng: np.random.Generator, n_holes=(1, 3), hole_frac=(0.08, 0.16)) -> Shape:
     """'blocks': 2-3 rectangles or ellipses (small models);
-    'polygon': a star-shaped polygon of 5-9 vertices with 1-3 elliptic holes."""
+    'polygon': a star-shaped polygon of 5-9 vertices with n_holes[0]..n_holes[1]
+    elliptic holes of radius hole_frac * size (fewer if they do not fit)."""
     half = size / 2.0
     if kind == "blocks":
         parts = []
@@ -102,9 +103,9 @@ def make_model_shape(kind: str, size: int, rng: np.random.Generator) -> Shape:
         poly = Polygon(rad * np.cos(ang), rad * np.sin(ang))
         holes = []
         rin = rad.min() * np.cos(np.pi / nv)  # inscribed radius bound
-        for _ in range(int(rng.integers(1, 4))):
+        for _ in range(int(rng.integers(n_holes[0], n_holes[1] + 1))):
             for _try in range(50):
-                hr = rng.uniform(0.08, 0.16) * size
+                hr = rng.uniform(*hole_frac) * size
                 hb = hr * rng.uniform(0.6, 1.0)
                 cr = rng.uniform(0.0, max(rin - hr - 4.0, 0.0))
                 ca = rng.uniform(0, 2 * np.pi)
@@ -260,6 +261,91 @@ CONFIGS = {
             noise=8.0, occl=0.40, gain=(0.5, 2.0), offset=(-40.0, 40.0), clutter=50, levels=5,
             tau_m=30.0, tau_s=80.0, theta_step_top=8.0, theta_range=360.0),
 }
+
+
+# C4: eight models of increasing size (level-0 point counts at tau_m = 30 about
+# 210, 305, 500, 750, 1100, 1700, 2500 and 3900), polygon with holes
+# (size, hole count range, hole radius range as a fraction of the size).
+C4_MODELS = [(40, (0, 0), (0.1, 0.1)), (52, (0, 0), (0.1, 0.1)), (64, (1, 1), (0.08, 0.14)),
+             (90, (1, 1), (0.08, 0.14)), (128, (2, 3), (0.08, 0.14)), (160, (3, 5), (0.07, 0.12)),
+             (208, (6, 8), (0.06, 0.10)), (256, (14, 18), (0.05, 0.08))]
+C4_SIZES = [(640, 480), (1280, 1024), (2448, 2048)]
+C4 = dict(name="C4 64 images x 8 models", n_images=64, levels=4, tau_m=30.0, tau_s=80.0, theta_step_top=1.0,
+          theta_range=360.0, noise=8.0, occl=0.30, gain=(0.5, 2.0), offset=(-40.0, 40.0), clutter=50,
+          inst=(1, 6))
+
+
+@dataclass
+class BatchScene:
+    image: np.ndarray
+    instances: list            # Instance poses
+    models: list               # model index of each instance
+
+
+def c4_model(k: int):
+    """(shape, model image) of C4 model k (0..7)."""
+    size, nh, hf = C4_MODELS[k]
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(BASE_SEED + 4, spawn_key=(10**6 + k,))))
+    shape = make_model_shape("polygon", size, rng, n_holes=nh, hole_frac=hf)
+    return shape, render_model(shape, size)
+
+
+def c4_image(index: int, shapes=None) -> BatchScene:
+    """Image `index` of C4: its size drawn from C4_SIZES, 1-6 instances of
+    models drawn uniformly (placed without overlap; fewer if they do not fit),
+    then the C2 distortions (occluders, gain and offset, clutter, noise)."""
+    cfg = C4
+    if shapes is None:
+        shapes = [c4_model(k)[0] for k in range(len(C4_MODELS))]
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(BASE_SEED + 4, spawn_key=(index,))))
+    W, H = C4_SIZES[int(rng.integers(0, len(C4_SIZES)))]
+    n_inst = int(rng.integers(cfg["inst"][0], cfg["inst"][1] + 1))
+    img = np.full((H, W), 40.0, np.float64)
+    taken, inst, mids = [], [], []
+    for _ in range(n_inst):
+        k = int(rng.integers(0, len(shapes)))
+        spot = _place(rng, W, H, shapes[k].radius, 1, taken)
+        if not spot:
+            continue
+        x, y = spot[0]
+        th = float(rng.uniform(0.0, 360.0))
+        _paint_instance(img, shapes[k], x, y, th, 200.0)
+        inst.append(Instance(float(x), float(y), th))
+        mids.append(k)
+    for it, k in zip(inst, mids):
+        size = C4_MODELS[k][0]
+        frac = rng.uniform(0.0, cfg["occl"])
+        area = frac * size * size
+        aspect = rng.uniform(0.5, 2.0)
+        rw, rh = np.sqrt(area * aspect), np.sqrt(area / aspect)
+        cx = it.x + rng.uniform(-0.5, 0.5) * size
+        cy = it.y + rng.uniform(-0.5, 0.5) * size
+        x0, x1 = int(max(0, np.rint(cx - rw / 2))), int(min(W, np.rint(cx + rw / 2)))
+        y0, y1 = int(max(0, np.rint(cy - rh / 2))), int(min(H, np.rint(cy + rh / 2)))
+        if x1 > x0 and y1 > y0:
+            img[y0:y1, x0:x1] = rng.uniform(0, 255)
+    img = rng.uniform(*cfg["gain"]) * img + rng.uniform(*cfg["offset"])
+    _clutter(img, rng, cfg["clutter"])
+    img = img + rng.normal(0.0, cfg["noise"], img.shape)
+    return BatchScene(np.clip(np.rint(img), 0, 255).astype(np.uint8), inst, mids)
+
+
+def c5_poses(scenes, n: int = 4096, seed: int = 5):
+    """C5 start poses: ground-truth instances of the C4 scenes, cycled to n,
+    each moved by U[-1.5, 1.5] px in x and y and U[-2, 2] degrees.  Returns
+    (image index, model index, start (x, y, theta), truth (x, y, theta))."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(BASE_SEED + 5, spawn_key=(seed,))))
+    gt = [(i, k, it) for i, sc in enumerate(scenes) for it, k in zip(sc.instances, sc.models)]
+    img_i = np.empty(n, np.int32)
+    mod_i = np.empty(n, np.int32)
+    start = np.empty((n, 3), np.float64)
+    truth = np.empty((n, 3), np.float64)
+    for j in range(n):
+        i, k, it = gt[j % len(gt)]
+        img_i[j], mod_i[j] = i, k
+        truth[j] = (it.x, it.y, it.theta)
+        start[j] = (it.x + rng.uniform(-1.5, 1.5), it.y + rng.uniform(-1.5, 1.5), it.theta + rng.uniform(-2, 2))
+    return img_i, mod_i, start, truth
 
 
 def scene_for_config(ci: int, index: int = 0, **override) -> Scene:

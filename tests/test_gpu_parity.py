@@ -383,13 +383,21 @@ def test_score_map_fp16(ci):
     g = O.field_pyramid(sc.image, L, cfg["tau_s"])[top]
     ml = om.levels[top]
     mw, m1, mk = O.top_map(g, ml.t, ml.d, 0.0, st, int(np.ceil(360.0 / st)))
-    ew, e1 = np.abs(sw - mw).max(), np.abs(s1 - m1).max()
+    # S_w is the maximum over angles, so it stays within the bound even where
+    # another angle wins; S_1 belongs to the winning angle and is compared
+    # where the angles agree, and against the oracle at the GPU's angle where
+    # they do not (which must then be an oracle tie within two bounds).
+    same = k == mk
+    ew, e1 = np.abs(sw - mw).max(), np.abs(s1 - m1)[same].max()
+    diff = np.argwhere(~same)
     print(f"FP16 map: max |dS_w| {ew:.3g} mean {np.abs(sw - mw).mean():.3g} p99 "
-          f"{np.quantile(np.abs(sw - mw), 0.99):.3g}; max |dS_1| {e1:.3g}")
+          f"{np.quantile(np.abs(sw - mw), 0.99):.3g}; max |dS_1| (same angle) {e1:.3g}; "
+          f"angle differs at {len(diff)} of {k.size}")
     assert ew <= TOL16 and e1 <= TOL16
-    for (j, i) in np.argwhere(k != mk)[:200]:
+    for (j, i) in diff:
         a = O.score(g, ml.t, ml.d, int(i), int(j), O.theta(0.0, st, int(k[j, i])))
         assert abs(a[0] - mw[j, i]) <= 2 * TOL16, (i, j)
+        assert abs(a[0] - sw[j, i]) <= TOL16 and abs(a[1] - s1[j, i]) <= TOL16, (i, j)
 
 
 def test_score_poses_fp16():
@@ -512,3 +520,40 @@ def test_batch_pyramids_match_oracle():
                 assert np.abs(gf.cpu().numpy().astype(np.float64) - of).max() <= 6e-8
         finally:
             pyr._h = ctypes.c_void_p()  # owned by the batch
+
+
+def test_batch_graph_replays_match_eager(monkeypatch):
+    """The captured graph gives the eager batch's detections on every replay,
+    with eager work and new image contents between replays; the search's
+    work list (XCD-binned, longest first) changes nothing either."""
+    P = _P()
+    case("batch graph replays")
+    cfg = synth.CONFIGS[2]
+    scenes = [synth.scene_for_config(2, i) for i in range(4)]
+    rng = np.random.default_rng(4244)
+    m2 = synth.render_model(synth.make_model_shape("polygon", 80, rng), 80)
+    models = [P.Model(scenes[0].model, 4, cfg["tau_m"]), P.Model(m2, 4, cfg["tau_m"])]
+    sp = P.SearchParams(theta_step_top=2.0)
+    images = [torch.from_numpy(s.image).cuda() for s in scenes[:3]]
+    b = P.Batch(models, images, 4, cfg["tau_s"], sp, precision=1)
+    b.run()
+    eager = b.results()
+    monkeypatch.setenv("TM_DENSE_WORKLIST", "0")
+    b0 = P.Batch(models, images, 4, cfg["tau_s"], sp, precision=1)
+    b0.run()
+    plain = b0.results()
+    assert all(_poses_equal(a, c) for a, c in zip(eager, plain))
+    for r in range(3):
+        b.out.zero_()
+        b.n_out.zero_()
+        torch.cuda.synchronize()
+        b.run(graph=True)
+        torch.cuda.synchronize()
+        got = b.results()
+        assert all(_poses_equal(a, c) for a, c in zip(got, eager)), r
+    images[0].copy_(torch.from_numpy(scenes[3].image).cuda())
+    b0.run()
+    ref = b0.results()
+    b.run(graph=True)
+    got = b.results()
+    assert all(_poses_equal(a, c) for a, c in zip(got, ref))
