@@ -9,11 +9,21 @@ before timing starts.
 
 Two legs, as the metric asks: FP32 plain (one detection per call, timed as
 a side measurement) and the batched path (the timed steps): a step is one
-enqueue of all --batch images (FP16 direction storage with FP32 accumulation
-by default).  Prints one JSON line; `value` is pose evaluations per second of
-the batched leg (exhaustive top-level poses; refinement adds 27 x candidates x
-3 per detection and is not counted); the plain leg, detections/s, taps/s and
-the agreement of top-1 poses between the legs are given beside it.
+graph launch of all --batch images (FP16 direction storage with FP32
+accumulation by default).  Prints one JSON line; `value` is pose evaluations
+per second of the batched leg (exhaustive top-level poses; refinement adds 27
+x candidates x 3 per detection and is not counted); the plain leg,
+detections/s, taps/s and the agreement of top-1 poses between the legs are
+given beside it.  The search kernel's own duration (for the roofline entry)
+comes from HIP events around its launches in a few eager batched steps after
+the timed region, on the same stream.
+
+--c4 adds the mixed batch (64 images of 640x480 to 2448x2048 against 8 models,
+one graph launch per step) and the continuous refinement of 4096 poses over
+its pairs (10 ascent steps).  --copy-probe ends the run with one 256 MiB
+elementwise copy, the calibration of the HBM byte counters; --traffic-from
+turns two rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE) into the committed
+per-launch traffic figure of the search kernel.
 """
 from __future__ import annotations
 
@@ -43,7 +53,56 @@ def parse():
                     help="direction storage of the batched leg (fp16: FP32 accumulation)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="time budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--eager", action="store_true", help="batched leg as plain enqueues instead of a graph launch")
+    ap.add_argument("--c4", action="store_true", help="also time the 64 x 8 mixed batch and the C5 refinement")
+    ap.add_argument("--copy-probe", action="store_true", help="end with a 256 MiB elementwise copy (counter scale)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the search kernel's traffic entry from two rocprofv3 --pmc CSV files and exit")
     return ap.parse_args()
+
+
+COPY_PROBE_BYTES = 256 << 20
+KERNEL_SRC = os.path.join(ROOT, "paper_2112_05576_amd", "csrc", "k_score.hip")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "dense_c2_traffic.json")
+
+
+def _pmc_rows(path, counter):
+    """(kernel name, value) per dispatch of one counter, in dispatch order."""
+    import csv
+
+    rows = []
+    for r in csv.DictReader(open(path)):
+        if r.get("Counter_Name") == counter:
+            rows.append((int(r.get("Dispatch_Id", len(rows))), r.get("Kernel_Name", ""), float(r["Counter_Value"]),
+                         int(r.get("Grid_Size", 0))))
+    rows.sort()
+    return [(n, v, g) for _, n, v, g in rows]
+
+
+def traffic_from(fetch_csv, write_csv):
+    """HBM bytes per launch of the search kernel: its FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads
+    for the final 256 MiB elementwise copy of --copy-probe (read 256 MiB,
+    write 256 MiB)."""
+    out = {"kernel_sha256": hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()}
+    for key, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        rows = _pmc_rows(path, counter)
+        probe_name, probe, _ = rows[-1]
+        if "elementwise" not in probe_name:
+            raise SystemExit(f"last dispatch in {path} is not the copy probe: {probe_name[:80]}")
+        # the batched launches: the search dispatches with the largest grid
+        grids = [g for n, _, g in rows if "k_dense_fast" in n]
+        if not grids:
+            raise SystemExit(f"no k_dense_fast dispatch in {path}")
+        dense = [v for n, v, g in rows if "k_dense_fast" in n and g == max(grids)]
+        scale = COPY_PROBE_BYTES / probe  # bytes per counted KiB
+        out[key] = {"kib_per_launch": sum(dense) / len(dense), "probe_kib": probe, "scale_bytes_per_kib": scale,
+                    "bytes_per_launch": sum(dense) / len(dense) * scale, "launches": len(dense)}
+    out["bytes_per_launch"] = out["fetch"]["bytes_per_launch"] + out["write"]["bytes_per_launch"]
+    os.makedirs(os.path.dirname(TRAFFIC_JSON), exist_ok=True)
+    with open(TRAFFIC_JSON, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
 
 
 def cpu_baseline(scenes, cfg, budget_s):
@@ -69,14 +128,13 @@ def cpu_baseline(scenes, cfg, budget_s):
             "sample": f"{n_img} full detections of 640x480 images (4 levels, 360 top angles), {dt:.1f} s"}
 
 
-def traffic_entry(kernel_src):
+def traffic_entry():
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
     taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "dense_c2_traffic.json")
-    if not os.path.exists(path):
+    if not os.path.exists(TRAFFIC_JSON):
         return None
-    d = json.load(open(path))
-    h = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()
+    d = json.load(open(TRAFFIC_JSON))
+    h = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
     if d.get("kernel_sha256") != h:
         return None
     return d.get("bytes_per_launch")
@@ -87,8 +145,82 @@ def gt_hit(d, sc):
                               abs((d[0]["theta"] - it.theta + 180) % 360 - 180) <= 2.0 for it in sc.instances)
 
 
+def _ang(a, b):
+    return np.abs((a - b + 180.0) % 360.0 - 180.0)
+
+
+def c4_legs(P, torch, steps, warmup):
+    """The mixed batch (FP16, graph launch) and the continuous refinement."""
+    import synth
+
+    cfg = synth.C4
+    L = cfg["levels"]
+    mods = [synth.c4_model(k) for k in range(len(synth.C4_MODELS))]
+    scenes = [synth.c4_image(i, [m[0] for m in mods]) for i in range(cfg["n_images"])]
+    models = [P.Model(m[1], L, cfg["tau_m"]) for m in mods]
+    imgs = [torch.from_numpy(s.image).cuda() for s in scenes]
+    sp = P.SearchParams(theta_step_top=cfg["theta_step_top"])
+    K = int(np.ceil(360.0 / cfg["theta_step_top"]))
+    b = P.Batch(models, imgs, L, cfg["tau_s"], sp, precision=P.TM_FP16)
+    for _ in range(warmup):
+        b.run(graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.run(graph=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    res = b.results()
+    nm = len(models)
+    poses = sum((s.image.shape[0] >> (L - 1)) * (s.image.shape[1] >> (L - 1)) for s in scenes) * nm * K
+    taps = sum((s.image.shape[0] >> (L - 1)) * (s.image.shape[1] >> (L - 1)) * m.level_info(L - 1)[2]
+               for s in scenes for m in models) * K * 9
+    found = total = 0
+    for i, s in enumerate(scenes):
+        for it, k in zip(s.instances, s.models):
+            total += 1
+            d = res[i * nm + k]
+            found += any(np.hypot(x["x"] - it.x, x["y"] - it.y) <= 2.0 and _ang(x["theta"], it.theta) <= 2.0
+                         for x in d)
+    c4 = {"workload": f"{len(scenes)} images (640x480 / 1280x1024 / 2448x2048) x {nm} models "
+                      f"({', '.join(str(m.level_info(0)[2]) for m in models)} level-0 points), FP16, graph launch",
+          "ms_per_step": dt * 1e3, "detections_per_sec": len(scenes) * nm / dt, "pose_evals_per_sec": poses / dt,
+          "taps_per_sec": taps / dt, "instances_found": f"{found}/{total}"}
+    # C5: 4096 poses near the truth, 10 ascent steps on FP32 fields
+    b32 = P.Batch(models, imgs, L, cfg["tau_s"], sp, precision=P.TM_FP32)
+    b32.run()
+    img_i, mod_i, start, truth = synth.c5_poses(scenes)
+    pairs = torch.from_numpy(img_i * nm + mod_i).cuda()
+    st = torch.from_numpy(start.astype(np.float32)).cuda()
+    b32.refine_continuous(st, pairs, steps=10)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        newp, _ = b32.refine_continuous(st, pairs, steps=10)
+    torch.cuda.synchronize()
+    dt5 = (time.perf_counter() - t0) / reps
+    newp = newp.cpu().numpy().astype(np.float64)
+    e0 = np.abs(start - truth)
+    e1 = np.abs(newp - truth)
+    e0[:, 2], e1[:, 2] = _ang(start[:, 2], truth[:, 2]), _ang(newp[:, 2], truth[:, 2])
+
+    def stats(e):
+        return {k: {"mean": float(e[:, j].mean()), "p95": float(np.percentile(e[:, j], 95)),
+                    "max": float(e[:, j].max())} for j, k in enumerate(("dx", "dy", "dtheta_deg"))}
+
+    c5 = {"workload": "4096 poses of the mixed batch's instances, +-1.5 px / +-2 deg, 10 ascent steps (gradient "
+                      "kernel + FP64 line search of 6 step lengths per step)",
+          "ms_per_refinement": dt5 * 1e3, "poses_per_sec": len(start) / dt5,
+          "error_start": stats(e0), "error_refined": stats(e1)}
+    return c4, c5
+
+
 def main():
     args = parse()
+    if args.traffic_from:
+        traffic_from(*args.traffic_from)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is single-GPU by design.",
               file=sys.stderr)
@@ -141,25 +273,29 @@ def main():
 
     # ---- leg 2 (the timed steps): all images in one batched enqueue
     batch = P.Batch([model], imgs, L, cfg["tau_s"], sp, precision=prec_b)
+    graph = not args.eager
     for _ in range(args.warmup):
-        batch.run()
-    torch.cuda.synchronize()
-    P.timing_read()
-    P.timing_enable(True)
+        batch.run(graph=graph)
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record(stream)
     for _ in range(args.steps):
-        batch.run()
+        batch.run(graph=graph)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    P.timing_enable(False)
-    dense_ms, launches = P.timing_read()
     elapsed = max(wall, ev0.elapsed_time(ev1) / 1e3)
     bdets = batch.results()
+    # the search kernel's duration: HIP events around its launches (same stream)
+    P.timing_read()
+    P.timing_enable(True)
+    for _ in range(max(5, min(args.steps, 20))):
+        batch.run()
+    torch.cuda.synchronize()
+    P.timing_enable(False)
+    dense_ms, launches = P.timing_read()
 
     same_top1 = sum(1 for a, b in zip(plain_dets, bdets)
                     if len(a) and len(b) and (int(a[0]["x"]), int(a[0]["y"]), int(a[0]["k"])) ==
@@ -170,7 +306,6 @@ def main():
     dense_avg_s = dense_ms / max(launches, 1) / 1e3
     flops = taps_per_det * nb * FLOP_PER_TAP
     achieved = flops / dense_avg_s / 1e12
-    kernel_src = os.path.join(ROOT, "paper_2112_05576_amd", "csrc", "k_score.hip")
     dets_per_s = nb * args.steps / elapsed
     res = {
         "metric": "pose-evals/sec and detections/sec at 640x480 (FP32 plain vs FP16 batched, equal top-1)",
@@ -188,7 +323,7 @@ def main():
         "config": {"workload": f"{nb} images of 640x480 (3 instances of a 128x128 polygon model each) per step, "
                                "4 levels, 1 deg top step (80x60x360 top poses per image), full detection",
                    "images_per_step": nb, "levels": L, "top_angles": K, "model_points_top": n_top,
-                   "path": f"{args.precision}-batched"},
+                   "path": f"{args.precision}-batched" + ("" if args.eager else ", graph launch")},
         "detections_per_sec": dets_per_s,
         "taps_per_sec": taps_per_det * dets_per_s,
         "fp32_plain": {"pose_evals_per_sec": poses_per_det * plain_steps / plain_s,
@@ -199,11 +334,19 @@ def main():
         "top1_ground_truth_hits": {"fp32_plain": f"{hits_plain}/{nb}", "batched": f"{hits_batch}/{nb}"},
         "roofline": {"kernel": "k_dense_fast (exhaustive top-level search, all images of the step)", "bound": "alu",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_entry(kernel_src),
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_entry(),
                      "launch_us": dense_avg_s * 1e6, "flop_per_launch": flops},
     }
+    if args.c4:
+        res["c4"], res["c5"] = c4_legs(P, torch, max(2, args.steps // 10), 1)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(scenes[:8], cfg, args.cpu_seconds)
+    if args.copy_probe:
+        x = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        torch.neg(x, out=y)
+        torch.cuda.synchronize()
     print(json.dumps(res), flush=True)
 
 
