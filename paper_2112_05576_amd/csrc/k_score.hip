@@ -60,7 +60,48 @@ __device__ __forceinline__ float hmax3(float v)
     }
 }
 
+// Eight window maxima at once (the strip's rows): two v_max_f32 with a DPP
+// source per row, one s_nop 1 ahead of them for the two wait states a DPP
+// read needs after a VALU write of its source.
+__device__ __forceinline__ void hmax3x8(const float (&v)[8], float (&m)[8])
+{
+    asm("s_nop 1\n\t"
+        "v_max_f32_dpp %0, %8, %8 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_max_f32_dpp %1, %9, %9 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_max_f32_dpp %2, %10, %10 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_max_f32_dpp %3, %11, %11 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_max_f32_dpp %4, %12, %12 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_max_f32_dpp %5, %13, %13 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_max_f32_dpp %6, %14, %14 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_max_f32_dpp %7, %15, %15 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_max_f32_dpp %0, %8, %0 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_max_f32_dpp %1, %9, %1 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_max_f32_dpp %2, %10, %2 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_max_f32_dpp %3, %11, %3 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_max_f32_dpp %4, %12, %4 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_max_f32_dpp %5, %13, %5 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_max_f32_dpp %6, %14, %6 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+        "v_max_f32_dpp %7, %15, %7 wave_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "=&v"(m[0]), "=&v"(m[1]), "=&v"(m[2]), "=&v"(m[3]), "=&v"(m[4]), "=&v"(m[5]), "=&v"(m[6]), "=&v"(m[7])
+        : "v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(v[4]), "v"(v[5]), "v"(v[6]), "v"(v[7]));
+}
+
 typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+
+// The rotated table as seen by the search kernel: read through the constant
+// address space, so that the wave-uniform entries arrive by scalar loads.
+typedef const __attribute__((address_space(4))) TabEntry CTabEntry;
+
+__device__ __forceinline__ TabEntry tab_entry(CTabEntry* t)
+{
+    TabEntry e;
+    e.qx = t->qx;
+    e.qy = t->qy;
+    e.rx = t->rx;
+    e.ry = t->ry;
+    e.rh = t->rh;
+    return e;
+}
 
 // Storage of one field pixel in the LDS tile and its dot product with a
 // table entry's rotated direction: FP32 pairs, or FP16 pairs with the
@@ -73,6 +114,11 @@ struct Px<TM_FP32> {
     static __device__ __forceinline__ T zero() { return make_float2(0.f, 0.f); }
     static __device__ __forceinline__ T load(const void* f, size_t o) { return reinterpret_cast<const float2*>(f)[o]; }
     static __device__ __forceinline__ float dot(const TabEntry& e, T g) { return e.rx * g.x + e.ry * g.y; }
+    template <bool ASM>
+    static __device__ __forceinline__ float dot_t(const TabEntry& e, T g)
+    {
+        return dot(e, g);
+    }
 };
 template <>
 struct Px<TM_FP16> {
@@ -82,6 +128,19 @@ struct Px<TM_FP16> {
     static __device__ __forceinline__ float dot(const TabEntry& e, T g)
     {
         return __builtin_amdgcn_fdot2(__builtin_bit_cast(h2_t, e.rh), __builtin_bit_cast(h2_t, g), 0.0f, false);
+    }
+    // ASM: the VOP3P form with an inline zero addend (the builtin becomes
+    // v_dot2c with an accumulator cleared by a move per product).
+    template <bool ASM>
+    static __device__ __forceinline__ float dot_t(const TabEntry& e, T g)
+    {
+        if constexpr (ASM) {
+            float d;
+            asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(d) : "s"(e.rh), "v"(g));
+            return d;
+        } else {
+            return dot(e, g);
+        }
     }
 };
 
@@ -94,7 +153,10 @@ struct FastArgs {
     const int2* work;   // optional work list: block b runs (pair, block) work[b]; pair < 0: nothing
 };
 
-template <int G, int R, int LC, int PREC, bool ASM>
+// VAR: 0 compiler-built products and window maxima; 1 the same with the
+// VOP3P dot and the DPP-folded maxima written out; 2, 3, 4 as 1 with 2, 4, 8
+// table entries fetched per loop step (one scalar-load wait per step).
+template <int G, int R, int LC, int PREC, int VAR>
 __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc* __restrict__ pairs)
 {
     using T = typename Px<PREC>::T;
@@ -137,7 +199,7 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc*
     const int seg = lane / G, li = lane - seg * G;
     const int row0 = (wy * NS + seg) * R;  // first output row of the strip, tile-relative
     const T* lbase = tile + (halo - 1 + row0) * LC + (halo - 1 + li);
-    const TabEntry* __restrict__ tab = P.tab;
+    CTabEntry* tab = (CTabEntry*)P.tab;
     const int n_pad = P.n_pad;
     const float n_f = (float)P.n[a.level];
 
@@ -151,7 +213,7 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc*
     }
     const int k0 = chunk * a.A, k1 = min(a.K, k0 + a.A);
     for (int k = k0 + wa; k < k1; k += a.WA) {
-        const TabEntry* __restrict__ Tb = tab + (size_t)k * n_pad;
+        CTabEntry* Tb = tab + (size_t)k * n_pad;
         float tw[R], t1[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -166,21 +228,47 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc*
                 p1[r] = 0.f;
             }
             const int i1 = min(n_pad, i0 + kBlock);
-#pragma unroll 2
-            for (int i = i0; i < i1; ++i) {
-                const TabEntry e = Tb[i];
+            constexpr bool ASM = VAR > 0;
+            // one point: its R+2 products down the strip, the vertical then
+            // the horizontal window maxima, added in point order
+            auto point = [&](const TabEntry& e) {
                 const T* p = lbase + (int)e.qy * LC + (int)e.qx;
                 float D[R + 2];
 #pragma unroll
-                for (int rr = 0; rr < R + 2; ++rr) D[rr] = Px<PREC>::dot(e, p[rr * LC]);
+                for (int rr = 0; rr < R + 2; ++rr) D[rr] = Px<PREC>::template dot_t<ASM>(e, p[rr * LC]);
                 float V[R];
 #pragma unroll
                 for (int r = 0; r < R; ++r) V[r] = fmaxf(fmaxf(D[r], D[r + 1]), D[r + 2]);
+                if constexpr (ASM && R == 8) {
+                    float M[R];
+                    hmax3x8(V, M);
 #pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    pw[r] += hmax3<ASM>(V[r]);
-                    p1[r] += D[r + 1];
+                    for (int r = 0; r < R; ++r) {
+                        pw[r] += M[r];
+                        p1[r] += D[r + 1];
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        pw[r] += hmax3<ASM>(V[r]);
+                        p1[r] += D[r + 1];
+                    }
                 }
+            };
+            if constexpr (VAR >= 2) {
+                // U entries fetched together, then U points in order; block
+                // lengths are multiples of 8 (the table is padded to 8)
+                constexpr int U = VAR == 2 ? 2 : (VAR == 3 ? 4 : 8);
+                for (int i = i0; i < i1; i += U) {
+                    TabEntry e[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) e[u] = tab_entry(Tb + i + u);
+#pragma unroll
+                    for (int u = 0; u < U; ++u) point(e[u]);
+                }
+            } else {
+#pragma unroll 2
+                for (int i = i0; i < i1; ++i) point(tab_entry(Tb + i));
             }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -412,7 +500,7 @@ constexpr int kLC[] = {64, 96, 128, 192, 256};
 // Launch-shape knobs of the search kernel: waves stacked in y per workgroup,
 // waves splitting the angle chunk, angles per wave, and the window-max form.
 // Defaults can be overridden by TM_DENSE_WY / TM_DENSE_WA / TM_DENSE_APW /
-// TM_DENSE_ASM (tuning runs).
+// TM_DENSE_ASM (0 to 4: the search kernel variant; tuning runs).
 int knob(const char* name, int dflt, int lo, int hi)
 {
     const char* v = getenv(name);
@@ -423,31 +511,43 @@ int knob(const char* name, int dflt, int lo, int hi)
 
 // d == nullptr: only raise the kernel's LDS limit (done once, before any
 // launch, so that no attribute call happens while a stream is captured).
-template <int G, int R, int LC, int PREC, bool ASM>
+template <int G, int R, int LC, int PREC, int VAR>
 hipError_t launch_fast_t(const DensePlan& p, const FastArgs& a, const PairDesc* d, int npairs, hipStream_t s)
 {
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dense_fast<G, R, LC, PREC, ASM>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dense_fast<G, R, LC, PREC, VAR>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
     if (!d) return hipSuccess;
     const dim3 grid = a.work ? dim3(p.n_work) : dim3(p.max_blocks, npairs);
-    hipLaunchKernelGGL((k_dense_fast<G, R, LC, PREC, ASM>), grid, dim3(64 * p.WY * p.WA), p.lds, s, a, d);
+    hipLaunchKernelGGL((k_dense_fast<G, R, LC, PREC, VAR>), grid, dim3(64 * p.WY * p.WA), p.lds, s, a, d);
     return hipGetLastError();
 }
 
-template <int PREC, bool ASM>
+template <int PREC, int VAR>
 hipError_t launch_fast_p(const DensePlan& p, const FastArgs& a, const PairDesc* d, int npairs, hipStream_t s)
 {
     switch (p.LC) {
-        case 64: return launch_fast_t<32, 8, 64, PREC, ASM>(p, a, d, npairs, s);
-        case 96: return launch_fast_t<32, 8, 96, PREC, ASM>(p, a, d, npairs, s);
-        case 128: return launch_fast_t<32, 8, 128, PREC, ASM>(p, a, d, npairs, s);
-        case 192: return launch_fast_t<32, 8, 192, PREC, ASM>(p, a, d, npairs, s);
-        default: return launch_fast_t<32, 8, 256, PREC, ASM>(p, a, d, npairs, s);
+        case 64: return launch_fast_t<32, 8, 64, PREC, VAR>(p, a, d, npairs, s);
+        case 96: return launch_fast_t<32, 8, 96, PREC, VAR>(p, a, d, npairs, s);
+        case 128: return launch_fast_t<32, 8, 128, PREC, VAR>(p, a, d, npairs, s);
+        case 192: return launch_fast_t<32, 8, 192, PREC, VAR>(p, a, d, npairs, s);
+        default: return launch_fast_t<32, 8, 256, PREC, VAR>(p, a, d, npairs, s);
+    }
+}
+
+template <int PREC>
+hipError_t launch_fast_v(const DensePlan& p, const FastArgs& a, const PairDesc* d, int npairs, hipStream_t s)
+{
+    switch (p.variant) {
+        case 1: return launch_fast_p<PREC, 1>(p, a, d, npairs, s);
+        case 2: return launch_fast_p<PREC, 2>(p, a, d, npairs, s);
+        case 3: return launch_fast_p<PREC, 3>(p, a, d, npairs, s);
+        case 4: return launch_fast_p<PREC, 4>(p, a, d, npairs, s);
+        default: return launch_fast_p<PREC, 0>(p, a, d, npairs, s);
     }
 }
 
@@ -473,7 +573,7 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
         p.max_np = max(p.max_np, g[i].gw * g[i].gh);
     }
     p.fast = s.sx == 1 && s.sy == 1 && s.win == 3;
-    p.asm_dpp = knob("TM_DENSE_ASM", 0, 0, 1) != 0;
+    p.variant = knob("TM_DENSE_ASM", 0, 0, 4);
     if (p.fast) {
         p.G = 32;
         p.R = 8;
@@ -582,10 +682,8 @@ hipError_t prepare_dense(const SearchDesc& s, const DensePlan& p)
     if (!p.fast) return hipSuccess;
     FastArgs a = {};
     if (s.precision == TM_FP16)
-        return p.asm_dpp ? launch_fast_p<TM_FP16, true>(p, a, nullptr, 0, nullptr)
-                         : launch_fast_p<TM_FP16, false>(p, a, nullptr, 0, nullptr);
-    return p.asm_dpp ? launch_fast_p<TM_FP32, true>(p, a, nullptr, 0, nullptr)
-                     : launch_fast_p<TM_FP32, false>(p, a, nullptr, 0, nullptr);
+        return launch_fast_v<TM_FP16>(p, a, nullptr, 0, nullptr);
+    return launch_fast_v<TM_FP32>(p, a, nullptr, 0, nullptr);
 }
 
 hipError_t launch_dense(const SearchDesc& s, const DensePlan& p, const PairDesc* d, int npairs, hipStream_t st,
@@ -606,11 +704,9 @@ hipError_t launch_dense(const SearchDesc& s, const DensePlan& p, const PairDesc*
         a.C = p.C;
         a.work = p.work;
         if (s.precision == TM_FP16)
-            e = p.asm_dpp ? launch_fast_p<TM_FP16, true>(p, a, d, npairs, st)
-                          : launch_fast_p<TM_FP16, false>(p, a, d, npairs, st);
+            e = launch_fast_v<TM_FP16>(p, a, d, npairs, st);
         else
-            e = p.asm_dpp ? launch_fast_p<TM_FP32, true>(p, a, d, npairs, st)
-                          : launch_fast_p<TM_FP32, false>(p, a, d, npairs, st);
+            e = launch_fast_v<TM_FP32>(p, a, d, npairs, st);
     } else {
         GenericArgs a;
         a.level = s.level;

@@ -173,7 +173,8 @@ struct SearchDesc {
 
 // Launch plan of the exhaustive search, common to all pairs.
 struct DensePlan {
-    bool fast, asm_dpp;
+    bool fast;
+    int variant;                // search kernel form (k_dense_fast VAR)
     int G, R, LC, WY, WA;
     int A, C;                   // angles per workgroup, chunks of angles
     size_t lds;
