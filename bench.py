@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eager", action="store_true", help="batched leg as plain enqueues instead of a graph launch")
     ap.add_argument("--c4", action="store_true", help="also time the 64 x 8 mixed batch and the C5 refinement")
+    ap.add_argument("--paper", action="store_true",
+                    help="also time the paper's own search shape (812x617, 3 px / 3 deg steps, 90 deg, one level)")
     ap.add_argument("--copy-probe", action="store_true", help="end with a 256 MiB elementwise copy (counter scale)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the search kernel's traffic entry from two rocprofv3 --pmc CSV files and exit")
@@ -216,6 +218,54 @@ def c4_legs(P, torch, steps, warmup):
     return c4, c5
 
 
+def paper_leg(P, torch, steps, with_oracle):
+    """The search of the paper's experiment on synthetic 812x617 frames: every
+    3rd pixel, 31 angles over 90 degrees, one level, the single best pose;
+    one tm_detect per frame (FP32, the generic search path)."""
+    import synth
+
+    scenes = [synth.scene_for_config(6, i) for i in range(8)]
+    cfg = scenes[0].config
+    imgs = [torch.from_numpy(s.image).cuda() for s in scenes]
+    model = P.Model(scenes[0].model, 1, cfg["tau_m"])
+    kw = dict(step_x=3, step_y=3, theta_min=0.0, theta_range=90.0, theta_step_top=3.0, max_matches=1)
+    sp = P.SearchParams(**kw)
+    pyr = P.Pyramid(imgs[0], 1, cfg["tau_s"])
+    outs = torch.empty((len(imgs), 1, P.tm.POSE_WORDS), dtype=torch.int32, device="cuda")
+    nout = torch.zeros((len(imgs),), dtype=torch.int32, device="cuda")
+
+    def one(i):
+        j = i % len(imgs)
+        pyr.update(imgs[j])
+        P.detect_async(model, pyr, sp, outs[j], nout[j:j + 1])
+
+    for i in range(len(imgs)):
+        one(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        one(i)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    dets = [P.poses_to_numpy(outs[j], int(nout[j].item())) for j in range(len(imgs))]
+    hits = sum(gt_hit(d, sc) for d, sc in zip(dets, scenes))
+    poses = 271 * 206 * 31
+    res = {"workload": "812x617 frames, 1 instance of a 96x96 polygon model (847 points), steps 3 px / 3 px / 3 deg "
+                       "over 90 deg (271x206x31 poses), 1 level, best pose; FP32, one detection per call",
+           "ms_per_detection": dt * 1e3, "pose_evals_per_sec": poses / dt, "top1_ground_truth_hits":
+           f"{hits}/{len(imgs)}"}
+    if with_oracle:
+        import oracle as O
+
+        osp = O.SearchParams(**kw)
+        t0 = time.perf_counter()
+        O.detect(scenes[0].image, scenes[0].model, O.PyrParams(1, cfg["tau_s"]), O.PyrParams(1, cfg["tau_m"]), osp,
+                 nthreads=O.default_threads())
+        res["oracle_ms_per_detection"] = (time.perf_counter() - t0) * 1e3
+        res["oracle_threads"] = O.default_threads()
+    return res
+
+
 def main():
     args = parse()
     if args.traffic_from:
@@ -339,6 +389,8 @@ def main():
     }
     if args.c4:
         res["c4"], res["c5"] = c4_legs(P, torch, max(2, args.steps // 10), 1)
+    if args.paper:
+        res["paper_shape"] = paper_leg(P, torch, max(8, args.steps), not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(scenes[:8], cfg, args.cpu_seconds)
     if args.copy_probe:

@@ -212,15 +212,16 @@ def _clutter(img, rng, count):
 def render_scene(rng: np.random.Generator, W: int, H: int, shape: Shape, model_size: int,
                  n_inst: int, noise: float, occl_max: float = 0.0, gain=(1.0, 1.0),
                  offset=(0.0, 0.0), clutter: int = 0, fg: float = 200.0, bg: float = 40.0,
-                 cfg: dict | None = None) -> Scene:
-    """Render n_inst posed instances, then apply the distortions in order:
-    occluders, global gain and offset, clutter, Gaussian noise, clip and round."""
+                 cfg: dict | None = None, theta_max: float = 360.0) -> Scene:
+    """Render n_inst posed instances (angles U[0, theta_max)), then apply the
+    distortions in order: occluders, global gain and offset, clutter, Gaussian
+    noise, clip and round."""
     img = np.full((H, W), bg, np.float64)
     taken = []
     spots = _place(rng, W, H, shape.radius, n_inst, taken)
     inst = []
     for (x, y) in spots:
-        th = float(rng.uniform(0.0, 360.0))
+        th = float(rng.uniform(0.0, theta_max))
         _paint_instance(img, shape, x, y, th, fg)
         inst.append(Instance(float(x), float(y), th))
     if occl_max > 0:
@@ -260,6 +261,15 @@ CONFIGS = {
     3: dict(name="C3 2048x2048 large frame", W=2048, H=2048, model_size=256, shape="polygon", n_inst=5,
             noise=8.0, occl=0.40, gain=(0.5, 2.0), offset=(-40.0, 40.0), clutter=50, levels=5,
             tau_m=30.0, tau_s=80.0, theta_step_top=8.0, theta_range=360.0),
+    # The paper's own experiment (Sec. III): 812x617 frames, search over every
+    # 3rd pixel in x and y and 90 degrees in 3 degree steps, one level, one best
+    # pose.  Its Basler samples are not available; this stands in for them with
+    # one instance of a 96x96 polygon model at an angle inside the range and
+    # the C2 distortions.
+    6: dict(name="paper-shaped 812x617", W=812, H=617, model_size=96, shape="polygon", n_inst=1,
+            noise=8.0, occl=0.30, gain=(0.5, 2.0), offset=(-40.0, 40.0), clutter=50, levels=1,
+            tau_m=30.0, tau_s=80.0, theta_step_top=3.0, theta_range=90.0, step_xy=3, theta_max_inst=90.0,
+            max_matches=1),
 }
 
 
@@ -357,7 +367,8 @@ def scene_for_config(ci: int, index: int = 0, **override) -> Scene:
     shape_rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(BASE_SEED + ci, spawn_key=(10**6,))))
     shape = make_model_shape(cfg["shape"], cfg["model_size"], shape_rng)
     return render_scene(rng, cfg["W"], cfg["H"], shape, cfg["model_size"], cfg["n_inst"], cfg["noise"],
-                        cfg["occl"], cfg["gain"], cfg["offset"], cfg["clutter"], cfg=cfg)
+                        cfg["occl"], cfg["gain"], cfg["offset"], cfg["clutter"], cfg=cfg,
+                        theta_max=cfg.get("theta_max_inst", 360.0))
 
 
 def paste_rot90(model: np.ndarray, W: int, H: int, ux: int, uy: int, quarter: int, bg: int = 40) -> np.ndarray:

@@ -557,3 +557,24 @@ def test_batch_graph_replays_match_eager(monkeypatch):
     b.run(graph=True)
     got = b.results()
     assert all(_poses_equal(a, c) for a, c in zip(got, ref))
+
+
+@pytest.mark.parametrize("index", [0, 1, 2])
+def test_paper_shaped_search_matches_oracle(index):
+    """The paper's own search (812x617, every 3rd pixel, 90 degrees in 3 degree
+    steps, one level, one best pose) on the generic search path."""
+    P = _P()
+    sc = synth.scene_for_config(6, index)
+    cfg = sc.config
+    case(f"paper-shaped frame {index}")
+    kw = dict(step_x=3, step_y=3, theta_min=0.0, theta_range=90.0, theta_step_top=3.0, max_matches=1)
+    osp = O.SearchParams(**kw)
+    tr = O.detect(sc.image, sc.model, O.PyrParams(1, cfg["tau_s"]), O.PyrParams(1, cfg["tau_m"]), osp)
+    gm = P.Model(sc.model, 1, cfg["tau_m"])
+    pyr = P.Pyramid(sc.image, 1, cfg["tau_s"])
+    got = P.detect(gm, pyr, P.SearchParams(**kw))
+    ref = tr.detections
+    print(f"GPU {[(int(d['x']), int(d['y']), int(d['k']), float(d['sw'])) for d in got]}")
+    print(f"FP64 {[(d.x, d.y, d.k, d.sw) for d in ref]}, truth {sc.instances}")
+    assert len(got) == len(ref) == 1
+    _match_detections(got, ref, tr.fields, tr.model, osp, 1)
