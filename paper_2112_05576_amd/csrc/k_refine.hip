@@ -4,15 +4,21 @@
 // (2x + a, 2y + b, 2k + c), a, b, c in {-1, 0, 1}, with the same windowed
 // score (Eq. 1) and keeping the best by the selection key.
 //
-// One launch per level.  The grid is (candidate x angle c x chunk of model
-// points, pair), so that a level spreads over hundreds of workgroups.  A
-// workgroup first picks its candidate's pose at the level above from that
-// level's partial sums (every workgroup of the candidate makes the same pick,
-// in the same order), then forms q_i and r_i of its points in FP64, reads the
-// 5x5 field block covering the 3x3 windows of the 9 translations with all 25
-// loads in flight, and accumulates 9 windowed votes and 9 centre votes.  Sums
-// are combined by a fixed butterfly per wave and in wave order across the
-// workgroup, then across chunks in chunk order at the pick.
+// One pass per level, by one of two kernels with the same arithmetic:
+//  * k_refine_level, one workgroup per (candidate, angle c): each thread takes
+//    every 256th model point, forms q_i and r_i in FP64, reads the 5x5 field
+//    block covering the 3x3 windows of the 9 translations straight from
+//    memory (two points' 50 loads in flight), and accumulates 9 windowed and
+//    9 centre votes;
+//  * k_refine_tile, one workgroup per candidate: the candidate's whole field
+//    block (side 2 rad + 5 around (2x, 2y)) is first staged in LDS with
+//    coalesced loads, then the three angles are scored as above with the taps
+//    read from LDS.
+// A thread adds its points in increasing order and the workgroup combines the
+// threads by a fixed butterfly per wave and the waves in order, in both
+// kernels, so their sums are bit-identical and a launch may take either (the
+// staged one pays off once a launch holds many candidates).  The next level
+// (or the final pick) picks the best of the 27 sums.
 #include "tm_device.h"
 
 namespace tmk {
@@ -21,26 +27,21 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
+constexpr size_t kTileMax = 128 * 1024;  // largest staged field block
 
 // Best of the 27 poses around (x, y, k) (a pose of level l+1) at level l, from
-// the partial sums part[g][chunk][m] (m < 9: S_w of translation m, m >= 9:
-// S_1).  Runs on one wave; every lane returns the result.
-__device__ void pick27(const float* __restrict__ part, int chunks, int x, int y, int k, int W, int H, int n, int K,
-                       int full, float* bw, float* b1, int* bx, int* by, int* bk)
+// the sums part[g][m] (m < 9: S_w of translation m, m >= 9: S_1).  Runs on
+// one wave; every lane returns the result.
+__device__ void pick27(const float* __restrict__ part, int x, int y, int k, int W, int H, int n, int K, int full,
+                       float* bw, float* b1, int* bx, int* by, int* bk)
 {
     const int lane = threadIdx.x & 63;
     const int m = lane < 27 ? lane : 26;
     const int g = m / 9, t = m % 9, b = t / 3, u = t % 3;
     const int kg = angle_index(2 * k + g - 1, K, full);
     const int xx = 2 * x + u - 1, yy = 2 * y + b - 1;
-    float sw = 0.f, s1 = 0.f;
-    for (int ch = 0; ch < chunks; ++ch) {
-        const float* p = part + ((size_t)g * chunks + ch) * 18;
-        sw += p[t];
-        s1 += p[9 + t];
-    }
-    sw /= (float)n;
-    s1 /= (float)n;
+    const float sw = part[g * 18 + t] / (float)n;
+    const float s1 = part[g * 18 + 9 + t] / (float)n;
     const bool ok = lane < 27 && xx >= 0 && yy >= 0 && xx < W && yy < H;
     float kw = ok ? sw : -INFINITY, k1 = ok ? s1 : -INFINITY;
     int kx = ok ? xx : 0x7fffffff, ky = ok ? yy : 0x7fffffff, kk = ok ? kg : 0x7fffffff;
@@ -63,149 +64,49 @@ __device__ void pick27(const float* __restrict__ part, int chunks, int x, int y,
     *bk = kk;
 }
 
-__device__ __forceinline__ int chunks_of(int n) { return (n + kThreads - 1) / kThreads; }
-
 struct LevelArgs {
     int level;             // l, the level scored
-    int max_chunks;        // largest chunk count of level l over the pairs (grid stride)
-    int pick;              // 1: pick the pose of level l+1 from its partials; 0: poses are given
+    int pick;              // 1: pick the pose of level l+1 from its sums; 0: poses are given
     int K, K_above;        // angles of levels l and l+1
     double step, step_above;
     int full, win, max_cand;
     double theta_min;
     int src;               // centre buffer read (0/1); the other one is written
+    int staged;            // pairs with rtile[level] set are refined by k_refine_tile
 };
 
-template <int PREC>
-__global__ __launch_bounds__(kThreads) void k_refine_level(LevelArgs a, const PairDesc* __restrict__ pairs)
+// The 9 windowed votes and 9 centre votes of one point from the 5x5 block of
+// field values around its projection (taps outside the image vote 0).
+__device__ __forceinline__ void votes5x5(const float2 (&gv)[5][5], const bool (&rin)[5], const bool (&cin)[5], float fx,
+                                         float fy, float (&aw)[9], float (&a1)[9])
 {
-    __shared__ float red[kWaves][18];
-    __shared__ int cur[3];
-    const PairDesc& P = pairs[blockIdx.y];
-    const int l = a.level;
-    const int chunks = chunks_of(P.n[l]);
-    const int chunk = blockIdx.x % a.max_chunks;
-    const int g = (blockIdx.x / a.max_chunks) % 3;
-    const int c = blockIdx.x / (a.max_chunks * 3);
-    if (chunk >= chunks) return;
-    int count = a.max_cand;
-    if (P.ncand) count = min(count, *P.ncand);
-    if (c >= count) return;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    float D[5][5];
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+        for (int u = 0; u < 5; ++u) {
+            const float d = fx * gv[v][u].x + fy * gv[v][u].y;
+            D[v][u] = (rin[v] && cin[u]) ? d : 0.0f;
+        }
+    float hm[5][3];
+#pragma unroll
+    for (int v = 0; v < 5; ++v)
+#pragma unroll
+        for (int u = 0; u < 3; ++u) hm[v][u] = fmaxf(fmaxf(D[v][u], D[v][u + 1]), D[v][u + 2]);
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            aw[b * 3 + u] += fmaxf(fmaxf(hm[b][u], hm[b + 1][u]), hm[b + 2][u]);
+            a1[b * 3 + u] += D[b + 1][u + 1];
+        }
+}
 
-    if (threadIdx.x < 64) {
-        int x, y, k;
-        float sw, s1;
-        if (a.pick) {
-            const tm_pose ctr = P.ctr[a.src][c];
-            const int la = l + 1;
-            pick27(P.part[la] + (size_t)c * 3 * chunks_of(P.n[la]) * 18, chunks_of(P.n[la]), ctr.x, ctr.y, ctr.k,
-                   P.W[la], P.H[la], P.n[la], a.K_above, a.full, &sw, &s1, &x, &y, &k);
-        } else {
-            const tm_pose p = P.cand[c];
-            x = p.x;
-            y = p.y;
-            k = p.k;
-            sw = p.score_w;
-            s1 = p.score_1;
-        }
-        if (lane == 0) {
-            cur[0] = x;
-            cur[1] = y;
-            cur[2] = k;
-            if (g == 0 && chunk == 0) {
-                tm_pose o;
-                o.x = x;
-                o.y = y;
-                o.k = k;
-                o.level = l + 1;
-                o.theta_deg = (float)level_theta(a.theta_min, a.step_above, k);
-                o.score_w = sw;
-                o.score_1 = s1;
-                o.reserved = 0;
-                P.ctr[a.src ^ 1][c] = o;
-            }
-        }
-    }
-    __syncthreads();
-    const int x = cur[0], y = cur[1], k = cur[2];
-    const void* field = P.field[l];
-    const int W = P.W[l], H = P.H[l], n = P.n[l];
-    const ModelPoint* __restrict__ pts = P.pts[l];
-    const int kc = angle_index(2 * k + g - 1, a.K, a.full);
-    double cs, sn;
-    sincos_deg(level_theta(a.theta_min, a.step, kc), &cs, &sn);
-    float aw[9], a1[9];
-#pragma unroll
-    for (int m = 0; m < 9; ++m) {
-        aw[m] = 0.f;
-        a1[m] = 0.f;
-    }
-    const int per = (n + chunks - 1) / chunks;
-    const int i0 = chunk * per, i1 = min(n, i0 + per);
-    const int wh = (a.win - 1) / 2;
-    for (int i = i0 + (int)threadIdx.x; i < i1; i += kThreads) {
-        int qx, qy;
-        double rx, ry;
-        project_point(pts[i], cs, sn, &qx, &qy, &rx, &ry);
-        const float fx = (float)rx, fy = (float)ry;
-        const int px = 2 * x + qx, py = 2 * y + qy;
-        if (wh == 1) {
-            // the 5x5 block covering the 3x3 windows of the 9 translations:
-            // all 25 loads are issued before any is used
-            int col[5];
-            size_t rowoff[5];
-            bool cin[5], rin[5];
-#pragma unroll
-            for (int u = 0; u < 5; ++u) {
-                const int xx = px - 2 + u, yy = py - 2 + u;
-                cin[u] = (unsigned)xx < (unsigned)W;
-                rin[u] = (unsigned)yy < (unsigned)H;
-                col[u] = min(max(xx, 0), W - 1);
-                rowoff[u] = (size_t)min(max(yy, 0), H - 1) * W;
-            }
-            float2 gv[5][5];
-#pragma unroll
-            for (int v = 0; v < 5; ++v)
-#pragma unroll
-                for (int u = 0; u < 5; ++u) gv[v][u] = field_load<PREC>(field, rowoff[v] + col[u]);
-            __builtin_amdgcn_sched_barrier(0);
-            float D[5][5];
-#pragma unroll
-            for (int v = 0; v < 5; ++v)
-#pragma unroll
-                for (int u = 0; u < 5; ++u) {
-                    const float d = fx * gv[v][u].x + fy * gv[v][u].y;
-                    D[v][u] = (rin[v] && cin[u]) ? d : 0.0f;
-                }
-            float hm[5][3];
-#pragma unroll
-            for (int v = 0; v < 5; ++v)
-#pragma unroll
-                for (int u = 0; u < 3; ++u) hm[v][u] = fmaxf(fmaxf(D[v][u], D[v][u + 1]), D[v][u + 2]);
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-#pragma unroll
-                for (int u = 0; u < 3; ++u) {
-                    aw[b * 3 + u] += fmaxf(fmaxf(hm[b][u], hm[b + 1][u]), hm[b + 2][u]);
-                    a1[b * 3 + u] += D[b + 1][u + 1];
-                }
-        } else {
-            // any odd window: direct evaluation of each translation
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-#pragma unroll
-                for (int u = 0; u < 3; ++u) {
-                    const int cx = px + u - 1, cy = py + b - 1;
-                    float best = -INFINITY;
-                    for (int dy = -wh; dy <= wh; ++dy)
-                        for (int dx = -wh; dx <= wh; ++dx)
-                            best = fmaxf(best, field_dot<PREC>(field, W, H, cx + dx, cy + dy, fx, fy));
-                    aw[b * 3 + u] += best;
-                    a1[b * 3 + u] += field_dot<PREC>(field, W, H, cx, cy, fx, fy);
-                }
-        }
-    }
+// The workgroup's 18 sums: a fixed butterfly per wave, then the waves in
+// order; written to out[0..17].  Ends with a barrier (red may be reused).
+__device__ __forceinline__ void block_sum18(float (&aw)[9], float (&a1)[9], float (*red)[18], float* out)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int m = 0; m < 9; ++m) {
 #pragma unroll
@@ -225,7 +126,247 @@ __global__ __launch_bounds__(kThreads) void k_refine_level(LevelArgs a, const Pa
     if (threadIdx.x < 18) {
         float s = 0.f;
         for (int w = 0; w < kWaves; ++w) s += red[w][threadIdx.x];
-        P.part[l][(((size_t)c * 3 + g) * chunks + chunk) * 18 + threadIdx.x] = s;
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// The candidate's pose at the level above: picked by the first wave from that
+// level's sums (or the candidate itself on the first refined level),
+// published in cur[0..2]; `writer` also records it as the centre.
+__device__ void take_centre(const LevelArgs& a, const PairDesc& P, int c, bool writer, int* cur)
+{
+    const int l = a.level;
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x < 64) {
+        int x, y, k;
+        float sw, s1;
+        if (a.pick) {
+            const tm_pose ctr = P.ctr[a.src][c];
+            const int la = l + 1;
+            pick27(P.part[la] + (size_t)c * 54, ctr.x, ctr.y, ctr.k, P.W[la], P.H[la], P.n[la], a.K_above, a.full,
+                   &sw, &s1, &x, &y, &k);
+        } else {
+            const tm_pose p = P.cand[c];
+            x = p.x;
+            y = p.y;
+            k = p.k;
+            sw = p.score_w;
+            s1 = p.score_1;
+        }
+        if (lane == 0) {
+            cur[0] = x;
+            cur[1] = y;
+            cur[2] = k;
+            if (writer) {
+                tm_pose o;
+                o.x = x;
+                o.y = y;
+                o.k = k;
+                o.level = l + 1;
+                o.theta_deg = (float)level_theta(a.theta_min, a.step_above, k);
+                o.score_w = sw;
+                o.score_1 = s1;
+                o.reserved = 0;
+                P.ctr[a.src ^ 1][c] = o;
+            }
+        }
+    }
+}
+
+// Block geometry of one point at (px, py): in-image rows and columns of the
+// 5x5 block, clamped column indices and row offsets.
+struct Block5 {
+    bool rin[5], cin[5];
+    int col[5];
+    size_t rowoff[5];
+};
+
+__device__ __forceinline__ void block5(int px, int py, int W, int H, Block5& b)
+{
+#pragma unroll
+    for (int u = 0; u < 5; ++u) {
+        const int xx = px - 2 + u, yy = py - 2 + u;
+        b.cin[u] = (unsigned)xx < (unsigned)W;
+        b.rin[u] = (unsigned)yy < (unsigned)H;
+        b.col[u] = min(max(xx, 0), W - 1);
+        b.rowoff[u] = (size_t)min(max(yy, 0), H - 1) * W;
+    }
+}
+
+template <int PREC>
+__global__ __launch_bounds__(kThreads) void k_refine_level(LevelArgs a, const PairDesc* __restrict__ pairs)
+{
+    __shared__ float red[kWaves][18];
+    __shared__ int cur[3];
+    const PairDesc& P = pairs[blockIdx.y];
+    const int l = a.level;
+    if (a.staged && P.rtile[l]) return;  // this pair's level is refined by k_refine_tile
+    const int g = blockIdx.x % 3;
+    const int c = blockIdx.x / 3;
+    int count = a.max_cand;
+    if (P.ncand) count = min(count, *P.ncand);
+    if (c >= count) return;
+    take_centre(a, P, c, g == 0, cur);
+    __syncthreads();
+    const int x = cur[0], y = cur[1], k = cur[2];
+    const void* field = P.field[l];
+    const int W = P.W[l], H = P.H[l], n = P.n[l];
+    const ModelPoint* __restrict__ pts = P.pts[l];
+    const int kc = angle_index(2 * k + g - 1, a.K, a.full);
+    double cs, sn;
+    sincos_deg(level_theta(a.theta_min, a.step, kc), &cs, &sn);
+    float aw[9], a1[9];
+#pragma unroll
+    for (int m = 0; m < 9; ++m) {
+        aw[m] = 0.f;
+        a1[m] = 0.f;
+    }
+    const int wh = (a.win - 1) / 2;
+    if (wh == 1) {
+        // two points per step (this thread's next two), their 50 loads issued
+        // before any is used; votes added in point order
+        for (int i = threadIdx.x; i < n; i += 2 * kThreads) {
+            const int j = i + kThreads;
+            const bool two = j < n;
+            int qx0, qy0, qx1 = 0, qy1 = 0;
+            double rx0, ry0, rx1 = 0, ry1 = 0;
+            project_point(pts[i], cs, sn, &qx0, &qy0, &rx0, &ry0);
+            if (two) project_point(pts[j], cs, sn, &qx1, &qy1, &rx1, &ry1);
+            Block5 b0, b1;
+            block5(2 * x + qx0, 2 * y + qy0, W, H, b0);
+            block5(2 * x + qx1, 2 * y + qy1, W, H, b1);
+            float2 g0[5][5], g1[5][5];
+#pragma unroll
+            for (int v = 0; v < 5; ++v)
+#pragma unroll
+                for (int u = 0; u < 5; ++u) {
+                    g0[v][u] = field_load<PREC>(field, b0.rowoff[v] + b0.col[u]);
+                    g1[v][u] = field_load<PREC>(field, b1.rowoff[v] + b1.col[u]);
+                }
+            __builtin_amdgcn_sched_barrier(0);
+            votes5x5(g0, b0.rin, b0.cin, (float)rx0, (float)ry0, aw, a1);
+            if (two) votes5x5(g1, b1.rin, b1.cin, (float)rx1, (float)ry1, aw, a1);
+        }
+    } else {
+        // any odd window: direct evaluation of each translation
+        for (int i = threadIdx.x; i < n; i += kThreads) {
+            int qx, qy;
+            double rx, ry;
+            project_point(pts[i], cs, sn, &qx, &qy, &rx, &ry);
+            const float fx = (float)rx, fy = (float)ry;
+            const int px = 2 * x + qx, py = 2 * y + qy;
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int u = 0; u < 3; ++u) {
+                    const int cx = px + u - 1, cy = py + b - 1;
+                    float best = -INFINITY;
+                    for (int dy = -wh; dy <= wh; ++dy)
+                        for (int dx = -wh; dx <= wh; ++dx)
+                            best = fmaxf(best, field_dot<PREC>(field, W, H, cx + dx, cy + dy, fx, fy));
+                    aw[b * 3 + u] += best;
+                    a1[b * 3 + u] += field_dot<PREC>(field, W, H, cx, cy, fx, fy);
+                }
+        }
+    }
+    block_sum18(aw, a1, red, P.part[l] + ((size_t)c * 3 + g) * 18);
+}
+
+// Raw field element as stored (FP32 pair, or the half2 bits) and its FP32 value.
+template <int PREC>
+struct Raw;
+template <>
+struct Raw<TM_FP32> {
+    using T = float2;
+    static __device__ __forceinline__ T zero() { return make_float2(0.f, 0.f); }
+    static __device__ __forceinline__ T load(const void* f, size_t o) { return reinterpret_cast<const float2*>(f)[o]; }
+    static __device__ __forceinline__ float2 value(T v) { return v; }
+};
+template <>
+struct Raw<TM_FP16> {
+    using T = __half2;
+    static __device__ __forceinline__ T zero() { return __floats2half2_rn(0.f, 0.f); }
+    static __device__ __forceinline__ T load(const void* f, size_t o) { return reinterpret_cast<const __half2*>(f)[o]; }
+    static __device__ __forceinline__ float2 value(T v) { return __half22float2(v); }
+};
+
+template <int PREC>
+__global__ __launch_bounds__(kThreads) void k_refine_tile(LevelArgs a, const PairDesc* __restrict__ pairs)
+{
+    using T = typename Raw<PREC>::T;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ float red[kWaves][18];
+    __shared__ int cur[3];
+    const PairDesc& P = pairs[blockIdx.y];
+    const int l = a.level;
+    if (!P.rtile[l]) return;
+    const int c = blockIdx.x;
+    int count = a.max_cand;
+    if (P.ncand) count = min(count, *P.ncand);
+    if (c >= count) return;
+    take_centre(a, P, c, true, cur);
+    __syncthreads();
+    const int x = cur[0], y = cur[1], k = cur[2];
+    const void* field = P.field[l];
+    const int W = P.W[l], H = P.H[l], n = P.n[l];
+    const ModelPoint* __restrict__ pts = P.pts[l];
+    const int rad = P.rad_l[l];
+    const int S = 2 * rad + 5, SS = S * S;
+    const int ox = 2 * x - rad - 2, oy = 2 * y - rad - 2;
+    T* tile = reinterpret_cast<T*>(smem);
+    // stage: 8 loads in flight per thread (clamped addresses, zero selected
+    // outside the image)
+    constexpr int kU = 8;
+    for (int e0 = threadIdx.x; e0 < SS; e0 += kU * kThreads) {
+        T v[kU];
+        bool ok[kU];
+#pragma unroll
+        for (int j = 0; j < kU; ++j) {
+            const int e = min(e0 + j * kThreads, SS - 1);
+            const int r = e / S, cc = e - r * S;
+            const int gx = ox + cc, gy = oy + r;
+            ok[j] = (unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H;
+            v[j] = Raw<PREC>::load(field, (size_t)min(max(gy, 0), H - 1) * W + min(max(gx, 0), W - 1));
+        }
+#pragma unroll
+        for (int j = 0; j < kU; ++j) {
+            const int e = e0 + j * kThreads;
+            if (e < SS) tile[e] = ok[j] ? v[j] : Raw<PREC>::zero();
+        }
+    }
+    __syncthreads();
+    for (int g = 0; g < 3; ++g) {
+        const int kc = angle_index(2 * k + g - 1, a.K, a.full);
+        double cs, sn;
+        sincos_deg(level_theta(a.theta_min, a.step, kc), &cs, &sn);
+        float aw[9], a1[9];
+#pragma unroll
+        for (int m = 0; m < 9; ++m) {
+            aw[m] = 0.f;
+            a1[m] = 0.f;
+        }
+        for (int i = threadIdx.x; i < n; i += kThreads) {
+            int qx, qy;
+            double rx, ry;
+            project_point(pts[i], cs, sn, &qx, &qy, &rx, &ry);
+            const int px = 2 * x + qx, py = 2 * y + qy;
+            // |q| < rad per component, so the block covers px - 2 .. px + 2
+            const T* b = tile + (size_t)(py - 2 - oy) * S + (px - 2 - ox);
+            bool cin[5], rin[5];
+            float2 gv[5][5];
+#pragma unroll
+            for (int u = 0; u < 5; ++u) {
+                cin[u] = (unsigned)(px - 2 + u) < (unsigned)W;
+                rin[u] = (unsigned)(py - 2 + u) < (unsigned)H;
+            }
+#pragma unroll
+            for (int v = 0; v < 5; ++v)
+#pragma unroll
+                for (int u = 0; u < 5; ++u) gv[v][u] = Raw<PREC>::value(b[v * S + u]);
+            votes5x5(gv, rin, cin, (float)rx, (float)ry, aw, a1);
+        }
+        block_sum18(aw, a1, red, P.part[l] + ((size_t)c * 3 + g) * 18);
     }
 }
 
@@ -246,8 +387,8 @@ __global__ __launch_bounds__(64) void k_refine_pick(PickArgs a, const PairDesc* 
     const tm_pose ctr = P.ctr[a.src][c];
     float sw, s1;
     int x, y, k;
-    pick27(P.part[0] + (size_t)c * 3 * chunks_of(P.n[0]) * 18, chunks_of(P.n[0]), ctr.x, ctr.y, ctr.k, P.W[0], P.H[0],
-           P.n[0], a.K0, a.full, &sw, &s1, &x, &y, &k);
+    pick27(P.part[0] + (size_t)c * 54, ctr.x, ctr.y, ctr.k, P.W[0], P.H[0], P.n[0], a.K0, a.full, &sw, &s1, &x, &y,
+           &k);
     if (threadIdx.x == 0) {
         tm_pose o;
         o.x = x;
@@ -264,18 +405,41 @@ __global__ __launch_bounds__(64) void k_refine_pick(PickArgs a, const PairDesc* 
 
 }  // namespace
 
-int refine_chunks(int n) { return (n + kThreads - 1) / kThreads; }
+size_t refine_tile_bytes(int rad, int precision)
+{
+    const size_t S = 2 * (size_t)rad + 5;
+    return S * S * (precision == TM_FP16 ? 4 : 8);
+}
 
-hipError_t launch_refine(const SearchDesc& s, const PairDesc* d, int npairs, int from_level, const int* max_chunks,
+bool refine_tile_fits(int rad, int precision, int win)
+{
+    return win == 3 && refine_tile_bytes(rad, precision) <= kTileMax;
+}
+
+hipError_t prepare_refine()
+{
+    static bool done = false;
+    if (done) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_refine_tile<TM_FP32>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileMax);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_refine_tile<TM_FP16>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileMax);
+    if (e == hipSuccess) done = true;
+    return e;
+}
+
+hipError_t launch_refine(const SearchDesc& s, const PairDesc* d, int npairs, int from_level, const RefinePlan& rp,
                          hipStream_t st)
 {
     if (from_level <= 0 || npairs == 0) return hipSuccess;
     from_level = min(from_level, s.L - 1);
+    hipError_t e = prepare_refine();
+    if (e != hipSuccess) return e;
     int src = 0;
     for (int l = from_level - 1; l >= 0; --l) {
         LevelArgs a;
         a.level = l;
-        a.max_chunks = max_chunks[l];
         a.pick = l < from_level - 1;
         a.K = s.K[l];
         a.K_above = s.K[l + 1];
@@ -286,13 +450,25 @@ hipError_t launch_refine(const SearchDesc& s, const PairDesc* d, int npairs, int
         a.max_cand = s.max_cand;
         a.theta_min = s.theta_min;
         a.src = src;
-        dim3 grid((unsigned)(s.max_cand * 3 * a.max_chunks), npairs);
-        if (s.precision == TM_FP16)
-            hipLaunchKernelGGL(k_refine_level<TM_FP16>, grid, dim3(kThreads), 0, st, a, d);
-        else
-            hipLaunchKernelGGL(k_refine_level<TM_FP32>, grid, dim3(kThreads), 0, st, a, d);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        a.staged = rp.staged;
+        if (!rp.staged || rp.gather[l]) {
+            dim3 grid((unsigned)(s.max_cand * 3), npairs);
+            if (s.precision == TM_FP16)
+                hipLaunchKernelGGL(k_refine_level<TM_FP16>, grid, dim3(kThreads), 0, st, a, d);
+            else
+                hipLaunchKernelGGL(k_refine_level<TM_FP32>, grid, dim3(kThreads), 0, st, a, d);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+        if (rp.staged && rp.tile_bytes[l] > 0) {
+            dim3 grid((unsigned)s.max_cand, npairs);
+            if (s.precision == TM_FP16)
+                hipLaunchKernelGGL(k_refine_tile<TM_FP16>, grid, dim3(kThreads), rp.tile_bytes[l], st, a, d);
+            else
+                hipLaunchKernelGGL(k_refine_tile<TM_FP32>, grid, dim3(kThreads), rp.tile_bytes[l], st, a, d);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
         src ^= 1;
     }
     PickArgs pa;

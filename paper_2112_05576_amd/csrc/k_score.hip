@@ -573,7 +573,9 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
         p.max_np = max(p.max_np, g[i].gw * g[i].gh);
     }
     p.fast = s.sx == 1 && s.sy == 1 && s.win == 3;
-    p.variant = knob("TM_DENSE_ASM", 0, 0, 4);
+    // measured on the 64-image C2 batch: FP16 fastest with 4 entries per
+    // fetch (variant 3), FP32 with one (variant 1); both bit-identical to 0
+    p.variant = knob("TM_DENSE_ASM", s.precision == TM_FP16 ? 3 : 1, 0, 4);
     if (p.fast) {
         p.G = 32;
         p.R = 8;

@@ -250,7 +250,7 @@ tmk::PairGeom pair_geom(const tm_model* m, const tm_pyramid* p, int level, int s
 // Static part of a pair descriptor: the image's levels, the model's levels,
 // the rotated table of the searched level and the suppression distance.
 void pair_static(tmk::PairDesc* d, const tm_model* m, const tm_pyramid* p, const tmk::TabEntry* tab, int level,
-                 const tmk::PairGeom& g, const tmk::DensePlan& plan, float dmin)
+                 const tmk::PairGeom& g, const tmk::DensePlan& plan, float dmin, int win)
 {
     for (int l = 0; l < p->L; ++l) {
         d->field[l] = p->lv[l].field;
@@ -258,6 +258,8 @@ void pair_static(tmk::PairDesc* d, const tm_model* m, const tm_pyramid* p, const
         d->H[l] = p->lv[l].h;
         d->pts[l] = m->lv[l].pts;
         d->n[l] = m->lv[l].n;
+        d->rad_l[l] = m->lv[l].rad;
+        d->rtile[l] = tmk::refine_tile_fits(m->lv[l].rad, p->precision, win) ? 1 : 0;
     }
     d->tab = tab;
     d->n_pad = m->lv[level].n_pad;
@@ -312,7 +314,7 @@ size_t pair_scratch(tmk::PairDesc* d, const tm_model* m, const tmk::PairGeom& g,
         }
         for (int l = 0; l < L; ++l) {
             float* pl = reinterpret_cast<float*>(
-                take((size_t)max_cand * 3 * tmk::refine_chunks(m->lv[l].n) * 18 * sizeof(float)));
+                take((size_t)max_cand * 3 * 18 * sizeof(float)));
             if (base) d->part[l] = pl;
         }
     }
@@ -342,12 +344,26 @@ tm_status put_desc(tm_pyramid* p, const tmk::PairDesc& d, hipStream_t s, tmk::Pa
     return TM_OK;
 }
 
-void refine_max_chunks(const tm_model* const* models, int n_models, int L, int* mc)
+// Per level: the pairs refined by gathers and by the staged kernel (the same
+// rule as pair_static), with the grid and LDS sizes of each launch.  Staging
+// is used once a launch refines at least kStagedMin candidates.
+constexpr int kStagedMin = 512;
+
+tmk::RefinePlan refine_plan(const tm_model* const* models, int n_models, int L, int win, int precision,
+                            long long candidates)
 {
-    for (int l = 0; l < L; ++l) {
-        mc[l] = 1;
-        for (int j = 0; j < n_models; ++j) mc[l] = std::max(mc[l], tmk::refine_chunks(models[j]->lv[l].n));
-    }
+    tmk::RefinePlan rp;
+    memset(&rp, 0, sizeof(rp));
+    rp.staged = candidates >= kStagedMin;
+    for (int l = 0; l < L; ++l)
+        for (int j = 0; j < n_models; ++j) {
+            const tm_model_level& ml = models[j]->lv[l];
+            if (tmk::refine_tile_fits(ml.rad, precision, win))
+                rp.tile_bytes[l] = std::max(rp.tile_bytes[l], (int)tmk::refine_tile_bytes(ml.rad, precision));
+            else
+                rp.gather[l] = 1;
+        }
+    return rp;
 }
 
 }  // namespace
@@ -640,7 +656,7 @@ TM_EXPORT tm_status tm_score_map(const tm_model* m, tm_pyramid* p, int32_t level
     tmk::DensePlan plan = tmk::plan_dense(sd, &pg, 1);
     tmk::PairDesc d;
     memset(&d, 0, sizeof(d));
-    pair_static(&d, m, p, tab, level, pg, plan, 0.f);
+    pair_static(&d, m, p, tab, level, pg, plan, 0.f, sp->neighbourhood);
     st = ensure_ws(p, kDescBytes + pair_scratch(&d, m, pg, plan, p->L, 1, true, false, false, nullptr), s);
     if (st != TM_OK) return st;
     pair_scratch(&d, m, pg, plan, p->L, 1, true, false, false, reinterpret_cast<uint8_t*>(p->ws.ptr) + kDescBytes);
@@ -730,7 +746,7 @@ TM_EXPORT tm_status tm_detect(const tm_model* m, tm_pyramid* p, const tm_search_
     tmk::DensePlan plan = tmk::plan_dense(sd, &pg, 1);
     tmk::PairDesc d;
     memset(&d, 0, sizeof(d));
-    pair_static(&d, m, p, tab, top, pg, plan, default_dmin(m, sp));
+    pair_static(&d, m, p, tab, top, pg, plan, default_dmin(m, sp), sp->neighbourhood);
     const bool refine = p->L > 1;
     st = ensure_ws(p, kDescBytes + pair_scratch(&d, m, pg, plan, p->L, sp->max_candidates, true, true, refine, nullptr),
                    s);
@@ -748,9 +764,8 @@ TM_EXPORT tm_status tm_detect(const tm_model* m, tm_pyramid* p, const tm_search_
     HIP_TRY(tmk::launch_dense(sd, plan, dd, 1, s, ev0, ev1));
     HIP_TRY(tmk::launch_select(sd, dd, 1, pg.gw * pg.gh, s));
     if (refine) {
-        int mc[TM_MAX_LEVELS];
-        refine_max_chunks(&m, 1, p->L, mc);
-        HIP_TRY(tmk::launch_refine(sd, dd, 1, top, mc, s));
+        const tmk::RefinePlan rp = refine_plan(&m, 1, p->L, sp->neighbourhood, p->precision, sp->max_candidates);
+        HIP_TRY(tmk::launch_refine(sd, dd, 1, top, rp, s));
     }
     HIP_TRY(tmk::launch_final(sd, dd, 1, s));
     return TM_OK;
@@ -804,7 +819,7 @@ TM_EXPORT tm_status tm_refine(const tm_model* m, tm_pyramid* p, const tm_search_
     tmk::DensePlan plan = {};
     tmk::PairDesc d;
     memset(&d, 0, sizeof(d));
-    pair_static(&d, m, p, nullptr, from_level, pg, plan, 0.f);
+    pair_static(&d, m, p, nullptr, from_level, pg, plan, 0.f, sp->neighbourhood);
     st = ensure_ws(p, kDescBytes + pair_scratch(&d, m, pg, plan, p->L, n, false, false, true, nullptr), s);
     if (st != TM_OK) return st;
     pair_scratch(&d, m, pg, plan, p->L, n, false, false, true, reinterpret_cast<uint8_t*>(p->ws.ptr) + kDescBytes);
@@ -813,9 +828,8 @@ TM_EXPORT tm_status tm_refine(const tm_model* m, tm_pyramid* p, const tm_search_
     tmk::PairDesc* dd = nullptr;
     st = put_desc(p, d, s, &dd);
     if (st != TM_OK) return st;
-    int mc[TM_MAX_LEVELS];
-    refine_max_chunks(&m, 1, p->L, mc);
-    HIP_TRY(tmk::launch_refine(sd, dd, 1, from_level, mc, s));
+    const tmk::RefinePlan rp = refine_plan(&m, 1, p->L, sp->neighbourhood, p->precision, n);
+    HIP_TRY(tmk::launch_refine(sd, dd, 1, from_level, rp, s));
     return TM_OK;
 }
 
@@ -899,7 +913,7 @@ struct tm_batch_s {
     std::vector<const tm_model*> models;
     tmk::SearchDesc sd;
     tmk::DensePlan plan;
-    int max_chunks[TM_MAX_LEVELS];
+    tmk::RefinePlan rplan;
     int level_w[TM_MAX_LEVELS], level_h[TM_MAX_LEVELS];
     int max_field_blocks = 0, max_np = 0;
     void* scratch = nullptr;
@@ -977,7 +991,8 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
         tm_batch_free(b);
         return fail(TM_EDEVICE, "tm_batch_create: internal error in the search work list");
     }
-    refine_max_chunks(models, n_models, L, b->max_chunks);
+    b->rplan = refine_plan(models, n_models, L, sp->neighbourhood, pp->precision,
+                           (long long)b->npairs * sp->max_candidates);
     for (auto& q : pg) b->max_np = std::max(b->max_np, q.gw * q.gh);
 
     // one allocation: tables, descriptors, pyramid arguments, pair scratch
@@ -1031,7 +1046,7 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
             tmk::PairDesc& d = hd[q];
             memset(&d, 0, sizeof(d));
             pair_static(&d, models[j], b->pyrs[i], reinterpret_cast<tmk::TabEntry*>(base + tab_off[j]), top, pg[q],
-                        b->plan, default_dmin(models[j], sp));
+                        b->plan, default_dmin(models[j], sp), sp->neighbourhood);
             pair_scratch(&d, models[j], pg[q], b->plan, L, sp->max_candidates, true, true, refine,
                          base + pair_off[q]);
             d.out = out + (size_t)q * capacity;
@@ -1081,7 +1096,7 @@ tm_status batch_enqueue(tm_batch* b, hipStream_t s, bool timed)
     }
     HIP_TRY(tmk::launch_dense(b->sd, b->plan, b->d_pairs, b->npairs, s, ev0, ev1));
     HIP_TRY(tmk::launch_select(b->sd, b->d_pairs, b->npairs, b->max_np, s));
-    if (b->L > 1) HIP_TRY(tmk::launch_refine(b->sd, b->d_pairs, b->npairs, top, b->max_chunks, s));
+    if (b->L > 1) HIP_TRY(tmk::launch_refine(b->sd, b->d_pairs, b->npairs, top, b->rplan, s));
     HIP_TRY(tmk::launch_final(b->sd, b->d_pairs, b->npairs, s));
     return TM_OK;
 }
@@ -1099,6 +1114,7 @@ TM_EXPORT tm_status tm_batch_run_graph(tm_batch* b, void* stream)
     if (!b->graph) {
         // Capture on a private stream: nothing runs, the launches become nodes.
         HIP_TRY(tmk::prepare_dense(b->sd, b->plan));
+        HIP_TRY(tmk::prepare_refine());
         hipStream_t cs = nullptr;
         HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);

@@ -154,7 +154,9 @@ struct PairDesc {
     tm_pose* cand;                   // candidates [max_cand] (refined in place)
     int32_t* ncand;                  // their count (device); null: max_cand
     tm_pose* ctr[2];                 // refinement centres [max_cand]
-    float* part[kMaxLevels];         // refinement partials [max_cand][3][chunks_l][18]
+    float* part[kMaxLevels];         // refinement sums [max_cand][3][18]
+    int rad_l[kMaxLevels];           // bound on |q| components at each level
+    int rtile[kMaxLevels];           // 1: level refined by the staged kernel (partials: one chunk)
     tm_pose* out;                    // results [capacity]
     int32_t* n_out;                  // their count
 };
@@ -201,7 +203,20 @@ size_t dense_partials_bytes(const DensePlan& p, int np);
 // (every block of every pair exactly once).
 bool build_work(const DensePlan& p, const PairGeom* g, int npairs, std::vector<int2>& out);
 size_t select_scratch_bytes(int np);
-int refine_chunks(int n);
+// Refinement plan of a launch.  staged: pairs whose level block fits
+// (PairDesc.rtile) are refined by the staged kernel, the others by gathers;
+// otherwise all by gathers (both give bit-identical sums; staging pays off
+// once a launch holds many candidates).  Per level: whether any pair is
+// refined by gathers, and the largest staged block (0: none).
+struct RefinePlan {
+    int staged;
+    int gather[kMaxLevels];
+    int tile_bytes[kMaxLevels];
+};
+// LDS bytes of the staged field block of a level (side 2 rad + 5) and
+// whether the level is refined from it (window 3 and at most 128 KB).
+size_t refine_tile_bytes(int rad, int precision);
+bool refine_tile_fits(int rad, int precision, int win);
 
 // Kernel attributes of the plan's search kernel (call before capturing it).
 hipError_t prepare_dense(const SearchDesc& s, const DensePlan& p);
@@ -212,9 +227,10 @@ hipError_t launch_dense(const SearchDesc& s, const DensePlan& p, const PairDesc*
 // Candidates of every pair from its map: pair.cand / ncand (<= s.max_cand).
 hipError_t launch_select(const SearchDesc& s, const PairDesc* d, int npairs, int max_np, hipStream_t st);
 // Refine pair.cand (poses of level from_level) down to level 0, in place.
-// max_chunks[l]: largest refine_chunks(n[l]) over the pairs.
-hipError_t launch_refine(const SearchDesc& s, const PairDesc* d, int npairs, int from_level, const int* max_chunks,
+hipError_t launch_refine(const SearchDesc& s, const PairDesc* d, int npairs, int from_level, const RefinePlan& rp,
                          hipStream_t st);
+// Kernel attributes of the staged refinement (call before capturing it).
+hipError_t prepare_refine();
 // Final selection of every pair: pair.cand -> pair.out / n_out.
 hipError_t launch_final(const SearchDesc& s, const PairDesc* d, int npairs, hipStream_t st);
 

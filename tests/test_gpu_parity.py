@@ -470,11 +470,13 @@ def _poses_equal(a, b):
 @pytest.mark.parametrize("precision", [0, 1])
 def test_batch_equals_single_detections(precision):
     """One launch per stage over all (image, model) pairs gives exactly the
-    detections of the single-image calls (mixed sizes, two models)."""
+    detections of the single-image calls (mixed sizes, two models).  With 18
+    pairs x 32 candidates the batch refines from LDS-staged field blocks and
+    the single calls by gathers: the partial sums must still be identical."""
     P = _P()
     case(f"batch vs single precision={precision}")
     cfg = synth.CONFIGS[2]
-    scenes = [synth.scene_for_config(2, i) for i in range(3)]
+    scenes = [synth.scene_for_config(2, i) for i in range(8)]
     big = synth.scene_for_config(2, 7, W=1280, H=1024, n_inst=4)
     rng = np.random.default_rng(4242)
     m2 = synth.render_model(synth.make_model_shape("polygon", 96, rng), 96)
