@@ -129,20 +129,33 @@ struct Px<TM_FP16> {
     {
         return __builtin_amdgcn_fdot2(__builtin_bit_cast(h2_t, e.rh), __builtin_bit_cast(h2_t, g), 0.0f, false);
     }
-    // ASM: the VOP3P form with an inline zero addend (the builtin becomes
-    // v_dot2c with an accumulator cleared by a move per product).
     template <bool ASM>
     static __device__ __forceinline__ float dot_t(const TabEntry& e, T g)
     {
-        if constexpr (ASM) {
-            float d;
-            asm("v_dot2_f32_f16 %0, %1, %2, 0" : "=v"(d) : "s"(e.rh), "v"(g));
-            return d;
-        } else {
-            return dot(e, g);
-        }
+        return dot(e, g);
     }
 };
+
+// The ten products of one point down an 8-row strip (rows 0..9 of the
+// window) in the VOP3P form with an inline zero addend (the builtin becomes
+// v_dot2c with an accumulator cleared by a move per product).  A dot result
+// must not be read by another VALU instruction within 3 wait states, which
+// the compiler cannot see inside asm: five ordered pairs of products (each
+// waiting only for its own two LDS values), then s_nop 2, then a scheduling
+// barrier that no VALU instruction crosses, so every reader comes after the
+// wait states (LDS reads and scalar instructions may still move across).
+__device__ __forceinline__ void dots10_f16(uint32_t rh, const uint32_t (&g)[10], float (&d)[10])
+{
+#pragma unroll
+    for (int j = 0; j < 10; j += 2)
+        asm volatile(
+            "v_dot2_f32_f16 %0, %2, %3, 0\n\t"
+            "v_dot2_f32_f16 %1, %2, %4, 0"
+            : "=&v"(d[j]), "=&v"(d[j + 1])
+            : "s"(rh), "v"(g[j]), "v"(g[j + 1]));
+    asm volatile("s_nop 2");
+    __builtin_amdgcn_sched_barrier(0x0104);
+}
 
 struct FastArgs {
     int level;          // searched level
@@ -155,7 +168,8 @@ struct FastArgs {
 
 // VAR: 0 compiler-built products and window maxima; 1 the same with the
 // VOP3P dot and the DPP-folded maxima written out; 2, 3, 4 as 1 with 2, 4, 8
-// table entries fetched per loop step (one scalar-load wait per step).
+// table entries fetched per loop step (one scalar-load wait per step); 5 as 3
+// with the next step's entries requested behind this step's LDS reads.
 template <int G, int R, int LC, int PREC, int VAR>
 __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc* __restrict__ pairs)
 {
@@ -231,11 +245,20 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc*
             constexpr bool ASM = VAR > 0;
             // one point: its R+2 products down the strip, the vertical then
             // the horizontal window maxima, added in point order
-            auto point = [&](const TabEntry& e) {
+            // (fetch: the point's R+2 field values from LDS; compute: the rest)
+            auto fetch = [&](const TabEntry& e, T (&gv)[R + 2]) {
                 const T* p = lbase + (int)e.qy * LC + (int)e.qx;
-                float D[R + 2];
 #pragma unroll
-                for (int rr = 0; rr < R + 2; ++rr) D[rr] = Px<PREC>::template dot_t<ASM>(e, p[rr * LC]);
+                for (int rr = 0; rr < R + 2; ++rr) gv[rr] = p[rr * LC];
+            };
+            auto compute = [&](const TabEntry& e, const T (&gv)[R + 2]) {
+                float D[R + 2];
+                if constexpr (ASM && PREC == TM_FP16 && R == 8) {
+                    dots10_f16(e.rh, gv, D);
+                } else {
+#pragma unroll
+                    for (int rr = 0; rr < R + 2; ++rr) D[rr] = Px<PREC>::template dot_t<ASM>(e, gv[rr]);
+                }
                 float V[R];
 #pragma unroll
                 for (int r = 0; r < R; ++r) V[r] = fmaxf(fmaxf(D[r], D[r + 1]), D[r + 2]);
@@ -255,7 +278,35 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc*
                     }
                 }
             };
-            if constexpr (VAR >= 2) {
+            auto point = [&](const TabEntry& e) {
+                T gv[R + 2];
+                fetch(e, gv);
+                compute(e, gv);
+            };
+            if constexpr (VAR == 5) {
+                // 4 points per step, software-pipelined: the next step's table
+                // entries are requested after this step's LDS reads, so that
+                // the two waits overlap
+                constexpr int U = 4;
+                TabEntry e[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) e[u] = tab_entry(Tb + i0 + u);
+                for (int i = i0; i < i1; i += U) {
+                    T gv[U][R + 2];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) fetch(e[u], gv[u]);
+                    __builtin_amdgcn_sched_barrier(0);
+                    const int inext = i + U < i1 ? i + U : i;  // the last step re-reads its own entries
+                    TabEntry en[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) en[u] = tab_entry(Tb + inext + u);
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int u = 0; u < U; ++u) compute(e[u], gv[u]);
+#pragma unroll
+                    for (int u = 0; u < U; ++u) e[u] = en[u];
+                }
+            } else if constexpr (VAR >= 2) {
                 // U entries fetched together, then U points in order; block
                 // lengths are multiples of 8 (the table is padded to 8)
                 constexpr int U = VAR == 2 ? 2 : (VAR == 3 ? 4 : 8);
@@ -500,7 +551,7 @@ constexpr int kLC[] = {64, 96, 128, 192, 256};
 // Launch-shape knobs of the search kernel: waves stacked in y per workgroup,
 // waves splitting the angle chunk, angles per wave, and the window-max form.
 // Defaults can be overridden by TM_DENSE_WY / TM_DENSE_WA / TM_DENSE_APW /
-// TM_DENSE_ASM (0 to 4: the search kernel variant; tuning runs).
+// TM_DENSE_ASM (0 to 5: the search kernel variant; tuning runs).
 int knob(const char* name, int dflt, int lo, int hi)
 {
     const char* v = getenv(name);
@@ -547,6 +598,7 @@ hipError_t launch_fast_v(const DensePlan& p, const FastArgs& a, const PairDesc* 
         case 2: return launch_fast_p<PREC, 2>(p, a, d, npairs, s);
         case 3: return launch_fast_p<PREC, 3>(p, a, d, npairs, s);
         case 4: return launch_fast_p<PREC, 4>(p, a, d, npairs, s);
+        case 5: return launch_fast_p<PREC, 5>(p, a, d, npairs, s);
         default: return launch_fast_p<PREC, 0>(p, a, d, npairs, s);
     }
 }
@@ -573,9 +625,9 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
         p.max_np = max(p.max_np, g[i].gw * g[i].gh);
     }
     p.fast = s.sx == 1 && s.sy == 1 && s.win == 3;
-    // measured on the 64-image C2 batch: FP16 fastest with 4 entries per
-    // fetch (variant 3), FP32 with one (variant 1); both bit-identical to 0
-    p.variant = knob("TM_DENSE_ASM", s.precision == TM_FP16 ? 3 : 1, 0, 4);
+    // measured on the 64-image C2 batch: FP16 fastest with 8 entries per
+    // fetch (variant 4), FP32 with 4 (variant 3); all bit-identical to 0
+    p.variant = knob("TM_DENSE_ASM", s.precision == TM_FP16 ? 4 : 3, 0, 5);
     if (p.fast) {
         p.G = 32;
         p.R = 8;

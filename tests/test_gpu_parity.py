@@ -451,7 +451,8 @@ def test_search_kernel_shape_independence(precision, monkeypatch):
     pyr = P.Pyramid(sc.image, 4, cfg["tau_s"], precision=precision)
     sp = P.SearchParams(theta_step_top=1.0)
     ref = [t.clone() for t in P.score_map(gm, pyr, 3, sp)]
-    for wy, wa, apw, asm in [(1, 4, 1, 1), (2, 4, 1, 0), (1, 8, 2, 2), (1, 16, 1, 3), (4, 1, 3, 1), (1, 4, 1, 4), (2, 2, 1, 4)]:
+    for wy, wa, apw, asm in [(1, 4, 1, 1), (2, 4, 1, 0), (1, 8, 2, 2), (1, 16, 1, 3), (4, 1, 3, 5), (1, 4, 1, 4),
+                             (2, 2, 1, 5)]:
         monkeypatch.setenv("TM_DENSE_WY", str(wy))
         monkeypatch.setenv("TM_DENSE_WA", str(wa))
         monkeypatch.setenv("TM_DENSE_APW", str(apw))
