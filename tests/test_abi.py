@@ -76,6 +76,44 @@ def test_invalid_arguments_fail_before_the_device(L):
     L.tm_pyramid_free(None)
 
 
+def test_continuous_and_batch_entries_validate_first(L):
+    """The continuous score, batch and graph entries reject null handles,
+    negative counts and bad step-length lists before any device call."""
+    from paper_2112_05576_amd import tm
+
+    vp = ctypes.c_void_p
+    fake = vp(0x1000)  # never dereferenced: validation fails first
+    al = (ctypes.c_double * 3)(0.0, 0.5, 1.0)
+    assert L.tm_cont_score(None, None, 0, fake, 1, fake, None) == tm.TM_EINVAL
+    assert L.tm_cont_score(fake, fake, 0, fake, -1, fake, None) == tm.TM_EINVAL
+    assert L.tm_cont_score(fake, fake, 0, None, 1, fake, None) == tm.TM_EINVAL
+    assert L.tm_cont_score_backward(fake, fake, 0, fake, 1, None, None, None) == tm.TM_EINVAL
+    assert L.tm_cont_line_search(fake, fake, 0, fake, fake, 1, al, 0, None, None) == tm.TM_EINVAL
+    assert b"step lengths" in L.tm_last_error()
+    assert L.tm_cont_line_search(fake, fake, 0, fake, fake, 1, al, 17, None, None) == tm.TM_EINVAL
+    bad = (ctypes.c_double * 2)(0.0, float("nan"))
+    assert L.tm_cont_line_search(fake, fake, 0, fake, fake, 1, bad, 2, None, None) == tm.TM_EINVAL
+    assert b"non-finite" in L.tm_last_error()
+    assert L.tm_batch_run(None, None) == tm.TM_EINVAL
+    assert L.tm_batch_run_graph(None, None) == tm.TM_EINVAL
+    assert L.tm_batch_cont_score(None, 0, fake, 1, fake, None) == tm.TM_EINVAL
+    assert L.tm_batch_cont_score_backward(None, 0, fake, 1, None, fake, None) == tm.TM_EINVAL
+    assert L.tm_batch_cont_line_search(None, 0, fake, fake, 1, al, 3, None, None) == tm.TM_EINVAL
+    out = vp()
+    pp = tm.PyrParamsC(4, 30.0, tm.TM_FP32)
+    sp = tm.SearchParams().c()
+    one = (ctypes.c_int32 * 1)(64)
+    ptrs = (vp * 1)(fake)
+    assert L.tm_batch_create(ptrs, 0, ptrs, one, one, one, 1, ctypes.byref(pp), ctypes.byref(sp), fake, 8, fake, None,
+                             ctypes.byref(out)) == tm.TM_EINVAL
+    assert L.tm_batch_create(ptrs, 1, ptrs, one, one, one, 1, ctypes.byref(pp), ctypes.byref(sp), fake, 0, fake, None,
+                             ctypes.byref(out)) == tm.TM_EINVAL
+    assert L.tm_batch_create(ptrs, 1, ptrs, one, one, one, 1, ctypes.byref(pp), ctypes.byref(sp), None, 8, fake,
+                             None, ctypes.byref(out)) == tm.TM_EINVAL
+    assert not out.value
+    L.tm_batch_free(None)
+
+
 def test_search_params_validation(L):
     """Search parameters are checked before the handles are used."""
     from paper_2112_05576_amd import tm
