@@ -31,6 +31,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -54,6 +55,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="time budget of the oracle CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eager", action="store_true", help="batched leg as plain enqueues instead of a graph launch")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default search-kernel form (no autotuning)")
     ap.add_argument("--c4", action="store_true", help="also time the 64 x 8 mixed batch and the C5 refinement")
     ap.add_argument("--paper", action="store_true",
                     help="also time the paper's own search shape (812x617, 3 px / 3 deg steps, 90 deg, one level)")
@@ -76,9 +78,9 @@ def _pmc_rows(path, counter):
     for r in csv.DictReader(open(path)):
         if r.get("Counter_Name") == counter:
             rows.append((int(r.get("Dispatch_Id", len(rows))), r.get("Kernel_Name", ""), float(r["Counter_Value"]),
-                         int(r.get("Grid_Size", 0))))
+                         int(r.get("Grid_Size", 0)), int(r.get("Workgroup_Size", 0))))
     rows.sort()
-    return [(n, v, g) for _, n, v, g in rows]
+    return [(n, v, g, wg) for _, n, v, g, wg in rows]
 
 
 def traffic_from(fetch_csv, write_csv):
@@ -89,14 +91,20 @@ def traffic_from(fetch_csv, write_csv):
     out = {"kernel_sha256": hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()}
     for key, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
         rows = _pmc_rows(path, counter)
-        probe_name, probe, _ = rows[-1]
+        probe_name, probe, _, _ = rows[-1]
         if "elementwise" not in probe_name:
             raise SystemExit(f"last dispatch in {path} is not the copy probe: {probe_name[:80]}")
         # the batched launches: the search dispatches with the largest grid
-        grids = [g for n, _, g in rows if "k_dense_fast" in n]
+        # (run the counter passes with --no-tune, so that one form runs)
+        grids = [g for n, _, g, _ in rows if "k_dense_fast" in n]
         if not grids:
             raise SystemExit(f"no k_dense_fast dispatch in {path}")
-        dense = [v for n, v, g in rows if "k_dense_fast" in n and g == max(grids)]
+        sel = [(n, v, wg) for n, v, g, wg in rows if "k_dense_fast" in n and g == max(grids)]
+        if len({(n, wg) for n, _, wg in sel}) != 1:
+            raise SystemExit(f"several search forms in {path}: take the counters with --no-tune")
+        dense = [v for _, v, _ in sel]
+        out["form"] = {"variant": int(re.search(r"k_dense_fast<[^>]*,\s*(\d+)>", sel[0][0]).group(1)),
+                       "waves_per_chunk": sel[0][2] // 64}
         scale = COPY_PROBE_BYTES / probe  # bytes per counted KiB
         out[key] = {"kib_per_launch": sum(dense) / len(dense), "probe_kib": probe, "scale_bytes_per_kib": scale,
                     "bytes_per_launch": sum(dense) / len(dense) * scale, "launches": len(dense)}
@@ -130,14 +138,14 @@ def cpu_baseline(scenes, cfg, budget_s):
             "sample": f"{n_img} full detections of 640x480 images (4 levels, 360 top angles), {dt:.1f} s"}
 
 
-def traffic_entry():
+def traffic_entry(form):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source."""
+    taken on the current kernel source and on the search form now in use."""
     if not os.path.exists(TRAFFIC_JSON):
         return None
     d = json.load(open(TRAFFIC_JSON))
     h = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    if d.get("kernel_sha256") != h:
+    if d.get("kernel_sha256") != h or d.get("form") != form:
         return None
     return d.get("bytes_per_launch")
 
@@ -164,6 +172,7 @@ def c4_legs(P, torch, steps, warmup):
     sp = P.SearchParams(theta_step_top=cfg["theta_step_top"])
     K = int(np.ceil(360.0 / cfg["theta_step_top"]))
     b = P.Batch(models, imgs, L, cfg["tau_s"], sp, precision=P.TM_FP16)
+    tuned = b.tune(iterations=1)
     for _ in range(warmup):
         b.run(graph=True)
     torch.cuda.synchronize()
@@ -187,7 +196,7 @@ def c4_legs(P, torch, steps, warmup):
     c4 = {"workload": f"{len(scenes)} images (640x480 / 1280x1024 / 2448x2048) x {nm} models "
                       f"({', '.join(str(m.level_info(0)[2]) for m in models)} level-0 points), FP16, graph launch",
           "ms_per_step": dt * 1e3, "detections_per_sec": len(scenes) * nm / dt, "pose_evals_per_sec": poses / dt,
-          "taps_per_sec": taps / dt, "instances_found": f"{found}/{total}"}
+          "taps_per_sec": taps / dt, "instances_found": f"{found}/{total}", "search_form": tuned}
     # C5: 4096 poses near the truth, 10 ascent steps on FP32 fields
     b32 = P.Batch(models, imgs, L, cfg["tau_s"], sp, precision=P.TM_FP32)
     b32.run()
@@ -323,6 +332,8 @@ def main():
 
     # ---- leg 2 (the timed steps): all images in one batched enqueue
     batch = P.Batch([model], imgs, L, cfg["tau_s"], sp, precision=prec_b)
+    tuned = batch.tune(iterations=3) if not args.no_tune else None
+    form = batch.search_form()
     graph = not args.eager
     for _ in range(args.warmup):
         batch.run(graph=graph)
@@ -373,7 +384,8 @@ def main():
         "config": {"workload": f"{nb} images of 640x480 (3 instances of a 128x128 polygon model each) per step, "
                                "4 levels, 1 deg top step (80x60x360 top poses per image), full detection",
                    "images_per_step": nb, "levels": L, "top_angles": K, "model_points_top": n_top,
-                   "path": f"{args.precision}-batched" + ("" if args.eager else ", graph launch")},
+                   "path": f"{args.precision}-batched" + ("" if args.eager else ", graph launch"),
+                   "search_form": dict(form, tuned=tuned is not None)},
         "detections_per_sec": dets_per_s,
         "taps_per_sec": taps_per_det * dets_per_s,
         "fp32_plain": {"pose_evals_per_sec": poses_per_det * plain_steps / plain_s,
@@ -384,7 +396,7 @@ def main():
         "top1_ground_truth_hits": {"fp32_plain": f"{hits_plain}/{nb}", "batched": f"{hits_batch}/{nb}"},
         "roofline": {"kernel": "k_dense_fast (exhaustive top-level search, all images of the step)", "bound": "alu",
                      "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_entry(),
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_entry(form),
                      "launch_us": dense_avg_s * 1e6, "flop_per_launch": flops},
     }
     if args.c4:

@@ -237,6 +237,24 @@ tm_status tm_batch_run(tm_batch* batch, void* stream);
  * Search-kernel timing (tm_timing_enable) does not apply to graph launches. */
 tm_status tm_batch_run_graph(tm_batch* batch, void* stream);
 
+/* Autotuner of a batch's exhaustive search: runs the pyramid stage, then
+ * times every form of the search kernel (6 instruction-level variants × 2,
+ * 4, 8 or 16 waves sharing an angle chunk, where they fit in LDS) for
+ * `iterations` launches each (1 to 1000) on the bound images, and keeps the
+ * fastest for the batch's later runs (a captured graph is discarded and
+ * captured again by the next tm_batch_run_graph).  All forms give
+ * bit-identical results; tuning changes only time.  Waits for the device.
+ * variant_out, waves_out, us_out (each may be NULL): the choice and its mean
+ * time per launch (variant -1 when the batch uses the generic search, which
+ * has no forms to choose from). */
+tm_status tm_batch_tune(tm_batch* batch, int32_t iterations, void* stream, int32_t* variant_out, int32_t* waves_out,
+                        float* us_out);
+
+/* The form of the batch's exhaustive search now in use (default or tuned):
+ * kernel variant and waves sharing an angle chunk (-1 and 0 for the generic
+ * search). */
+tm_status tm_batch_search_form(const tm_batch* batch, int32_t* variant, int32_t* waves);
+
 /* The continuous score, its backward and the FP64 line search (as
  * tm_cont_score, tm_cont_score_backward and tm_cont_line_search) over the
  * pairs of a batch, against the fields its last run built: pose.pair names

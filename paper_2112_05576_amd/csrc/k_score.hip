@@ -632,8 +632,7 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
         p.G = 32;
         p.R = 8;
         p.WY = knob("TM_DENSE_WY", 1, 1, 4);
-        p.WA = knob("TM_DENSE_WA", 4, 1, 16);
-        if (p.WY * p.WA > 16) p.WA = 16 / p.WY;
+        p.WA = 4;  // provisional (LDS check); set below with the chunking
         const int TW = p.G - 2, TH = p.WY * (64 / p.G) * p.R;
         p.LC = 0;
         for (int lc : kLC)
@@ -641,9 +640,9 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
                 p.LC = lc;
                 break;
             }
-        const size_t tile_bytes = (size_t)(TH + 2 * max_halo) * p.LC * (s.precision == TM_FP16 ? 4 : 8);
+        p.tile_lds = (size_t)(TH + 2 * max_halo) * p.LC * (s.precision == TM_FP16 ? 4 : 8);
         const size_t comb_bytes = (size_t)12 * p.WA * TH * TW;
-        p.lds = tile_bytes > comb_bytes ? tile_bytes : comb_bytes;
+        p.lds = p.tile_lds > comb_bytes ? p.tile_lds : comb_bytes;
         if (p.LC == 0 || p.lds > 160 * 1024) p.fast = false;
     }
     if (p.fast) {
@@ -659,9 +658,16 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
         long long per_wave = units / 4096;
         if (per_wave < 1) per_wave = 1;
         per_wave = knob("TM_DENSE_APW", (int)per_wave, 1, 1 << 20);
-        p.A = (int)(per_wave * p.WA);
+        // chunks sized for 4 waves a chunk; the waves sharing a chunk: 16 once
+        // each would get 16 or more angles (large batches: the tile staged
+        // in LDS serves more waves; measured best on the 64-image C2 batch),
+        // else 4
+        p.A = (int)(per_wave * 4);
         p.C = (s.K[s.level] + p.A - 1) / p.A;
         p.max_blocks = max_tiles * p.C;
+        int wa = knob("TM_DENSE_WA", per_wave >= 16 ? 16 : 4, 1, 16);
+        if (p.WY * wa > 16) wa = 16 / p.WY;
+        if (!retune_dense(p, p.variant, wa)) retune_dense(p, p.variant, 4);
     } else {
         long long np_all = 0;
         for (int i = 0; i < npairs; ++i) np_all += (long long)g[i].gw * g[i].gh;
@@ -673,6 +679,19 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
         p.C = (s.K[s.level] + p.A - 1) / p.A;
     }
     return p;
+}
+
+bool retune_dense(DensePlan& p, int variant, int WA)
+{
+    if (!p.fast || variant < 0 || variant > 5 || WA < 1 || p.WY * WA > 16) return false;
+    const int TW = p.G - 2, TH = p.WY * (64 / p.G) * p.R;
+    const size_t comb_bytes = (size_t)12 * WA * TH * TW;
+    const size_t lds = p.tile_lds > comb_bytes ? p.tile_lds : comb_bytes;
+    if (lds > 160 * 1024) return false;
+    p.variant = variant;
+    p.WA = WA;
+    p.lds = lds;
+    return true;
 }
 
 bool build_work(const DensePlan& p, const PairGeom* g, int npairs, std::vector<int2>& out)

@@ -1142,6 +1142,71 @@ TM_EXPORT tm_status tm_batch_run_graph(tm_batch* b, void* stream)
     return TM_OK;
 }
 
+TM_EXPORT tm_status tm_batch_search_form(const tm_batch* b, int32_t* variant, int32_t* waves)
+{
+    if (!b || !variant || !waves) return fail(TM_EINVAL, "tm_batch_search_form: null argument");
+    *variant = b->plan.fast ? b->plan.variant : -1;
+    *waves = b->plan.fast ? b->plan.WA : 0;
+    return TM_OK;
+}
+
+TM_EXPORT tm_status tm_batch_tune(tm_batch* b, int32_t iterations, void* stream, int32_t* variant_out,
+                                  int32_t* waves_out, float* us_out)
+{
+    if (!b) return fail(TM_EINVAL, "tm_batch_tune: null batch");
+    if (iterations < 1 || iterations > 1000) return fail(TM_EINVAL, "tm_batch_tune: iterations must be 1..1000");
+    hipStream_t s = S(stream);
+    if (!b->plan.fast) {
+        if (variant_out) *variant_out = -1;
+        if (waves_out) *waves_out = 0;
+        if (us_out) *us_out = 0.f;
+        return TM_OK;  // the generic search has no forms to choose from
+    }
+    HIP_TRY(tmk::launch_pyramids_batch(b->d_pb, b->d_fa, b->n_images, b->L, b->level_w[0], b->level_h[0],
+                                       b->max_field_blocks, b->level_w, b->level_h, s));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        hipEventDestroy(e0);
+        return hip_fail(e, "tm_batch_tune: hipEventCreate");
+    }
+    tmk::DensePlan best = b->plan;
+    float best_ms = INFINITY;
+    static const int kWaves[] = {2, 4, 8, 16};
+    for (int v = 0; v <= 5 && e == hipSuccess; ++v)
+        for (int wa : kWaves) {
+            tmk::DensePlan p = b->plan;
+            if (!tmk::retune_dense(p, v, wa)) continue;
+            e = tmk::prepare_dense(b->sd, p);
+            if (e == hipSuccess) e = tmk::launch_dense(b->sd, p, b->d_pairs, b->npairs, s);  // warm-up
+            if (e == hipSuccess) e = hipEventRecord(e0, s);
+            for (int it = 0; it < iterations && e == hipSuccess; ++it)
+                e = tmk::launch_dense(b->sd, p, b->d_pairs, b->npairs, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = p;
+            }
+        }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "tm_batch_tune");
+    b->plan = best;
+    if (b->graph) {  // captured with the old form
+        hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    if (variant_out) *variant_out = best.variant;
+    if (waves_out) *waves_out = best.WA;
+    if (us_out) *us_out = best_ms * 1000.f / iterations;
+    return TM_OK;
+}
+
 namespace {
 tm_status batch_cont_check(const tm_batch* b, int level, int n, const void* poses, const void* out, const char* what)
 {

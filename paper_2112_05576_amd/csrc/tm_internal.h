@@ -180,6 +180,7 @@ struct DensePlan {
     int G, R, LC, WY, WA;
     int A, C;                   // angles per workgroup, chunks of angles
     size_t lds;
+    size_t tile_lds;            // the field tile's share of lds
     int max_blocks;             // workgroups of the largest pair (fast path)
     int max_np;                 // translations of the largest pair
     const int2* work = nullptr; // optional device work list (fast path, build_work)
@@ -192,6 +193,10 @@ struct PairGeom {
 };
 
 DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs);
+// Another form of a fast plan with the same tiles and angle chunks (so the
+// same scratch and work list): kernel variant and waves sharing a chunk.
+// false if the plan is not the fast path or the form does not fit.
+bool retune_dense(DensePlan& p, int variant, int WA);
 // Tile counts of a pair under a plan (fast path).
 void plan_tiles(const DensePlan& p, const PairGeom& g, int* tiles_x, int* tiles_y);
 size_t dense_partials_bytes(const DensePlan& p, int np);

@@ -79,6 +79,8 @@ def lib():
                                 ctypes.POINTER(SearchParamsC), _vp, _i32, _vp, _vp, ctypes.POINTER(_vp)],
             "tm_batch_run": [_vp, _vp],
             "tm_batch_run_graph": [_vp, _vp],
+            "tm_batch_tune": [_vp, _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_float)],
+            "tm_batch_search_form": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
             "tm_batch_cont_score": [_vp, _i32, _vp, _i32, _vp, _vp],
             "tm_batch_cont_score_backward": [_vp, _i32, _vp, _i32, _vp, _vp, _vp],
             "tm_batch_cont_line_search": [_vp, _i32, _vp, _vp, _i32, ctypes.POINTER(ctypes.c_double), _i32, _vp, _vp],
@@ -355,6 +357,20 @@ class Batch:
     @property
     def handle(self):
         return self._h
+
+    def tune(self, iterations: int = 3, stream=None) -> dict:
+        """Time every form of the search kernel on the bound images and keep
+        the fastest (results are bit-identical whichever runs)."""
+        v, w, us = _i32(), _i32(), ctypes.c_float()
+        _check(lib().tm_batch_tune(self._h, iterations, _vp(_stream(stream)), ctypes.byref(v), ctypes.byref(w),
+                                   ctypes.byref(us)))
+        return {"variant": v.value, "waves_per_chunk": w.value, "search_us": us.value}
+
+    def search_form(self) -> dict:
+        """The search-kernel form in use: variant and waves sharing a chunk."""
+        v, w = _i32(), _i32()
+        _check(lib().tm_batch_search_form(self._h, ctypes.byref(v), ctypes.byref(w)))
+        return {"variant": v.value, "waves_per_chunk": w.value}
 
     def cont_score(self, level: int, poses: torch.Tensor, pairs, stream=None) -> torch.Tensor:
         """S_c of (n, 3) poses on pairs[i] (image * n_models + model)."""

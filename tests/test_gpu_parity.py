@@ -581,3 +581,30 @@ def test_paper_shaped_search_matches_oracle(index):
     print(f"FP64 {[(d.x, d.y, d.k, d.sw) for d in ref]}, truth {sc.instances}")
     assert len(got) == len(ref) == 1
     _match_detections(got, ref, tr.fields, tr.model, osp, 1)
+
+
+def test_batch_tune_keeps_results():
+    """The autotuner only picks among bit-identical forms of the search: the
+    tuned batch returns exactly the detections of the untuned one, eager and
+    as a graph."""
+    P = _P()
+    case("batch autotune")
+    cfg = synth.CONFIGS[2]
+    scenes = [synth.scene_for_config(2, i) for i in range(6)]
+    models = [P.Model(scenes[0].model, 4, cfg["tau_m"])]
+    images = [torch.from_numpy(s.image).cuda() for s in scenes]
+    sp = P.SearchParams(theta_step_top=1.0)
+    for precision in (0, 1):
+        b = P.Batch(models, images, 4, cfg["tau_s"], sp, precision=precision)
+        b.run()
+        ref = b.results()
+        b.run(graph=True)  # a graph of the untuned form, to be discarded by tune()
+        torch.cuda.synchronize()
+        choice = b.tune(iterations=1)
+        print(f"precision {precision}: {choice}")
+        assert 0 <= choice["variant"] <= 5 and choice["waves_per_chunk"] in (2, 4, 8, 16)
+        assert choice["search_us"] > 0
+        b.run()
+        assert all(_poses_equal(a, c) for a, c in zip(b.results(), ref))
+        b.run(graph=True)
+        assert all(_poses_equal(a, c) for a, c in zip(b.results(), ref))
