@@ -401,21 +401,45 @@ __global__ __launch_bounds__(256) void k_dense_generic(GenericArgs a, const Pair
     int bk = -1;
     const int k0 = chunk * a.A, k1 = min(a.K, k0 + a.A);
     for (int k = k0; k < k1; ++k) {
-        const TabEntry* __restrict__ T = P.tab + (size_t)k * P.n_pad;
+        CTabEntry* T = (CTabEntry*)P.tab + (size_t)k * P.n_pad;  // wave-uniform: scalar loads
         float tw = 0.f, t1 = 0.f;
         for (int i0 = 0; i0 < n; i0 += kBlock) {
             float pw = 0.f, p1 = 0.f;
             const int i1 = min(n, i0 + kBlock);
-            for (int i = i0; i < i1; ++i) {
-                const TabEntry e = T[i];
-                const int px = x + e.qx, py = y + e.qy;
-                float best = -INFINITY;
-                for (int dy = -h; dy <= h; ++dy)
+            if (h == 1) {
+                // the paper's 3x3 window unrolled: the nine loads of a point
+                // (and of the next) are in flight together; same order of
+                // maxima as the general loop below
+#pragma unroll 2
+                for (int i = i0; i < i1; ++i) {
+                    const TabEntry e = tab_entry(T + i);
+                    const int px = x + e.qx, py = y + e.qy;
+                    float v[3][3];
+#pragma unroll
+                    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                        for (int dx = 0; dx < 3; ++dx)
+                            v[dy][dx] = field_dot<PREC>(field, W, H, px + dx - 1, py + dy - 1, e.rx, e.ry);
+                    float best = -INFINITY;
+#pragma unroll
+                    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                        for (int dx = 0; dx < 3; ++dx) best = fmaxf(best, v[dy][dx]);
+                    pw += best;
+                    p1 += v[1][1];
+                }
+            } else {
+                for (int i = i0; i < i1; ++i) {
+                    const TabEntry e = tab_entry(T + i);
+                    const int px = x + e.qx, py = y + e.qy;
+                    float best = -INFINITY;
+                    for (int dy = -h; dy <= h; ++dy)
 #pragma unroll 3
-                    for (int dx = -h; dx <= h; ++dx)
-                        best = fmaxf(best, field_dot<PREC>(field, W, H, px + dx, py + dy, e.rx, e.ry));
-                pw += best;
-                p1 += field_dot<PREC>(field, W, H, px, py, e.rx, e.ry);
+                        for (int dx = -h; dx <= h; ++dx)
+                            best = fmaxf(best, field_dot<PREC>(field, W, H, px + dx, py + dy, e.rx, e.ry));
+                    pw += best;
+                    p1 += field_dot<PREC>(field, W, H, px, py, e.rx, e.ry);
+                }
             }
             tw += pw;
             t1 += p1;
