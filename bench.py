@@ -115,9 +115,10 @@ def traffic_from(fetch_csv, write_csv):
     print(json.dumps(out))
 
 
-def cpu_baseline(scenes, cfg, budget_s):
+def cpu_baseline(scenes, cfg, budget_s, paper=False):
     """The FP64 oracle, as it is, on the host cores: full detections of the
-    same images until the time budget is spent."""
+    same images until the time budget is spent (and, with paper=True, one
+    detection of the paper-shaped search, timed on its own)."""
     import oracle as O
 
     threads = O.default_threads()
@@ -134,8 +135,18 @@ def cpu_baseline(scenes, cfg, budget_s):
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": poses / dt, "unit": "pose-evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_img} full detections of 640x480 images (4 levels, 360 top angles), {dt:.1f} s"}
+    res = {"value": poses / dt, "unit": "pose-evals/s", "cores": threads, "kind": "oracle",
+           "sample": f"{n_img} full detections of 640x480 images (4 levels, 360 top angles), {dt:.1f} s"}
+    if paper:
+        import synth
+
+        sc = synth.scene_for_config(6, 0)
+        pc = sc.config
+        osp = O.SearchParams(step_x=3, step_y=3, theta_min=0.0, theta_range=90.0, theta_step_top=3.0, max_matches=1)
+        t0 = time.perf_counter()
+        O.detect(sc.image, sc.model, O.PyrParams(1, pc["tau_s"]), O.PyrParams(1, pc["tau_m"]), osp, nthreads=threads)
+        res["paper_shape_ms_per_detection"] = (time.perf_counter() - t0) * 1e3
+    return res
 
 
 def traffic_entry(form):
@@ -227,7 +238,7 @@ def c4_legs(P, torch, steps, warmup):
     return c4, c5
 
 
-def paper_leg(P, torch, steps, with_oracle):
+def paper_leg(P, torch, steps):
     """The search of the paper's experiment on synthetic 812x617 frames: every
     3rd pixel, 31 angles over 90 degrees, one level, the single best pose;
     one tm_detect per frame (FP32, the generic search path)."""
@@ -263,15 +274,6 @@ def paper_leg(P, torch, steps, with_oracle):
                        "over 90 deg (271x206x31 poses), 1 level, best pose; FP32, one detection per call",
            "ms_per_detection": dt * 1e3, "pose_evals_per_sec": poses / dt, "top1_ground_truth_hits":
            f"{hits}/{len(imgs)}"}
-    if with_oracle:
-        import oracle as O
-
-        osp = O.SearchParams(**kw)
-        t0 = time.perf_counter()
-        O.detect(scenes[0].image, scenes[0].model, O.PyrParams(1, cfg["tau_s"]), O.PyrParams(1, cfg["tau_m"]), osp,
-                 nthreads=O.default_threads())
-        res["oracle_ms_per_detection"] = (time.perf_counter() - t0) * 1e3
-        res["oracle_threads"] = O.default_threads()
     return res
 
 
@@ -402,9 +404,9 @@ def main():
     if args.c4:
         res["c4"], res["c5"] = c4_legs(P, torch, max(2, args.steps // 10), 1)
     if args.paper:
-        res["paper_shape"] = paper_leg(P, torch, max(8, args.steps), not args.no_cpu_baseline)
+        res["paper_shape"] = paper_leg(P, torch, max(8, args.steps))
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(scenes[:8], cfg, args.cpu_seconds)
+        res["cpu_baseline"] = cpu_baseline(scenes[:8], cfg, args.cpu_seconds, paper=args.paper)
     if args.copy_probe:
         x = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
