@@ -87,6 +87,20 @@ def lib():
         L.orc_cont_score.argtypes = [_f64p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, _f64p, ctypes.c_double,
                                      ctypes.c_double, ctypes.c_double, ctypes.POINTER(ctypes.c_double), _f64p]
         L.orc_cont_score.restype = None
+        L.orc_project.argtypes = [ctypes.c_int, _i32p, _f64p, ctypes.c_double, ctypes.c_double, _i32p, _f64p]
+        L.orc_project.restype = None
+        L.orc_scale.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_int]
+        L.orc_scale.restype = ctypes.c_double
+        L.orc_top_map_sim.argtypes = [_f64p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, _f64p,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                      _f64p, _f64p, _i32p, ctypes.c_int]
+        L.orc_top_map_sim.restype = None
+        L.orc_refine_level_sim.argtypes = [_f64p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, _f64p,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_int, _i32p, _i32p, _i32p, _f64p, _f64p]
+        L.orc_refine_level_sim.restype = None
         _lib = L
     return _lib
 
@@ -123,6 +137,14 @@ class SearchParams:
     nms_min_dist: float = 0.0  # level-0 pixels; <= 0 selects 0.5 x model radius
     max_candidates: int = 32
     max_matches: int = 8
+    # similarity pose (O13-O15): scales scale_min + j * scale_step, j < scale_count
+    scale_min: float = 1.0
+    scale_step: float = 0.0
+    scale_count: int = 1
+
+    @property
+    def similarity(self) -> bool:
+        return self.scale_count > 1 or self.scale_min != 1.0
 
 
 # ------------------------------------------------------------- O1 .. O4
@@ -238,11 +260,26 @@ def rotate(t: np.ndarray, d: np.ndarray, theta_deg: float):
     return q, r
 
 
+def project(t: np.ndarray, d: np.ndarray, theta_deg: float, sigma: float):
+    """O13, the similarity projection: (q, r) = (round(sigma R t), R d)."""
+    n = len(t)
+    t = np.ascontiguousarray(t, np.int32)
+    d = np.ascontiguousarray(d, np.float64)
+    q = np.empty((n, 2), np.int32)
+    r = np.empty((n, 2), np.float64)
+    lib().orc_project(n, t, d, float(theta_deg), float(sigma), q, r)
+    return q, r
+
+
+def scale(sigma_min: float, sigma_step: float, j: int) -> float:
+    return float(lib().orc_scale(float(sigma_min), float(sigma_step), int(j)))
+
+
 # ------------------------------------------------------------- O7, O8
-def score(g: np.ndarray, t, d, ux: int, uy: int, theta_deg: float, win: int = 3):
-    """Eq. (1) at one pose: returns (S_w, S_1)."""
+def score(g: np.ndarray, t, d, ux: int, uy: int, theta_deg: float, win: int = 3, sigma: float = 1.0):
+    """Eq. (1) at one pose (scale sigma: O13): returns (S_w, S_1)."""
     H, W, _ = g.shape
-    q, r = rotate(t, d, theta_deg)
+    q, r = rotate(t, d, theta_deg) if sigma == 1.0 else project(t, d, theta_deg, sigma)
     sw = ctypes.c_double()
     s1 = ctypes.c_double()
     lib().orc_score(np.ascontiguousarray(g), W, H, len(t), q, r, int(ux), int(uy), int(win),
@@ -262,6 +299,21 @@ def top_map(g: np.ndarray, t, d, theta_min: float, step: float, K: int, sx: int 
                       np.ascontiguousarray(d, np.float64), float(theta_min), float(step), int(K),
                       int(sx), int(sy), int(win), mw, m1, mk,
                       int(nthreads if nthreads else default_threads()))
+    return mw, m1, mk
+
+
+def top_map_sim(g: np.ndarray, t, d, theta_min: float, step: float, K: int, sigma_min: float, sigma_step: float,
+                S: int, sx: int = 1, sy: int = 1, win: int = 3, nthreads: int | None = None):
+    """O14: best (S_w, S_1, m = j K + k) per translation over angles and scales."""
+    H, W, _ = g.shape
+    Gw, Gh = (W + sx - 1) // sx, (H + sy - 1) // sy
+    mw = np.empty((Gh, Gw), np.float64)
+    m1 = np.empty((Gh, Gw), np.float64)
+    mk = np.empty((Gh, Gw), np.int32)
+    lib().orc_top_map_sim(np.ascontiguousarray(g), W, H, len(t), np.ascontiguousarray(t, np.int32),
+                          np.ascontiguousarray(d, np.float64), float(theta_min), float(step), int(K),
+                          float(sigma_min), float(sigma_step), int(S), int(sx), int(sy), int(win), mw, m1, mk,
+                          int(nthreads if nthreads else default_threads()))
     return mw, m1, mk
 
 
@@ -320,6 +372,19 @@ def refine_level(g, ml: ModelLevel, cand: Candidates, theta_min: float, step_l: 
     return c
 
 
+def refine_level_sim(g, ml: ModelLevel, cand: Candidates, theta_min: float, step_l: float, K: int, K_above: int,
+                     full: bool, win: int, sigma_min: float, sigma_step: float) -> Candidates:
+    """O15: one coarse-to-fine step at each candidate's scale; k holds m = j K + k."""
+    H, W, _ = g.shape
+    c = Candidates(cand.x.astype(np.int32).copy(), cand.y.astype(np.int32).copy(),
+                   cand.k.astype(np.int32).copy(), cand.sw.astype(np.float64).copy(),
+                   cand.s1.astype(np.float64).copy())
+    lib().orc_refine_level_sim(np.ascontiguousarray(g), W, H, len(ml.t), ml.t, ml.d, float(theta_min),
+                               float(step_l), int(K), int(K_above), int(bool(full)), int(win), float(sigma_min),
+                               float(sigma_step), len(c), c.x, c.y, c.k, c.sw, c.s1)
+    return c
+
+
 def final(cand: Candidates, min_score: float, dmin: float, max_out: int) -> Candidates:
     """O11: key sort, greedy NMS at level 0, score floor, at most max_out."""
     c = Candidates(cand.x.astype(np.int32).copy(), cand.y.astype(np.int32).copy(),
@@ -338,6 +403,8 @@ class Detection:
     theta: float
     sw: float
     s1: float
+    j: int = 0          # scale index (similarity pose)
+    scale: float = 1.0
 
 
 @dataclass
@@ -366,18 +433,33 @@ def detect(search: np.ndarray, model_img: np.ndarray, pp_search: PyrParams, pp_m
     step_top = level_step(sp, L, top)
     K_top = level_count(sp, step_top)
     ml = model.levels[top]
-    mw, m1, mk = top_map(fields[top], ml.t, ml.d, sp.theta_min, step_top, K_top, sp.step_x, sp.step_y,
-                         sp.neighbourhood, nthreads)
+    if sp.similarity:
+        mw, m1, mk = top_map_sim(fields[top], ml.t, ml.d, sp.theta_min, step_top, K_top, sp.scale_min,
+                                 sp.scale_step, sp.scale_count, sp.step_x, sp.step_y, sp.neighbourhood, nthreads)
+    else:
+        mw, m1, mk = top_map(fields[top], ml.t, ml.d, sp.theta_min, step_top, K_top, sp.step_x, sp.step_y,
+                             sp.neighbourhood, nthreads)
     cand = select(mw, m1, mk, sp.step_x, sp.step_y, top, sp.min_score, dmin, sp.max_candidates)
     refined = []
     cur = cand
+    K_above = K_top
     for l in range(L - 2, -1, -1):
         step_l = level_step(sp, L, l)
-        cur = refine_level(fields[l], model.levels[l], cur, sp.theta_min, step_l, level_count(sp, step_l),
-                           full, sp.neighbourhood)
+        K_l = level_count(sp, step_l)
+        if sp.similarity:
+            cur = refine_level_sim(fields[l], model.levels[l], cur, sp.theta_min, step_l, K_l, K_above, full,
+                                   sp.neighbourhood, sp.scale_min, sp.scale_step)
+        else:
+            cur = refine_level(fields[l], model.levels[l], cur, sp.theta_min, step_l, K_l, full,
+                               sp.neighbourhood)
+        K_above = K_l
         refined.append(cur)
     fin = final(cur, sp.min_score, dmin, sp.max_matches)
     step0 = level_step(sp, L, 0)
-    dets = [Detection(int(x), int(y), int(k), theta(sp.theta_min, step0, int(k)), float(w), float(s))
-            for x, y, k, w, s in fin.rows()]
+    K0 = level_count(sp, step0)
+    dets = []
+    for x, y, m, w, s in fin.rows():
+        j, k = (m // K0, m % K0) if sp.similarity else (0, m)
+        dets.append(Detection(int(x), int(y), int(k), theta(sp.theta_min, step0, int(k)), float(w), float(s),
+                              j, scale(sp.scale_min, sp.scale_step, j) if sp.similarity else 1.0))
     return DetectTrace(fields, model, (mw, m1, mk), cand, refined, dets)

@@ -22,6 +22,11 @@
  *   O9  candidates: local max + greedy NMS   Sec. II, paras. 3-4 (generalised)
  *   O10 coarse-to-fine refinement            Sec. II, para. 2 (top image first)
  *   O11 final selection                      Sec. II, para. 3
+ *   O12 continuous (bilinear) score          extension beside Eq. (1)
+ *   O13 similarity projection (scale)        Sec. II (other projection types
+ *                                            than the rigid Eq. (2))
+ *   O14 exhaustive (x, y, theta, scale)      as O8 over angles x scales
+ *   O15 refinement at a chosen scale         as O10, scale kept
  * Where the paper is silent the reading taken is stated at the function.
  */
 #include <math.h>
@@ -526,4 +531,130 @@ ORC_API void orc_cont_score(const double* g, int W, int H, int n, const int32_t*
     grad[0] = gx / (double)n;
     grad[1] = gy / (double)n;
     grad[2] = k * gt / (double)n;
+}
+
+/* ----------------------------------------------------------------- O13 */
+/* The paper names other projection types than its rigid Eq. (2); this is the
+ * similarity pose: p_i = sigma R(theta) t_i + u.  q_i rounds sigma times the
+ * rotated offset (rotation first, as in O6, then the product with sigma) with
+ * the same half-up rule and 1e-9 snap; r_i = R(theta) d_i, since a uniform
+ * scale leaves directions unchanged.  sigma = 1 gives O6 exactly. */
+ORC_API void orc_project(int n, const int32_t* t, const double* d, double theta_deg, double sigma,
+                         int32_t* q, double* r)
+{
+    double c, s;
+    orc_sincos_deg(theta_deg, &c, &s);
+    for (int i = 0; i < n; ++i) {
+        double tx = (double)t[2 * i], ty = (double)t[2 * i + 1];
+        double vx = c * tx - s * ty;
+        double vy = s * tx + c * ty;
+        vx = sigma * vx;
+        vy = sigma * vy;
+        q[2 * i + 0] = (int32_t)floor(vx + 0.5 + 1e-9);
+        q[2 * i + 1] = (int32_t)floor(vy + 0.5 + 1e-9);
+        double dx = d[2 * i], dy = d[2 * i + 1];
+        r[2 * i + 0] = c * dx - s * dy;
+        r[2 * i + 1] = s * dx + c * dy;
+    }
+}
+
+/* Scale j of the grid sigma_min + j * sigma_step (a product, not a running
+ * sum). */
+ORC_API double orc_scale(double sigma_min, double sigma_step, int j)
+{
+    return sigma_min + (double)j * sigma_step;
+}
+
+/* ----------------------------------------------------------------- O14 */
+/* O8 over angles and scales: every translation on the step grid, every angle
+ * k < K and scale j < S; the pose index is m = j K + k (scale-major), and per
+ * translation the best m is kept by the key (S_w desc, S_1 desc, m asc):
+ * indices visited in ascending order, replaced only by a strictly better
+ * score.  With S = 1 and sigma 1 this is O8. */
+ORC_API void orc_top_map_sim(const double* g, int W, int H, int n, const int32_t* t, const double* d,
+                             double theta_min, double step, int K, double sigma_min, double sigma_step, int S,
+                             int sx, int sy, int win, double* mapw, double* map1, int32_t* mapk, int nthreads)
+{
+    int Gw = (W + sx - 1) / sx, Gh = (H + sy - 1) / sy;
+    int M = K * S;
+    int32_t* q = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)n * M);
+    double* r = (double*)malloc(sizeof(double) * 2 * (size_t)n * M);
+    for (int j = 0; j < S; ++j)
+        for (int k = 0; k < K; ++k) {
+            int m = j * K + k;
+            orc_project(n, t, d, orc_theta(theta_min, step, k), orc_scale(sigma_min, sigma_step, j),
+                        q + 2 * (size_t)n * m, r + 2 * (size_t)n * m);
+        }
+    if (nthreads < 1) nthreads = 1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+    for (int y = 0; y < Gh; ++y) {
+        for (int x = 0; x < Gw; ++x) {
+            double bw = -INFINITY, b1 = -INFINITY;
+            int bm = -1;
+            for (int m = 0; m < M; ++m) {
+                double sw, s1;
+                orc_score(g, W, H, n, q + 2 * (size_t)n * m, r + 2 * (size_t)n * m, x * sx, y * sy, win, &sw,
+                          &s1);
+                if (sw > bw || (sw == bw && s1 > b1)) {
+                    bw = sw;
+                    b1 = s1;
+                    bm = m;
+                }
+            }
+            size_t o = (size_t)y * Gw + x;
+            mapw[o] = bw;
+            map1[o] = b1;
+            mapk[o] = bm;
+        }
+    }
+    free(q);
+    free(r);
+}
+
+/* ----------------------------------------------------------------- O15 */
+/* O10 at the candidate's scale: a candidate of level l+1 carries the pose
+ * index m = j K_above + k; at level l the 27 poses (2x+a, 2y+b, 2k+c) are
+ * scored at scale j (the scale grid is the same on every level, so there is
+ * nothing finer to refine) and the best by the key (S_w, S_1, x, y, then the
+ * level-l index j K + k') replaces the candidate, written back as that index.
+ * With one scale this is O10. */
+ORC_API void orc_refine_level_sim(const double* g, int W, int H, int n, const int32_t* t, const double* d,
+                                  double theta_min, double step_l, int K, int K_above, int full, int win,
+                                  double sigma_min, double sigma_step, int nc, int32_t* cx, int32_t* cy, int32_t* cm,
+                                  double* cw, double* c1)
+{
+    int32_t* q = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)n);
+    double* r = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+    for (int c = 0; c < nc; ++c) {
+        int j = cm[c] / K_above, k0 = cm[c] % K_above;
+        double sigma = orc_scale(sigma_min, sigma_step, j);
+        orc_cand best = {-INFINITY, -INFINITY, 0, 0, 0};
+        int have = 0;
+        for (int dk = -1; dk <= 1; ++dk) {
+            int k = orc_angle_index(2 * k0 + dk, K, full);
+            orc_project(n, t, d, orc_theta(theta_min, step_l, k), sigma, q, r);
+            for (int b = -1; b <= 1; ++b) {
+                for (int a = -1; a <= 1; ++a) {
+                    int x = 2 * cx[c] + a, y = 2 * cy[c] + b;
+                    if (x < 0 || x >= W || y < 0 || y >= H) continue;
+                    orc_cand me;
+                    orc_score(g, W, H, n, q, r, x, y, win, &me.sw, &me.s1);
+                    me.x = x;
+                    me.y = y;
+                    me.k = j * K + k;
+                    if (!have || orc_better(&me, &best)) {
+                        best = me;
+                        have = 1;
+                    }
+                }
+            }
+        }
+        cx[c] = best.x;
+        cy[c] = best.y;
+        cm[c] = best.k;
+        cw[c] = best.sw;
+        c1[c] = best.s1;
+    }
+    free(q);
+    free(r);
 }

@@ -21,6 +21,7 @@ from .workloads import (  # noqa: F401
     make_model_shape,
     paste_rot90,
     render_model,
+    render_posed,
     render_scene,
     scene_for_config,
 )

@@ -117,16 +117,18 @@ def make_model_shape(kind: str, size: int, rng: np.random.Generator, n_holes=(1,
     raise ValueError(kind)
 
 
-def _coverage(shape: Shape, X: np.ndarray, Y: np.ndarray, ux: float, uy: float, theta_deg: float):
-    """Fraction of each pixel (X, Y) covered by the shape posed at (u, theta)."""
+def _coverage(shape: Shape, X: np.ndarray, Y: np.ndarray, ux: float, uy: float, theta_deg: float,
+              scale: float = 1.0):
+    """Fraction of each pixel (X, Y) covered by the shape posed at (u, theta)
+    and scaled by `scale` about its reference point."""
     c, s = np.cos(np.deg2rad(theta_deg)), np.sin(np.deg2rad(theta_deg))
     acc = np.zeros(X.shape, np.float64)
     for oy in _SUB:
         for ox in _SUB:
             px = X + ox - ux
             py = Y + oy - uy
-            tx = c * px + s * py  # R(theta)^T (p - u)
-            ty = -s * px + c * py
+            tx = (c * px + s * py) / scale  # R(theta)^T (p - u) / scale
+            ty = (-s * px + c * py) / scale
             acc += shape.contains(tx, ty)
     return acc / 16.0
 
@@ -143,6 +145,7 @@ class Instance:
     x: float
     y: float
     theta: float
+    scale: float = 1.0
 
 
 @dataclass
@@ -167,13 +170,13 @@ def _place(rng, W, H, radius, count, taken):
     return out
 
 
-def _paint_instance(img, shape, ux, uy, theta, fg):
+def _paint_instance(img, shape, ux, uy, theta, fg, scale=1.0):
     H, W = img.shape
-    r = shape.radius + 2
+    r = shape.radius * scale + 2
     x0, x1 = max(0, int(np.floor(ux - r))), min(W, int(np.ceil(ux + r)) + 1)
     y0, y1 = max(0, int(np.floor(uy - r))), min(H, int(np.ceil(uy + r)) + 1)
     Y, X = np.mgrid[y0:y1, x0:x1].astype(np.float64)
-    cov = _coverage(shape, X, Y, ux, uy, theta)
+    cov = _coverage(shape, X, Y, ux, uy, theta, scale)
     sub = img[y0:y1, x0:x1]
     img[y0:y1, x0:x1] = sub + (fg - sub) * cov
 
@@ -212,18 +215,20 @@ def _clutter(img, rng, count):
 def render_scene(rng: np.random.Generator, W: int, H: int, shape: Shape, model_size: int,
                  n_inst: int, noise: float, occl_max: float = 0.0, gain=(1.0, 1.0),
                  offset=(0.0, 0.0), clutter: int = 0, fg: float = 200.0, bg: float = 40.0,
-                 cfg: dict | None = None, theta_max: float = 360.0) -> Scene:
-    """Render n_inst posed instances (angles U[0, theta_max)), then apply the
+                 cfg: dict | None = None, theta_max: float = 360.0, scales=None) -> Scene:
+    """Render n_inst posed instances (angles U[0, theta_max); with `scales`
+    (lo, hi), each instance also scaled by U[lo, hi]), then apply the
     distortions in order: occluders, global gain and offset, clutter, Gaussian
     noise, clip and round."""
     img = np.full((H, W), bg, np.float64)
     taken = []
-    spots = _place(rng, W, H, shape.radius, n_inst, taken)
+    spots = _place(rng, W, H, shape.radius * (scales[1] if scales else 1.0), n_inst, taken)
     inst = []
     for (x, y) in spots:
         th = float(rng.uniform(0.0, theta_max))
-        _paint_instance(img, shape, x, y, th, fg)
-        inst.append(Instance(float(x), float(y), th))
+        sc = float(rng.uniform(*scales)) if scales else 1.0
+        _paint_instance(img, shape, x, y, th, fg, sc)
+        inst.append(Instance(float(x), float(y), th, sc))
     if occl_max > 0:
         for it in inst:
             frac = rng.uniform(0.0, occl_max)
@@ -270,6 +275,13 @@ CONFIGS = {
             noise=8.0, occl=0.30, gain=(0.5, 2.0), offset=(-40.0, 40.0), clutter=50, levels=1,
             tau_m=30.0, tau_s=80.0, theta_step_top=3.0, theta_range=90.0, step_xy=3, theta_max_inst=90.0,
             max_matches=1),
+    # Similarity pose (x, y, theta, scale): C2 scenes whose instances are also
+    # scaled by U[0.8, 1.2]; searched over scales 0.8 .. 1.2 in steps of 0.1,
+    # 3 levels (a 32-pixel model at the top) and 4 degree top steps.
+    7: dict(name="similarity 640x480", W=640, H=480, model_size=128, shape="polygon", n_inst=3,
+            noise=8.0, occl=0.30, gain=(0.5, 2.0), offset=(-40.0, 40.0), clutter=50, levels=3,
+            tau_m=30.0, tau_s=80.0, theta_step_top=4.0, theta_range=360.0, scales=(0.8, 1.2),
+            scale_min=0.8, scale_step=0.1, scale_count=5),
 }
 
 
@@ -368,7 +380,16 @@ def scene_for_config(ci: int, index: int = 0, **override) -> Scene:
     shape = make_model_shape(cfg["shape"], cfg["model_size"], shape_rng)
     return render_scene(rng, cfg["W"], cfg["H"], shape, cfg["model_size"], cfg["n_inst"], cfg["noise"],
                         cfg["occl"], cfg["gain"], cfg["offset"], cfg["clutter"], cfg=cfg,
-                        theta_max=cfg.get("theta_max_inst", 360.0))
+                        theta_max=cfg.get("theta_max_inst", 360.0), scales=cfg.get("scales"))
+
+
+def render_posed(shape: Shape, W: int, H: int, x: float, y: float, theta: float, scale: float = 1.0,
+                 fg: float = 200.0, bg: float = 40.0) -> np.ndarray:
+    """A clean W x H image with one instance of `shape` at pose (x, y, theta)
+    and scale, drawn analytically (no distortions)."""
+    img = np.full((H, W), bg, np.float64)
+    _paint_instance(img, shape, x, y, theta, fg, scale)
+    return np.clip(np.rint(img), 0, 255).astype(np.uint8)
 
 
 def paste_rot90(model: np.ndarray, W: int, H: int, ux: int, uy: int, quarter: int, bg: int = 40) -> np.ndarray:

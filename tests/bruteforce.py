@@ -42,21 +42,21 @@ def model(img, tau):
     return t, d
 
 
-def rotate(t, d, theta_deg):
+def rotate(t, d, theta_deg, sigma=1.0):
     th = np.deg2rad(theta_deg)
     c, s = np.cos(th), np.sin(th)
     R = np.array([[c, -s], [s, c]])
     v = t.astype(np.float64) @ R.T
-    q = np.floor(v + 0.5 + 1e-9).astype(np.int64)
+    q = np.floor(sigma * v + 0.5 + 1e-9).astype(np.int64)
     r = d @ R.T
     return q, r
 
 
-def score_volume(g, t, d, thetas, win=3):
-    """S_w and S_1 for every (k, y, x): arrays of shape (K, H, W)."""
+def score_volume(g, t, d, thetas, win=3, sigma=1.0):
+    """S_w and S_1 for every (k, y, x) at scale sigma: arrays of shape (K, H, W)."""
     H, W, _ = g.shape
     h = (win - 1) // 2
-    P = 2 * (np.abs(t).max() + 2 + h) + 2
+    P = 2 * (int(np.ceil(sigma * np.abs(t).max())) + 2 + h) + 2
     gp = np.zeros((H + 2 * P, W + 2 * P, 2))
     gp[P:P + H, P:P + W] = g
     K = len(thetas)
@@ -65,7 +65,7 @@ def score_volume(g, t, d, thetas, win=3):
     ys, xs = np.mgrid[0:H, 0:W]
     n = len(t)
     for k, th in enumerate(thetas):
-        q, r = rotate(t, d, th)
+        q, r = rotate(t, d, th, sigma)
         best = np.full((n, H, W), -np.inf)
         centre = None
         for dy in range(-h, h + 1):
