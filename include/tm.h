@@ -85,6 +85,14 @@ typedef struct {
     float nms_min_dist;           /* level-0 pixels; <= 0: half the model radius */
     int32_t max_candidates;       /* 1 .. 1024, kept after the top level      */
     int32_t max_matches;          /* >= 1, returned by tm_detect              */
+    /* Similarity pose (the paper names other projection types than its rigid
+     * Eq. (2)): p = sigma R(theta) t + u over the scales scale_min + j *
+     * scale_step, j < scale_count.  The top level is searched over every
+     * (angle, scale); lower levels refine (x, y, theta) at the chosen scale.
+     * scale_count 1 with scale_min 1 is the rigid search. */
+    double scale_min;             /* > 0 (1 for the rigid search)              */
+    double scale_step;            /* >= 0                                      */
+    int32_t scale_count;          /* 1 .. 64                                   */
 } tm_search_params;
 
 /* A pose with its scores.  (x, y) is in pixels of `level`; k indexes the
@@ -98,7 +106,7 @@ typedef struct {
     float theta_deg;
     float score_w;
     float score_1;
-    int32_t reserved;
+    int32_t j;                    /* scale index (0 for the rigid search)     */
 } tm_pose;
 
 /* An arbitrary pose to score: integer translation, any angle. */

@@ -73,6 +73,8 @@ struct LevelArgs {
     double theta_min;
     int src;               // centre buffer read (0/1); the other one is written
     int staged;            // pairs with rtile[level] set are refined by k_refine_tile
+    double sigma_min, sigma_step;  // scale grid; a candidate keeps its scale index j
+    int S;                         // scales (indices outside 0 .. S-1 are clamped)
 };
 
 // The 9 windowed votes and 9 centre votes of one point from the 5x5 block of
@@ -133,31 +135,37 @@ __device__ __forceinline__ void block_sum18(float (&aw)[9], float (&a1)[9], floa
 
 // The candidate's pose at the level above: picked by the first wave from that
 // level's sums (or the candidate itself on the first refined level),
-// published in cur[0..2]; `writer` also records it as the centre.
+// published in cur[0..3] (x, y, angle index, scale index); `writer` also
+// records it as the centre.  The 27 poses of a pick share the scale, so the
+// key's last component (the pose index j K + k) orders them as k does.
 __device__ void take_centre(const LevelArgs& a, const PairDesc& P, int c, bool writer, int* cur)
 {
     const int l = a.level;
     const int lane = threadIdx.x & 63;
     if (threadIdx.x < 64) {
-        int x, y, k;
+        int x, y, k, j;
         float sw, s1;
         if (a.pick) {
             const tm_pose ctr = P.ctr[a.src][c];
             const int la = l + 1;
             pick27(P.part[la] + (size_t)c * 54, ctr.x, ctr.y, ctr.k, P.W[la], P.H[la], P.n[la], a.K_above, a.full,
                    &sw, &s1, &x, &y, &k);
+            j = ctr.j;
         } else {
             const tm_pose p = P.cand[c];
             x = p.x;
             y = p.y;
             k = p.k;
+            j = p.j;
             sw = p.score_w;
             s1 = p.score_1;
         }
+        j = min(max(j, 0), a.S - 1);  // poses given by a caller may name any scale
         if (lane == 0) {
             cur[0] = x;
             cur[1] = y;
             cur[2] = k;
+            cur[3] = j;
             if (writer) {
                 tm_pose o;
                 o.x = x;
@@ -167,7 +175,7 @@ __device__ void take_centre(const LevelArgs& a, const PairDesc& P, int c, bool w
                 o.theta_deg = (float)level_theta(a.theta_min, a.step_above, k);
                 o.score_w = sw;
                 o.score_1 = s1;
-                o.reserved = 0;
+                o.j = j;
                 P.ctr[a.src ^ 1][c] = o;
             }
         }
@@ -198,7 +206,7 @@ template <int PREC>
 __global__ __launch_bounds__(kThreads) void k_refine_level(LevelArgs a, const PairDesc* __restrict__ pairs)
 {
     __shared__ float red[kWaves][18];
-    __shared__ int cur[3];
+    __shared__ int cur[4];
     const PairDesc& P = pairs[blockIdx.y];
     const int l = a.level;
     if (a.staged && P.rtile[l]) return;  // this pair's level is refined by k_refine_tile
@@ -210,6 +218,7 @@ __global__ __launch_bounds__(kThreads) void k_refine_level(LevelArgs a, const Pa
     take_centre(a, P, c, g == 0, cur);
     __syncthreads();
     const int x = cur[0], y = cur[1], k = cur[2];
+    const double sigma = scale_of(a.sigma_min, a.sigma_step, cur[3]);
     const void* field = P.field[l];
     const int W = P.W[l], H = P.H[l], n = P.n[l];
     const ModelPoint* __restrict__ pts = P.pts[l];
@@ -231,8 +240,8 @@ __global__ __launch_bounds__(kThreads) void k_refine_level(LevelArgs a, const Pa
             const bool two = j < n;
             int qx0, qy0, qx1 = 0, qy1 = 0;
             double rx0, ry0, rx1 = 0, ry1 = 0;
-            project_point(pts[i], cs, sn, &qx0, &qy0, &rx0, &ry0);
-            if (two) project_point(pts[j], cs, sn, &qx1, &qy1, &rx1, &ry1);
+            project_point_s(pts[i], cs, sn, sigma, &qx0, &qy0, &rx0, &ry0);
+            if (two) project_point_s(pts[j], cs, sn, sigma, &qx1, &qy1, &rx1, &ry1);
             Block5 b0, b1;
             block5(2 * x + qx0, 2 * y + qy0, W, H, b0);
             block5(2 * x + qx1, 2 * y + qy1, W, H, b1);
@@ -253,7 +262,7 @@ __global__ __launch_bounds__(kThreads) void k_refine_level(LevelArgs a, const Pa
         for (int i = threadIdx.x; i < n; i += kThreads) {
             int qx, qy;
             double rx, ry;
-            project_point(pts[i], cs, sn, &qx, &qy, &rx, &ry);
+            project_point_s(pts[i], cs, sn, sigma, &qx, &qy, &rx, &ry);
             const float fx = (float)rx, fy = (float)ry;
             const int px = 2 * x + qx, py = 2 * y + qy;
 #pragma unroll
@@ -297,7 +306,7 @@ __global__ __launch_bounds__(kThreads) void k_refine_tile(LevelArgs a, const Pai
     using T = typename Raw<PREC>::T;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ float red[kWaves][18];
-    __shared__ int cur[3];
+    __shared__ int cur[4];
     const PairDesc& P = pairs[blockIdx.y];
     const int l = a.level;
     if (!P.rtile[l]) return;
@@ -308,6 +317,7 @@ __global__ __launch_bounds__(kThreads) void k_refine_tile(LevelArgs a, const Pai
     take_centre(a, P, c, true, cur);
     __syncthreads();
     const int x = cur[0], y = cur[1], k = cur[2];
+    const double sigma = scale_of(a.sigma_min, a.sigma_step, cur[3]);
     const void* field = P.field[l];
     const int W = P.W[l], H = P.H[l], n = P.n[l];
     const ModelPoint* __restrict__ pts = P.pts[l];
@@ -349,7 +359,7 @@ __global__ __launch_bounds__(kThreads) void k_refine_tile(LevelArgs a, const Pai
         for (int i = threadIdx.x; i < n; i += kThreads) {
             int qx, qy;
             double rx, ry;
-            project_point(pts[i], cs, sn, &qx, &qy, &rx, &ry);
+            project_point_s(pts[i], cs, sn, sigma, &qx, &qy, &rx, &ry);
             const int px = 2 * x + qx, py = 2 * y + qy;
             // |q| < rad per component, so the block covers px - 2 .. px + 2
             const T* b = tile + (size_t)(py - 2 - oy) * S + (px - 2 - ox);
@@ -398,7 +408,7 @@ __global__ __launch_bounds__(64) void k_refine_pick(PickArgs a, const PairDesc* 
         o.theta_deg = (float)level_theta(a.theta_min, a.step0, k);
         o.score_w = sw;
         o.score_1 = s1;
-        o.reserved = 0;
+        o.j = ctr.j;  // written by take_centre, already in range
         P.cand[c] = o;
     }
 }
@@ -451,6 +461,9 @@ hipError_t launch_refine(const SearchDesc& s, const PairDesc* d, int npairs, int
         a.theta_min = s.theta_min;
         a.src = src;
         a.staged = rp.staged;
+        a.sigma_min = s.sigma_min;
+        a.sigma_step = s.sigma_step;
+        a.S = s.S > 0 ? s.S : 1;
         if (!rp.staged || rp.gather[l]) {
             dim3 grid((unsigned)(s.max_cand * 3), npairs);
             if (s.precision == TM_FP16)

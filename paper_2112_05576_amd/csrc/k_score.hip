@@ -676,7 +676,7 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
         for (int i = 0; i < npairs; ++i) {
             int tx, ty;
             plan_tiles(p, g[i], &tx, &ty);
-            units += (long long)tx * ty * s.K[s.level];
+            units += (long long)tx * ty * poses_per_translation(s);
             max_tiles = max(max_tiles, tx * ty);
         }
         long long per_wave = units / 4096;
@@ -687,7 +687,7 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
         // in LDS serves more waves; measured best on the 64-image C2 batch),
         // else 4
         p.A = (int)(per_wave * 4);
-        p.C = (s.K[s.level] + p.A - 1) / p.A;
+        p.C = (poses_per_translation(s) + p.A - 1) / p.A;
         p.max_blocks = max_tiles * p.C;
         int wa = knob("TM_DENSE_WA", per_wave >= 16 ? 16 : 4, 1, 16);
         if (p.WY * wa > 16) wa = 16 / p.WY;
@@ -697,10 +697,10 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
         for (int i = 0; i < npairs; ++i) np_all += (long long)g[i].gw * g[i].gh;
         const long long blocks = (np_all + 255) / 256;
         long long C = (2048 + blocks - 1) / blocks;  // enough workgroups to fill the chip
-        if (C > s.K[s.level]) C = s.K[s.level];
+        if (C > poses_per_translation(s)) C = poses_per_translation(s);
         if (C < 1) C = 1;
-        p.A = (int)((s.K[s.level] + C - 1) / C);
-        p.C = (s.K[s.level] + p.A - 1) / p.A;
+        p.A = (int)((poses_per_translation(s) + C - 1) / C);
+        p.C = (poses_per_translation(s) + p.A - 1) / p.A;
     }
     return p;
 }
@@ -794,7 +794,7 @@ hipError_t launch_dense(const SearchDesc& s, const DensePlan& p, const PairDesc*
     if (p.fast) {
         FastArgs a;
         a.level = s.level;
-        a.K = s.K[s.level];
+        a.K = poses_per_translation(s);
         a.A = p.A;
         a.WY = p.WY;
         a.WA = p.WA;
@@ -807,7 +807,7 @@ hipError_t launch_dense(const SearchDesc& s, const DensePlan& p, const PairDesc*
     } else {
         GenericArgs a;
         a.level = s.level;
-        a.K = s.K[s.level];
+        a.K = poses_per_translation(s);
         a.A = p.A;
         a.sx = s.sx;
         a.sy = s.sy;

@@ -149,6 +149,7 @@ struct SelectArgs {
     int sx, sy, level, cap;
     float min_score;
     double theta_min, step_level;
+    int K;  // angles of the level: map index m = j K + k (0: m is the angle index)
 };
 
 // One workgroup per pair (blockIdx.y).
@@ -224,14 +225,15 @@ __global__ __launch_bounds__(1024) void k_select(SelectArgs sa, const PairDesc* 
     for (int t = threadIdx.x; t < m; t += blockDim.x) {
         const int c = acc_i[t];
         tm_pose o;
+        const int mi = a.k[c];
         o.x = a.x[c];
         o.y = a.y[c];
-        o.k = a.k[c];
+        o.k = sa.K > 0 ? mi % sa.K : mi;
+        o.j = sa.K > 0 ? mi / sa.K : 0;
         o.level = level;
-        o.theta_deg = (float)level_theta(theta_min, step_level, a.k[c]);
+        o.theta_deg = (float)level_theta(theta_min, step_level, o.k);
         o.score_w = a.sw[c];
         o.score_1 = a.s1[c];
-        o.reserved = 0;
         out[t] = o;
     }
     if (threadIdx.x == 0) *n_out = m;
@@ -243,6 +245,7 @@ struct FinalArgs {
     int max_cand, cap;
     float min_score;
     double theta_min, step0;
+    int K0;  // angles of level 0; the key's last component is m = j K0 + k
 };
 
 // One workgroup per pair (blockIdx.y).
@@ -276,7 +279,7 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs fa, const PairDesc* __r
         u_s1[idx] = c.score_1;
         u_x[idx] = c.x;
         u_y[idx] = c.y;
-        u_k[idx] = c.k;
+        u_k[idx] = c.j * fa.K0 + c.k;
     }
     __syncthreads();
     const int N = count;
@@ -298,14 +301,15 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs fa, const PairDesc* __r
     for (int t = threadIdx.x; t < m; t += blockDim.x) {
         const int c = acc_i[t];
         tm_pose o;
+        const int mi = a.k[c];
         o.x = a.x[c];
         o.y = a.y[c];
-        o.k = a.k[c];
+        o.k = mi % fa.K0;
+        o.j = mi / fa.K0;
         o.level = 0;
         o.score_w = a.sw[c];
         o.score_1 = a.s1[c];
-        o.theta_deg = (float)level_theta(theta_min, step0, a.k[c]);
-        o.reserved = 0;
+        o.theta_deg = (float)level_theta(theta_min, step0, o.k);
         out[t] = o;
     }
     if (threadIdx.x == 0) *n_out = m;
@@ -326,6 +330,7 @@ hipError_t launch_select(const SearchDesc& s, const PairDesc* d, int npairs, int
     a.min_score = s.min_score;
     a.theta_min = s.theta_min;
     a.step_level = s.step[s.level];
+    a.K = s.S > 1 ? s.K[s.level] : 0;
     hipLaunchKernelGGL(k_select, dim3(1, npairs), dim3(1024), 0, st, a, d);
     return hipGetLastError();
 }
@@ -338,6 +343,7 @@ hipError_t launch_final(const SearchDesc& s, const PairDesc* d, int npairs, hipS
     a.min_score = s.min_score;
     a.theta_min = s.theta_min;
     a.step0 = s.step[0];
+    a.K0 = s.K[0] > 0 ? s.K[0] : 1;
     hipLaunchKernelGGL(k_final, dim3(1, npairs), dim3(256), 0, st, a, d);
     return hipGetLastError();
 }

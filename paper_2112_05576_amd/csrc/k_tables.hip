@@ -1,6 +1,7 @@
-// Rotated model tables: Eq. (2) applied to every model point of one level at
-// every angle theta_min + k*step of the level's grid, in FP64, stored as the
-// integer position offset and the FP32 / FP16 rotated direction.
+// Projected model tables: Eq. (2) (with a scale factor for the similarity
+// pose) applied to every model point of one level at every angle
+// theta_min + k*step of the level's grid and every scale, in FP64, stored as
+// the integer position offset and the FP32 / FP16 rotated direction.
 #include "tm_device.h"
 
 namespace tmk {
@@ -8,10 +9,12 @@ namespace tmk {
 namespace {
 
 __global__ __launch_bounds__(256) void k_tables(const ModelPoint* __restrict__ pts, int n, int n_pad,
-                                                 double theta_min, double step, TabEntry* __restrict__ tab)
+                                                 double theta_min, double step, int K, double sigma_min,
+                                                 double sigma_step, TabEntry* __restrict__ tab)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int k = blockIdx.y;
+    const int m = blockIdx.y;  // j * K + k
+    const int k = m % K, j = m / K;
     if (i >= n_pad) return;
     TabEntry e;
     if (i < n) {
@@ -19,7 +22,7 @@ __global__ __launch_bounds__(256) void k_tables(const ModelPoint* __restrict__ p
         sincos_deg(level_theta(theta_min, step, k), &c, &s);
         int qx, qy;
         double rx, ry;
-        project_point(pts[i], c, s, &qx, &qy, &rx, &ry);
+        project_point_s(pts[i], c, s, scale_of(sigma_min, sigma_step, j), &qx, &qy, &rx, &ry);
         e.qx = (int16_t)qx;
         e.qy = (int16_t)qy;
         e.rx = (float)rx;
@@ -34,7 +37,7 @@ __global__ __launch_bounds__(256) void k_tables(const ModelPoint* __restrict__ p
         e.ry = 0.0f;
         e.rh = 0u;
     }
-    tab[(size_t)k * n_pad + i] = e;
+    tab[(size_t)m * n_pad + i] = e;
 }
 
 __global__ __launch_bounds__(256) void k_table_export(const TabEntry* __restrict__ tab, int n, int n_pad, int K,
@@ -53,10 +56,11 @@ __global__ __launch_bounds__(256) void k_table_export(const TabEntry* __restrict
 }  // namespace
 
 hipError_t launch_tables(const ModelPoint* pts, int n, int n_pad, double theta_min, double step, int K,
-                         TabEntry* tab, hipStream_t s)
+                         double sigma_min, double sigma_step, int S, TabEntry* tab, hipStream_t s)
 {
-    dim3 grid((n_pad + 255) / 256, K);
-    hipLaunchKernelGGL(k_tables, grid, dim3(256), 0, s, pts, n, n_pad, theta_min, step, tab);
+    dim3 grid((n_pad + 255) / 256, K * S);
+    hipLaunchKernelGGL(k_tables, grid, dim3(256), 0, s, pts, n, n_pad, theta_min, step, K, sigma_min, sigma_step,
+                       tab);
     return hipGetLastError();
 }
 

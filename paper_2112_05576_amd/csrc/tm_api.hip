@@ -83,7 +83,18 @@ struct Grid {
     double step[TM_MAX_LEVELS];
     int K[TM_MAX_LEVELS];
     int full;
+    int S;                         // scales
+    double sigma_min, sigma_step;  // scale grid
+    double sigma_max;              // largest scale (>= 1 for the radius bounds)
 };
+
+// Bound on |q| components of a model level's points over all angles at
+// scales up to sigma_max: |round(sigma R t)| <= sigma |t| + 1.
+int scaled_rad(const tm_model_level& ml, double sigma_max)
+{
+    if (sigma_max <= 1.0) return ml.rad;
+    return std::max(ml.rad, (int)ceil(sigma_max * sqrt((double)ml.radius2)) + 1);
+}
 
 tm_status check_search(const tm_search_params* sp, const char* what)
 {
@@ -100,6 +111,11 @@ tm_status check_search(const tm_search_params* sp, const char* what)
     if (sp->max_matches < 1) return fail(TM_EINVAL, "%s: max_matches must be >= 1", what);
     if (!isfinite(sp->min_score) || !isfinite(sp->nms_min_dist))
         return fail(TM_EINVAL, "%s: min_score and nms_min_dist must be finite", what);
+    if (sp->scale_count < 1 || sp->scale_count > 64) return fail(TM_EINVAL, "%s: scale_count must be 1..64", what);
+    if (!(sp->scale_min > 0.0) || !isfinite(sp->scale_min) || !(sp->scale_step >= 0.0) || !isfinite(sp->scale_step))
+        return fail(TM_EINVAL, "%s: scale_min must be > 0 and scale_step >= 0", what);
+    if (sp->scale_min + (sp->scale_count - 1) * sp->scale_step > 16.0)
+        return fail(TM_EINVAL, "%s: scales above 16", what);
     return TM_OK;
 }
 
@@ -113,6 +129,13 @@ tm_status make_grid(const tm_search_params* sp, int L, Grid* g)
         if (K > 65535.0) return fail(TM_EINVAL, "angle grid too fine: %g angles at level %d", K, l);
         g->K[l] = (int)K;
     }
+    g->S = sp->scale_count;
+    g->sigma_min = sp->scale_min;
+    g->sigma_step = sp->scale_step;
+    g->sigma_max = std::max(1.0, sp->scale_min + (sp->scale_count - 1) * sp->scale_step);
+    if ((long long)g->K[L - 1] * g->S > 65535)
+        return fail(TM_EINVAL, "%d angles x %d scales at the top level: more than 65535 poses per translation",
+                    g->K[L - 1], g->S);
     return TM_OK;
 }
 
@@ -168,17 +191,19 @@ tm_status ensure_ws(tm_pyramid* p, size_t bytes, hipStream_t s)
 }
 
 // Rotated table of the model's `level` for a grid; cached on the model.
-tm_status get_table(const tm_model* mc, int level, double theta_min, double step, int K, hipStream_t s,
-                    const tmk::TabEntry** out)
+tm_status get_table(const tm_model* mc, int level, double theta_min, double step, int K, const Grid& g,
+                    hipStream_t s, const tmk::TabEntry** out)
 {
     tm_model* m = const_cast<tm_model*>(mc);
     tm_model_table_cache& c = m->cache;
     const tm_model_level& ml = m->lv[level];
-    if (c.tab && c.level == level && c.theta_min == theta_min && c.step == step && c.K == K) {
+    if (scaled_rad(ml, g.sigma_max) > 32000) return fail(TM_EINVAL, "model too large for the scale range");
+    if (c.tab && c.level == level && c.theta_min == theta_min && c.step == step && c.K == K && c.S == g.S &&
+        c.sigma_min == g.sigma_min && c.sigma_step == g.sigma_step) {
         *out = c.tab;
         return TM_OK;
     }
-    size_t need = (size_t)K * ml.n_pad;
+    size_t need = (size_t)K * g.S * ml.n_pad;
     if (need > c.cap) {
         if (c.tab) {
             HIP_TRY(hipStreamSynchronize(s));
@@ -189,11 +214,15 @@ tm_status get_table(const tm_model* mc, int level, double theta_min, double step
         HIP_TRY(hipMalloc(&c.tab, need * sizeof(tmk::TabEntry)));
         c.cap = need;
     }
-    HIP_TRY(tmk::launch_tables(ml.pts, ml.n, ml.n_pad, theta_min, step, K, c.tab, s));
+    HIP_TRY(tmk::launch_tables(ml.pts, ml.n, ml.n_pad, theta_min, step, K, g.sigma_min, g.sigma_step, g.S, c.tab,
+                               s));
     c.level = level;
     c.theta_min = theta_min;
     c.step = step;
     c.K = K;
+    c.S = g.S;
+    c.sigma_min = g.sigma_min;
+    c.sigma_step = g.sigma_step;
     *out = c.tab;
     return TM_OK;
 }
@@ -232,17 +261,20 @@ tmk::SearchDesc make_search(const tm_search_params* sp, const Grid& g, int level
     s.min_score = sp->min_score;
     s.max_cand = sp->max_candidates;
     s.capacity = capacity;
+    s.S = g.S;
+    s.sigma_min = g.sigma_min;
+    s.sigma_step = g.sigma_step;
     return s;
 }
 
-tmk::PairGeom pair_geom(const tm_model* m, const tm_pyramid* p, int level, int sx, int sy)
+tmk::PairGeom pair_geom(const tm_model* m, const tm_pyramid* p, int level, int sx, int sy, double sigma_max)
 {
     tmk::PairGeom g;
     g.W = p->lv[level].w;
     g.H = p->lv[level].h;
     g.gw = (g.W + sx - 1) / sx;
     g.gh = (g.H + sy - 1) / sy;
-    g.rad = m->lv[level].rad;
+    g.rad = scaled_rad(m->lv[level], sigma_max);
     g.n = m->lv[level].n;
     return g;
 }
@@ -250,7 +282,7 @@ tmk::PairGeom pair_geom(const tm_model* m, const tm_pyramid* p, int level, int s
 // Static part of a pair descriptor: the image's levels, the model's levels,
 // the rotated table of the searched level and the suppression distance.
 void pair_static(tmk::PairDesc* d, const tm_model* m, const tm_pyramid* p, const tmk::TabEntry* tab, int level,
-                 const tmk::PairGeom& g, const tmk::DensePlan& plan, float dmin, int win)
+                 const tmk::PairGeom& g, const tmk::DensePlan& plan, float dmin, int win, double sigma_max)
 {
     for (int l = 0; l < p->L; ++l) {
         d->field[l] = p->lv[l].field;
@@ -258,12 +290,12 @@ void pair_static(tmk::PairDesc* d, const tm_model* m, const tm_pyramid* p, const
         d->H[l] = p->lv[l].h;
         d->pts[l] = m->lv[l].pts;
         d->n[l] = m->lv[l].n;
-        d->rad_l[l] = m->lv[l].rad;
-        d->rtile[l] = tmk::refine_tile_fits(m->lv[l].rad, p->precision, win) ? 1 : 0;
+        d->rad_l[l] = scaled_rad(m->lv[l], sigma_max);
+        d->rtile[l] = tmk::refine_tile_fits(d->rad_l[l], p->precision, win) ? 1 : 0;
     }
     d->tab = tab;
     d->n_pad = m->lv[level].n_pad;
-    d->rad = m->lv[level].rad;
+    d->rad = g.rad;
     d->gw = g.gw;
     d->gh = g.gh;
     tmk::plan_tiles(plan, g, &d->tiles_x, &d->tiles_y);
@@ -350,16 +382,16 @@ tm_status put_desc(tm_pyramid* p, const tmk::PairDesc& d, hipStream_t s, tmk::Pa
 constexpr int kStagedMin = 512;
 
 tmk::RefinePlan refine_plan(const tm_model* const* models, int n_models, int L, int win, int precision,
-                            long long candidates)
+                            long long candidates, double sigma_max)
 {
     tmk::RefinePlan rp;
     memset(&rp, 0, sizeof(rp));
     rp.staged = candidates >= kStagedMin;
     for (int l = 0; l < L; ++l)
         for (int j = 0; j < n_models; ++j) {
-            const tm_model_level& ml = models[j]->lv[l];
-            if (tmk::refine_tile_fits(ml.rad, precision, win))
-                rp.tile_bytes[l] = std::max(rp.tile_bytes[l], (int)tmk::refine_tile_bytes(ml.rad, precision));
+            const int rad = scaled_rad(models[j]->lv[l], sigma_max);
+            if (tmk::refine_tile_fits(rad, precision, win))
+                rp.tile_bytes[l] = std::max(rp.tile_bytes[l], (int)tmk::refine_tile_bytes(rad, precision));
             else
                 rp.gather[l] = 1;
         }
@@ -590,7 +622,12 @@ TM_EXPORT tm_status tm_model_table(const tm_model* m, int32_t level, double thet
     if (level < 0 || level >= m->L) return fail(TM_EINVAL, "tm_model_table: bad level %d", level);
     if (K < 1 || K > 65535 || !(step > 0.0)) return fail(TM_EINVAL, "tm_model_table: bad angle grid");
     const tmk::TabEntry* tab = nullptr;
-    tm_status st = get_table(m, level, theta_min, step, K, S(stream), &tab);
+    Grid rigid;
+    memset(&rigid, 0, sizeof(rigid));
+    rigid.S = 1;
+    rigid.sigma_min = 1.0;
+    rigid.sigma_max = 1.0;
+    tm_status st = get_table(m, level, theta_min, step, K, rigid, S(stream), &tab);
     if (st != TM_OK) return st;
     HIP_TRY(tmk::launch_table_export(tab, m->lv[level].n, m->lv[level].n_pad, K, q, r, S(stream)));
     return TM_OK;
@@ -649,14 +686,14 @@ TM_EXPORT tm_status tm_score_map(const tm_model* m, tm_pyramid* p, int32_t level
     if (st != TM_OK) return st;
     hipStream_t s = S(stream);
     const tmk::TabEntry* tab = nullptr;
-    st = get_table(m, level, sp->theta_min_deg, g.step[level], g.K[level], s, &tab);
+    st = get_table(m, level, sp->theta_min_deg, g.step[level], g.K[level], g, s, &tab);
     if (st != TM_OK) return st;
     tmk::SearchDesc sd = make_search(sp, g, level, p->precision, 1);
-    tmk::PairGeom pg = pair_geom(m, p, level, sp->step_x, sp->step_y);
+    tmk::PairGeom pg = pair_geom(m, p, level, sp->step_x, sp->step_y, g.sigma_max);
     tmk::DensePlan plan = tmk::plan_dense(sd, &pg, 1);
     tmk::PairDesc d;
     memset(&d, 0, sizeof(d));
-    pair_static(&d, m, p, tab, level, pg, plan, 0.f, sp->neighbourhood);
+    pair_static(&d, m, p, tab, level, pg, plan, 0.f, sp->neighbourhood, g.sigma_max);
     st = ensure_ws(p, kDescBytes + pair_scratch(&d, m, pg, plan, p->L, 1, true, false, false, nullptr), s);
     if (st != TM_OK) return st;
     pair_scratch(&d, m, pg, plan, p->L, 1, true, false, false, reinterpret_cast<uint8_t*>(p->ws.ptr) + kDescBytes);
@@ -739,14 +776,14 @@ TM_EXPORT tm_status tm_detect(const tm_model* m, tm_pyramid* p, const tm_search_
     hipStream_t s = S(stream);
     const int top = p->L - 1;
     const tmk::TabEntry* tab = nullptr;
-    st = get_table(m, top, sp->theta_min_deg, g.step[top], g.K[top], s, &tab);
+    st = get_table(m, top, sp->theta_min_deg, g.step[top], g.K[top], g, s, &tab);
     if (st != TM_OK) return st;
     tmk::SearchDesc sd = make_search(sp, g, top, p->precision, std::min(capacity, sp->max_matches));
-    tmk::PairGeom pg = pair_geom(m, p, top, sp->step_x, sp->step_y);
+    tmk::PairGeom pg = pair_geom(m, p, top, sp->step_x, sp->step_y, g.sigma_max);
     tmk::DensePlan plan = tmk::plan_dense(sd, &pg, 1);
     tmk::PairDesc d;
     memset(&d, 0, sizeof(d));
-    pair_static(&d, m, p, tab, top, pg, plan, default_dmin(m, sp), sp->neighbourhood);
+    pair_static(&d, m, p, tab, top, pg, plan, default_dmin(m, sp), sp->neighbourhood, g.sigma_max);
     const bool refine = p->L > 1;
     st = ensure_ws(p, kDescBytes + pair_scratch(&d, m, pg, plan, p->L, sp->max_candidates, true, true, refine, nullptr),
                    s);
@@ -764,7 +801,8 @@ TM_EXPORT tm_status tm_detect(const tm_model* m, tm_pyramid* p, const tm_search_
     HIP_TRY(tmk::launch_dense(sd, plan, dd, 1, s, ev0, ev1));
     HIP_TRY(tmk::launch_select(sd, dd, 1, pg.gw * pg.gh, s));
     if (refine) {
-        const tmk::RefinePlan rp = refine_plan(&m, 1, p->L, sp->neighbourhood, p->precision, sp->max_candidates);
+        const tmk::RefinePlan rp =
+            refine_plan(&m, 1, p->L, sp->neighbourhood, p->precision, sp->max_candidates, g.sigma_max);
         HIP_TRY(tmk::launch_refine(sd, dd, 1, top, rp, s));
     }
     HIP_TRY(tmk::launch_final(sd, dd, 1, s));
@@ -815,11 +853,11 @@ TM_EXPORT tm_status tm_refine(const tm_model* m, tm_pyramid* p, const tm_search_
     hipStream_t s = S(stream);
     tmk::SearchDesc sd = make_search(sp, g, from_level, p->precision, 1);
     sd.max_cand = n;
-    tmk::PairGeom pg = pair_geom(m, p, from_level, sp->step_x, sp->step_y);
+    tmk::PairGeom pg = pair_geom(m, p, from_level, sp->step_x, sp->step_y, g.sigma_max);
     tmk::DensePlan plan = {};
     tmk::PairDesc d;
     memset(&d, 0, sizeof(d));
-    pair_static(&d, m, p, nullptr, from_level, pg, plan, 0.f, sp->neighbourhood);
+    pair_static(&d, m, p, nullptr, from_level, pg, plan, 0.f, sp->neighbourhood, g.sigma_max);
     st = ensure_ws(p, kDescBytes + pair_scratch(&d, m, pg, plan, p->L, n, false, false, true, nullptr), s);
     if (st != TM_OK) return st;
     pair_scratch(&d, m, pg, plan, p->L, n, false, false, true, reinterpret_cast<uint8_t*>(p->ws.ptr) + kDescBytes);
@@ -828,7 +866,7 @@ TM_EXPORT tm_status tm_refine(const tm_model* m, tm_pyramid* p, const tm_search_
     tmk::PairDesc* dd = nullptr;
     st = put_desc(p, d, s, &dd);
     if (st != TM_OK) return st;
-    const tmk::RefinePlan rp = refine_plan(&m, 1, p->L, sp->neighbourhood, p->precision, n);
+    const tmk::RefinePlan rp = refine_plan(&m, 1, p->L, sp->neighbourhood, p->precision, n, g.sigma_max);
     HIP_TRY(tmk::launch_refine(sd, dd, 1, from_level, rp, s));
     return TM_OK;
 }
@@ -984,7 +1022,7 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
     std::vector<tmk::PairGeom> pg(b->npairs);
     for (int i = 0; i < n_images; ++i)
         for (int j = 0; j < n_models; ++j)
-            pg[i * n_models + j] = pair_geom(models[j], b->pyrs[i], top, sp->step_x, sp->step_y);
+            pg[i * n_models + j] = pair_geom(models[j], b->pyrs[i], top, sp->step_x, sp->step_y, g.sigma_max);
     b->plan = tmk::plan_dense(b->sd, pg.data(), b->npairs);
     std::vector<int2> work;
     if (!tmk::build_work(b->plan, pg.data(), b->npairs, work)) {
@@ -992,16 +1030,21 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
         return fail(TM_EDEVICE, "tm_batch_create: internal error in the search work list");
     }
     b->rplan = refine_plan(models, n_models, L, sp->neighbourhood, pp->precision,
-                           (long long)b->npairs * sp->max_candidates);
+                           (long long)b->npairs * sp->max_candidates, g.sigma_max);
     for (auto& q : pg) b->max_np = std::max(b->max_np, q.gw * q.gh);
 
     // one allocation: tables, descriptors, pyramid arguments, pair scratch
     const int K = g.K[top];
+    for (int j = 0; j < n_models; ++j)
+        if (scaled_rad(models[j]->lv[top], g.sigma_max) > 32000) {
+            tm_batch_free(b);
+            return fail(TM_EINVAL, "tm_batch_create: model too large for the scale range");
+        }
     std::vector<size_t> tab_off(n_models);
     size_t off = 0;
     for (int j = 0; j < n_models; ++j) {
         tab_off[j] = off;
-        off = align_up(off + (size_t)K * models[j]->lv[top].n_pad * sizeof(tmk::TabEntry), 256);
+        off = align_up(off + (size_t)K * g.S * models[j]->lv[top].n_pad * sizeof(tmk::TabEntry), 256);
     }
     const size_t desc_off = off;
     off = align_up(off + (size_t)b->npairs * sizeof(tmk::PairDesc), 256);
@@ -1032,8 +1075,8 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
     b->d_fa = reinterpret_cast<tmk::FieldsArg*>(base + fa_off);
     for (int j = 0; j < n_models; ++j) {
         const tm_model_level& ml = models[j]->lv[top];
-        e = tmk::launch_tables(ml.pts, ml.n, ml.n_pad, sp->theta_min_deg, g.step[top], K,
-                               reinterpret_cast<tmk::TabEntry*>(base + tab_off[j]), s);
+        e = tmk::launch_tables(ml.pts, ml.n, ml.n_pad, sp->theta_min_deg, g.step[top], K, g.sigma_min, g.sigma_step,
+                               g.S, reinterpret_cast<tmk::TabEntry*>(base + tab_off[j]), s);
         if (e != hipSuccess) {
             tm_batch_free(b);
             return hip_fail(e, "tm_batch_create: tables");
@@ -1046,7 +1089,7 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
             tmk::PairDesc& d = hd[q];
             memset(&d, 0, sizeof(d));
             pair_static(&d, models[j], b->pyrs[i], reinterpret_cast<tmk::TabEntry*>(base + tab_off[j]), top, pg[q],
-                        b->plan, default_dmin(models[j], sp), sp->neighbourhood);
+                        b->plan, default_dmin(models[j], sp), sp->neighbourhood, g.sigma_max);
             pair_scratch(&d, models[j], pg[q], b->plan, L, sp->max_candidates, true, true, refine,
                          base + pair_off[q]);
             d.out = out + (size_t)q * capacity;

@@ -45,6 +45,34 @@ __device__ __forceinline__ void project_point(const ModelPoint& p, double c, dou
     *ry = s * dx + c * dy;
 }
 
+// The similarity projection: q = floor(sigma (R t) + 0.5 + 1e-9), the
+// rotation first and then the product with sigma (rounded separately), and
+// r = R d.  sigma == 1 gives project_point exactly.
+__device__ __forceinline__ void project_point_s(const ModelPoint& p, double c, double s, double sigma, int* qx,
+                                                int* qy, double* rx, double* ry)
+{
+#pragma clang fp contract(off)
+    double tx = (double)p.tx, ty = (double)p.ty;
+    double vx = c * tx - s * ty;
+    double vy = s * tx + c * ty;
+    vx = sigma * vx;
+    vy = sigma * vy;
+    *qx = (int)floor(vx + 0.5 + 1e-9);
+    *qy = (int)floor(vy + 0.5 + 1e-9);
+    double gx = (double)p.gx, gy = (double)p.gy;
+    double m = sqrt(gx * gx + gy * gy);
+    double dx = gx / m, dy = gy / m;
+    *rx = c * dx - s * dy;
+    *ry = s * dx + c * dy;
+}
+
+// Scale j of the grid sigma_min + j * sigma_step.
+__device__ __forceinline__ double scale_of(double sigma_min, double sigma_step, int j)
+{
+#pragma clang fp contract(off)
+    return sigma_min + (double)j * sigma_step;
+}
+
 __device__ __forceinline__ double level_theta(double theta_min, double step, int k)
 {
 #pragma clang fp contract(off)

@@ -69,6 +69,8 @@ struct tm_model_table_cache {
     int level = -1;
     double theta_min = 0, step = 0;
     int K = 0;
+    int S = 0;
+    double sigma_min = 0, sigma_step = 0;
     tmk::TabEntry* tab = nullptr;  // device, K * n_pad entries
     size_t cap = 0;               // entries allocated
 };
@@ -124,9 +126,10 @@ hipError_t launch_sobel_fields(const PyrLevel* lv, int L, long long T2, int prec
 // counts into counts[l].
 hipError_t launch_model_points(const PyrLevel* lv, int L, long long T2, ModelPoint* const* pts, int* counts,
                                hipStream_t s);
-// Rotated table of one level for angles theta_min + k*step, k < K.
+// Projected table of one level for angles theta_min + k*step, k < K, and
+// scales sigma_min + j*sigma_step, j < S: entry [j*K + k][i].
 hipError_t launch_tables(const ModelPoint* pts, int n, int n_pad, double theta_min, double step, int K,
-                         TabEntry* tab, hipStream_t s);
+                         double sigma_min, double sigma_step, int S, TabEntry* tab, hipStream_t s);
 // Expand a table into plain int32 q pairs and float r pairs.
 hipError_t launch_table_export(const TabEntry* tab, int n, int n_pad, int K, int32_t* q, float* r, hipStream_t s);
 
@@ -171,7 +174,13 @@ struct SearchDesc {
     int full, win, sx, sy, precision;
     float min_score;
     int max_cand, capacity;
+    int S;                      // scales (1: rigid)
+    double sigma_min, sigma_step;
 };
+
+// Poses per translation at the searched level: angles x scales, indexed
+// m = j * K + k (scale-major).
+inline int poses_per_translation(const SearchDesc& s) { return s.K[s.level] * s.S; }
 
 // Launch plan of the exhaustive search, common to all pairs.
 struct DensePlan {

@@ -36,13 +36,14 @@ class SearchParamsC(ctypes.Structure):
     _fields_ = [("step_x", ctypes.c_int32), ("step_y", ctypes.c_int32), ("theta_min_deg", ctypes.c_double),
                 ("theta_range_deg", ctypes.c_double), ("theta_step_top_deg", ctypes.c_double),
                 ("neighbourhood", ctypes.c_int32), ("min_score", ctypes.c_float), ("nms_min_dist", ctypes.c_float),
-                ("max_candidates", ctypes.c_int32), ("max_matches", ctypes.c_int32)]
+                ("max_candidates", ctypes.c_int32), ("max_matches", ctypes.c_int32), ("scale_min", ctypes.c_double),
+                ("scale_step", ctypes.c_double), ("scale_count", ctypes.c_int32)]
 
 
-# tm_pose: x, y, k, level (int32), theta_deg, score_w, score_1 (float32), reserved
+# tm_pose: x, y, k, level (int32), theta_deg, score_w, score_1 (float32), j (scale index)
 POSE_WORDS = 8
 POSE_DTYPE = np.dtype([("x", "<i4"), ("y", "<i4"), ("k", "<i4"), ("level", "<i4"), ("theta", "<f4"),
-                       ("sw", "<f4"), ("s1", "<f4"), ("reserved", "<i4")])
+                       ("sw", "<f4"), ("s1", "<f4"), ("j", "<i4")])
 EVAL_DTYPE = np.dtype([("x", "<i4"), ("y", "<i4"), ("theta", "<f8")])
 
 _lib = None
@@ -143,11 +144,17 @@ class SearchParams:
     nms_min_dist: float = 0.0
     max_candidates: int = 32
     max_matches: int = 8
+    scale_min: float = 1.0     # similarity pose: scales scale_min + j * scale_step, j < scale_count
+    scale_step: float = 0.0
+    scale_count: int = 1
 
     def c(self) -> SearchParamsC:
         return SearchParamsC(self.step_x, self.step_y, self.theta_min, self.theta_range, self.theta_step_top,
                              self.neighbourhood, self.min_score, self.nms_min_dist, self.max_candidates,
-                             self.max_matches)
+                             self.max_matches, self.scale_min, self.scale_step, self.scale_count)
+
+    def scale(self, j: int) -> float:
+        return self.scale_min + j * self.scale_step
 
 
 class Model:
