@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--eager", action="store_true", help="batched leg as plain enqueues instead of a graph launch")
     ap.add_argument("--no-tune", action="store_true", help="keep the default search-kernel form (no autotuning)")
     ap.add_argument("--c4", action="store_true", help="also time the 64 x 8 mixed batch and the C5 refinement")
+    ap.add_argument("--similarity", action="store_true",
+                    help="also time the similarity-pose search (x, y, theta, scale) on 64 scaled 640x480 scenes")
     ap.add_argument("--paper", action="store_true",
                     help="also time the paper's own search shape (812x617, 3 px / 3 deg steps, 90 deg, one level)")
     ap.add_argument("--copy-probe", action="store_true", help="end with a 256 MiB elementwise copy (counter scale)")
@@ -238,6 +240,43 @@ def c4_legs(P, torch, steps, warmup):
     return c4, c5
 
 
+def similarity_leg(P, torch, steps):
+    """64 scaled 640x480 scenes (instances scaled by U[0.8, 1.2]) searched over
+    5 scales x 90 angles at the top of 3 levels, batched (FP16, graph launch,
+    tuned); ground-truth hits within 2 px, 2 degrees and 0.05 in scale."""
+    import synth
+
+    cfg = synth.CONFIGS[7]
+    L = cfg["levels"]
+    scenes = [synth.scene_for_config(7, i) for i in range(64)]
+    model = P.Model(scenes[0].model, L, cfg["tau_m"])
+    imgs = [torch.from_numpy(s.image).cuda() for s in scenes]
+    sp = P.SearchParams(theta_step_top=cfg["theta_step_top"], scale_min=cfg["scale_min"],
+                        scale_step=cfg["scale_step"], scale_count=cfg["scale_count"])
+    b = P.Batch([model], imgs, L, cfg["tau_s"], sp, precision=P.TM_FP16)
+    tuned = b.tune(iterations=2)
+    b.run(graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.run(graph=True)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    res = b.results()
+    K = int(np.ceil(360.0 / cfg["theta_step_top"]))
+    top = (480 >> (L - 1)) * (640 >> (L - 1)) * K * cfg["scale_count"]
+    hits = sum(len(d) > 0 and any(np.hypot(d[0]["x"] - it.x, d[0]["y"] - it.y) <= 2.0 and
+                                  _ang(d[0]["theta"], it.theta) <= 2.0 and
+                                  abs(sp.scale(int(d[0]["j"])) - it.scale) <= 0.05 for it in sc.instances)
+               for d, sc in zip(res, scenes))
+    return {"workload": f"64 images of 640x480 with 3 instances scaled by U[0.8, 1.2]; {L} levels, top level "
+                        f"{640 >> (L - 1)}x{480 >> (L - 1)} x {K} angles x {cfg['scale_count']} scales "
+                        f"({cfg['scale_min']} .. {sp.scale(cfg['scale_count'] - 1):.1f}); FP16, graph launch",
+            "ms_per_step": dt * 1e3, "detections_per_sec": len(scenes) / dt,
+            "pose_evals_per_sec": top * len(scenes) / dt, "top1_ground_truth_hits": f"{hits}/{len(scenes)}",
+            "search_form": tuned}
+
+
 def paper_leg(P, torch, steps):
     """The search of the paper's experiment on synthetic 812x617 frames: every
     3rd pixel, 31 angles over 90 degrees, one level, the single best pose;
@@ -405,6 +444,8 @@ def main():
         res["c4"], res["c5"] = c4_legs(P, torch, max(2, args.steps // 10), 1)
     if args.paper:
         res["paper_shape"] = paper_leg(P, torch, max(8, args.steps))
+    if args.similarity:
+        res["similarity"] = similarity_leg(P, torch, max(5, args.steps // 4))
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(scenes[:8], cfg, args.cpu_seconds, paper=args.paper)
     if args.copy_probe:
