@@ -66,12 +66,12 @@ def lib():
         L.orc_rotate.argtypes = [ctypes.c_int, _i32p, _f64p, ctypes.c_double, _i32p, _f64p]
         L.orc_rotate.restype = None
         L.orc_score.argtypes = [_f64p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, _f64p,
-                                ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                 ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.orc_score.restype = None
         L.orc_top_map.argtypes = [_f64p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, _f64p,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
-                                  ctypes.c_int, ctypes.c_int, _f64p, _f64p, _i32p, ctypes.c_int]
+                                  ctypes.c_int, ctypes.c_int, ctypes.c_int, _f64p, _f64p, _i32p, ctypes.c_int]
         L.orc_top_map.restype = None
         L.orc_select.argtypes = [_f64p, _f64p, _i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_float,
@@ -79,7 +79,7 @@ def lib():
         L.orc_select.restype = ctypes.c_int
         L.orc_refine_level.argtypes = [_f64p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, _f64p,
                                        ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
-                                       ctypes.c_int, ctypes.c_int, _i32p, _i32p, _i32p, _f64p, _f64p]
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, _i32p, _i32p, _f64p, _f64p]
         L.orc_refine_level.restype = None
         L.orc_final.argtypes = [ctypes.c_int, _i32p, _i32p, _i32p, _f64p, _f64p, ctypes.c_double,
                                 ctypes.c_float, ctypes.c_int]
@@ -94,13 +94,15 @@ def lib():
         L.orc_top_map_sim.argtypes = [_f64p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, _f64p,
                                       ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                                      _f64p, _f64p, _i32p, ctypes.c_int]
+                                      ctypes.c_int, _f64p, _f64p, _i32p, ctypes.c_int]
         L.orc_top_map_sim.restype = None
         L.orc_refine_level_sim.argtypes = [_f64p, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i32p, _f64p,
                                            ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int,
-                                           ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
-                                           ctypes.c_int, _i32p, _i32p, _i32p, _f64p, _f64p]
+                                           ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_int, _i32p, _i32p, _i32p, _f64p, _f64p]
         L.orc_refine_level_sim.restype = None
+        L.orc_grad_down.argtypes = [_i32p, _i32p, ctypes.c_int, ctypes.c_int, _i32p, _i32p]
+        L.orc_grad_down.restype = None
         _lib = L
     return _lib
 
@@ -120,6 +122,9 @@ class PyrParams:
     (gradient magnitude) threshold, on the scale of the integer Sobel."""
     levels: int = 1
     edge_thresh: float = 30.0
+    # "grey": pyramid of the grey image, edges per level (O3); "gradient": the
+    # pyramid of the full image's Sobel gradients (O17)
+    source: str = "grey"
 
 
 @dataclass
@@ -137,6 +142,9 @@ class SearchParams:
     nms_min_dist: float = 0.0  # level-0 pixels; <= 0 selects 0.5 x model radius
     max_candidates: int = 32
     max_matches: int = 8
+    # "all": every tap of the window votes, off-edge taps 0 (O7); "edge": edge
+    # taps only, 0 for a window without one (O16)
+    vote: str = "all"
     # similarity pose (O13-O15): scales scale_min + j * scale_step, j < scale_count
     scale_min: float = 1.0
     scale_step: float = 0.0
@@ -145,6 +153,18 @@ class SearchParams:
     @property
     def similarity(self) -> bool:
         return self.scale_count > 1 or self.scale_min != 1.0
+
+    @property
+    def vote_mode(self) -> int:
+        return _vote_mode(self.vote)
+
+
+def _vote_mode(vote) -> int:
+    if vote in ("all", 0):
+        return 0
+    if vote in ("edge", 1):
+        return 1
+    raise ValueError(f"vote must be 'all' or 'edge', got {vote!r}")
 
 
 # ------------------------------------------------------------- O1 .. O4
@@ -161,13 +181,38 @@ def edge_threshold(tau: float) -> int:
     return int(lib().orc_edge_threshold(float(np.float32(tau))))
 
 
-def edge_field(img: np.ndarray, tau: float) -> np.ndarray:
-    """Unit direction field (H, W, 2), zero off the edge set (O1 + O2)."""
-    gx, gy = sobel(img)
+def direction_field(gx: np.ndarray, gy: np.ndarray, tau: float) -> np.ndarray:
+    """O2 on integer gradients: unit direction field (H, W, 2), zero off the edge set."""
+    gx = np.ascontiguousarray(gx, np.int32)
+    gy = np.ascontiguousarray(gy, np.int32)
     H, W = gx.shape
     g = np.empty((H, W, 2), np.float64)
     lib().orc_edge_field(gx, gy, W, H, edge_threshold(tau), g)
     return g
+
+
+def edge_field(img: np.ndarray, tau: float) -> np.ndarray:
+    """Unit direction field (H, W, 2), zero off the edge set (O1 + O2)."""
+    return direction_field(*sobel(img), tau)
+
+
+def grad_down(gx: np.ndarray, gy: np.ndarray):
+    """O17: one step of the gradient-map pyramid (floored 2x2 means)."""
+    gx = np.ascontiguousarray(gx, np.int32)
+    gy = np.ascontiguousarray(gy, np.int32)
+    H, W = gx.shape
+    ox = np.empty((H // 2, W // 2), np.int32)
+    oy = np.empty((H // 2, W // 2), np.int32)
+    lib().orc_grad_down(gx, gy, W, H, ox, oy)
+    return ox, oy
+
+
+def gradient_pyramid(img: np.ndarray, levels: int):
+    """O17: Sobel gradients of the full image, then their pyramid."""
+    out = [sobel(img)]
+    for _ in range(1, levels):
+        out.append(grad_down(*out[-1]))
+    return out
 
 
 def pyr_down(img: np.ndarray) -> np.ndarray:
@@ -186,8 +231,14 @@ def pyramid(img: np.ndarray, levels: int):
     return out
 
 
-def field_pyramid(img: np.ndarray, levels: int, tau: float):
-    return [edge_field(lv, tau) for lv in pyramid(img, levels)]
+def field_pyramid(img: np.ndarray, levels: int, tau: float, source: str = "grey"):
+    """Direction field of every level: edges of each grey level (O3), or of
+    each level of the gradient-map pyramid (O17)."""
+    if source == "grey":
+        return [edge_field(lv, tau) for lv in pyramid(img, levels)]
+    if source == "gradient":
+        return [direction_field(gx, gy, tau) for gx, gy in gradient_pyramid(img, levels)]
+    raise ValueError(f"source must be 'grey' or 'gradient', got {source!r}")
 
 
 @dataclass
@@ -220,10 +271,9 @@ def model_points(g: np.ndarray):
 def build_model(img: np.ndarray, pp: PyrParams) -> Model:
     """O4: edge points of the model image on each pyramid level."""
     m = Model()
-    for lv in pyramid(img, pp.levels):
-        g = edge_field(lv, pp.edge_thresh)
+    for g in field_pyramid(img, pp.levels, pp.edge_thresh, pp.source):
         t, d = model_points(g)
-        m.levels.append(ModelLevel(t, d, lv.shape[1], lv.shape[0]))
+        m.levels.append(ModelLevel(t, d, g.shape[1], g.shape[0]))
     t0 = m.levels[0].t.astype(np.int64)
     m.radius2 = int((t0 ** 2).sum(axis=1).max()) if len(t0) else 0
     return m
@@ -276,19 +326,20 @@ def scale(sigma_min: float, sigma_step: float, j: int) -> float:
 
 
 # ------------------------------------------------------------- O7, O8
-def score(g: np.ndarray, t, d, ux: int, uy: int, theta_deg: float, win: int = 3, sigma: float = 1.0):
-    """Eq. (1) at one pose (scale sigma: O13): returns (S_w, S_1)."""
+def score(g: np.ndarray, t, d, ux: int, uy: int, theta_deg: float, win: int = 3, sigma: float = 1.0,
+          vote="all"):
+    """Eq. (1) at one pose (scale sigma: O13; vote "edge": O16): returns (S_w, S_1)."""
     H, W, _ = g.shape
     q, r = rotate(t, d, theta_deg) if sigma == 1.0 else project(t, d, theta_deg, sigma)
     sw = ctypes.c_double()
     s1 = ctypes.c_double()
-    lib().orc_score(np.ascontiguousarray(g), W, H, len(t), q, r, int(ux), int(uy), int(win),
+    lib().orc_score(np.ascontiguousarray(g), W, H, len(t), q, r, int(ux), int(uy), int(win), _vote_mode(vote),
                     ctypes.byref(sw), ctypes.byref(s1))
     return sw.value, s1.value
 
 
 def top_map(g: np.ndarray, t, d, theta_min: float, step: float, K: int, sx: int = 1, sy: int = 1,
-            win: int = 3, nthreads: int | None = None):
+            win: int = 3, nthreads: int | None = None, vote="all"):
     """O8: best (S_w, S_1, k) per translation of the step grid, shape (Gh, Gw)."""
     H, W, _ = g.shape
     Gw, Gh = (W + sx - 1) // sx, (H + sy - 1) // sy
@@ -297,13 +348,13 @@ def top_map(g: np.ndarray, t, d, theta_min: float, step: float, K: int, sx: int 
     mk = np.empty((Gh, Gw), np.int32)
     lib().orc_top_map(np.ascontiguousarray(g), W, H, len(t), np.ascontiguousarray(t, np.int32),
                       np.ascontiguousarray(d, np.float64), float(theta_min), float(step), int(K),
-                      int(sx), int(sy), int(win), mw, m1, mk,
+                      int(sx), int(sy), int(win), _vote_mode(vote), mw, m1, mk,
                       int(nthreads if nthreads else default_threads()))
     return mw, m1, mk
 
 
 def top_map_sim(g: np.ndarray, t, d, theta_min: float, step: float, K: int, sigma_min: float, sigma_step: float,
-                S: int, sx: int = 1, sy: int = 1, win: int = 3, nthreads: int | None = None):
+                S: int, sx: int = 1, sy: int = 1, win: int = 3, nthreads: int | None = None, vote="all"):
     """O14: best (S_w, S_1, m = j K + k) per translation over angles and scales."""
     H, W, _ = g.shape
     Gw, Gh = (W + sx - 1) // sx, (H + sy - 1) // sy
@@ -312,7 +363,8 @@ def top_map_sim(g: np.ndarray, t, d, theta_min: float, step: float, K: int, sigm
     mk = np.empty((Gh, Gw), np.int32)
     lib().orc_top_map_sim(np.ascontiguousarray(g), W, H, len(t), np.ascontiguousarray(t, np.int32),
                           np.ascontiguousarray(d, np.float64), float(theta_min), float(step), int(K),
-                          float(sigma_min), float(sigma_step), int(S), int(sx), int(sy), int(win), mw, m1, mk,
+                          float(sigma_min), float(sigma_step), int(S), int(sx), int(sy), int(win), _vote_mode(vote),
+                          mw, m1, mk,
                           int(nthreads if nthreads else default_threads()))
     return mw, m1, mk
 
@@ -360,27 +412,28 @@ def select(mw, m1, mk, sx: int, sy: int, level: int, min_score: float, dmin: flo
 
 
 def refine_level(g, ml: ModelLevel, cand: Candidates, theta_min: float, step_l: float, K: int,
-                 full: bool, win: int) -> Candidates:
+                 full: bool, win: int, vote="all") -> Candidates:
     """O10: one coarse-to-fine step (level l+1 -> l) of every candidate."""
     H, W, _ = g.shape
     c = Candidates(cand.x.astype(np.int32).copy(), cand.y.astype(np.int32).copy(),
                    cand.k.astype(np.int32).copy(), cand.sw.astype(np.float64).copy(),
                    cand.s1.astype(np.float64).copy())
     lib().orc_refine_level(np.ascontiguousarray(g), W, H, len(ml.t), ml.t, ml.d, float(theta_min),
-                           float(step_l), int(K), int(bool(full)), int(win), len(c), c.x, c.y, c.k,
+                           float(step_l), int(K), int(bool(full)), int(win), _vote_mode(vote), len(c), c.x, c.y, c.k,
                            c.sw, c.s1)
     return c
 
 
 def refine_level_sim(g, ml: ModelLevel, cand: Candidates, theta_min: float, step_l: float, K: int, K_above: int,
-                     full: bool, win: int, sigma_min: float, sigma_step: float) -> Candidates:
+                     full: bool, win: int, sigma_min: float, sigma_step: float, vote="all") -> Candidates:
     """O15: one coarse-to-fine step at each candidate's scale; k holds m = j K + k."""
     H, W, _ = g.shape
     c = Candidates(cand.x.astype(np.int32).copy(), cand.y.astype(np.int32).copy(),
                    cand.k.astype(np.int32).copy(), cand.sw.astype(np.float64).copy(),
                    cand.s1.astype(np.float64).copy())
     lib().orc_refine_level_sim(np.ascontiguousarray(g), W, H, len(ml.t), ml.t, ml.d, float(theta_min),
-                               float(step_l), int(K), int(K_above), int(bool(full)), int(win), float(sigma_min),
+                               float(step_l), int(K), int(K_above), int(bool(full)), int(win), _vote_mode(vote),
+                               float(sigma_min),
                                float(sigma_step), len(c), c.x, c.y, c.k, c.sw, c.s1)
     return c
 
@@ -424,9 +477,9 @@ def detect(search: np.ndarray, model_img: np.ndarray, pp_search: PyrParams, pp_m
     """O1-O11: full detection of one model in one search image."""
     L = pp_search.levels
     if model is None:
-        model = build_model(model_img, PyrParams(L, pp_model.edge_thresh))
+        model = build_model(model_img, PyrParams(L, pp_model.edge_thresh, pp_model.source))
     if fields is None:
-        fields = field_pyramid(search, L, pp_search.edge_thresh)
+        fields = field_pyramid(search, L, pp_search.edge_thresh, pp_search.source)
     full = sp.theta_range >= 360.0
     dmin = sp.nms_min_dist if sp.nms_min_dist > 0 else model.default_dmin
     top = L - 1
@@ -435,10 +488,11 @@ def detect(search: np.ndarray, model_img: np.ndarray, pp_search: PyrParams, pp_m
     ml = model.levels[top]
     if sp.similarity:
         mw, m1, mk = top_map_sim(fields[top], ml.t, ml.d, sp.theta_min, step_top, K_top, sp.scale_min,
-                                 sp.scale_step, sp.scale_count, sp.step_x, sp.step_y, sp.neighbourhood, nthreads)
+                                 sp.scale_step, sp.scale_count, sp.step_x, sp.step_y, sp.neighbourhood, nthreads,
+                                 sp.vote)
     else:
         mw, m1, mk = top_map(fields[top], ml.t, ml.d, sp.theta_min, step_top, K_top, sp.step_x, sp.step_y,
-                             sp.neighbourhood, nthreads)
+                             sp.neighbourhood, nthreads, sp.vote)
     cand = select(mw, m1, mk, sp.step_x, sp.step_y, top, sp.min_score, dmin, sp.max_candidates)
     refined = []
     cur = cand
@@ -448,10 +502,10 @@ def detect(search: np.ndarray, model_img: np.ndarray, pp_search: PyrParams, pp_m
         K_l = level_count(sp, step_l)
         if sp.similarity:
             cur = refine_level_sim(fields[l], model.levels[l], cur, sp.theta_min, step_l, K_l, K_above, full,
-                                   sp.neighbourhood, sp.scale_min, sp.scale_step)
+                                   sp.neighbourhood, sp.scale_min, sp.scale_step, sp.vote)
         else:
             cur = refine_level(fields[l], model.levels[l], cur, sp.theta_min, step_l, K_l, full,
-                               sp.neighbourhood)
+                               sp.neighbourhood, sp.vote)
         K_above = K_l
         refined.append(cur)
     fin = final(cur, sp.min_score, dmin, sp.max_matches)

@@ -27,6 +27,9 @@
  *                                            than the rigid Eq. (2))
  *   O14 exhaustive (x, y, theta, scale)      as O8 over angles x scales
  *   O15 refinement at a chosen scale         as O10, scale kept
+ *   O16 edge-taps-only vote (a reading)      Sec. II paras. 2-5 (the window)
+ *   O17 gradient-map pyramid (a reading)     Sec. II, para. 2 (edge extraction
+ *                                            followed by the pyramid)
  * Where the paper is silent the reading taken is stated at the function.
  */
 #include <math.h>
@@ -106,6 +109,35 @@ ORC_API void orc_pyr_down(const uint8_t* src, int W, int H, uint8_t* dst)
             int s = src[(size_t)(2 * y) * W + 2 * x] + src[(size_t)(2 * y) * W + 2 * x + 1] +
                     src[(size_t)(2 * y + 1) * W + 2 * x] + src[(size_t)(2 * y + 1) * W + 2 * x + 1];
             dst[(size_t)y * W2 + x] = (uint8_t)((s + 2) >> 2);
+        }
+    }
+}
+
+/* ----------------------------------------------------------------- O17 */
+/* The other reading of "edge extraction followed by an image pyramid"
+ * (Sec. II para. 2): the Sobel gradients of the full image are extracted once
+ * and the pyramid is built over the gradient maps, each component of level
+ * l+1 being the floored mean floor((s + 2) / 4) of the 2x2 block sum s of
+ * level l (the grey pyramid's rounding, on signed values); floor(W/2) x
+ * floor(H/2).  Edges and directions then follow O2 on every level with the
+ * same threshold. */
+static int32_t orc_floor_div4(int32_t v)
+{
+    int32_t q = v / 4;          /* C division truncates toward zero */
+    if (v % 4 != 0 && v < 0) q -= 1;
+    return q;
+}
+
+ORC_API void orc_grad_down(const int32_t* gx, const int32_t* gy, int W, int H, int32_t* ox, int32_t* oy)
+{
+    int W2 = W / 2, H2 = H / 2;
+    for (int y = 0; y < H2; ++y) {
+        for (int x = 0; x < W2; ++x) {
+            size_t a = (size_t)(2 * y) * W + 2 * x, b = a + W;
+            int32_t sx = gx[a] + gx[a + 1] + gx[b] + gx[b + 1];
+            int32_t sy = gy[a] + gy[a + 1] + gy[b] + gy[b + 1];
+            ox[(size_t)y * W2 + x] = orc_floor_div4(sx + 2);
+            oy[(size_t)y * W2 + x] = orc_floor_div4(sy + 2);
         }
     }
 }
@@ -213,9 +245,15 @@ ORC_API void orc_rotate(int n, const int32_t* t, const double* d, double theta_d
  * best cosine r_i . g over a win x win window centred on its projected
  * position u + q_i; pixels outside the image or off the edge set vote 0; the
  * sum is divided by the model's point count n (occluded points lower the
- * score, Sec. II para. 6).  S1 is the same sum with the centre tap only. */
+ * score, Sec. II para. 6).  S1 is the same sum with the centre tap only.
+ *
+ * O16, vote = 1: the other reading of the neighbouring search, in which only
+ * edge pixels of the window take part.  A point's vote is the best cosine over
+ * the edge pixels of its window, or 0 when the window holds none; pixels off
+ * the edge set (field (0, 0)) and outside the image are skipped instead of
+ * voting 0.  S1 is the same in both readings. */
 ORC_API void orc_score(const double* g, int W, int H, int n, const int32_t* q, const double* r,
-                       int ux, int uy, int win, double* Sw, double* S1)
+                       int ux, int uy, int win, int vote, double* Sw, double* S1)
 {
     int h = (win - 1) / 2;
     double sw = 0.0, s1 = 0.0;
@@ -223,17 +261,23 @@ ORC_API void orc_score(const double* g, int W, int H, int n, const int32_t* q, c
         int px = ux + q[2 * i], py = uy + q[2 * i + 1];
         double rx = r[2 * i], ry = r[2 * i + 1];
         double best = -INFINITY;
+        int edges = 0;
         for (int dy = -h; dy <= h; ++dy) {
             for (int dx = -h; dx <= h; ++dx) {
                 int X = px + dx, Y = py + dy;
                 double v = 0.0;
+                int edge = 0;
                 if (X >= 0 && X < W && Y >= 0 && Y < H) {
                     size_t o = (size_t)Y * W + X;
                     v = rx * g[2 * o] + ry * g[2 * o + 1];
+                    edge = g[2 * o] != 0.0 || g[2 * o + 1] != 0.0;
                 }
+                if (vote == 1 && !edge) continue;
+                edges += edge;
                 if (v > best) best = v;
             }
         }
+        if (vote == 1 && edges == 0) best = 0.0;
         double centre = 0.0;
         if (px >= 0 && px < W && py >= 0 && py < H) {
             size_t o = (size_t)py * W + px;
@@ -256,7 +300,7 @@ ORC_API void orc_score(const double* g, int W, int H, int n, const int32_t* q, c
  * > 1; every translation is independent, so the result does not depend on
  * it. */
 ORC_API void orc_top_map(const double* g, int W, int H, int n, const int32_t* t, const double* d,
-                         double theta_min, double step, int K, int sx, int sy, int win,
+                         double theta_min, double step, int K, int sx, int sy, int win, int vote,
                          double* mapw, double* map1, int32_t* mapk, int nthreads)
 {
     int Gw = (W + sx - 1) / sx, Gh = (H + sy - 1) / sy;
@@ -272,7 +316,7 @@ ORC_API void orc_top_map(const double* g, int W, int H, int n, const int32_t* t,
             int bk = -1;
             for (int k = 0; k < K; ++k) {
                 double sw, s1;
-                orc_score(g, W, H, n, q + 2 * (size_t)n * k, r + 2 * (size_t)n * k, i * sx, j * sy, win,
+                orc_score(g, W, H, n, q + 2 * (size_t)n * k, r + 2 * (size_t)n * k, i * sx, j * sy, win, vote,
                           &sw, &s1);
                 if (sw > bw || (sw == bw && s1 > b1)) {
                     bw = sw;
@@ -400,7 +444,7 @@ ORC_API int orc_select(const double* mapw, const double* map1, const int32_t* ma
  * best by the key replaces the candidate.  g, W, H describe level l; t, d its
  * model points; step_l and K the level's angle grid. */
 ORC_API void orc_refine_level(const double* g, int W, int H, int n, const int32_t* t, const double* d,
-                              double theta_min, double step_l, int K, int full, int win, int nc,
+                              double theta_min, double step_l, int K, int full, int win, int vote, int nc,
                               int32_t* cx, int32_t* cy, int32_t* ck, double* cw, double* c1)
 {
     int32_t* q = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)n);
@@ -416,7 +460,7 @@ ORC_API void orc_refine_level(const double* g, int W, int H, int n, const int32_
                     int x = 2 * cx[c] + a, y = 2 * cy[c] + b;
                     if (x < 0 || x >= W || y < 0 || y >= H) continue;
                     orc_cand me;
-                    orc_score(g, W, H, n, q, r, x, y, win, &me.sw, &me.s1);
+                    orc_score(g, W, H, n, q, r, x, y, win, vote, &me.sw, &me.s1);
                     me.x = x;
                     me.y = y;
                     me.k = k;
@@ -573,7 +617,8 @@ ORC_API double orc_scale(double sigma_min, double sigma_step, int j)
  * score.  With S = 1 and sigma 1 this is O8. */
 ORC_API void orc_top_map_sim(const double* g, int W, int H, int n, const int32_t* t, const double* d,
                              double theta_min, double step, int K, double sigma_min, double sigma_step, int S,
-                             int sx, int sy, int win, double* mapw, double* map1, int32_t* mapk, int nthreads)
+                             int sx, int sy, int win, int vote, double* mapw, double* map1, int32_t* mapk,
+                             int nthreads)
 {
     int Gw = (W + sx - 1) / sx, Gh = (H + sy - 1) / sy;
     int M = K * S;
@@ -593,8 +638,8 @@ ORC_API void orc_top_map_sim(const double* g, int W, int H, int n, const int32_t
             int bm = -1;
             for (int m = 0; m < M; ++m) {
                 double sw, s1;
-                orc_score(g, W, H, n, q + 2 * (size_t)n * m, r + 2 * (size_t)n * m, x * sx, y * sy, win, &sw,
-                          &s1);
+                orc_score(g, W, H, n, q + 2 * (size_t)n * m, r + 2 * (size_t)n * m, x * sx, y * sy, win, vote,
+                          &sw, &s1);
                 if (sw > bw || (sw == bw && s1 > b1)) {
                     bw = sw;
                     b1 = s1;
@@ -620,7 +665,7 @@ ORC_API void orc_top_map_sim(const double* g, int W, int H, int n, const int32_t
  * With one scale this is O10. */
 ORC_API void orc_refine_level_sim(const double* g, int W, int H, int n, const int32_t* t, const double* d,
                                   double theta_min, double step_l, int K, int K_above, int full, int win,
-                                  double sigma_min, double sigma_step, int nc, int32_t* cx, int32_t* cy, int32_t* cm,
+                                  int vote, double sigma_min, double sigma_step, int nc, int32_t* cx, int32_t* cy, int32_t* cm,
                                   double* cw, double* c1)
 {
     int32_t* q = (int32_t*)malloc(sizeof(int32_t) * 2 * (size_t)n);
@@ -638,7 +683,7 @@ ORC_API void orc_refine_level_sim(const double* g, int W, int H, int n, const in
                     int x = 2 * cx[c] + a, y = 2 * cy[c] + b;
                     if (x < 0 || x >= W || y < 0 || y >= H) continue;
                     orc_cand me;
-                    orc_score(g, W, H, n, q, r, x, y, win, &me.sw, &me.s1);
+                    orc_score(g, W, H, n, q, r, x, y, win, vote, &me.sw, &me.s1);
                     me.x = x;
                     me.y = y;
                     me.k = j * K + k;

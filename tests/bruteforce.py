@@ -52,13 +52,30 @@ def rotate(t, d, theta_deg, sigma=1.0):
     return q, r
 
 
-def score_volume(g, t, d, thetas, win=3, sigma=1.0):
-    """S_w and S_1 for every (k, y, x) at scale sigma: arrays of shape (K, H, W)."""
+def grad_pyramid(img, levels):
+    """Sobel gradients of the full image, then 2x2 block sums floored after
+    adding 2 (numpy floor division), level by level."""
+    gx, gy = sobel(img)
+    out = [(gx, gy)]
+    for _ in range(1, levels):
+        H, W = gx.shape
+        h2, w2 = H // 2, W // 2
+        gx = np.floor_divide(gx[:2 * h2, :2 * w2].reshape(h2, 2, w2, 2).sum(axis=(1, 3)) + 2, 4)
+        gy = np.floor_divide(gy[:2 * h2, :2 * w2].reshape(h2, 2, w2, 2).sum(axis=(1, 3)) + 2, 4)
+        out.append((gx, gy))
+    return out
+
+
+def score_volume(g, t, d, thetas, win=3, sigma=1.0, vote="all"):
+    """S_w and S_1 for every (k, y, x) at scale sigma: arrays of shape (K, H, W).
+    vote "edge": only taps on the edge set (a nonzero field) enter the window
+    maximum, and a window without one votes 0."""
     H, W, _ = g.shape
     h = (win - 1) // 2
     P = 2 * (int(np.ceil(sigma * np.abs(t).max())) + 2 + h) + 2
     gp = np.zeros((H + 2 * P, W + 2 * P, 2))
     gp[P:P + H, P:P + W] = g
+    edge = np.any(gp != 0, axis=-1)
     K = len(thetas)
     Sw = np.zeros((K, H, W))
     S1 = np.zeros((K, H, W))
@@ -73,9 +90,13 @@ def score_volume(g, t, d, thetas, win=3, sigma=1.0):
                 X = xs[None] + q[:, 0, None, None] + dx + P
                 Y = ys[None] + q[:, 1, None, None] + dy + P
                 v = gp[Y, X, 0] * r[:, 0, None, None] + gp[Y, X, 1] * r[:, 1, None, None]
-                best = np.maximum(best, v)
                 if dx == 0 and dy == 0:
                     centre = v
+                if vote == "edge":
+                    v = np.where(edge[Y, X], v, -np.inf)
+                best = np.maximum(best, v)
+        if vote == "edge":
+            best = np.where(np.isneginf(best), 0.0, best)
         Sw[k] = best.sum(axis=0) / n
         S1[k] = centre.sum(axis=0) / n
     return Sw, S1
