@@ -52,19 +52,35 @@ typedef enum {
 
 typedef enum { TM_FP32 = 0, TM_FP16 = 1 } tm_precision;
 
+/* Where the pyramid's gradients come from (Sec. II para. 2 names edge
+ * extraction followed by the image pyramid; either order can be read there).
+ * GREY: the grey image is reduced level by level and the Sobel pair is taken
+ * on every level.  GRADIENT: the Sobel pair of the full image is taken once
+ * and the gradient maps are reduced, each component of level l+1 being
+ * floor((s + 2) / 4) of the 2x2 block sum s of level l. */
+typedef enum { TM_PYR_GREY = 0, TM_PYR_GRADIENT = 1 } tm_pyr_source;
+
+/* Which taps of a model point's window vote (Sec. II paras. 3-5, the
+ * neighbouring search).  ALL: every tap, off the edge set and outside the
+ * image with cosine 0.  EDGE: only taps on the edge set; a window without one
+ * votes 0.  The centre-tap score S_1 is the same under both. */
+typedef enum { TM_VOTE_ALL = 0, TM_VOTE_EDGE = 1 } tm_vote;
+
 #define TM_MAX_LEVELS 8
 
 /* Pyramid and edge parameters (Sec. II para. 2: edge detection threshold,
  * number of pyramid levels).  A pixel is an edge iff gx^2 + gy^2 >
  * floor(edge_thresh^2), gx and gy being the integer 3x3 Sobel responses
  * (zero on the one-pixel image frame); level l+1 is the 2x2 rounded mean of
- * level l, floor(w/2) x floor(h/2).  `precision` selects how the search
- * pyramid stores unit gradient directions (FP32, or FP16 with FP32
- * accumulation); models ignore it. */
+ * level l, floor(w/2) x floor(h/2) (with `source` TM_PYR_GRADIENT the
+ * gradient maps are reduced instead, see tm_pyr_source).  `precision`
+ * selects how the search pyramid stores unit gradient directions (FP32, or
+ * FP16 with FP32 accumulation); models ignore it. */
 typedef struct {
     int32_t levels;       /* 1 .. TM_MAX_LEVELS                       */
     float edge_thresh;    /* >= 0, on the scale of the integer Sobel  */
     int32_t precision;    /* tm_precision                             */
+    int32_t source;       /* tm_pyr_source (TM_PYR_GREY: the default) */
 } tm_pyr_params;
 
 /* Search parameters (Sec. II para. 2: step sizes in x, y and theta, the
@@ -93,6 +109,7 @@ typedef struct {
     double scale_min;             /* > 0 (1 for the rigid search)              */
     double scale_step;            /* >= 0                                      */
     int32_t scale_count;          /* 1 .. 64                                   */
+    int32_t vote;                 /* tm_vote (TM_VOTE_ALL: the default)        */
 } tm_search_params;
 
 /* A pose with its scores.  (x, y) is in pixels of `level`; k indexes the
@@ -146,10 +163,11 @@ tm_status tm_update_pyramid(tm_pyramid* pyr, const uint8_t* img_dev, int32_t pit
 
 /* Eq. (1) at n arbitrary poses of one level: scores_dev[2i] = S_w,
  * scores_dev[2i+1] = S_1 for poses_dev[i].  `neighbourhood` is the odd window
- * side (3 in the paper).  Model points whose window falls outside the image
- * vote 0; the sum is divided by the model's point count at that level. */
+ * side (3 in the paper), `vote` a tm_vote.  Model points whose window falls
+ * outside the image vote 0; the sum is divided by the model's point count at
+ * that level. */
 tm_status tm_score_poses(const tm_model* model, const tm_pyramid* pyr, int32_t level,
-                         int32_t neighbourhood, const tm_eval_pose* poses_dev, int32_t n,
+                         int32_t neighbourhood, int32_t vote, const tm_eval_pose* poses_dev, int32_t n,
                          float* scores_dev, void* stream);
 
 /* Exhaustive search of one level (Sec. II para. 3, Fig. 2): for every

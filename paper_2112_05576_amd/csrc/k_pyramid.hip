@@ -110,6 +110,63 @@ __device__ __forceinline__ void sobel_at(const uint8_t* __restrict__ img, int W,
     *gy = (g + 2 * h + i) - (a + 2 * b + c);
 }
 
+__device__ __forceinline__ uint32_t pack_grad(int gx, int gy)
+{
+    return (uint32_t)(uint16_t)(int16_t)gx | ((uint32_t)(uint16_t)(int16_t)gy << 16);
+}
+
+__device__ __forceinline__ void unpack_grad(uint32_t v, int* gx, int* gy)
+{
+    *gx = (int)(int16_t)(v & 0xFFFFu);
+    *gy = (int)(int16_t)(v >> 16);
+}
+
+// The gradient pair of a pixel of level l: read from the gradient-map pyramid
+// where there is one, else the Sobel pair of the level's image.
+__device__ __forceinline__ void level_grad(const uint8_t* img, const uint32_t* grad, int W, int H, int x, int y,
+                                           int* gx, int* gy)
+{
+    if (grad)
+        unpack_grad(grad[(size_t)y * W + x], gx, gy);
+    else
+        sobel_at(img, W, H, x, y, gx, gy);
+}
+
+// One level of the gradient-map pyramid, one thread per pixel: level 0 is the
+// Sobel pair of the full image; level l > 0 takes the 2x2 block of level l-1
+// and floors (s + 2) / 4 per component (an arithmetic shift by 2 is a floored
+// division of the signed sum).  Components stay within the Sobel range
+// |g| <= 1020, so they pack as int16.  grid: (pixels / 256, image).
+template <bool BATCH>
+__global__ __launch_bounds__(256) void k_grad_level(FieldsArg one, const FieldsArg* __restrict__ many, int l)
+{
+    const FieldsArg& a = BATCH ? many[blockIdx.y] : one;
+    if (l >= a.L) return;
+    const int W = a.w[l], H = a.h[l];
+    const int idx = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (idx >= W * H) return;
+    const int y = idx / W, x = idx - y * W;
+    int gx, gy;
+    if (l == 0) {
+        sobel_at(a.img[0], W, H, x, y, &gx, &gy);
+    } else {
+        const int Wp = a.w[l - 1];
+        const uint32_t* __restrict__ src = a.grad[l - 1] + (size_t)(2 * y) * Wp + 2 * x;
+        int sx = 0, sy = 0;
+        const uint32_t v[4] = {src[0], src[1], src[Wp], src[Wp + 1]};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int u, w;
+            unpack_grad(v[j], &u, &w);
+            sx += u;
+            sy += w;
+        }
+        gx = (sx + 2) >> 2;
+        gy = (sy + 2) >> 2;
+    }
+    a.grad[l][idx] = pack_grad(gx, gy);
+}
+
 // Unit gradient direction of every pixel of every level: (gx, gy)/|g| formed
 // in FP64 and rounded once to the storage precision where gx^2 + gy^2 > T2,
 // (0, 0) elsewhere.  Each thread covers 4 consecutive pixels of a row.
@@ -128,12 +185,13 @@ __global__ __launch_bounds__(256) void k_sobel_fields(FieldsArg one, const Field
     const int y = idx / qw, x0 = (idx % qw) * 4;
     if (y >= H) return;
     const uint8_t* img = a.img[l];
+    const uint32_t* grad = a.grad[l];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int x = x0 + i;
         if (x >= W) break;
         int gx, gy;
-        sobel_at(img, W, H, x, y, &gx, &gy);
+        level_grad(img, grad, W, H, x, y, &gx, &gy);
         const long long m2 = (long long)gx * gx + (long long)gy * gy;
         double dx = 0.0, dy = 0.0;
         if (m2 > T2) {
@@ -152,6 +210,7 @@ __global__ __launch_bounds__(256) void k_sobel_fields(FieldsArg one, const Field
 
 struct PointsArg {
     const uint8_t* img[kMaxLevels];
+    const uint32_t* grad[kMaxLevels];  // gradient-map pyramid, or null
     ModelPoint* pts[kMaxLevels];
     int w[kMaxLevels];
     int h[kMaxLevels];
@@ -170,10 +229,11 @@ __global__ __launch_bounds__(1024) void k_model_points(PointsArg a, long long T2
     const int per = (N + 1023) / 1024;
     const int p0 = min(N, (int)threadIdx.x * per), p1 = min(N, p0 + per);
     const uint8_t* img = a.img[l];
+    const uint32_t* grad = a.grad[l];
     int cnt = 0;
     for (int p = p0; p < p1; ++p) {
         int gx, gy;
-        sobel_at(img, W, H, p % W, p / W, &gx, &gy);
+        level_grad(img, grad, W, H, p % W, p / W, &gx, &gy);
         cnt += ((long long)gx * gx + (long long)gy * gy > T2) ? 1 : 0;
     }
     scan[threadIdx.x] = cnt;
@@ -188,7 +248,7 @@ __global__ __launch_bounds__(1024) void k_model_points(PointsArg a, long long T2
     const int cx = W / 2, cy = H / 2;
     for (int p = p0; p < p1; ++p) {
         int x = p % W, y = p / W, gx, gy;
-        sobel_at(img, W, H, x, y, &gx, &gy);
+        level_grad(img, grad, W, H, x, y, &gx, &gy);
         if ((long long)gx * gx + (long long)gy * gy > T2) {
             ModelPoint mp;
             mp.tx = (int16_t)(x - cx);
@@ -226,6 +286,7 @@ FieldsArg fields_arg(const PyrLevel* lv, int L, long long T2, int precision)
     int blocks = 0;
     for (int l = 0; l < L; ++l) {
         a.img[l] = lv[l].img;
+        a.grad[l] = lv[l].grad;
         a.field[l] = lv[l].field;
         a.w[l] = lv[l].w;
         a.h[l] = lv[l].h;
@@ -251,6 +312,17 @@ hipError_t launch_pyr_build(const uint8_t* src, int src_pitch, const PyrLevel* l
     return hipGetLastError();
 }
 
+hipError_t launch_grad_pyramid(const PyrLevel* lv, int L, hipStream_t s)
+{
+    FieldsArg a = fields_arg(lv, L, 0, TM_FP32);
+    for (int l = 0; l < L; ++l) {
+        if (!a.grad[l]) return hipErrorInvalidValue;
+        const long long px = (long long)a.w[l] * a.h[l];
+        hipLaunchKernelGGL(k_grad_level<false>, dim3((unsigned)((px + 255) / 256)), dim3(256), 0, s, a, nullptr, l);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_sobel_fields(const PyrLevel* lv, int L, long long T2, int precision, hipStream_t s)
 {
     FieldsArg a = fields_arg(lv, L, T2, precision);
@@ -260,7 +332,7 @@ hipError_t launch_sobel_fields(const PyrLevel* lv, int L, long long T2, int prec
 
 hipError_t launch_pyramids_batch(const PyrBuildArg* pb, const FieldsArg* fa, int n_images, int L, int max_w,
                                  int max_h, int max_field_blocks, const int* level_w, const int* level_h,
-                                 hipStream_t s)
+                                 bool gradient, hipStream_t s)
 {
     for (int base = 0;; base += 6) {
         const int top = min(L - 1, base + 6);
@@ -271,6 +343,12 @@ hipError_t launch_pyramids_batch(const PyrBuildArg* pb, const FieldsArg* fa, int
     }
     (void)max_w;
     (void)max_h;
+    // level_w x level_h bounds every image's level; the kernel checks its own size
+    for (int l = 0; gradient && l < L; ++l) {
+        const long long px = (long long)level_w[l] * level_h[l];
+        hipLaunchKernelGGL(k_grad_level<true>, dim3((unsigned)((px + 255) / 256), n_images), dim3(256), 0, s,
+                           FieldsArg{}, fa, l);
+    }
     hipLaunchKernelGGL(k_sobel_fields<true>, dim3(max_field_blocks, n_images), dim3(256), 0, s, FieldsArg{}, fa);
     return hipGetLastError();
 }
@@ -281,6 +359,7 @@ hipError_t launch_model_points(const PyrLevel* lv, int L, long long T2, ModelPoi
     PointsArg a = {};
     for (int l = 0; l < L; ++l) {
         a.img[l] = lv[l].img;
+        a.grad[l] = lv[l].grad;
         a.pts[l] = pts[l];
         a.w[l] = lv[l].w;
         a.h[l] = lv[l].h;

@@ -76,30 +76,38 @@ struct LevelArgs {
     double sigma_min, sigma_step;  // scale grid; a candidate keeps its scale index j
     int S;                         // scales (indices outside 0 .. S-1 are clamped)
 };
+// (the window reading, tm_vote, is the kernels' VOTE template argument)
 
 // The 9 windowed votes and 9 centre votes of one point from the 5x5 block of
-// field values around its projection (taps outside the image vote 0).
+// field values around its projection (taps outside the image vote 0).  VOTE
+// 1: the edge-taps-only window (off-edge and outside taps enter the maxima as
+// kOffEdge, each maximum is finished by vote_finish); centre votes as in 0.
+template <int VOTE>
 __device__ __forceinline__ void votes5x5(const float2 (&gv)[5][5], const bool (&rin)[5], const bool (&cin)[5], float fx,
                                          float fy, float (&aw)[9], float (&a1)[9])
 {
-    float D[5][5];
+    float D[5][5], E[5][5];
 #pragma unroll
     for (int v = 0; v < 5; ++v)
 #pragma unroll
         for (int u = 0; u < 5; ++u) {
             const float d = fx * gv[v][u].x + fy * gv[v][u].y;
             D[v][u] = (rin[v] && cin[u]) ? d : 0.0f;
+            if constexpr (VOTE == 1)
+                E[v][u] = (rin[v] && cin[u] && on_edge(gv[v][u])) ? d : kOffEdge;
+            else
+                E[v][u] = D[v][u];
         }
     float hm[5][3];
 #pragma unroll
     for (int v = 0; v < 5; ++v)
 #pragma unroll
-        for (int u = 0; u < 3; ++u) hm[v][u] = fmaxf(fmaxf(D[v][u], D[v][u + 1]), D[v][u + 2]);
+        for (int u = 0; u < 3; ++u) hm[v][u] = fmaxf(fmaxf(E[v][u], E[v][u + 1]), E[v][u + 2]);
 #pragma unroll
     for (int b = 0; b < 3; ++b)
 #pragma unroll
         for (int u = 0; u < 3; ++u) {
-            aw[b * 3 + u] += fmaxf(fmaxf(hm[b][u], hm[b + 1][u]), hm[b + 2][u]);
+            aw[b * 3 + u] += win_finish<VOTE>(fmaxf(fmaxf(hm[b][u], hm[b + 1][u]), hm[b + 2][u]));
             a1[b * 3 + u] += D[b + 1][u + 1];
         }
 }
@@ -202,7 +210,7 @@ __device__ __forceinline__ void block5(int px, int py, int W, int H, Block5& b)
     }
 }
 
-template <int PREC>
+template <int PREC, int VOTE>
 __global__ __launch_bounds__(kThreads) void k_refine_level(LevelArgs a, const PairDesc* __restrict__ pairs)
 {
     __shared__ float red[kWaves][18];
@@ -254,8 +262,8 @@ __global__ __launch_bounds__(kThreads) void k_refine_level(LevelArgs a, const Pa
                     g1[v][u] = field_load<PREC>(field, b1.rowoff[v] + b1.col[u]);
                 }
             __builtin_amdgcn_sched_barrier(0);
-            votes5x5(g0, b0.rin, b0.cin, (float)rx0, (float)ry0, aw, a1);
-            if (two) votes5x5(g1, b1.rin, b1.cin, (float)rx1, (float)ry1, aw, a1);
+            votes5x5<VOTE>(g0, b0.rin, b0.cin, (float)rx0, (float)ry0, aw, a1);
+            if (two) votes5x5<VOTE>(g1, b1.rin, b1.cin, (float)rx1, (float)ry1, aw, a1);
         }
     } else {
         // any odd window: direct evaluation of each translation
@@ -273,8 +281,8 @@ __global__ __launch_bounds__(kThreads) void k_refine_level(LevelArgs a, const Pa
                     float best = -INFINITY;
                     for (int dy = -wh; dy <= wh; ++dy)
                         for (int dx = -wh; dx <= wh; ++dx)
-                            best = fmaxf(best, field_dot<PREC>(field, W, H, cx + dx, cy + dy, fx, fy));
-                    aw[b * 3 + u] += best;
+                            best = fmaxf(best, field_win_tap<PREC, VOTE>(field, W, H, cx + dx, cy + dy, fx, fy));
+                    aw[b * 3 + u] += win_finish<VOTE>(best);
                     a1[b * 3 + u] += field_dot<PREC>(field, W, H, cx, cy, fx, fy);
                 }
         }
@@ -300,7 +308,7 @@ struct Raw<TM_FP16> {
     static __device__ __forceinline__ float2 value(T v) { return __half22float2(v); }
 };
 
-template <int PREC>
+template <int PREC, int VOTE>
 __global__ __launch_bounds__(kThreads) void k_refine_tile(LevelArgs a, const PairDesc* __restrict__ pairs)
 {
     using T = typename Raw<PREC>::T;
@@ -374,7 +382,7 @@ __global__ __launch_bounds__(kThreads) void k_refine_tile(LevelArgs a, const Pai
             for (int v = 0; v < 5; ++v)
 #pragma unroll
                 for (int u = 0; u < 5; ++u) gv[v][u] = Raw<PREC>::value(b[v * S + u]);
-            votes5x5(gv, rin, cin, (float)rx, (float)ry, aw, a1);
+            votes5x5<VOTE>(gv, rin, cin, (float)rx, (float)ry, aw, a1);
         }
         block_sum18(aw, a1, red, P.part[l] + ((size_t)c * 3 + g) * 18);
     }
@@ -430,14 +438,39 @@ hipError_t prepare_refine()
 {
     static bool done = false;
     if (done) return hipSuccess;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_refine_tile<TM_FP32>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileMax);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_refine_tile<TM_FP16>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileMax);
-    if (e == hipSuccess) done = true;
-    return e;
+    const void* k[] = {reinterpret_cast<const void*>(&k_refine_tile<TM_FP32, 0>),
+                       reinterpret_cast<const void*>(&k_refine_tile<TM_FP16, 0>),
+                       reinterpret_cast<const void*>(&k_refine_tile<TM_FP32, 1>),
+                       reinterpret_cast<const void*>(&k_refine_tile<TM_FP16, 1>)};
+    for (const void* f : k) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileMax);
+        if (e != hipSuccess) return e;
+    }
+    done = true;
+    return hipSuccess;
 }
+
+namespace {
+template <int VOTE>
+void launch_level_kernels(const SearchDesc& s, const PairDesc* d, int npairs, const RefinePlan& rp, int l,
+                          const LevelArgs& a, hipStream_t st)
+{
+    if (!rp.staged || rp.gather[l]) {
+        dim3 grid((unsigned)(s.max_cand * 3), npairs);
+        if (s.precision == TM_FP16)
+            hipLaunchKernelGGL((k_refine_level<TM_FP16, VOTE>), grid, dim3(kThreads), 0, st, a, d);
+        else
+            hipLaunchKernelGGL((k_refine_level<TM_FP32, VOTE>), grid, dim3(kThreads), 0, st, a, d);
+    }
+    if (rp.staged && rp.tile_bytes[l] > 0) {
+        dim3 grid((unsigned)s.max_cand, npairs);
+        if (s.precision == TM_FP16)
+            hipLaunchKernelGGL((k_refine_tile<TM_FP16, VOTE>), grid, dim3(kThreads), rp.tile_bytes[l], st, a, d);
+        else
+            hipLaunchKernelGGL((k_refine_tile<TM_FP32, VOTE>), grid, dim3(kThreads), rp.tile_bytes[l], st, a, d);
+    }
+}
+}  // namespace
 
 hipError_t launch_refine(const SearchDesc& s, const PairDesc* d, int npairs, int from_level, const RefinePlan& rp,
                          hipStream_t st)
@@ -464,24 +497,12 @@ hipError_t launch_refine(const SearchDesc& s, const PairDesc* d, int npairs, int
         a.sigma_min = s.sigma_min;
         a.sigma_step = s.sigma_step;
         a.S = s.S > 0 ? s.S : 1;
-        if (!rp.staged || rp.gather[l]) {
-            dim3 grid((unsigned)(s.max_cand * 3), npairs);
-            if (s.precision == TM_FP16)
-                hipLaunchKernelGGL(k_refine_level<TM_FP16>, grid, dim3(kThreads), 0, st, a, d);
-            else
-                hipLaunchKernelGGL(k_refine_level<TM_FP32>, grid, dim3(kThreads), 0, st, a, d);
-            e = hipGetLastError();
-            if (e != hipSuccess) return e;
-        }
-        if (rp.staged && rp.tile_bytes[l] > 0) {
-            dim3 grid((unsigned)s.max_cand, npairs);
-            if (s.precision == TM_FP16)
-                hipLaunchKernelGGL(k_refine_tile<TM_FP16>, grid, dim3(kThreads), rp.tile_bytes[l], st, a, d);
-            else
-                hipLaunchKernelGGL(k_refine_tile<TM_FP32>, grid, dim3(kThreads), rp.tile_bytes[l], st, a, d);
-            e = hipGetLastError();
-            if (e != hipSuccess) return e;
-        }
+        if (s.vote)
+            launch_level_kernels<1>(s, d, npairs, rp, l, a, st);
+        else
+            launch_level_kernels<0>(s, d, npairs, rp, l, a, st);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
         src ^= 1;
     }
     PickArgs pa;

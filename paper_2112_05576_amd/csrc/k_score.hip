@@ -114,6 +114,11 @@ struct Px<TM_FP32> {
     static __device__ __forceinline__ T zero() { return make_float2(0.f, 0.f); }
     static __device__ __forceinline__ T load(const void* f, size_t o) { return reinterpret_cast<const float2*>(f)[o]; }
     static __device__ __forceinline__ float dot(const TabEntry& e, T g) { return e.rx * g.x + e.ry * g.y; }
+    // on the edge set: not (+-0, +-0)
+    static __device__ __forceinline__ bool edge(T g)
+    {
+        return ((__float_as_uint(g.x) | __float_as_uint(g.y)) << 1) != 0u;
+    }
     template <bool ASM>
     static __device__ __forceinline__ float dot_t(const TabEntry& e, T g)
     {
@@ -129,6 +134,7 @@ struct Px<TM_FP16> {
     {
         return __builtin_amdgcn_fdot2(__builtin_bit_cast(h2_t, e.rh), __builtin_bit_cast(h2_t, g), 0.0f, false);
     }
+    static __device__ __forceinline__ bool edge(T g) { return (g & 0x7FFF7FFFu) != 0u; }
     template <bool ASM>
     static __device__ __forceinline__ float dot_t(const TabEntry& e, T g)
     {
@@ -170,7 +176,10 @@ struct FastArgs {
 // VOP3P dot and the DPP-folded maxima written out; 2, 3, 4 as 1 with 2, 4, 8
 // table entries fetched per loop step (one scalar-load wait per step); 5 as 3
 // with the next step's entries requested behind this step's LDS reads.
-template <int G, int R, int LC, int PREC, int VAR>
+// VOTE 1: the edge-taps-only window (off-edge products replaced by kOffEdge
+// before the maxima, each window maximum finished by vote_finish); the centre
+// sum takes the plain products in both readings.
+template <int G, int R, int LC, int PREC, int VAR, int VOTE>
 __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc* __restrict__ pairs)
 {
     using T = typename Px<PREC>::T;
@@ -259,21 +268,29 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc*
 #pragma unroll
                     for (int rr = 0; rr < R + 2; ++rr) D[rr] = Px<PREC>::template dot_t<ASM>(e, gv[rr]);
                 }
+                float E[R + 2];
+#pragma unroll
+                for (int rr = 0; rr < R + 2; ++rr) {
+                    if constexpr (VOTE == 1)
+                        E[rr] = Px<PREC>::edge(gv[rr]) ? D[rr] : kOffEdge;
+                    else
+                        E[rr] = D[rr];
+                }
                 float V[R];
 #pragma unroll
-                for (int r = 0; r < R; ++r) V[r] = fmaxf(fmaxf(D[r], D[r + 1]), D[r + 2]);
+                for (int r = 0; r < R; ++r) V[r] = fmaxf(fmaxf(E[r], E[r + 1]), E[r + 2]);
                 if constexpr (ASM && R == 8) {
                     float M[R];
                     hmax3x8(V, M);
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        pw[r] += M[r];
+                        pw[r] += win_finish<VOTE>(M[r]);
                         p1[r] += D[r + 1];
                     }
                 } else {
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
-                        pw[r] += hmax3<ASM>(V[r]);
+                        pw[r] += win_finish<VOTE>(hmax3<ASM>(V[r]));
                         p1[r] += D[r + 1];
                     }
                 }
@@ -381,8 +398,8 @@ struct GenericArgs {
 
 // Any step and window: one thread per grid translation, taps read from
 // global memory (clamped addresses, no branches).  grid: (translations,
-// chunk, pair).
-template <int PREC>
+// chunk, pair).  VOTE as in k_dense_fast.
+template <int PREC, int VOTE>
 __global__ __launch_bounds__(256) void k_dense_generic(GenericArgs a, const PairDesc* __restrict__ pairs)
 {
     const PairDesc& P = pairs[blockIdx.z];
@@ -419,14 +436,17 @@ __global__ __launch_bounds__(256) void k_dense_generic(GenericArgs a, const Pair
                     for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
                         for (int dx = 0; dx < 3; ++dx)
-                            v[dy][dx] = field_dot<PREC>(field, W, H, px + dx - 1, py + dy - 1, e.rx, e.ry);
+                            v[dy][dx] = field_win_tap<PREC, VOTE>(field, W, H, px + dx - 1, py + dy - 1, e.rx, e.ry);
                     float best = -INFINITY;
 #pragma unroll
                     for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
                         for (int dx = 0; dx < 3; ++dx) best = fmaxf(best, v[dy][dx]);
-                    pw += best;
-                    p1 += v[1][1];
+                    pw += win_finish<VOTE>(best);
+                    if constexpr (VOTE == 1)
+                        p1 += field_dot<PREC>(field, W, H, px, py, e.rx, e.ry);
+                    else
+                        p1 += v[1][1];
                 }
             } else {
                 for (int i = i0; i < i1; ++i) {
@@ -436,8 +456,8 @@ __global__ __launch_bounds__(256) void k_dense_generic(GenericArgs a, const Pair
                     for (int dy = -h; dy <= h; ++dy)
 #pragma unroll 3
                         for (int dx = -h; dx <= h; ++dx)
-                            best = fmaxf(best, field_dot<PREC>(field, W, H, px + dx, py + dy, e.rx, e.ry));
-                    pw += best;
+                            best = fmaxf(best, field_win_tap<PREC, VOTE>(field, W, H, px + dx, py + dy, e.rx, e.ry));
+                    pw += win_finish<VOTE>(best);
                     p1 += field_dot<PREC>(field, W, H, px, py, e.rx, e.ry);
                 }
             }
@@ -529,8 +549,8 @@ __global__ __launch_bounds__(256) void k_reduce_chunks(int C, const PairDesc* __
 
 // One wave per pose: lanes take points i = lane, lane + 64, ...; each point's
 // rotation is formed in FP64, its window read from global memory; per-lane
-// sums are combined by a fixed butterfly.
-template <int PREC>
+// sums are combined by a fixed butterfly.  VOTE as in k_dense_fast.
+template <int PREC, int VOTE>
 __global__ __launch_bounds__(256) void k_sparse(const void* __restrict__ field, int W, int H,
                                                  const ModelPoint* __restrict__ pts, int n, int win,
                                                  const tm_eval_pose* __restrict__ poses, int np,
@@ -554,8 +574,8 @@ __global__ __launch_bounds__(256) void k_sparse(const void* __restrict__ field, 
         for (int dy = -h; dy <= h; ++dy)
 #pragma unroll 3
             for (int dx = -h; dx <= h; ++dx)
-                best = fmaxf(best, field_dot<PREC>(field, W, H, px + dx, py + dy, fx, fy));
-        sw += best;
+                best = fmaxf(best, field_win_tap<PREC, VOTE>(field, W, H, px + dx, py + dy, fx, fy));
+        sw += win_finish<VOTE>(best);
         s1 += field_dot<PREC>(field, W, H, px, py, fx, fy);
     }
 #pragma unroll
@@ -586,37 +606,42 @@ int knob(const char* name, int dflt, int lo, int hi)
 
 // d == nullptr: only raise the kernel's LDS limit (done once, before any
 // launch, so that no attribute call happens while a stream is captured).
-template <int G, int R, int LC, int PREC, int VAR>
+template <int G, int R, int LC, int PREC, int VAR, int VOTE>
 hipError_t launch_fast_t(const DensePlan& p, const FastArgs& a, const PairDesc* d, int npairs, hipStream_t s)
 {
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dense_fast<G, R, LC, PREC, VAR>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dense_fast<G, R, LC, PREC, VAR, VOTE>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
     if (!d) return hipSuccess;
     const dim3 grid = a.work ? dim3(p.n_work) : dim3(p.max_blocks, npairs);
-    hipLaunchKernelGGL((k_dense_fast<G, R, LC, PREC, VAR>), grid, dim3(64 * p.WY * p.WA), p.lds, s, a, d);
+    hipLaunchKernelGGL((k_dense_fast<G, R, LC, PREC, VAR, VOTE>), grid, dim3(64 * p.WY * p.WA), p.lds, s, a, d);
     return hipGetLastError();
 }
 
-template <int PREC, int VAR>
+template <int PREC, int VAR, int VOTE = 0>
 hipError_t launch_fast_p(const DensePlan& p, const FastArgs& a, const PairDesc* d, int npairs, hipStream_t s)
 {
     switch (p.LC) {
-        case 64: return launch_fast_t<32, 8, 64, PREC, VAR>(p, a, d, npairs, s);
-        case 96: return launch_fast_t<32, 8, 96, PREC, VAR>(p, a, d, npairs, s);
-        case 128: return launch_fast_t<32, 8, 128, PREC, VAR>(p, a, d, npairs, s);
-        case 192: return launch_fast_t<32, 8, 192, PREC, VAR>(p, a, d, npairs, s);
-        default: return launch_fast_t<32, 8, 256, PREC, VAR>(p, a, d, npairs, s);
+        case 64: return launch_fast_t<32, 8, 64, PREC, VAR, VOTE>(p, a, d, npairs, s);
+        case 96: return launch_fast_t<32, 8, 96, PREC, VAR, VOTE>(p, a, d, npairs, s);
+        case 128: return launch_fast_t<32, 8, 128, PREC, VAR, VOTE>(p, a, d, npairs, s);
+        case 192: return launch_fast_t<32, 8, 192, PREC, VAR, VOTE>(p, a, d, npairs, s);
+        default: return launch_fast_t<32, 8, 256, PREC, VAR, VOTE>(p, a, d, npairs, s);
     }
 }
+
+// The edge-taps reading is built in one form per precision, the default one
+// (retune_dense offers no other).
+constexpr int vote_variant(int precision) { return precision == TM_FP16 ? 4 : 3; }
 
 template <int PREC>
 hipError_t launch_fast_v(const DensePlan& p, const FastArgs& a, const PairDesc* d, int npairs, hipStream_t s)
 {
+    if (p.vote) return launch_fast_p<PREC, vote_variant(PREC), 1>(p, a, d, npairs, s);
     switch (p.variant) {
         case 1: return launch_fast_p<PREC, 1>(p, a, d, npairs, s);
         case 2: return launch_fast_p<PREC, 2>(p, a, d, npairs, s);
@@ -649,9 +674,10 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
         p.max_np = max(p.max_np, g[i].gw * g[i].gh);
     }
     p.fast = s.sx == 1 && s.sy == 1 && s.win == 3;
+    p.vote = s.vote;
     // measured on the 64-image C2 batch: FP16 fastest with 8 entries per
     // fetch (variant 4), FP32 with 4 (variant 3); all bit-identical to 0
-    p.variant = knob("TM_DENSE_ASM", s.precision == TM_FP16 ? 4 : 3, 0, 5);
+    p.variant = p.vote ? vote_variant(s.precision) : knob("TM_DENSE_ASM", vote_variant(s.precision), 0, 5);
     if (p.fast) {
         p.G = 32;
         p.R = 8;
@@ -708,6 +734,7 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
 bool retune_dense(DensePlan& p, int variant, int WA)
 {
     if (!p.fast || variant < 0 || variant > 5 || WA < 1 || p.WY * WA > 16) return false;
+    if (p.vote && variant != p.variant) return false;
     const int TW = p.G - 2, TH = p.WY * (64 / p.G) * p.R;
     const size_t comb_bytes = (size_t)12 * WA * TH * TW;
     const size_t lds = p.tile_lds > comb_bytes ? p.tile_lds : comb_bytes;
@@ -813,10 +840,17 @@ hipError_t launch_dense(const SearchDesc& s, const DensePlan& p, const PairDesc*
         a.sy = s.sy;
         a.win = s.win;
         dim3 grid((p.max_np + 255) / 256, p.C, npairs);
-        if (s.precision == TM_FP16)
-            hipLaunchKernelGGL(k_dense_generic<TM_FP16>, grid, dim3(256), 0, st, a, d);
-        else
-            hipLaunchKernelGGL(k_dense_generic<TM_FP32>, grid, dim3(256), 0, st, a, d);
+        if (s.precision == TM_FP16) {
+            if (s.vote)
+                hipLaunchKernelGGL((k_dense_generic<TM_FP16, 1>), grid, dim3(256), 0, st, a, d);
+            else
+                hipLaunchKernelGGL((k_dense_generic<TM_FP16, 0>), grid, dim3(256), 0, st, a, d);
+        } else {
+            if (s.vote)
+                hipLaunchKernelGGL((k_dense_generic<TM_FP32, 1>), grid, dim3(256), 0, st, a, d);
+            else
+                hipLaunchKernelGGL((k_dense_generic<TM_FP32, 0>), grid, dim3(256), 0, st, a, d);
+        }
         e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
@@ -829,16 +863,29 @@ hipError_t launch_dense(const SearchDesc& s, const DensePlan& p, const PairDesc*
     return hipGetLastError();
 }
 
+template <int PREC, int VOTE>
+void launch_sparse_t(const void* field, int W, int H, const ModelPoint* pts, int n, int win, const tm_eval_pose* poses,
+                     int np, float* scores, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_sparse<PREC, VOTE>), dim3((np + 3) / 4), dim3(256), 0, s, field, W, H, pts, n, win, poses,
+                       np, scores);
+}
+
 hipError_t launch_sparse(const void* field, int W, int H, int precision, const ModelPoint* pts, int n, int win,
-                         const tm_eval_pose* poses, int np, float* scores, hipStream_t s)
+                         int vote, const tm_eval_pose* poses, int np, float* scores, hipStream_t s)
 {
     if (np == 0) return hipSuccess;
-    if (precision == TM_FP16)
-        hipLaunchKernelGGL(k_sparse<TM_FP16>, dim3((np + 3) / 4), dim3(256), 0, s, field, W, H, pts, n, win, poses,
-                           np, scores);
-    else
-        hipLaunchKernelGGL(k_sparse<TM_FP32>, dim3((np + 3) / 4), dim3(256), 0, s, field, W, H, pts, n, win, poses,
-                           np, scores);
+    if (precision == TM_FP16) {
+        if (vote)
+            launch_sparse_t<TM_FP16, 1>(field, W, H, pts, n, win, poses, np, scores, s);
+        else
+            launch_sparse_t<TM_FP16, 0>(field, W, H, pts, n, win, poses, np, scores, s);
+    } else {
+        if (vote)
+            launch_sparse_t<TM_FP32, 1>(field, W, H, pts, n, win, poses, np, scores, s);
+        else
+            launch_sparse_t<TM_FP32, 0>(field, W, H, pts, n, win, poses, np, scores, s);
+    }
     return hipGetLastError();
 }
 

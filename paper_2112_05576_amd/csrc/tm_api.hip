@@ -52,6 +52,8 @@ tm_status check_image(const uint8_t* img, int w, int h, int pitch, const tm_pyr_
         return fail(TM_EINVAL, "%s: edge_thresh must be finite and >= 0", what);
     if (p->precision != TM_FP32 && p->precision != TM_FP16)
         return fail(TM_EINVAL, "%s: precision must be TM_FP32 or TM_FP16", what);
+    if (p->source != TM_PYR_GREY && p->source != TM_PYR_GRADIENT)
+        return fail(TM_EINVAL, "%s: source must be TM_PYR_GREY or TM_PYR_GRADIENT", what);
     if (pitch < w) return fail(TM_EINVAL, "%s: pitch %d < width %d", what, pitch, w);
     const long long minside = 3LL << (p->levels - 1);
     if (w < minside || h < minside)
@@ -116,6 +118,8 @@ tm_status check_search(const tm_search_params* sp, const char* what)
         return fail(TM_EINVAL, "%s: scale_min must be > 0 and scale_step >= 0", what);
     if (sp->scale_min + (sp->scale_count - 1) * sp->scale_step > 16.0)
         return fail(TM_EINVAL, "%s: scales above 16", what);
+    if (sp->vote != TM_VOTE_ALL && sp->vote != TM_VOTE_EDGE)
+        return fail(TM_EINVAL, "%s: vote must be TM_VOTE_ALL or TM_VOTE_EDGE", what);
     return TM_OK;
 }
 
@@ -255,6 +259,7 @@ tmk::SearchDesc make_search(const tm_search_params* sp, const Grid& g, int level
     s.theta_min = sp->theta_min_deg;
     s.full = g.full;
     s.win = sp->neighbourhood;
+    s.vote = sp->vote;
     s.sx = sp->step_x;
     s.sy = sp->step_y;
     s.precision = precision;
@@ -414,6 +419,7 @@ tm_status alloc_pyramid(int w, int h, const tm_pyr_params* pp, tm_pyramid** out)
     if (!p) return fail(TM_ENOMEM, "pyramid: host allocation");
     p->L = pp->levels;
     p->precision = pp->precision;
+    p->source = pp->source;
     p->tau = pp->edge_thresh;
     p->T2 = thresh_sq(pp->edge_thresh);
     hipGetDevice(&p->dev);
@@ -421,12 +427,15 @@ tm_status alloc_pyramid(int w, int h, const tm_pyr_params* pp, tm_pyramid** out)
     level_sizes(w, h, p->L, ws, hs);
     const size_t fsz = pp->precision == TM_FP16 ? 4 : 8;
     size_t total = 0;
-    size_t img_off[TM_MAX_LEVELS], fld_off[TM_MAX_LEVELS];
+    size_t img_off[TM_MAX_LEVELS], fld_off[TM_MAX_LEVELS], grd_off[TM_MAX_LEVELS];
+    const bool gradient = pp->source == TM_PYR_GRADIENT;
     for (int l = 0; l < p->L; ++l) {
         img_off[l] = total;
         total = align_up(total + (size_t)ws[l] * hs[l], 256);
         fld_off[l] = total;
         total = align_up(total + (size_t)ws[l] * hs[l] * fsz, 256);
+        grd_off[l] = total;
+        if (gradient) total = align_up(total + (size_t)ws[l] * hs[l] * 4, 256);
     }
     hipError_t e = hipMalloc(&p->block, total);
     if (e != hipSuccess) {
@@ -438,6 +447,8 @@ tm_status alloc_pyramid(int w, int h, const tm_pyr_params* pp, tm_pyramid** out)
         p->lv[l].h = hs[l];
         p->lv[l].img = reinterpret_cast<uint8_t*>(p->block) + img_off[l];
         p->lv[l].field = reinterpret_cast<uint8_t*>(p->block) + fld_off[l];
+        p->lv[l].grad = gradient ? reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(p->block) + grd_off[l])
+                                 : nullptr;
     }
     *out = p;
     return TM_OK;
@@ -469,6 +480,7 @@ TM_EXPORT tm_status tm_update_pyramid(tm_pyramid* p, const uint8_t* img, int32_t
     if (!p || !img) return fail(TM_EINVAL, "tm_update_pyramid: null argument");
     if (pitch < p->lv[0].w) return fail(TM_EINVAL, "tm_update_pyramid: pitch %d < width %d", pitch, p->lv[0].w);
     HIP_TRY(tmk::launch_pyr_build(img, pitch, p->lv, p->L, S(stream)));
+    if (p->source == TM_PYR_GRADIENT) HIP_TRY(tmk::launch_grad_pyramid(p->lv, p->L, S(stream)));
     HIP_TRY(tmk::launch_sobel_fields(p->lv, p->L, p->T2, p->precision, S(stream)));
     return TM_OK;
 }
@@ -495,10 +507,13 @@ TM_EXPORT tm_status tm_build_model(const uint8_t* img, int32_t w, int32_t h, int
     level_sizes(w, h, L, ws, hs);
     // temporary uint8 pyramid and point buffers of full capacity
     tmk::PyrLevel lv[TM_MAX_LEVELS] = {};
-    size_t total = 0, img_off[TM_MAX_LEVELS], pts_off[TM_MAX_LEVELS];
+    size_t total = 0, img_off[TM_MAX_LEVELS], pts_off[TM_MAX_LEVELS], grd_off[TM_MAX_LEVELS];
+    const bool gradient = pp->source == TM_PYR_GRADIENT;
     for (int l = 0; l < L; ++l) {
         img_off[l] = total;
         total = align_up(total + (size_t)ws[l] * hs[l], 256);
+        grd_off[l] = total;
+        if (gradient) total = align_up(total + (size_t)ws[l] * hs[l] * 4, 256);
     }
     for (int l = 0; l < L; ++l) {
         pts_off[l] = total;
@@ -514,11 +529,13 @@ TM_EXPORT tm_status tm_build_model(const uint8_t* img, int32_t w, int32_t h, int
         lv[l].h = hs[l];
         lv[l].img = reinterpret_cast<uint8_t*>(tmp) + img_off[l];
         lv[l].field = nullptr;
+        lv[l].grad = gradient ? reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(tmp) + grd_off[l]) : nullptr;
         pts[l] = reinterpret_cast<tmk::ModelPoint*>(reinterpret_cast<uint8_t*>(tmp) + pts_off[l]);
     }
     int* counts = reinterpret_cast<int*>(reinterpret_cast<uint8_t*>(tmp) + cnt_off);
     const long long T2 = thresh_sq(pp->edge_thresh);
     hipError_t e = tmk::launch_pyr_build(img, pitch, lv, L, s);
+    if (e == hipSuccess && gradient) e = tmk::launch_grad_pyramid(lv, L, s);
     if (e == hipSuccess) e = tmk::launch_model_points(lv, L, T2, pts, counts, s);
     int hc[TM_MAX_LEVELS] = {};
     if (e == hipSuccess) e = hipMemcpyAsync(hc, counts, sizeof(int) * L, hipMemcpyDeviceToHost, s);
@@ -540,6 +557,7 @@ TM_EXPORT tm_status tm_build_model(const uint8_t* img, int32_t w, int32_t h, int
     }
     m->L = L;
     m->tau = pp->edge_thresh;
+    m->source = pp->source;
     hipGetDevice(&m->dev);
     for (int l = 0; l < L; ++l) {
         tm_model_level& ml = m->lv[l];
@@ -658,17 +676,19 @@ TM_EXPORT tm_status tm_pyramid_read(const tm_pyramid* p, int32_t level, uint8_t*
     return TM_OK;
 }
 
-TM_EXPORT tm_status tm_score_poses(const tm_model* m, const tm_pyramid* p, int32_t level, int32_t win,
+TM_EXPORT tm_status tm_score_poses(const tm_model* m, const tm_pyramid* p, int32_t level, int32_t win, int32_t vote,
                                    const tm_eval_pose* poses, int32_t n, float* scores, void* stream)
 {
     tm_status st = check_pair(m, p, "tm_score_poses");
     if (st != TM_OK) return st;
     if (level < 0 || level >= p->L) return fail(TM_EINVAL, "tm_score_poses: bad level %d", level);
     if (win < 1 || win % 2 == 0 || win > 31) return fail(TM_EINVAL, "tm_score_poses: window must be odd in [1, 31]");
+    if (vote != TM_VOTE_ALL && vote != TM_VOTE_EDGE)
+        return fail(TM_EINVAL, "tm_score_poses: vote must be TM_VOTE_ALL or TM_VOTE_EDGE");
     if (n < 0) return fail(TM_EINVAL, "tm_score_poses: n < 0");
     if (n > 0 && (!poses || !scores)) return fail(TM_EINVAL, "tm_score_poses: null buffer");
     HIP_TRY(tmk::launch_sparse(p->lv[level].field, p->lv[level].w, p->lv[level].h, p->precision, m->lv[level].pts,
-                              m->lv[level].n, win, poses, n, scores, S(stream)));
+                              m->lv[level].n, win, vote, poses, n, scores, S(stream)));
     return TM_OK;
 }
 
@@ -1131,7 +1151,8 @@ tm_status batch_enqueue(tm_batch* b, hipStream_t s, bool timed)
 {
     const int top = b->L - 1;
     HIP_TRY(tmk::launch_pyramids_batch(b->d_pb, b->d_fa, b->n_images, b->L, b->level_w[0], b->level_h[0],
-                                       b->max_field_blocks, b->level_w, b->level_h, s));
+                                       b->max_field_blocks, b->level_w, b->level_h,
+                                       b->pyrs[0]->source == TM_PYR_GRADIENT, s));
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (timed) {
         tm_status st = timing_pair(&ev0, &ev1);
@@ -1206,7 +1227,8 @@ TM_EXPORT tm_status tm_batch_tune(tm_batch* b, int32_t iterations, void* stream,
         return TM_OK;  // the generic search has no forms to choose from
     }
     HIP_TRY(tmk::launch_pyramids_batch(b->d_pb, b->d_fa, b->n_images, b->L, b->level_w[0], b->level_h[0],
-                                       b->max_field_blocks, b->level_w, b->level_h, s));
+                                       b->max_field_blocks, b->level_w, b->level_h,
+                                       b->pyrs[0]->source == TM_PYR_GRADIENT, s));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
     hipError_t e = hipEventCreate(&e1);

@@ -114,6 +114,49 @@ __device__ __forceinline__ float field_dot(const void* field, int W, int H, int 
     return in ? v : 0.0f;
 }
 
+// Edge-taps-only window (tm_vote TM_VOTE_EDGE).  A tap off the edge set
+// (stored direction (0, 0)) or outside the image enters the window maximum as
+// kOffEdge = -2, below every cosine; a maximum of -2 (no edge tap) then votes
+// 0.  vote_finish does that by clearing bit 30 of the FP32 pattern: -2.0f is
+// 0xC0000000 and becomes -0.0f, while every cosine has |v| < 2 (unit vectors,
+// FP16 rounding included), so its bit 30 is clear and it passes unchanged.
+constexpr float kOffEdge = -2.0f;
+
+__device__ __forceinline__ float vote_finish(float m) { return __int_as_float(__float_as_int(m) & (int)0xBFFFFFFF); }
+
+__device__ __forceinline__ bool on_edge(float2 g) { return g.x != 0.0f || g.y != 0.0f; }
+
+// A window operand of the edge-taps reading at (x, y): the cosine on the edge
+// set, kOffEdge elsewhere.
+template <int PREC>
+__device__ __forceinline__ float field_vote_tap(const void* field, int W, int H, int x, int y, float rx, float ry)
+{
+    const bool in = (unsigned)x < (unsigned)W && (unsigned)y < (unsigned)H;
+    const int xc = min(max(x, 0), W - 1), yc = min(max(y, 0), H - 1);
+    const float2 g = field_load<PREC>(field, (size_t)yc * W + xc);
+    const float v = rx * g.x + ry * g.y;
+    return in && on_edge(g) ? v : kOffEdge;
+}
+
+// Window operand under either reading (VOTE 0: all taps, 1: edge taps).
+template <int PREC, int VOTE>
+__device__ __forceinline__ float field_win_tap(const void* field, int W, int H, int x, int y, float rx, float ry)
+{
+    if constexpr (VOTE == 1)
+        return field_vote_tap<PREC>(field, W, H, x, y, rx, ry);
+    else
+        return field_dot<PREC>(field, W, H, x, y, rx, ry);
+}
+
+template <int VOTE>
+__device__ __forceinline__ float win_finish(float m)
+{
+    if constexpr (VOTE == 1)
+        return vote_finish(m);
+    else
+        return m;
+}
+
 // The selection key: S_w desc, S_1 desc, then position x asc, y asc, then
 // angle index asc.  true iff (aw, a1, ax, ay, ak) ranks strictly before b.
 __device__ __forceinline__ bool key_better(float aw, float a1, int ax, int ay, int ak, float bw, float b1, int bx,

@@ -36,6 +36,7 @@ struct PyrLevel {
     int w, h;
     uint8_t* img;   // w*h bytes, row-major
     void* field;    // w*h float2 (FP32) or half2 (FP16), row-major
+    uint32_t* grad; // gradient-map pyramid only: w*h packed int16 pairs (gx low, gy high); else null
 };
 
 struct Workspace {
@@ -48,6 +49,7 @@ struct Workspace {
 struct tm_pyramid_s {
     int L = 0;
     int precision = TM_FP32;
+    int source = TM_PYR_GREY;
     float tau = 0.f;
     long long T2 = 0;
     int dev = 0;
@@ -78,6 +80,7 @@ struct tm_model_table_cache {
 struct tm_model_s {
     int L = 0;
     float tau = 0.f;
+    int source = TM_PYR_GREY;
     int dev = 0;
     tm_model_level lv[tmk::kMaxLevels];
     tm_model_table_cache cache;
@@ -101,6 +104,7 @@ struct PyrBuildArg {
 
 struct FieldsArg {
     const uint8_t* img[kMaxLevels];
+    uint32_t* grad[kMaxLevels];  // gradient-map pyramid (all null: gradients of each grey level)
     void* field[kMaxLevels];
     int w[kMaxLevels];
     int h[kMaxLevels];
@@ -113,14 +117,19 @@ struct FieldsArg {
 PyrBuildArg pyr_build_arg(const uint8_t* src, int src_pitch, const PyrLevel* lv, int L);
 FieldsArg fields_arg(const PyrLevel* lv, int L, long long T2, int precision);
 // Pyramids and fields of n_images images in one pass (pb, fa: device arrays);
-// level_w/level_h: largest level sizes over the images.
+// level_w/level_h: largest level sizes over the images; gradient: build the
+// gradient-map pyramids (fa[i].grad) before the fields.
 hipError_t launch_pyramids_batch(const PyrBuildArg* pb, const FieldsArg* fa, int n_images, int L, int max_w,
                                  int max_h, int max_field_blocks, const int* level_w, const int* level_h,
-                                 hipStream_t s);
+                                 bool gradient, hipStream_t s);
 
 // Level-0 copy (pitched source) and uint8 levels base+1 .. top.
 hipError_t launch_pyr_build(const uint8_t* src, int src_pitch, const PyrLevel* lv, int L, hipStream_t s);
-// Unit direction fields of levels 0 .. L-1 (FP32 or FP16).
+// Gradient-map pyramid: the Sobel pair of level 0's image into grad[0],
+// then floored 2x2 means level by level (levels with grad set).
+hipError_t launch_grad_pyramid(const PyrLevel* lv, int L, hipStream_t s);
+// Unit direction fields of levels 0 .. L-1 (FP32 or FP16), from lv[l].grad
+// where set, else from the Sobel pair of the level's image.
 hipError_t launch_sobel_fields(const PyrLevel* lv, int L, long long T2, int precision, hipStream_t s);
 // Row-major edge points of each model level into pts[l] (capacity w*h),
 // counts into counts[l].
@@ -172,6 +181,7 @@ struct SearchDesc {
     double step[kMaxLevels];    // angle step per level
     double theta_min;
     int full, win, sx, sy, precision;
+    int vote;                   // tm_vote: which taps of a window vote
     float min_score;
     int max_cand, capacity;
     int S;                      // scales (1: rigid)
@@ -185,6 +195,7 @@ inline int poses_per_translation(const SearchDesc& s) { return s.K[s.level] * s.
 // Launch plan of the exhaustive search, common to all pairs.
 struct DensePlan {
     bool fast;
+    int vote;                   // tm_vote (the edge-taps reading has one kernel form)
     int variant;                // search kernel form (k_dense_fast VAR)
     int G, R, LC, WY, WA;
     int A, C;                   // angles per workgroup, chunks of angles
@@ -259,6 +270,6 @@ hipError_t launch_line_search(const PairDesc* d, int batched, int npairs, int le
 
 // One wave per pose: S_w and S_1 of arbitrary poses.
 hipError_t launch_sparse(const void* field, int W, int H, int precision, const ModelPoint* pts, int n, int win,
-                         const tm_eval_pose* poses, int np, float* scores, hipStream_t s);
+                         int vote, const tm_eval_pose* poses, int np, float* scores, hipStream_t s);
 
 }  // namespace tmk

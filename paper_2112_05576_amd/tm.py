@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(_HERE, "lib", "libtm.so")
 
 TM_OK, TM_EINVAL, TM_ENOMEM, TM_EDEVICE, TM_ECAPACITY = 0, -1, -2, -3, -4
 TM_FP32, TM_FP16 = 0, 1
+TM_PYR_GREY, TM_PYR_GRADIENT = 0, 1
+TM_VOTE_ALL, TM_VOTE_EDGE = 0, 1
 MAX_LEVELS = 8
 
 
@@ -29,7 +31,8 @@ class TMError(RuntimeError):
 
 
 class PyrParamsC(ctypes.Structure):
-    _fields_ = [("levels", ctypes.c_int32), ("edge_thresh", ctypes.c_float), ("precision", ctypes.c_int32)]
+    _fields_ = [("levels", ctypes.c_int32), ("edge_thresh", ctypes.c_float), ("precision", ctypes.c_int32),
+                ("source", ctypes.c_int32)]
 
 
 class SearchParamsC(ctypes.Structure):
@@ -37,7 +40,7 @@ class SearchParamsC(ctypes.Structure):
                 ("theta_range_deg", ctypes.c_double), ("theta_step_top_deg", ctypes.c_double),
                 ("neighbourhood", ctypes.c_int32), ("min_score", ctypes.c_float), ("nms_min_dist", ctypes.c_float),
                 ("max_candidates", ctypes.c_int32), ("max_matches", ctypes.c_int32), ("scale_min", ctypes.c_double),
-                ("scale_step", ctypes.c_double), ("scale_count", ctypes.c_int32)]
+                ("scale_step", ctypes.c_double), ("scale_count", ctypes.c_int32), ("vote", ctypes.c_int32)]
 
 
 # tm_pose: x, y, k, level (int32), theta_deg, score_w, score_1 (float32), j (scale index)
@@ -62,7 +65,7 @@ def lib():
             "tm_build_model": [_vp, _i32, _i32, _i32, ctypes.POINTER(PyrParamsC), _vp, ctypes.POINTER(_vp)],
             "tm_build_pyramid": [_vp, _i32, _i32, _i32, ctypes.POINTER(PyrParamsC), _vp, ctypes.POINTER(_vp)],
             "tm_update_pyramid": [_vp, _vp, _i32, _vp],
-            "tm_score_poses": [_vp, _vp, _i32, _i32, _vp, _i32, _vp, _vp],
+            "tm_score_poses": [_vp, _vp, _i32, _i32, _i32, _vp, _i32, _vp, _vp],
             "tm_score_map": [_vp, _vp, _i32, ctypes.POINTER(SearchParamsC), _vp, _vp, _vp, _vp],
             "tm_select": [_vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, ctypes.c_float, ctypes.c_float, _vp, _i32,
                           _vp, _vp],
@@ -147,11 +150,12 @@ class SearchParams:
     scale_min: float = 1.0     # similarity pose: scales scale_min + j * scale_step, j < scale_count
     scale_step: float = 0.0
     scale_count: int = 1
+    vote: int = 0              # TM_VOTE_ALL, or TM_VOTE_EDGE: only edge taps of a window vote
 
     def c(self) -> SearchParamsC:
         return SearchParamsC(self.step_x, self.step_y, self.theta_min, self.theta_range, self.theta_step_top,
                              self.neighbourhood, self.min_score, self.nms_min_dist, self.max_candidates,
-                             self.max_matches, self.scale_min, self.scale_step, self.scale_count)
+                             self.max_matches, self.scale_min, self.scale_step, self.scale_count, self.vote)
 
     def scale(self, j: int) -> float:
         return self.scale_min + j * self.scale_step
@@ -160,10 +164,10 @@ class SearchParams:
 class Model:
     """Edge-point model of a template image on every pyramid level."""
 
-    def __init__(self, img, levels: int, edge_thresh: float, stream=None):
+    def __init__(self, img, levels: int, edge_thresh: float, stream=None, source: int = 0):
         img = _dev_u8(img)
         self._h = _vp()
-        p = PyrParamsC(levels, edge_thresh, TM_FP32)
+        p = PyrParamsC(levels, edge_thresh, TM_FP32, source)
         H, W = img.shape
         _check(lib().tm_build_model(_vp(img.data_ptr()), W, H, img.stride(0), ctypes.byref(p),
                                     _vp(_stream(stream)), ctypes.byref(self._h)))
@@ -208,10 +212,11 @@ class Model:
 class Pyramid:
     """Grey-level pyramid and unit-direction field of a search image."""
 
-    def __init__(self, img, levels: int, edge_thresh: float, precision: int = TM_FP32, stream=None):
+    def __init__(self, img, levels: int, edge_thresh: float, precision: int = TM_FP32, stream=None,
+                 source: int = 0):
         img = _dev_u8(img)
         self._h = _vp()
-        p = PyrParamsC(levels, edge_thresh, precision)
+        p = PyrParamsC(levels, edge_thresh, precision, source)
         H, W = img.shape
         _check(lib().tm_build_pyramid(_vp(img.data_ptr()), W, H, img.stride(0), ctypes.byref(p),
                                       _vp(_stream(stream)), ctypes.byref(self._h)))
@@ -261,7 +266,8 @@ def poses_to_numpy(t: torch.Tensor, n: int | None = None) -> np.ndarray:
     return a if n is None else a[:n]
 
 
-def score_poses(model: Model, pyr: Pyramid, level: int, x, y, theta, neighbourhood: int = 3, stream=None):
+def score_poses(model: Model, pyr: Pyramid, level: int, x, y, theta, neighbourhood: int = 3, stream=None,
+                vote: int = 0):
     """S_w and S_1 (float32 tensor (n, 2)) of integer translations x, y and angles theta (degrees)."""
     ep = np.zeros(len(x), EVAL_DTYPE)
     ep["x"] = np.asarray(x, np.int32)
@@ -269,7 +275,7 @@ def score_poses(model: Model, pyr: Pyramid, level: int, x, y, theta, neighbourho
     ep["theta"] = np.asarray(theta, np.float64)
     dev = torch.from_numpy(ep.view(np.uint8)).cuda()
     out = torch.empty((len(ep), 2), dtype=torch.float32, device="cuda")
-    _check(lib().tm_score_poses(model.handle, pyr.handle, level, neighbourhood, _vp(dev.data_ptr()), len(ep),
+    _check(lib().tm_score_poses(model.handle, pyr.handle, level, neighbourhood, vote, _vp(dev.data_ptr()), len(ep),
                                 _vp(out.data_ptr()), _vp(_stream(stream))))
     return out
 
@@ -335,7 +341,7 @@ class Batch:
     `n_out` (pairs,), pair = image * n_models + model."""
 
     def __init__(self, models, images, levels: int, edge_thresh: float, sp: SearchParams,
-                 precision: int = TM_FP32, capacity: int | None = None, stream=None):
+                 precision: int = TM_FP32, capacity: int | None = None, stream=None, source: int = 0):
         self.images = [_dev_u8(im) for im in images]
         self.models = list(models)
         self.capacity = capacity or sp.max_matches
@@ -348,7 +354,7 @@ class Batch:
         ws = (_i32 * ni)(*[im.shape[1] for im in self.images])
         hs = (_i32 * ni)(*[im.shape[0] for im in self.images])
         ps = (_i32 * ni)(*[im.stride(0) for im in self.images])
-        pp = PyrParamsC(levels, edge_thresh, precision)
+        pp = PyrParamsC(levels, edge_thresh, precision, source)
         c = sp.c()
         self._h = _vp()
         _check(lib().tm_batch_create(mh, nm, ih, ws, hs, ps, ni, ctypes.byref(pp), ctypes.byref(c),

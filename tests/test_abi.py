@@ -59,6 +59,10 @@ def test_invalid_arguments_fail_before_the_device(L):
     assert L.tm_build_pyramid(fake, 64, 64, 64, ctypes.byref(bad), None, ctypes.byref(out)) == tm.TM_EINVAL
     bad = tm.PyrParamsC(4, 30.0, 7)
     assert L.tm_build_pyramid(fake, 64, 64, 64, ctypes.byref(bad), None, ctypes.byref(out)) == tm.TM_EINVAL
+    bad = tm.PyrParamsC(4, 30.0, tm.TM_FP32, 2)  # neither pyramid source
+    assert L.tm_build_pyramid(fake, 64, 64, 64, ctypes.byref(bad), None, ctypes.byref(out)) == tm.TM_EINVAL
+    assert b"source" in L.tm_last_error()
+    assert L.tm_build_model(fake, 64, 64, 64, ctypes.byref(bad), None, ctypes.byref(out)) == tm.TM_EINVAL
     assert L.tm_build_pyramid(fake, 64, 64, 32, ctypes.byref(pp), None, ctypes.byref(out)) == tm.TM_EINVAL
     # 4 levels need at least 3 * 2^3 = 24 pixels a side
     assert L.tm_build_pyramid(fake, 23, 64, 64, ctypes.byref(pp), None, ctypes.byref(out)) == tm.TM_EINVAL
@@ -69,7 +73,7 @@ def test_invalid_arguments_fail_before_the_device(L):
     assert L.tm_select(fake, fake, fake, 4, 4, 1, 1, 0, 0.5, 1.0, fake, 0, fake, None) == tm.TM_EINVAL
     assert L.tm_select(fake, fake, fake, 4, 4, 0, 1, 0, 0.5, 1.0, fake, 8, fake, None) == tm.TM_EINVAL
     assert L.tm_refine(None, None, ctypes.byref(sp), 3, fake, 1, None) == tm.TM_EINVAL
-    assert L.tm_score_poses(None, None, 0, 3, fake, 1, fake, None) == tm.TM_EINVAL
+    assert L.tm_score_poses(None, None, 0, 3, 0, fake, 1, fake, None) == tm.TM_EINVAL
     assert L.tm_model_level_info(None, 0, None, None, None) == tm.TM_EINVAL
     assert L.tm_pyramid_read(None, 0, None, None, None) == tm.TM_EINVAL
     L.tm_model_free(None)
@@ -111,6 +115,10 @@ def test_continuous_and_batch_entries_validate_first(L):
                              ctypes.byref(out)) == tm.TM_EINVAL
     assert L.tm_batch_create(ptrs, 1, ptrs, one, one, one, 1, ctypes.byref(pp), ctypes.byref(sp), None, 8, fake,
                              None, ctypes.byref(out)) == tm.TM_EINVAL
+    badv = tm.SearchParams(vote=2).c()  # neither window reading
+    assert L.tm_batch_create(ptrs, 1, ptrs, one, one, one, 1, ctypes.byref(pp), ctypes.byref(badv), fake, 8, fake,
+                             None, ctypes.byref(out)) == tm.TM_EINVAL
+    assert b"vote" in L.tm_last_error()
     assert not out.value
     L.tm_batch_free(None)
 

@@ -209,8 +209,8 @@ def test_edge_vote_order_relation_and_window_one(oracle_mod):
 
 @pytest.mark.parametrize("source,vote", [("gradient", "all"), ("grey", "edge"), ("gradient", "edge")])
 def test_detect_with_readings_finds_the_instances(oracle_mod, source, vote):
-    cfg = synth.CONFIGS[1]
-    sc = synth.scene_for_config(1, 0)
+    cfg = synth.CONFIGS[2]
+    sc = synth.scene_for_config(2, 1)
     L = cfg["levels"]
     tr = oracle_mod.detect(sc.image, sc.model, oracle_mod.PyrParams(L, cfg["tau_s"], source),
                            oracle_mod.PyrParams(L, cfg["tau_m"], source),
