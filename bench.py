@@ -20,7 +20,12 @@ the timed region, on the same stream.
 
 --c4 adds the mixed batch (64 images of 640x480 to 2448x2048 against 8 models,
 one graph launch per step) and the continuous refinement of 4096 poses over
-its pairs (10 ascent steps).  --copy-probe ends the run with one 256 MiB
+its pairs (10 ascent steps).  --paper times the search of the paper's own
+experiment shape (812x617, 3 px / 3 px / 3 deg steps over 90 deg, one level);
+--similarity the similarity pose (angles x scales); --readings the four
+combinations of pyramid source (grey image or gradient maps) and window vote
+(all taps or edge taps only), with their ground-truth matches.  --copy-probe
+ends the run with one 256 MiB
 elementwise copy, the calibration of the HBM byte counters; --traffic-from
 turns two rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE) into the committed
 per-launch traffic figure of the search kernel.
@@ -61,6 +66,8 @@ def parse():
                     help="also time the similarity-pose search (x, y, theta, scale) on 64 scaled 640x480 scenes")
     ap.add_argument("--paper", action="store_true",
                     help="also time the paper's own search shape (812x617, 3 px / 3 deg steps, 90 deg, one level)")
+    ap.add_argument("--readings", action="store_true",
+                    help="also time and score the four combinations of pyramid source and window vote")
     ap.add_argument("--copy-probe", action="store_true", help="end with a 256 MiB elementwise copy (counter scale)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the search kernel's traffic entry from two rocprofv3 --pmc CSV files and exit")
@@ -277,6 +284,55 @@ def similarity_leg(P, torch, steps):
             "search_form": tuned}
 
 
+def readings_leg(P, torch, steps):
+    """The two readings of the method that the paper leaves open, each on and
+    off: the pyramid of the grey image or of the gradient maps, and a window
+    vote over all taps or over edge taps only.  Per combination the headline
+    batch (64 C2 scenes of 640x480, FP16, graph launch, tuned) is timed, and
+    its detections are matched against the ground truth: top-1 hits, the
+    instances found by any detection (within 2 px and 2 degrees, and within
+    2 px alone) and the detections within 2 px of no instance."""
+    import synth
+
+    cfg = synth.CONFIGS[2]
+    L = cfg["levels"]
+    scenes = [synth.scene_for_config(2, i) for i in range(64)]
+    imgs = [torch.from_numpy(s.image).cuda() for s in scenes]
+    n_inst = sum(len(sc.instances) for sc in scenes)
+    out = {}
+    for src_name, src in (("grey", P.TM_PYR_GREY), ("gradient", P.TM_PYR_GRADIENT)):
+        model = P.Model(scenes[0].model, L, cfg["tau_m"], source=src)
+        for vote_name, vote in (("all", P.TM_VOTE_ALL), ("edge", P.TM_VOTE_EDGE)):
+            sp = P.SearchParams(theta_step_top=cfg["theta_step_top"], vote=vote)
+            b = P.Batch([model], imgs, L, cfg["tau_s"], sp, precision=P.TM_FP16, source=src)
+            b.tune(iterations=2)
+            b.run(graph=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                b.run(graph=True)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            res = b.results()
+            found = found_xy = stray = 0
+            for d, sc in zip(res, scenes):
+                at = [[np.hypot(x["x"] - it.x, x["y"] - it.y) <= 2.0 for it in sc.instances] for x in d]
+                near = [[a and _ang(x["theta"], it.theta) <= 2.0 for a, it in zip(row, sc.instances)]
+                        for row, x in zip(at, d)]
+                found += sum(any(row[i] for row in near) for i in range(len(sc.instances)))
+                found_xy += sum(any(row[i] for row in at) for i in range(len(sc.instances)))
+                stray += sum(not any(row) for row in at)
+            out[f"{src_name}_pyramid+{vote_name}_taps"] = {
+                "ms_per_step": dt * 1e3, "detections_per_sec": len(scenes) / dt,
+                "top1_ground_truth_hits": f"{sum(gt_hit(d, sc) for d, sc in zip(res, scenes))}/{len(scenes)}",
+                "instances_found": f"{found}/{n_inst}", "instances_found_xy_only": f"{found_xy}/{n_inst}",
+                "unmatched_detections": stray,
+                "model_points_top": model.level_info(L - 1)[2], "search_form": b.search_form()}
+    out["workload"] = ("64 images of 640x480 (3 instances each), 4 levels, 1 deg top step, FP16, graph launch; "
+                       "matches within 2 px and 2 deg")
+    return out
+
+
 def paper_leg(P, torch, steps):
     """The search of the paper's experiment on synthetic 812x617 frames: every
     3rd pixel, 31 angles over 90 degrees, one level, the single best pose;
@@ -446,6 +502,8 @@ def main():
         res["paper_shape"] = paper_leg(P, torch, max(8, args.steps))
     if args.similarity:
         res["similarity"] = similarity_leg(P, torch, max(5, args.steps // 4))
+    if args.readings:
+        res["readings"] = readings_leg(P, torch, max(5, args.steps // 4))
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(scenes[:8], cfg, args.cpu_seconds, paper=args.paper)
     if args.copy_probe:

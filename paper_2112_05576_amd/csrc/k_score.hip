@@ -114,11 +114,8 @@ struct Px<TM_FP32> {
     static __device__ __forceinline__ T zero() { return make_float2(0.f, 0.f); }
     static __device__ __forceinline__ T load(const void* f, size_t o) { return reinterpret_cast<const float2*>(f)[o]; }
     static __device__ __forceinline__ float dot(const TabEntry& e, T g) { return e.rx * g.x + e.ry * g.y; }
-    // on the edge set: not (+-0, +-0)
-    static __device__ __forceinline__ bool edge(T g)
-    {
-        return ((__float_as_uint(g.x) | __float_as_uint(g.y)) << 1) != 0u;
-    }
+    // on the edge set: the field and the tile padding hold non-edges as (+0, +0)
+    static __device__ __forceinline__ bool edge(T g) { return (__float_as_uint(g.x) | __float_as_uint(g.y)) != 0u; }
     template <bool ASM>
     static __device__ __forceinline__ float dot_t(const TabEntry& e, T g)
     {
@@ -134,7 +131,8 @@ struct Px<TM_FP16> {
     {
         return __builtin_amdgcn_fdot2(__builtin_bit_cast(h2_t, e.rh), __builtin_bit_cast(h2_t, g), 0.0f, false);
     }
-    static __device__ __forceinline__ bool edge(T g) { return (g & 0x7FFF7FFFu) != 0u; }
+    // non-edges are the half2 (+0, +0), bit pattern 0
+    static __device__ __forceinline__ bool edge(T g) { return g != 0u; }
     template <bool ASM>
     static __device__ __forceinline__ float dot_t(const TabEntry& e, T g)
     {
