@@ -163,6 +163,7 @@ __device__ __forceinline__ void dots10_f16(uint32_t rh, const uint32_t (&g)[10],
 
 struct FastArgs {
     int level;          // searched level
+    int tr;             // 1: lanes run along y and strips along x (the tile transposed)
     int K;              // angles
     int A;              // angles per workgroup
     int WY, WA;         // waves stacked in y, waves splitting the angles
@@ -192,25 +193,39 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc*
         bx = wv.y;
         if (pr < 0) return;
     }
+    // Tile frame: u runs along the lanes (the tile's columns, TW per
+    // segment), v along the strips (its rows, TH).  tr 0: u = x, v = y; tr 1:
+    // u = y, v = x, which fits some level shapes with fewer idle lanes (the
+    // 3x3 window is symmetric, so the scores are the same).
     const PairDesc& P = pairs[pr];
-    const int n_tiles = P.tiles_x * P.tiles_y;
+    const int n_tiles = P.tiles_x * P.tiles_y;  // tiles along u, v
     if (bx >= n_tiles * a.C) return;
     const int TH = a.WY * NS * R;
     const int chunk = bx / n_tiles;
     const int tid = bx % n_tiles;
-    const int X0 = (tid % P.tiles_x) * TW, Y0 = (tid / P.tiles_x) * TH;
+    const int U0 = (tid % P.tiles_x) * TW, V0 = (tid / P.tiles_x) * TH;
     const int W = P.W[a.level], H = P.H[a.level];
     const void* field = P.field[a.level];
     const int halo = P.rad + 1;
     const int LR = TH + 2 * halo;
     const int fc = TW + 2 * halo;
+    const bool tr = a.tr != 0;
 
+    // stage tile[v][u]; consecutive threads take consecutive x
     for (int e = threadIdx.x; e < LR * fc; e += blockDim.x) {
-        const int r = e / fc, c = e - r * fc;
-        const int x = X0 - halo + c, y = Y0 - halo + r;
-        T v = Px<PREC>::zero();
-        if (x >= 0 && x < W && y >= 0 && y < H) v = Px<PREC>::load(field, (size_t)y * W + x);
-        tile[r * LC + c] = v;
+        int r, c;
+        if (tr) {
+            c = e / LR;
+            r = e - c * LR;
+        } else {
+            r = e / fc;
+            c = e - r * fc;
+        }
+        const int u = U0 - halo + c, v = V0 - halo + r;
+        const int x = tr ? v : u, y = tr ? u : v;
+        T val = Px<PREC>::zero();
+        if (x >= 0 && x < W && y >= 0 && y < H) val = Px<PREC>::load(field, (size_t)y * W + x);
+        tile[r * LC + c] = val;
     }
     __syncthreads();
 
@@ -254,7 +269,8 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc*
             // the horizontal window maxima, added in point order
             // (fetch: the point's R+2 field values from LDS; compute: the rest)
             auto fetch = [&](const TabEntry& e, T (&gv)[R + 2]) {
-                const T* p = lbase + (int)e.qy * LC + (int)e.qx;
+                const int qu = tr ? (int)e.qy : (int)e.qx, qv = tr ? (int)e.qx : (int)e.qy;
+                const T* p = lbase + qv * LC + qu;
 #pragma unroll
                 for (int rr = 0; rr < R + 2; ++rr) gv[rr] = p[rr * LC];
             };
@@ -370,8 +386,8 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc*
     }
     __syncthreads();
     for (int p = threadIdx.x; p < npos; p += blockDim.x) {
-        const int py = p / TW, px = p - py * TW;
-        const int X = X0 + px, Y = Y0 + py;
+        const int pv = p / TW, pu = p - pv * TW;
+        const int X = tr ? V0 + pv : U0 + pu, Y = tr ? U0 + pu : V0 + pv;
         if (X >= W || Y >= H) continue;
         float w0 = cw[p], s0 = c1[p];
         int kk = ck[p];
@@ -659,8 +675,9 @@ void plan_tiles(const DensePlan& p, const PairGeom& g, int* tiles_x, int* tiles_
         return;
     }
     const int TW = p.G - 2, TH = p.WY * (64 / p.G) * p.R;
-    *tiles_x = (g.W + TW - 1) / TW;
-    *tiles_y = (g.H + TH - 1) / TH;
+    const int Wu = p.tr ? g.H : g.W, Hv = p.tr ? g.W : g.H;  // extents along the lanes and the strips
+    *tiles_x = (Wu + TW - 1) / TW;
+    *tiles_y = (Hv + TH - 1) / TH;
 }
 
 DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
@@ -692,6 +709,20 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
         const size_t comb_bytes = (size_t)12 * p.WA * TH * TW;
         p.lds = p.tile_lds > comb_bytes ? p.tile_lds : comb_bytes;
         if (p.LC == 0 || p.lds > 160 * 1024) p.fast = false;
+    }
+    if (p.fast) {
+        // orientation: the one whose tiles leave fewer translations idle over
+        // the whole launch (ties: lanes along x)
+        long long cover[2] = {0, 0};
+        for (int t = 0; t < 2; ++t) {
+            p.tr = t;
+            for (int i = 0; i < npairs; ++i) {
+                int tx, ty;
+                plan_tiles(p, g[i], &tx, &ty);
+                cover[t] += (long long)tx * ty;
+            }
+        }
+        p.tr = knob("TM_DENSE_TR", cover[1] < cover[0] ? 1 : 0, 0, 1);
     }
     if (p.fast) {
         // about four waves per SIMD over the whole batch, whole angles per wave
@@ -819,6 +850,7 @@ hipError_t launch_dense(const SearchDesc& s, const DensePlan& p, const PairDesc*
     if (p.fast) {
         FastArgs a;
         a.level = s.level;
+        a.tr = p.tr;
         a.K = poses_per_translation(s);
         a.A = p.A;
         a.WY = p.WY;

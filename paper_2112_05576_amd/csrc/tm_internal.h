@@ -154,7 +154,7 @@ struct PairDesc {
     const TabEntry* tab;             // rotated table of the searched level, [K][n_pad]
     int n_pad, rad;                  // table padding; bound on |q| at the searched level
     int gw, gh;                      // translation grid of the searched level
-    int tiles_x, tiles_y;            // search tiles (fast path)
+    int tiles_x, tiles_y;            // search tiles along the lanes and the strips (fast path)
     float dmin;                      // suppression distance, level-0 pixels
     float* pw;                       // chunk partials [C][gh][gw]: best S_w,
     float* p1;                       //   S_1,
@@ -197,6 +197,7 @@ struct DensePlan {
     bool fast;
     int vote;                   // tm_vote (the edge-taps reading has one kernel form)
     int variant;                // search kernel form (k_dense_fast VAR)
+    int tr;                     // 1: lanes along y, strips along x (FastArgs.tr)
     int G, R, LC, WY, WA;
     int A, C;                   // angles per workgroup, chunks of angles
     size_t lds;

@@ -451,14 +451,42 @@ def test_search_kernel_shape_independence(precision, monkeypatch):
     pyr = P.Pyramid(sc.image, 4, cfg["tau_s"], precision=precision)
     sp = P.SearchParams(theta_step_top=1.0)
     ref = [t.clone() for t in P.score_map(gm, pyr, 3, sp)]
-    for wy, wa, apw, asm in [(1, 4, 1, 1), (2, 4, 1, 0), (1, 8, 2, 2), (1, 16, 1, 3), (4, 1, 3, 5), (1, 4, 1, 4),
-                             (2, 2, 1, 5)]:
+    for wy, wa, apw, asm, tr in [(1, 4, 1, 1, 0), (2, 4, 1, 0, 1), (1, 8, 2, 2, 0), (1, 16, 1, 3, 1),
+                                 (4, 1, 3, 5, 0), (1, 4, 1, 4, 0), (1, 16, 1, 4, 1), (2, 2, 1, 5, 1)]:
         monkeypatch.setenv("TM_DENSE_WY", str(wy))
         monkeypatch.setenv("TM_DENSE_WA", str(wa))
         monkeypatch.setenv("TM_DENSE_APW", str(apw))
         monkeypatch.setenv("TM_DENSE_ASM", str(asm))
+        monkeypatch.setenv("TM_DENSE_TR", str(tr))
         got = P.score_map(gm, pyr, 3, sp)
-        assert all(torch.equal(x, y) for x, y in zip(ref, got)), (wy, wa, apw, asm)
+        assert all(torch.equal(x, y) for x, y in zip(ref, got)), (wy, wa, apw, asm, tr)
+
+
+@pytest.mark.parametrize("H,W", [(61, 67), (40, 201), (201, 40), (41, 95)])
+def test_search_orientation_independence(H, W, monkeypatch):
+    """Lanes along x or along y (the tile transposed): bit-identical maps on
+    ragged shapes, both equal to the oracle's within the bar."""
+    P = _P()
+    case(f"orientations {W}x{H}")
+    rng = np.random.default_rng(950 + H + W)
+    shape = synth.make_model_shape("blocks", 24, rng)
+    model = synth.render_model(shape, 24)
+    sc = synth.render_scene(rng, W, H, shape, 24, 1, 5.0, clutter=6)
+    gm = P.Model(model, 1, 30.0)
+    sp = P.SearchParams(theta_step_top=7.5)
+    maps = []
+    for prec in (0, 1):
+        pyr = P.Pyramid(sc.image, 1, 30.0, precision=prec)
+        per = []
+        for tr in (0, 1):
+            monkeypatch.setenv("TM_DENSE_TR", str(tr))
+            per.append([t.clone() for t in P.score_map(gm, pyr, 0, sp)])
+        assert all(torch.equal(x, y) for x, y in zip(*per)), prec
+        maps.append(per[0])
+    om = O.build_model(model, O.PyrParams(1, 30.0))
+    g = O.edge_field(sc.image, 30.0)
+    ref = O.top_map(g, om.levels[0].t, om.levels[0].d, 0.0, 7.5, 48)
+    _check_map(maps[0], ref, g, om.levels[0], 0.0, 7.5, 1, 1, 3)
 
 
 # ------------------------------------------------------------ batches
