@@ -112,8 +112,9 @@ def traffic_from(fetch_csv, write_csv):
         if len({(n, wg) for n, _, wg in sel}) != 1:
             raise SystemExit(f"several search forms in {path}: take the counters with --no-tune")
         dense = [v for _, v, _ in sel]
-        out["form"] = {"variant": int(re.search(r"k_dense_fast<[^>]*,\s*(\d+)>", sel[0][0]).group(1)),
-                       "waves_per_chunk": sel[0][2] // 64}
+        # template arguments: G, R, LC, PREC, VAR (the variant), VOTE
+        targs = [int(t) for t in re.search(r"k_dense_fast<([^>]*)>", sel[0][0]).group(1).split(",")]
+        out["form"] = {"variant": targs[4], "waves_per_chunk": sel[0][2] // 64}
         scale = COPY_PROBE_BYTES / probe  # bytes per counted KiB
         out[key] = {"kib_per_launch": sum(dense) / len(dense), "probe_kib": probe, "scale_bytes_per_kib": scale,
                     "bytes_per_launch": sum(dense) / len(dense) * scale, "launches": len(dense)}
