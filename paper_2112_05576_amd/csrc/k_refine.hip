@@ -78,23 +78,59 @@ struct LevelArgs {
 };
 // (the window reading, tm_vote, is the kernels' VOTE template argument)
 
+// Field element as stored (FP32 pair, or the half2 bits), the rotated model
+// direction in the form its product takes (FP32 pair, or half2), and the
+// product: FP32 products and sum, or v_dot2_f32_f16 (FP32 result) as in the
+// FP16 search.
+typedef _Float16 rh2_t __attribute__((ext_vector_type(2)));
+template <int PREC>
+struct Raw;
+template <>
+struct Raw<TM_FP32> {
+    using T = float2;
+    using R = float2;
+    static __device__ __forceinline__ T zero() { return make_float2(0.f, 0.f); }
+    static __device__ __forceinline__ T load(const void* f, size_t o) { return reinterpret_cast<const float2*>(f)[o]; }
+    static __device__ __forceinline__ R dir(double rx, double ry) { return make_float2((float)rx, (float)ry); }
+    static __device__ __forceinline__ float dot(R r, T g) { return r.x * g.x + r.y * g.y; }
+    static __device__ __forceinline__ bool edge(T g) { return g.x != 0.0f || g.y != 0.0f; }
+};
+template <>
+struct Raw<TM_FP16> {
+    using T = uint32_t;
+    using R = uint32_t;
+    static __device__ __forceinline__ T zero() { return 0u; }
+    static __device__ __forceinline__ T load(const void* f, size_t o) { return reinterpret_cast<const uint32_t*>(f)[o]; }
+    static __device__ __forceinline__ R dir(double rx, double ry)
+    {
+        const __half2 h = __floats2half2_rn((float)rx, (float)ry);
+        return __builtin_bit_cast(uint32_t, h);
+    }
+    static __device__ __forceinline__ float dot(R r, T g)
+    {
+        return __builtin_amdgcn_fdot2(__builtin_bit_cast(rh2_t, r), __builtin_bit_cast(rh2_t, g), 0.0f, false);
+    }
+    // non-edges are stored as the half2 (+0, +0), bit pattern 0
+    static __device__ __forceinline__ bool edge(T g) { return g != 0u; }
+};
+
 // The 9 windowed votes and 9 centre votes of one point from the 5x5 block of
 // field values around its projection (taps outside the image vote 0).  VOTE
 // 1: the edge-taps-only window (off-edge and outside taps enter the maxima as
 // kOffEdge, each maximum is finished by vote_finish); centre votes as in 0.
-template <int VOTE>
-__device__ __forceinline__ void votes5x5(const float2 (&gv)[5][5], const bool (&rin)[5], const bool (&cin)[5], float fx,
-                                         float fy, float (&aw)[9], float (&a1)[9])
+template <int PREC, int VOTE>
+__device__ __forceinline__ void votes5x5(const typename Raw<PREC>::T (&gv)[5][5], const bool (&rin)[5],
+                                         const bool (&cin)[5], typename Raw<PREC>::R r, float (&aw)[9], float (&a1)[9])
 {
     float D[5][5], E[5][5];
 #pragma unroll
     for (int v = 0; v < 5; ++v)
 #pragma unroll
         for (int u = 0; u < 5; ++u) {
-            const float d = fx * gv[v][u].x + fy * gv[v][u].y;
+            const float d = Raw<PREC>::dot(r, gv[v][u]);
             D[v][u] = (rin[v] && cin[u]) ? d : 0.0f;
             if constexpr (VOTE == 1)
-                E[v][u] = (rin[v] && cin[u] && on_edge(gv[v][u])) ? d : kOffEdge;
+                E[v][u] = (rin[v] && cin[u] && Raw<PREC>::edge(gv[v][u])) ? d : kOffEdge;
             else
                 E[v][u] = D[v][u];
         }
@@ -230,6 +266,7 @@ __global__ __launch_bounds__(kThreads) void k_refine_level(LevelArgs a, const Pa
     const void* field = P.field[l];
     const int W = P.W[l], H = P.H[l], n = P.n[l];
     const ModelPoint* __restrict__ pts = P.pts[l];
+    const double2* __restrict__ dir = P.dir[l];
     const int kc = angle_index(2 * k + g - 1, a.K, a.full);
     double cs, sn;
     sincos_deg(level_theta(a.theta_min, a.step, kc), &cs, &sn);
@@ -248,29 +285,31 @@ __global__ __launch_bounds__(kThreads) void k_refine_level(LevelArgs a, const Pa
             const bool two = j < n;
             int qx0, qy0, qx1 = 0, qy1 = 0;
             double rx0, ry0, rx1 = 0, ry1 = 0;
-            project_point_s(pts[i], cs, sn, sigma, &qx0, &qy0, &rx0, &ry0);
-            if (two) project_point_s(pts[j], cs, sn, sigma, &qx1, &qy1, &rx1, &ry1);
+            const double2 d0 = dir[i], d1 = dir[two ? j : i];
+            project_dir_s(pts[i], d0.x, d0.y, cs, sn, sigma, &qx0, &qy0, &rx0, &ry0);
+            if (two) project_dir_s(pts[j], d1.x, d1.y, cs, sn, sigma, &qx1, &qy1, &rx1, &ry1);
             Block5 b0, b1;
             block5(2 * x + qx0, 2 * y + qy0, W, H, b0);
             block5(2 * x + qx1, 2 * y + qy1, W, H, b1);
-            float2 g0[5][5], g1[5][5];
+            typename Raw<PREC>::T g0[5][5], g1[5][5];
 #pragma unroll
             for (int v = 0; v < 5; ++v)
 #pragma unroll
                 for (int u = 0; u < 5; ++u) {
-                    g0[v][u] = field_load<PREC>(field, b0.rowoff[v] + b0.col[u]);
-                    g1[v][u] = field_load<PREC>(field, b1.rowoff[v] + b1.col[u]);
+                    g0[v][u] = Raw<PREC>::load(field, b0.rowoff[v] + b0.col[u]);
+                    g1[v][u] = Raw<PREC>::load(field, b1.rowoff[v] + b1.col[u]);
                 }
             __builtin_amdgcn_sched_barrier(0);
-            votes5x5<VOTE>(g0, b0.rin, b0.cin, (float)rx0, (float)ry0, aw, a1);
-            if (two) votes5x5<VOTE>(g1, b1.rin, b1.cin, (float)rx1, (float)ry1, aw, a1);
+            votes5x5<PREC, VOTE>(g0, b0.rin, b0.cin, Raw<PREC>::dir(rx0, ry0), aw, a1);
+            if (two) votes5x5<PREC, VOTE>(g1, b1.rin, b1.cin, Raw<PREC>::dir(rx1, ry1), aw, a1);
         }
     } else {
         // any odd window: direct evaluation of each translation
         for (int i = threadIdx.x; i < n; i += kThreads) {
             int qx, qy;
             double rx, ry;
-            project_point_s(pts[i], cs, sn, sigma, &qx, &qy, &rx, &ry);
+            const double2 d = dir[i];
+            project_dir_s(pts[i], d.x, d.y, cs, sn, sigma, &qx, &qy, &rx, &ry);
             const float fx = (float)rx, fy = (float)ry;
             const int px = 2 * x + qx, py = 2 * y + qy;
 #pragma unroll
@@ -289,24 +328,6 @@ __global__ __launch_bounds__(kThreads) void k_refine_level(LevelArgs a, const Pa
     }
     block_sum18(aw, a1, red, P.part[l] + ((size_t)c * 3 + g) * 18);
 }
-
-// Raw field element as stored (FP32 pair, or the half2 bits) and its FP32 value.
-template <int PREC>
-struct Raw;
-template <>
-struct Raw<TM_FP32> {
-    using T = float2;
-    static __device__ __forceinline__ T zero() { return make_float2(0.f, 0.f); }
-    static __device__ __forceinline__ T load(const void* f, size_t o) { return reinterpret_cast<const float2*>(f)[o]; }
-    static __device__ __forceinline__ float2 value(T v) { return v; }
-};
-template <>
-struct Raw<TM_FP16> {
-    using T = __half2;
-    static __device__ __forceinline__ T zero() { return __floats2half2_rn(0.f, 0.f); }
-    static __device__ __forceinline__ T load(const void* f, size_t o) { return reinterpret_cast<const __half2*>(f)[o]; }
-    static __device__ __forceinline__ float2 value(T v) { return __half22float2(v); }
-};
 
 template <int PREC, int VOTE>
 __global__ __launch_bounds__(kThreads) void k_refine_tile(LevelArgs a, const PairDesc* __restrict__ pairs)
@@ -329,6 +350,7 @@ __global__ __launch_bounds__(kThreads) void k_refine_tile(LevelArgs a, const Pai
     const void* field = P.field[l];
     const int W = P.W[l], H = P.H[l], n = P.n[l];
     const ModelPoint* __restrict__ pts = P.pts[l];
+    const double2* __restrict__ dir = P.dir[l];
     const int rad = P.rad_l[l];
     const int S = 2 * rad + 5, SS = S * S;
     const int ox = 2 * x - rad - 2, oy = 2 * y - rad - 2;
@@ -367,12 +389,13 @@ __global__ __launch_bounds__(kThreads) void k_refine_tile(LevelArgs a, const Pai
         for (int i = threadIdx.x; i < n; i += kThreads) {
             int qx, qy;
             double rx, ry;
-            project_point_s(pts[i], cs, sn, sigma, &qx, &qy, &rx, &ry);
+            const double2 d = dir[i];
+            project_dir_s(pts[i], d.x, d.y, cs, sn, sigma, &qx, &qy, &rx, &ry);
             const int px = 2 * x + qx, py = 2 * y + qy;
             // |q| < rad per component, so the block covers px - 2 .. px + 2
             const T* b = tile + (size_t)(py - 2 - oy) * S + (px - 2 - ox);
             bool cin[5], rin[5];
-            float2 gv[5][5];
+            T gv[5][5];
 #pragma unroll
             for (int u = 0; u < 5; ++u) {
                 cin[u] = (unsigned)(px - 2 + u) < (unsigned)W;
@@ -381,8 +404,8 @@ __global__ __launch_bounds__(kThreads) void k_refine_tile(LevelArgs a, const Pai
 #pragma unroll
             for (int v = 0; v < 5; ++v)
 #pragma unroll
-                for (int u = 0; u < 5; ++u) gv[v][u] = Raw<PREC>::value(b[v * S + u]);
-            votes5x5<VOTE>(gv, rin, cin, (float)rx, (float)ry, aw, a1);
+                for (int u = 0; u < 5; ++u) gv[v][u] = b[v * S + u];
+            votes5x5<PREC, VOTE>(gv, rin, cin, Raw<PREC>::dir(rx, ry), aw, a1);
         }
         block_sum18(aw, a1, red, P.part[l] + ((size_t)c * 3 + g) * 18);
     }

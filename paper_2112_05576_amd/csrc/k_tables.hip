@@ -40,6 +40,18 @@ __global__ __launch_bounds__(256) void k_tables(const ModelPoint* __restrict__ p
     tab[(size_t)m * n_pad + i] = e;
 }
 
+// FP64 unit direction of every model point, stored once per model level so
+// that the refinement, which projects each point at 3 angles for every
+// candidate, does not form the square root and the divisions again.
+__global__ __launch_bounds__(256) void k_unit_dirs(const ModelPoint* __restrict__ pts, int n, double2* __restrict__ dir)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double dx, dy;
+    unit_dir(pts[i], &dx, &dy);
+    dir[i] = make_double2(dx, dy);
+}
+
 __global__ __launch_bounds__(256) void k_table_export(const TabEntry* __restrict__ tab, int n, int n_pad, int K,
                                                        int32_t* __restrict__ q, float* __restrict__ r)
 {
@@ -61,6 +73,13 @@ hipError_t launch_tables(const ModelPoint* pts, int n, int n_pad, double theta_m
     dim3 grid((n_pad + 255) / 256, K * S);
     hipLaunchKernelGGL(k_tables, grid, dim3(256), 0, s, pts, n, n_pad, theta_min, step, K, sigma_min, sigma_step,
                        tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_unit_dirs(const ModelPoint* pts, int n, double2* dir, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_unit_dirs, dim3((n + 255) / 256), dim3(256), 0, s, pts, n, dir);
     return hipGetLastError();
 }
 

@@ -294,6 +294,7 @@ void pair_static(tmk::PairDesc* d, const tm_model* m, const tm_pyramid* p, const
         d->W[l] = p->lv[l].w;
         d->H[l] = p->lv[l].h;
         d->pts[l] = m->lv[l].pts;
+        d->dir[l] = m->lv[l].dir;
         d->n[l] = m->lv[l].n;
         d->rad_l[l] = scaled_rad(m->lv[l], sigma_max);
         d->rtile[l] = tmk::refine_tile_fits(d->rad_l[l], p->precision, win) ? 1 : 0;
@@ -570,6 +571,9 @@ TM_EXPORT tm_status tm_build_model(const uint8_t* img, int32_t w, int32_t h, int
         if (e == hipSuccess) e = hipMalloc(&ml.pts, sizeof(tmk::ModelPoint) * ml.n);
         if (e == hipSuccess)
             e = hipMemcpy(ml.pts, hp.data(), sizeof(tmk::ModelPoint) * ml.n, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMalloc(&ml.dir, sizeof(double2) * ml.n);
+        if (e == hipSuccess) e = tmk::launch_unit_dirs(ml.pts, ml.n, ml.dir, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) {
             hipFree(tmp);
             tm_model_free(m);
@@ -589,8 +593,10 @@ TM_EXPORT tm_status tm_build_model(const uint8_t* img, int32_t w, int32_t h, int
 TM_EXPORT void tm_model_free(tm_model* m)
 {
     if (!m) return;
-    for (int l = 0; l < m->L; ++l)
+    for (int l = 0; l < m->L; ++l) {
         if (m->lv[l].pts) hipFree(m->lv[l].pts);
+        if (m->lv[l].dir) hipFree(m->lv[l].dir);
+    }
     if (m->cache.tab) hipFree(m->cache.tab);
     delete m;
 }
@@ -911,6 +917,7 @@ tm_status cont_prepare(const tm_model* m, tm_pyramid* p, int level, size_t extra
         d.W[l] = p->lv[l].w;
         d.H[l] = p->lv[l].h;
         d.pts[l] = m->lv[l].pts;
+        d.dir[l] = m->lv[l].dir;
         d.n[l] = m->lv[l].n;
     }
     return put_desc(p, d, s, dd);

@@ -45,11 +45,22 @@ __device__ __forceinline__ void project_point(const ModelPoint& p, double c, dou
     *ry = s * dx + c * dy;
 }
 
-// The similarity projection: q = floor(sigma (R t) + 0.5 + 1e-9), the
-// rotation first and then the product with sigma (rounded separately), and
-// r = R d.  sigma == 1 gives project_point exactly.
-__device__ __forceinline__ void project_point_s(const ModelPoint& p, double c, double s, double sigma, int* qx,
-                                                int* qy, double* rx, double* ry)
+// The model point's unit direction d = g / |g| in FP64 (the same operations
+// as in project_point, so a stored copy gives the same bits).
+__device__ __forceinline__ void unit_dir(const ModelPoint& p, double* dx, double* dy)
+{
+#pragma clang fp contract(off)
+    double gx = (double)p.gx, gy = (double)p.gy;
+    double m = sqrt(gx * gx + gy * gy);
+    *dx = gx / m;
+    *dy = gy / m;
+}
+
+// The similarity projection with the unit direction given: q = floor(sigma
+// (R t) + 0.5 + 1e-9), the rotation first and then the product with sigma
+// (rounded separately), and r = R d.
+__device__ __forceinline__ void project_dir_s(const ModelPoint& p, double dx, double dy, double c, double s,
+                                              double sigma, int* qx, int* qy, double* rx, double* ry)
 {
 #pragma clang fp contract(off)
     double tx = (double)p.tx, ty = (double)p.ty;
@@ -59,11 +70,18 @@ __device__ __forceinline__ void project_point_s(const ModelPoint& p, double c, d
     vy = sigma * vy;
     *qx = (int)floor(vx + 0.5 + 1e-9);
     *qy = (int)floor(vy + 0.5 + 1e-9);
-    double gx = (double)p.gx, gy = (double)p.gy;
-    double m = sqrt(gx * gx + gy * gy);
-    double dx = gx / m, dy = gy / m;
     *rx = c * dx - s * dy;
     *ry = s * dx + c * dy;
+}
+
+// The similarity projection of a model point.  sigma == 1 gives
+// project_point exactly.
+__device__ __forceinline__ void project_point_s(const ModelPoint& p, double c, double s, double sigma, int* qx,
+                                                int* qy, double* rx, double* ry)
+{
+    double dx, dy;
+    unit_dir(p, &dx, &dy);
+    project_dir_s(p, dx, dy, c, s, sigma, qx, qy, rx, ry);
 }
 
 // Scale j of the grid sigma_min + j * sigma_step.

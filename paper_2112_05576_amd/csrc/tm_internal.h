@@ -65,6 +65,7 @@ struct tm_model_level {
     int radius2 = 0;    // max |t|^2
     int rad = 0;        // bound on |q| components over all angles
     tmk::ModelPoint* pts = nullptr;  // device, n entries
+    double2* dir = nullptr;          // device, n FP64 unit directions g/|g|
 };
 
 struct tm_model_table_cache {
@@ -139,6 +140,8 @@ hipError_t launch_model_points(const PyrLevel* lv, int L, long long T2, ModelPoi
 // scales sigma_min + j*sigma_step, j < S: entry [j*K + k][i].
 hipError_t launch_tables(const ModelPoint* pts, int n, int n_pad, double theta_min, double step, int K,
                          double sigma_min, double sigma_step, int S, TabEntry* tab, hipStream_t s);
+// FP64 unit direction g/|g| of every point (the arithmetic of the projection).
+hipError_t launch_unit_dirs(const ModelPoint* pts, int n, double2* dir, hipStream_t s);
 // Expand a table into plain int32 q pairs and float r pairs.
 hipError_t launch_table_export(const TabEntry* tab, int n, int n_pad, int K, int32_t* q, float* r, hipStream_t s);
 
@@ -150,6 +153,7 @@ struct PairDesc {
     const void* field[kMaxLevels];   // direction field per level
     int W[kMaxLevels], H[kMaxLevels];
     const ModelPoint* pts[kMaxLevels];
+    const double2* dir[kMaxLevels];  // FP64 unit directions of the points
     int n[kMaxLevels];
     const TabEntry* tab;             // rotated table of the searched level, [K][n_pad]
     int n_pad, rad;                  // table padding; bound on |q| at the searched level
