@@ -96,32 +96,43 @@ def traffic_from(fetch_csv, write_csv):
     """HBM bytes per launch of the search kernel: its FETCH_SIZE and
     WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads
     for the final 256 MiB elementwise copy of --copy-probe (read 256 MiB,
-    write 256 MiB)."""
+    write 256 MiB).  Run the counter passes with tuning on: the tuner
+    dispatches every form of the search kernel over the same batch, so one
+    pass per counter gives the figure of each form (variant, waves per
+    chunk), and the bench line takes the one of the form it runs."""
     out = {"kernel_sha256": hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()}
+    per = {}
     for key, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
         rows = _pmc_rows(path, counter)
         probe_name, probe, _, _ = rows[-1]
         if "elementwise" not in probe_name:
             raise SystemExit(f"last dispatch in {path} is not the copy probe: {probe_name[:80]}")
-        # the batched launches: the search dispatches with the largest grid
-        # (run the counter passes with --no-tune, so that one form runs)
-        grids = [g for n, _, g, _ in rows if "k_dense_fast" in n]
-        if not grids:
-            raise SystemExit(f"no k_dense_fast dispatch in {path}")
-        sel = [(n, v, wg) for n, v, g, wg in rows if "k_dense_fast" in n and g == max(grids)]
-        if len({(n, wg) for n, _, wg in sel}) != 1:
-            raise SystemExit(f"several search forms in {path}: take the counters with --no-tune")
-        dense = [v for _, v, _ in sel]
-        # template arguments: G, R, LC, PREC, VAR (the variant), VOTE
-        targs = [int(t) for t in re.search(r"k_dense_fast<([^>]*)>", sel[0][0]).group(1).split(",")]
-        out["form"] = {"variant": targs[4], "waves_per_chunk": sel[0][2] // 64}
         scale = COPY_PROBE_BYTES / probe  # bytes per counted KiB
-        out[key] = {"kib_per_launch": sum(dense) / len(dense), "probe_kib": probe, "scale_bytes_per_kib": scale,
-                    "bytes_per_launch": sum(dense) / len(dense) * scale, "launches": len(dense)}
-    out["bytes_per_launch"] = out["fetch"]["bytes_per_launch"] + out["write"]["bytes_per_launch"]
+        out[f"{key}_probe_kib"] = probe
+        out[f"{key}_scale_bytes_per_kib"] = scale
+        # the batched launches: the search dispatches with the most
+        # workgroups (every form of the batch runs the same work list)
+        blocks = [g // wg for n, _, g, wg in rows if "k_dense_fast" in n]
+        if not blocks:
+            raise SystemExit(f"no k_dense_fast dispatch in {path}")
+        for n, v, g, wg in rows:
+            if "k_dense_fast" not in n or g // wg != max(blocks):
+                continue
+            # template arguments: G, R, LC, PREC, VAR (the variant), VOTE
+            targs = [int(t) for t in re.search(r"k_dense_fast<([^>]*)>", n).group(1).split(",")]
+            f = per.setdefault((targs[4], wg // 64), {"variant": targs[4], "waves_per_chunk": wg // 64})
+            f.setdefault(key, []).append(v * scale)
+    forms = []
+    for f in per.values():
+        if "fetch" not in f or "write" not in f:
+            continue
+        fb, wb = sum(f["fetch"]) / len(f["fetch"]), sum(f["write"]) / len(f["write"])
+        forms.append({"variant": f["variant"], "waves_per_chunk": f["waves_per_chunk"], "fetch_bytes": fb,
+                      "write_bytes": wb, "bytes_per_launch": fb + wb, "launches": len(f["fetch"])})
+    out["forms"] = sorted(forms, key=lambda f: (f["variant"], f["waves_per_chunk"]))
     os.makedirs(os.path.dirname(TRAFFIC_JSON), exist_ok=True)
-    with open(TRAFFIC_JSON, "w") as f:
-        json.dump(out, f, indent=1)
+    with open(TRAFFIC_JSON, "w") as fh:
+        json.dump(out, fh, indent=1)
     print(json.dumps(out))
 
 
@@ -161,14 +172,17 @@ def cpu_baseline(scenes, cfg, budget_s, paper=False):
 
 def traffic_entry(form):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source and on the search form now in use."""
+    taken on the current kernel source, for the search form now in use."""
     if not os.path.exists(TRAFFIC_JSON):
         return None
     d = json.load(open(TRAFFIC_JSON))
     h = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    if d.get("kernel_sha256") != h or d.get("form") != form:
+    if d.get("kernel_sha256") != h:
         return None
-    return d.get("bytes_per_launch")
+    for f in d.get("forms", []):
+        if (f["variant"], f["waves_per_chunk"]) == (form.get("variant"), form.get("waves_per_chunk")):
+            return f["bytes_per_launch"]
+    return None
 
 
 def gt_hit(d, sc):
