@@ -266,8 +266,9 @@ tm_status tm_batch_run_graph(tm_batch* batch, void* stream);
 /* Autotuner of a batch's exhaustive search: runs the pyramid stage, then
  * times every form of the search kernel (6 instruction-level variants × 2,
  * 4, 8 or 16 waves sharing an angle chunk, where they fit in LDS) for
- * `iterations` launches each (1 to 1000) on the bound images, and keeps the
- * fastest for the batch's later runs (a captured graph is discarded and
+ * `iterations` launches each (1 to 1000) on the bound images, twice over
+ * (a form's time is the smaller of its two rounds), and keeps the fastest
+ * for the batch's later runs (a captured graph is discarded and
  * captured again by the next tm_batch_run_graph).  All forms give
  * bit-identical results; tuning changes only time.  Waits for the device.
  * variant_out, waves_out, us_out (each may be NULL): the choice and its mean
