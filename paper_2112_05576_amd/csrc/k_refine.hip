@@ -12,8 +12,8 @@
 //    9 centre votes;
 //  * k_refine_tile, one workgroup per candidate: the candidate's whole field
 //    block (side 2 rad + 5 around (2x, 2y)) is first staged in LDS with
-//    coalesced loads, then the three angles are scored as above with the taps
-//    read from LDS.
+//    coalesced loads, then three groups of 256 threads score the three
+//    angles as above with the taps read from LDS.
 // A thread adds its points in increasing order and the workgroup combines the
 // threads by a fixed butterfly per wave and the waves in order, in both
 // kernels, so their sums are bit-identical and a launch may take either (the
@@ -148,11 +148,13 @@ __device__ __forceinline__ void votes5x5(const typename Raw<PREC>::T (&gv)[5][5]
         }
 }
 
-// The workgroup's 18 sums: a fixed butterfly per wave, then the waves in
-// order; written to out[0..17].  Ends with a barrier (red may be reused).
-__device__ __forceinline__ void block_sum18(float (&aw)[9], float (&a1)[9], float (*red)[18], float* out)
+// The 18 sums of a group of kThreads threads (t: the thread's index in its
+// group): a fixed butterfly per wave, then the group's waves in order;
+// written to out[0..17].  Every thread of the workgroup must call it (it
+// holds two workgroup barriers; red may be reused afterwards).
+__device__ __forceinline__ void block_sum18(float (&aw)[9], float (&a1)[9], float (*red)[18], float* out, int t)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = t & 63, wv = t >> 6;
 #pragma unroll
     for (int m = 0; m < 9; ++m) {
 #pragma unroll
@@ -169,10 +171,10 @@ __device__ __forceinline__ void block_sum18(float (&aw)[9], float (&a1)[9], floa
         }
     }
     __syncthreads();
-    if (threadIdx.x < 18) {
+    if (t < 18) {
         float s = 0.f;
-        for (int w = 0; w < kWaves; ++w) s += red[w][threadIdx.x];
-        out[threadIdx.x] = s;
+        for (int w = 0; w < kWaves; ++w) s += red[w][t];
+        out[t] = s;
     }
     __syncthreads();
 }
@@ -326,15 +328,22 @@ __global__ __launch_bounds__(kThreads) void k_refine_level(LevelArgs a, const Pa
                 }
         }
     }
-    block_sum18(aw, a1, red, P.part[l] + ((size_t)c * 3 + g) * 18);
+    block_sum18(aw, a1, red, P.part[l] + ((size_t)c * 3 + g) * 18, threadIdx.x);
 }
 
+// One workgroup per candidate, three groups of kThreads threads, group g
+// scoring angle 2k + g - 1 from the one staged block: thread t of a group
+// takes the points t, t + kThreads, ... as a thread of k_refine_level does,
+// and each group reduces as one of its workgroups, so the sums are the same
+// bits.  Three times the waves of one group share the block's LDS.
+constexpr int kTileGroups = 3;
+
 template <int PREC, int VOTE>
-__global__ __launch_bounds__(kThreads) void k_refine_tile(LevelArgs a, const PairDesc* __restrict__ pairs)
+__global__ __launch_bounds__(kThreads * kTileGroups) void k_refine_tile(LevelArgs a, const PairDesc* __restrict__ pairs)
 {
     using T = typename Raw<PREC>::T;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ float red[kWaves][18];
+    __shared__ float red[kTileGroups][kWaves][18];
     __shared__ int cur[4];
     const PairDesc& P = pairs[blockIdx.y];
     const int l = a.level;
@@ -357,13 +366,13 @@ __global__ __launch_bounds__(kThreads) void k_refine_tile(LevelArgs a, const Pai
     T* tile = reinterpret_cast<T*>(smem);
     // stage: 8 loads in flight per thread (clamped addresses, zero selected
     // outside the image)
-    constexpr int kU = 8;
-    for (int e0 = threadIdx.x; e0 < SS; e0 += kU * kThreads) {
+    constexpr int kU = 8, kAll = kThreads * kTileGroups;
+    for (int e0 = threadIdx.x; e0 < SS; e0 += kU * kAll) {
         T v[kU];
         bool ok[kU];
 #pragma unroll
         for (int j = 0; j < kU; ++j) {
-            const int e = min(e0 + j * kThreads, SS - 1);
+            const int e = min(e0 + j * kAll, SS - 1);
             const int r = e / S, cc = e - r * S;
             const int gx = ox + cc, gy = oy + r;
             ok[j] = (unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H;
@@ -371,12 +380,13 @@ __global__ __launch_bounds__(kThreads) void k_refine_tile(LevelArgs a, const Pai
         }
 #pragma unroll
         for (int j = 0; j < kU; ++j) {
-            const int e = e0 + j * kThreads;
+            const int e = e0 + j * kAll;
             if (e < SS) tile[e] = ok[j] ? v[j] : Raw<PREC>::zero();
         }
     }
     __syncthreads();
-    for (int g = 0; g < 3; ++g) {
+    {
+        const int g = threadIdx.x / kThreads, t = threadIdx.x - g * kThreads;
         const int kc = angle_index(2 * k + g - 1, a.K, a.full);
         double cs, sn;
         sincos_deg(level_theta(a.theta_min, a.step, kc), &cs, &sn);
@@ -386,7 +396,7 @@ __global__ __launch_bounds__(kThreads) void k_refine_tile(LevelArgs a, const Pai
             aw[m] = 0.f;
             a1[m] = 0.f;
         }
-        for (int i = threadIdx.x; i < n; i += kThreads) {
+        for (int i = t; i < n; i += kThreads) {
             int qx, qy;
             double rx, ry;
             const double2 d = dir[i];
@@ -407,7 +417,7 @@ __global__ __launch_bounds__(kThreads) void k_refine_tile(LevelArgs a, const Pai
                 for (int u = 0; u < 5; ++u) gv[v][u] = b[v * S + u];
             votes5x5<PREC, VOTE>(gv, rin, cin, Raw<PREC>::dir(rx, ry), aw, a1);
         }
-        block_sum18(aw, a1, red, P.part[l] + ((size_t)c * 3 + g) * 18);
+        block_sum18(aw, a1, red[g], P.part[l] + ((size_t)c * 3 + g) * 18, t);
     }
 }
 
@@ -488,9 +498,11 @@ void launch_level_kernels(const SearchDesc& s, const PairDesc* d, int npairs, co
     if (rp.staged && rp.tile_bytes[l] > 0) {
         dim3 grid((unsigned)s.max_cand, npairs);
         if (s.precision == TM_FP16)
-            hipLaunchKernelGGL((k_refine_tile<TM_FP16, VOTE>), grid, dim3(kThreads), rp.tile_bytes[l], st, a, d);
+            hipLaunchKernelGGL((k_refine_tile<TM_FP16, VOTE>), grid, dim3(kThreads * kTileGroups), rp.tile_bytes[l],
+                               st, a, d);
         else
-            hipLaunchKernelGGL((k_refine_tile<TM_FP32, VOTE>), grid, dim3(kThreads), rp.tile_bytes[l], st, a, d);
+            hipLaunchKernelGGL((k_refine_tile<TM_FP32, VOTE>), grid, dim3(kThreads * kTileGroups), rp.tile_bytes[l],
+                               st, a, d);
     }
 }
 }  // namespace
