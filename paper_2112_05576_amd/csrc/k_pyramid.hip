@@ -169,7 +169,9 @@ __global__ __launch_bounds__(256) void k_grad_level(FieldsArg one, const FieldsA
 
 // Unit gradient direction of every pixel of every level: (gx, gy)/|g| formed
 // in FP64 and rounded once to the storage precision where gx^2 + gy^2 > T2,
-// (0, 0) elsewhere.  Each thread covers 4 consecutive pixels of a row.
+// (0, 0) elsewhere.  Each thread covers 4 consecutive pixels of a row; their
+// 3 x 6 neighbourhood (or their 4 gradient pairs) is loaded at once, before
+// any of the four is computed, so a thread waits for memory once.
 template <bool BATCH>
 __global__ __launch_bounds__(256) void k_sobel_fields(FieldsArg one, const FieldsArg* __restrict__ many)
 {
@@ -184,14 +186,42 @@ __global__ __launch_bounds__(256) void k_sobel_fields(FieldsArg one, const Field
     const int idx = ((int)blockIdx.x - a.block0[l]) * 256 + (int)threadIdx.x;
     const int y = idx / qw, x0 = (idx % qw) * 4;
     if (y >= H) return;
-    const uint8_t* img = a.img[l];
-    const uint32_t* grad = a.grad[l];
+    const uint8_t* __restrict__ img = a.img[l];
+    const uint32_t* __restrict__ grad = a.grad[l];
+    int gxv[4], gyv[4];
+    if (grad) {
+        uint32_t v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) v[i] = grad[(size_t)y * W + min(x0 + i, W - 1)];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) unpack_grad(v[i], &gxv[i], &gyv[i]);
+    } else {
+        // rows y-1 .. y+1, columns x0-1 .. x0+4, at clamped addresses: a
+        // clamped value only ever feeds a pixel of the one-pixel frame,
+        // whose gradient is 0
+        int p[3][6];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            const size_t row = (size_t)min(max(y - 1 + r, 0), H - 1) * W;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) p[r][c] = img[row + min(max(x0 - 1 + c, 0), W - 1)];
+        }
+        const bool row_in = y >= 1 && y <= H - 2;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int x = x0 + i;
+            const bool in = row_in && x >= 1 && x <= W - 2;
+            const int gx = (p[0][i + 2] + 2 * p[1][i + 2] + p[2][i + 2]) - (p[0][i] + 2 * p[1][i] + p[2][i]);
+            const int gy = (p[2][i] + 2 * p[2][i + 1] + p[2][i + 2]) - (p[0][i] + 2 * p[0][i + 1] + p[0][i + 2]);
+            gxv[i] = in ? gx : 0;
+            gyv[i] = in ? gy : 0;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int x = x0 + i;
         if (x >= W) break;
-        int gx, gy;
-        level_grad(img, grad, W, H, x, y, &gx, &gy);
+        const int gx = gxv[i], gy = gyv[i];
         const long long m2 = (long long)gx * gx + (long long)gy * gy;
         double dx = 0.0, dy = 0.0;
         if (m2 > T2) {
