@@ -277,6 +277,15 @@ tm_status tm_batch_run_graph(tm_batch* batch, void* stream);
 tm_status tm_batch_tune(tm_batch* batch, int32_t iterations, void* stream, int32_t* variant_out, int32_t* waves_out,
                         float* us_out);
 
+/* Use the given form of the search kernel for the batch's later runs (a
+ * form reported by tm_batch_tune or tm_batch_search_form of a batch of the
+ * same shape, say): TM_EINVAL if it does not apply (variant 0..5, 1..16
+ * waves sharing a chunk, within LDS; the edge-taps vote has one variant per
+ * precision; -1 is accepted, and changes nothing, for a batch on the generic
+ * search).  Results do not depend on the form.  A captured graph is
+ * discarded and captured again by the next tm_batch_run_graph. */
+tm_status tm_batch_set_form(tm_batch* batch, int32_t variant, int32_t waves);
+
 /* The form of the batch's exhaustive search now in use (default or tuned):
  * kernel variant and waves sharing an angle chunk (-1 and 0 for the generic
  * search). */

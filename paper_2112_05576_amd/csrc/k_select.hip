@@ -246,6 +246,8 @@ struct FinalArgs {
     float min_score;
     double theta_min, step0;
     int K0;  // angles of level 0; the key's last component is m = j K0 + k
+    tm_pose* out;    // one pair: results here instead of at the pair's own buffers (null: the pair's)
+    int32_t* n_out;
 };
 
 // One workgroup per pair (blockIdx.y).
@@ -258,8 +260,8 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs fa, const PairDesc* __r
     const float min_score = fa.min_score;
     const double dmin2 = (double)P.dmin * (double)P.dmin;
     const double theta_min = fa.theta_min, step0 = fa.step0;
-    tm_pose* __restrict__ out = P.out;
-    int32_t* __restrict__ n_out = P.n_out;
+    tm_pose* __restrict__ out = fa.out ? fa.out : P.out;
+    int32_t* __restrict__ n_out = fa.out ? fa.n_out : P.n_out;
     __shared__ float u_sw[kFinCap], u_s1[kFinCap];
     __shared__ int u_x[kFinCap], u_y[kFinCap], u_k[kFinCap];
     __shared__ float l_sw[kFinCap], l_s1[kFinCap];
@@ -335,9 +337,12 @@ hipError_t launch_select(const SearchDesc& s, const PairDesc* d, int npairs, int
     return hipGetLastError();
 }
 
-hipError_t launch_final(const SearchDesc& s, const PairDesc* d, int npairs, hipStream_t st)
+hipError_t launch_final(const SearchDesc& s, const PairDesc* d, int npairs, hipStream_t st, tm_pose* out,
+                        int32_t* n_out)
 {
     FinalArgs a;
+    a.out = npairs == 1 ? out : nullptr;
+    a.n_out = n_out;
     a.max_cand = s.max_cand;
     a.cap = s.capacity;
     a.min_score = s.min_score;

@@ -816,8 +816,8 @@ TM_EXPORT tm_status tm_detect(const tm_model* m, tm_pyramid* p, const tm_search_
     if (st != TM_OK) return st;
     pair_scratch(&d, m, pg, plan, p->L, sp->max_candidates, true, true, refine,
                  reinterpret_cast<uint8_t*>(p->ws.ptr) + kDescBytes);
-    d.out = out;
-    d.n_out = n_out;
+    // the outputs go to the final kernel as arguments, so the descriptor (and
+    // its device copy) stays the same across calls that write elsewhere
     tmk::PairDesc* dd = nullptr;
     st = put_desc(p, d, s, &dd);
     if (st != TM_OK) return st;
@@ -831,7 +831,7 @@ TM_EXPORT tm_status tm_detect(const tm_model* m, tm_pyramid* p, const tm_search_
             refine_plan(&m, 1, p->L, sp->neighbourhood, p->precision, sp->max_candidates, g.sigma_max);
         HIP_TRY(tmk::launch_refine(sd, dd, 1, top, rp, s));
     }
-    HIP_TRY(tmk::launch_final(sd, dd, 1, s));
+    HIP_TRY(tmk::launch_final(sd, dd, 1, s, out, n_out));
     return TM_OK;
 }
 
@@ -1210,6 +1210,26 @@ TM_EXPORT tm_status tm_batch_run_graph(tm_batch* b, void* stream)
         if (st != TM_OK) return st;
     }
     HIP_TRY(hipGraphLaunch(b->graph, S(stream)));
+    return TM_OK;
+}
+
+TM_EXPORT tm_status tm_batch_set_form(tm_batch* b, int32_t variant, int32_t waves)
+{
+    if (!b) return fail(TM_EINVAL, "tm_batch_set_form: null batch");
+    if (!b->plan.fast) {
+        if (variant == -1) return TM_OK;
+        return fail(TM_EINVAL, "tm_batch_set_form: the batch uses the generic search, which has no forms");
+    }
+    tmk::DensePlan p = b->plan;
+    if (!tmk::retune_dense(p, variant, waves))
+        return fail(TM_EINVAL, "tm_batch_set_form: variant %d with %d waves per chunk does not apply to this batch",
+                    variant, waves);
+    HIP_TRY(tmk::prepare_dense(b->sd, p));
+    b->plan = p;
+    if (b->graph) {  // captured with the old form
+        hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
     return TM_OK;
 }
 

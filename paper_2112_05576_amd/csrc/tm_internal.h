@@ -262,7 +262,10 @@ hipError_t launch_refine(const SearchDesc& s, const PairDesc* d, int npairs, int
 // Kernel attributes of the staged refinement (call before capturing it).
 hipError_t prepare_refine();
 // Final selection of every pair: pair.cand -> pair.out / n_out.
-hipError_t launch_final(const SearchDesc& s, const PairDesc* d, int npairs, hipStream_t st);
+// out / n_out (one pair only, optional): write there instead of the pair's
+// own result buffers, so a descriptor need not change with the caller's output.
+hipError_t launch_final(const SearchDesc& s, const PairDesc* d, int npairs, hipStream_t st, tm_pose* out = nullptr,
+                        int32_t* n_out = nullptr);
 
 // Continuous score (forward) or its backward of n poses; d: descriptor array
 // of npairs entries (batched: pose.pair selects, else descriptor 0).

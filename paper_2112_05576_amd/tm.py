@@ -85,6 +85,7 @@ def lib():
             "tm_batch_run_graph": [_vp, _vp],
             "tm_batch_tune": [_vp, _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_float)],
             "tm_batch_search_form": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
+            "tm_batch_set_form": [_vp, _i32, _i32],
             "tm_batch_cont_score": [_vp, _i32, _vp, _i32, _vp, _vp],
             "tm_batch_cont_score_backward": [_vp, _i32, _vp, _i32, _vp, _vp, _vp],
             "tm_batch_cont_line_search": [_vp, _i32, _vp, _vp, _i32, ctypes.POINTER(ctypes.c_double), _i32, _vp, _vp],
@@ -378,6 +379,10 @@ class Batch:
         _check(lib().tm_batch_tune(self._h, iterations, _vp(_stream(stream)), ctypes.byref(v), ctypes.byref(w),
                                    ctypes.byref(us)))
         return {"variant": v.value, "waves_per_chunk": w.value, "search_us": us.value}
+
+    def set_form(self, variant: int, waves_per_chunk: int):
+        """Use this search-kernel form (e.g. another batch's tuned one) from now on."""
+        _check(lib().tm_batch_set_form(self._h, int(variant), int(waves_per_chunk)))
 
     def search_form(self) -> dict:
         """The search-kernel form in use: variant and waves sharing a chunk."""

@@ -636,3 +636,12 @@ def test_batch_tune_keeps_results():
         assert all(_poses_equal(a, c) for a, c in zip(b.results(), ref))
         b.run(graph=True)
         assert all(_poses_equal(a, c) for a, c in zip(b.results(), ref))
+        # another batch of the same shape takes the tuned form as it is, and
+        # a form that does not apply is refused
+        b2 = P.Batch(models, images, 4, cfg["tau_s"], sp, precision=precision)
+        b2.set_form(choice["variant"], choice["waves_per_chunk"])
+        assert b2.search_form() == {"variant": choice["variant"], "waves_per_chunk": choice["waves_per_chunk"]}
+        b2.run(graph=True)
+        assert all(_poses_equal(a, c) for a, c in zip(b2.results(), ref))
+        with pytest.raises(P.TMError):
+            b2.set_form(9, 4)
