@@ -19,6 +19,7 @@
 #include <stdlib.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "tm_device.h"
 
@@ -161,6 +162,39 @@ __device__ __forceinline__ void dots10_f16(uint32_t rh, const uint32_t (&g)[10],
     __builtin_amdgcn_sched_barrier(0x0104);
 }
 
+// The same ten products with a per-pixel addend: the tile of the FP16
+// edge-taps form holds, beside each half2, the FP32 value it adds to its
+// products (0 on the edge set, kOffEdge elsewhere), so that a product comes
+// out of v_dot2_f32_f16 as a window operand of that form in one instruction.
+// Hazard handling as in dots10_f16.
+__device__ __forceinline__ void dots10_f16_biased(uint32_t rh, const uint2 (&g)[10], float (&d)[10])
+{
+#pragma unroll
+    for (int j = 0; j < 10; j += 2)
+        asm volatile(
+            "v_dot2_f32_f16 %0, %2, %3, %4\n\t"
+            "v_dot2_f32_f16 %1, %2, %5, %6"
+            : "=&v"(d[j]), "=&v"(d[j + 1])
+            : "s"(rh), "v"(g[j].x), "v"(g[j].y), "v"(g[j + 1].x), "v"(g[j + 1].y));
+    asm volatile("s_nop 2");
+    __builtin_amdgcn_sched_barrier(0x0104);
+}
+
+// Tile element of the search kernel: the field pixel as stored, or for the
+// FP16 edge-taps form (BIASED) the half2 and the FP32 bits of its addend.
+template <int PREC, int VOTE>
+struct TileOf {
+    static constexpr bool BIASED = PREC == TM_FP16 && VOTE == 1;
+    using T = std::conditional_t<BIASED, uint2, typename Px<PREC>::T>;
+    static __device__ __forceinline__ T make(typename Px<PREC>::T v)
+    {
+        if constexpr (BIASED)
+            return make_uint2(v, v != 0u ? 0u : __float_as_uint(kOffEdge));
+        else
+            return v;
+    }
+};
+
 struct FastArgs {
     int level;          // searched level
     int tr;             // 1: lanes run along y and strips along x (the tile transposed)
@@ -177,11 +211,16 @@ struct FastArgs {
 // with the next step's entries requested behind this step's LDS reads.
 // VOTE 1: the edge-taps-only window (off-edge products replaced by kOffEdge
 // before the maxima, each window maximum finished by vote_finish); the centre
-// sum takes the plain products in both readings.
+// sum takes the plain products in both readings.  In FP16 the replacement is
+// the addend stored with each tile pixel (TileOf), and the centre sum takes
+// vote_finish of the product, which is the plain product on the edge set and
+// -0 elsewhere.
 template <int G, int R, int LC, int PREC, int VAR, int VOTE>
 __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc* __restrict__ pairs)
 {
-    using T = typename Px<PREC>::T;
+    using Tile = TileOf<PREC, VOTE>;
+    using T = typename Tile::T;
+    using PT = typename Px<PREC>::T;
     extern __shared__ __align__(16) unsigned char smem[];
     T* tile = reinterpret_cast<T*>(smem);
     constexpr int NS = 64 / G;   // segments per wave
@@ -223,9 +262,9 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc*
         }
         const int u = U0 - halo + c, v = V0 - halo + r;
         const int x = tr ? v : u, y = tr ? u : v;
-        T val = Px<PREC>::zero();
+        PT val = Px<PREC>::zero();
         if (x >= 0 && x < W && y >= 0 && y < H) val = Px<PREC>::load(field, (size_t)y * W + x);
-        tile[r * LC + c] = val;
+        tile[r * LC + c] = Tile::make(val);
     }
     __syncthreads();
 
@@ -276,19 +315,26 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc*
             };
             auto compute = [&](const TabEntry& e, const T (&gv)[R + 2]) {
                 float D[R + 2];
-                if constexpr (ASM && PREC == TM_FP16 && R == 8) {
-                    dots10_f16(e.rh, gv, D);
-                } else {
-#pragma unroll
-                    for (int rr = 0; rr < R + 2; ++rr) D[rr] = Px<PREC>::template dot_t<ASM>(e, gv[rr]);
-                }
                 float E[R + 2];
+                if constexpr (Tile::BIASED) {
+                    static_assert(ASM && R == 8, "the biased tile has the written-out form only");
+                    dots10_f16_biased(e.rh, gv, E);
 #pragma unroll
-                for (int rr = 0; rr < R + 2; ++rr) {
-                    if constexpr (VOTE == 1)
-                        E[rr] = Px<PREC>::edge(gv[rr]) ? D[rr] : kOffEdge;
-                    else
-                        E[rr] = D[rr];
+                    for (int rr = 1; rr <= R; ++rr) D[rr] = vote_finish(E[rr]);
+                } else {
+                    if constexpr (ASM && PREC == TM_FP16 && R == 8) {
+                        dots10_f16(e.rh, gv, D);
+                    } else {
+#pragma unroll
+                        for (int rr = 0; rr < R + 2; ++rr) D[rr] = Px<PREC>::template dot_t<ASM>(e, gv[rr]);
+                    }
+#pragma unroll
+                    for (int rr = 0; rr < R + 2; ++rr) {
+                        if constexpr (VOTE == 1)
+                            E[rr] = Px<PREC>::edge(gv[rr]) ? D[rr] : kOffEdge;
+                        else
+                            E[rr] = D[rr];
+                    }
                 }
                 float V[R];
 #pragma unroll
@@ -705,7 +751,9 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
                 p.LC = lc;
                 break;
             }
-        p.tile_lds = (size_t)(TH + 2 * max_halo) * p.LC * (s.precision == TM_FP16 ? 4 : 8);
+        // FP16 pixels take 4 bytes (8 with the edge-taps addend), FP32 8
+        const size_t px_bytes = s.precision == TM_FP16 ? (p.vote ? 8 : 4) : 8;
+        p.tile_lds = (size_t)(TH + 2 * max_halo) * p.LC * px_bytes;
         const size_t comb_bytes = (size_t)12 * p.WA * TH * TW;
         p.lds = p.tile_lds > comb_bytes ? p.tile_lds : comb_bytes;
         if (p.LC == 0 || p.lds > 160 * 1024) p.fast = false;
