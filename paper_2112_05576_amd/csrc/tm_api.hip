@@ -423,7 +423,10 @@ tm_status alloc_pyramid(int w, int h, const tm_pyr_params* pp, tm_pyramid** out)
     p->source = pp->source;
     p->tau = pp->edge_thresh;
     p->T2 = thresh_sq(pp->edge_thresh);
-    hipGetDevice(&p->dev);
+    if (hipGetDevice(&p->dev) != hipSuccess) {
+        delete p;
+        return fail(TM_EDEVICE, "pyramid: hipGetDevice");
+    }
     int ws[TM_MAX_LEVELS], hs[TM_MAX_LEVELS];
     level_sizes(w, h, p->L, ws, hs);
     const size_t fsz = pp->precision == TM_FP16 ? 4 : 8;
@@ -489,8 +492,8 @@ TM_EXPORT tm_status tm_update_pyramid(tm_pyramid* p, const uint8_t* img, int32_t
 TM_EXPORT void tm_pyramid_free(tm_pyramid* p)
 {
     if (!p) return;
-    if (p->block) hipFree(p->block);
-    if (p->ws.ptr) hipFree(p->ws.ptr);
+    if (p->block) (void)hipFree(p->block);
+    if (p->ws.ptr) (void)hipFree(p->ws.ptr);
     delete p;
 }
 
@@ -542,24 +545,28 @@ TM_EXPORT tm_status tm_build_model(const uint8_t* img, int32_t w, int32_t h, int
     if (e == hipSuccess) e = hipMemcpyAsync(hc, counts, sizeof(int) * L, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
-        hipFree(tmp);
+        (void)hipFree(tmp);
         return hip_fail(e, "tm_build_model");
     }
     for (int l = 0; l < L; ++l) {
         if (hc[l] < 1) {
-            hipFree(tmp);
+            (void)hipFree(tmp);
             return fail(TM_EINVAL, "tm_build_model: level %d has no edge point above the threshold", l);
         }
     }
     tm_model* m = new (std::nothrow) tm_model_s();
     if (!m) {
-        hipFree(tmp);
+        (void)hipFree(tmp);
         return fail(TM_ENOMEM, "tm_build_model: host allocation");
     }
     m->L = L;
     m->tau = pp->edge_thresh;
     m->source = pp->source;
-    hipGetDevice(&m->dev);
+    if (hipGetDevice(&m->dev) != hipSuccess) {
+        (void)hipFree(tmp);
+        delete m;
+        return fail(TM_EDEVICE, "tm_build_model: hipGetDevice");
+    }
     for (int l = 0; l < L; ++l) {
         tm_model_level& ml = m->lv[l];
         ml.w = ws[l];
@@ -575,7 +582,7 @@ TM_EXPORT tm_status tm_build_model(const uint8_t* img, int32_t w, int32_t h, int
         if (e == hipSuccess) e = tmk::launch_unit_dirs(ml.pts, ml.n, ml.dir, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) {
-            hipFree(tmp);
+            (void)hipFree(tmp);
             tm_model_free(m);
             return hip_fail(e, "tm_build_model: point copy");
         }
@@ -585,7 +592,7 @@ TM_EXPORT tm_status tm_build_model(const uint8_t* img, int32_t w, int32_t h, int
         // |round(R t)| <= |t| + 1 per component
         ml.rad = (int)ceil(sqrt((double)r2)) + 1;
     }
-    hipFree(tmp);
+    (void)hipFree(tmp);
     *out = m;
     return TM_OK;
 }
@@ -594,10 +601,10 @@ TM_EXPORT void tm_model_free(tm_model* m)
 {
     if (!m) return;
     for (int l = 0; l < m->L; ++l) {
-        if (m->lv[l].pts) hipFree(m->lv[l].pts);
-        if (m->lv[l].dir) hipFree(m->lv[l].dir);
+        if (m->lv[l].pts) (void)hipFree(m->lv[l].pts);
+        if (m->lv[l].dir) (void)hipFree(m->lv[l].dir);
     }
-    if (m->cache.tab) hipFree(m->cache.tab);
+    if (m->cache.tab) (void)hipFree(m->cache.tab);
     delete m;
 }
 
@@ -993,10 +1000,10 @@ struct tm_batch_s {
 TM_EXPORT void tm_batch_free(tm_batch* b)
 {
     if (!b) return;
-    if (b->graph) hipGraphExecDestroy(b->graph);
-    if (b->ls_buf) hipFree(b->ls_buf);
+    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    if (b->ls_buf) (void)hipFree(b->ls_buf);
     for (tm_pyramid* p : b->pyrs) tm_pyramid_free(p);
-    if (b->scratch) hipFree(b->scratch);
+    if (b->scratch) (void)hipFree(b->scratch);
     delete b;
 }
 
@@ -1202,11 +1209,11 @@ TM_EXPORT tm_status tm_batch_run_graph(tm_batch* b, void* stream)
                     st = hip_fail(e, "tm_batch_run_graph: instantiate");
                 }
             }
-            if (g) hipGraphDestroy(g);
+            if (g) (void)hipGraphDestroy(g);
         } else {
             st = hip_fail(e, "tm_batch_run_graph: begin capture");
         }
-        hipStreamDestroy(cs);
+        (void)hipStreamDestroy(cs);
         if (st != TM_OK) return st;
     }
     HIP_TRY(hipGraphLaunch(b->graph, S(stream)));
@@ -1227,7 +1234,7 @@ TM_EXPORT tm_status tm_batch_set_form(tm_batch* b, int32_t variant, int32_t wave
     HIP_TRY(tmk::prepare_dense(b->sd, p));
     b->plan = p;
     if (b->graph) {  // captured with the old form
-        hipGraphExecDestroy(b->graph);
+        (void)hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
     }
     return TM_OK;
@@ -1260,7 +1267,7 @@ TM_EXPORT tm_status tm_batch_tune(tm_batch* b, int32_t iterations, void* stream,
     HIP_TRY(hipEventCreate(&e0));
     hipError_t e = hipEventCreate(&e1);
     if (e != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return hip_fail(e, "tm_batch_tune: hipEventCreate");
     }
     // every form that fits, timed in two rounds (each form's time is the
@@ -1296,12 +1303,12 @@ TM_EXPORT tm_status tm_batch_tune(tm_batch* b, int32_t iterations, void* stream,
             best_ms = form_ms[f];
             best = forms[f];
         }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (e != hipSuccess) return hip_fail(e, "tm_batch_tune");
     b->plan = best;
     if (b->graph) {  // captured with the old form
-        hipGraphExecDestroy(b->graph);
+        (void)hipGraphExecDestroy(b->graph);
         b->graph = nullptr;
     }
     if (variant_out) *variant_out = best.variant;
