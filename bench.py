@@ -129,9 +129,12 @@ def traffic_from(fetch_csv, write_csv):
     for f in per.values():
         if "fetch" not in f or "write" not in f:
             continue
-        fb, wb = sum(f["fetch"]) / len(f["fetch"]), sum(f["write"]) / len(f["write"])
+        # the median launch: a batch's first launch after its creation reads
+        # its inputs from cold caches and is not the steady state
+        fb, wb = float(np.median(f["fetch"])), float(np.median(f["write"]))
         forms.append({"variant": f["variant"], "waves_per_chunk": f["waves_per_chunk"], "fetch_bytes": fb,
-                      "write_bytes": wb, "bytes_per_launch": fb + wb, "launches": len(f["fetch"])})
+                      "write_bytes": wb, "bytes_per_launch": fb + wb, "launches": len(f["fetch"]),
+                      "fetch_bytes_max": max(f["fetch"])})
     out["forms"] = sorted(forms, key=lambda f: (f["variant"], f["waves_per_chunk"]))
     os.makedirs(os.path.dirname(TRAFFIC_JSON), exist_ok=True)
     with open(TRAFFIC_JSON, "w") as fh:
