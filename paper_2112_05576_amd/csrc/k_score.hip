@@ -785,14 +785,13 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
         long long per_wave = units / 4096;
         if (per_wave < 1) per_wave = 1;
         per_wave = knob("TM_DENSE_APW", (int)per_wave, 1, 1 << 20);
-        // chunks sized for 4 waves a chunk; the waves sharing a chunk: 16 once
-        // each would get 16 or more angles (large batches: the tile staged
-        // in LDS serves more waves; measured best on the 64-image C2 batch),
-        // else 4
+        // chunks sized for 4 waves a chunk, 4 waves sharing a chunk (measured
+        // best on the 64-image C2 batch, alone and with a second batch in
+        // flight beside it; the autotuner may choose otherwise per batch)
         p.A = (int)(per_wave * 4);
         p.C = (poses_per_translation(s) + p.A - 1) / p.A;
         p.max_blocks = max_tiles * p.C;
-        int wa = knob("TM_DENSE_WA", per_wave >= 16 ? 16 : 4, 1, 16);
+        int wa = knob("TM_DENSE_WA", 4, 1, 16);
         if (p.WY * wa > 16) wa = 16 / p.WY;
         if (!retune_dense(p, p.variant, wa)) retune_dense(p, p.variant, 4);
     } else {
