@@ -456,69 +456,101 @@ struct GenericArgs {
     int level, K, A, sx, sy, win;
 };
 
-// Any step and window: one thread per grid translation, taps read from
-// global memory (clamped addresses, no branches).  grid: (translations,
-// chunk, pair).  VOTE as in k_dense_fast.
+// The searched level's field copied with a zero border of P.pad pixels on
+// every side (P.pW x P.pH elements), so that the generic search reads any tap
+// of any window without clamping: zero is a non-edge direction, which votes
+// 0, exactly as a tap outside the image does.  grid: (padded pixels, pair).
+template <int PREC>
+__global__ __launch_bounds__(256) void k_pad_field(int level, const PairDesc* __restrict__ pairs)
+{
+    using T = typename Px<PREC>::T;
+    const PairDesc& P = pairs[blockIdx.y];
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= P.pW * P.pH) return;
+    const int yy = idx / P.pW, xx = idx - yy * P.pW;
+    const int x = xx - P.pad, y = yy - P.pad, W = P.W[level], H = P.H[level];
+    T v = Px<PREC>::zero();
+    if (x >= 0 && x < W && y >= 0 && y < H) v = Px<PREC>::load(P.field[level], (size_t)y * W + x);
+    reinterpret_cast<T*>(P.pfield)[idx] = v;
+}
+
+// Any step and window: one thread per grid translation, taps read from the
+// zero-bordered copy of the field (no clamping, one address add per tap);
+// products as in the fast kernel (Px::dot).  The 3x3 window takes four points
+// per step over the padded table (padding entries, q = 0 and r = 0, add
+// exactly 0; blocks keep their bounds since 8 divides 32).  VOTE as in
+// k_dense_fast.  grid: (translations, chunk, pair).
 template <int PREC, int VOTE>
 __global__ __launch_bounds__(256) void k_dense_generic(GenericArgs a, const PairDesc* __restrict__ pairs)
 {
+    using T = typename Px<PREC>::T;
     const PairDesc& P = pairs[blockIdx.z];
     const int gw = P.gw, gh = P.gh;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     const int chunk = blockIdx.y;
     if (p >= gw * gh) return;
-    const int W = P.W[a.level], H = P.H[a.level];
-    const void* field = P.field[a.level];
+    const T* __restrict__ pf = reinterpret_cast<const T*>(P.pfield);
+    const int pW = P.pW, pad = P.pad;
     const int n = P.n[a.level];
     const float n_f = (float)n;
     const int gy = p / gw, gx = p - gy * gw;
     const int x = gx * a.sx, y = gy * a.sy;
     const int h = (a.win - 1) / 2;
+    // the window's top-left tap of a point at offset (0, 0)
+    const int origin = (y + pad - h) * pW + (x + pad - h);
+    auto win_op = [&](const TabEntry& e, T g) {
+        const float d = Px<PREC>::dot(e, g);
+        if constexpr (VOTE == 1)
+            return Px<PREC>::edge(g) ? d : kOffEdge;
+        else
+            return d;
+    };
     float bw = -INFINITY, b1 = -INFINITY;
     int bk = -1;
     const int k0 = chunk * a.A, k1 = min(a.K, k0 + a.A);
     for (int k = k0; k < k1; ++k) {
-        CTabEntry* T = (CTabEntry*)P.tab + (size_t)k * P.n_pad;  // wave-uniform: scalar loads
+        CTabEntry* Tb = (CTabEntry*)P.tab + (size_t)k * P.n_pad;  // wave-uniform: scalar loads
         float tw = 0.f, t1 = 0.f;
-        for (int i0 = 0; i0 < n; i0 += kBlock) {
+        const int nl = h == 1 ? P.n_pad : n;
+        for (int i0 = 0; i0 < nl; i0 += kBlock) {
             float pw = 0.f, p1 = 0.f;
-            const int i1 = min(n, i0 + kBlock);
+            const int i1 = min(nl, i0 + kBlock);
             if (h == 1) {
-                // the paper's 3x3 window unrolled: the nine loads of a point
-                // (and of the next) are in flight together; same order of
-                // maxima as the general loop below
-#pragma unroll 2
-                for (int i = i0; i < i1; ++i) {
-                    const TabEntry e = tab_entry(T + i);
-                    const int px = x + e.qx, py = y + e.qy;
-                    float v[3][3];
+                constexpr int U = 4;
+                for (int i = i0; i < i1; i += U) {
+                    TabEntry e[U];
 #pragma unroll
-                    for (int dy = 0; dy < 3; ++dy)
+                    for (int u = 0; u < U; ++u) e[u] = tab_entry(Tb + i + u);
+                    T g[U][3][3];
 #pragma unroll
-                        for (int dx = 0; dx < 3; ++dx)
-                            v[dy][dx] = field_win_tap<PREC, VOTE>(field, W, H, px + dx - 1, py + dy - 1, e.rx, e.ry);
-                    float best = -INFINITY;
+                    for (int u = 0; u < U; ++u) {
+                        const T* b = pf + origin + (int)e[u].qy * pW + (int)e[u].qx;
 #pragma unroll
-                    for (int dy = 0; dy < 3; ++dy)
+                        for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-                        for (int dx = 0; dx < 3; ++dx) best = fmaxf(best, v[dy][dx]);
-                    pw += win_finish<VOTE>(best);
-                    if constexpr (VOTE == 1)
-                        p1 += field_dot<PREC>(field, W, H, px, py, e.rx, e.ry);
-                    else
-                        p1 += v[1][1];
+                            for (int dx = 0; dx < 3; ++dx) g[u][dy][dx] = b[dy * pW + dx];
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        float best = -INFINITY;
+#pragma unroll
+                        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                            for (int dx = 0; dx < 3; ++dx) best = fmaxf(best, win_op(e[u], g[u][dy][dx]));
+                        pw += win_finish<VOTE>(best);
+                        p1 += Px<PREC>::dot(e[u], g[u][1][1]);
+                    }
                 }
             } else {
                 for (int i = i0; i < i1; ++i) {
-                    const TabEntry e = tab_entry(T + i);
-                    const int px = x + e.qx, py = y + e.qy;
+                    const TabEntry e = tab_entry(Tb + i);
+                    const T* b = pf + origin + (int)e.qy * pW + (int)e.qx;
                     float best = -INFINITY;
-                    for (int dy = -h; dy <= h; ++dy)
+                    for (int dy = 0; dy <= 2 * h; ++dy)
 #pragma unroll 3
-                        for (int dx = -h; dx <= h; ++dx)
-                            best = fmaxf(best, field_win_tap<PREC, VOTE>(field, W, H, px + dx, py + dy, e.rx, e.ry));
+                        for (int dx = 0; dx <= 2 * h; ++dx) best = fmaxf(best, win_op(e, b[dy * pW + dx]));
                     pw += win_finish<VOTE>(best);
-                    p1 += field_dot<PREC>(field, W, H, px, py, e.rx, e.ry);
+                    p1 += Px<PREC>::dot(e, b[h * pW + h]);
                 }
             }
             tw += pw;
@@ -795,6 +827,14 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
         if (p.WY * wa > 16) wa = 16 / p.WY;
         if (!retune_dense(p, p.variant, wa)) retune_dense(p, p.variant, 4);
     } else {
+        // the generic search reads a copy of the field with a zero border of
+        // rad + h + 1 pixels (rad bounds every |q| component)
+        p.px_bytes = s.precision == TM_FP16 ? 4 : 8;
+        p.win_h = (s.win - 1) / 2;
+        for (int i = 0; i < npairs; ++i) {
+            const long long pad = g[i].rad + p.win_h + 1;
+            p.max_pad_px = max(p.max_pad_px, (long long)(g[i].W + 2 * pad) * (g[i].H + 2 * pad));
+        }
         long long np_all = 0;
         for (int i = 0; i < npairs; ++i) np_all += (long long)g[i].gw * g[i].gh;
         const long long blocks = (np_all + 255) / 256;
@@ -916,6 +956,11 @@ hipError_t launch_dense(const SearchDesc& s, const DensePlan& p, const PairDesc*
         a.sx = s.sx;
         a.sy = s.sy;
         a.win = s.win;
+        const dim3 pgrid((unsigned)((p.max_pad_px + 255) / 256), npairs);
+        if (s.precision == TM_FP16)
+            hipLaunchKernelGGL(k_pad_field<TM_FP16>, pgrid, dim3(256), 0, st, s.level, d);
+        else
+            hipLaunchKernelGGL(k_pad_field<TM_FP32>, pgrid, dim3(256), 0, st, s.level, d);
         dim3 grid((p.max_np + 255) / 256, p.C, npairs);
         if (s.precision == TM_FP16) {
             if (s.vote)

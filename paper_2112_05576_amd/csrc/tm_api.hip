@@ -325,6 +325,18 @@ size_t pair_scratch(tmk::PairDesc* d, const tm_model* m, const tmk::PairGeom& g,
         const size_t C = (size_t)plan.C;
         float* pw = reinterpret_cast<float*>(take(tmk::dense_partials_bytes(plan, (int)np)));
         float* mw = reinterpret_cast<float*>(take(np * 12));
+        if (!plan.fast) {
+            // the generic search's zero-bordered copy of the searched field
+            const int pad = g.rad + plan.win_h + 1;
+            const int pW = g.W + 2 * pad, pH = g.H + 2 * pad;
+            uint8_t* pf = take((size_t)pW * pH * plan.px_bytes);
+            if (base) {
+                d->pfield = pf;
+                d->pW = pW;
+                d->pH = pH;
+                d->pad = pad;
+            }
+        }
         if (base) {
             d->pw = pw;
             d->p1 = pw + C * np;

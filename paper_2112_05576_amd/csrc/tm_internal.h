@@ -173,6 +173,8 @@ struct PairDesc {
     float* part[kMaxLevels];         // refinement sums [max_cand][3][18]
     int rad_l[kMaxLevels];           // bound on |q| components at each level
     int rtile[kMaxLevels];           // 1: level refined by the staged kernel (partials: one chunk)
+    void* pfield;                    // generic search: the searched field with a zero border
+    int pW, pH, pad;                 //   its size and border width
     tm_pose* out;                    // results [capacity]
     int32_t* n_out;                  // their count
 };
@@ -210,6 +212,10 @@ struct DensePlan {
     int max_np;                 // translations of the largest pair
     const int2* work = nullptr; // optional device work list (fast path, build_work)
     int n_work = 0;
+    // generic path: bytes per field pixel, window half-width, and the largest
+    // zero-bordered field copy over the pairs (pixels)
+    int px_bytes = 0, win_h = 0;
+    long long max_pad_px = 0;
 };
 
 // The searched level of one pair, for planning.
