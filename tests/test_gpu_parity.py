@@ -201,6 +201,18 @@ def test_score_map_shapes_and_paths(H, W, sx, sy, win, rng_deg):
     K = O.level_count(osp, step)
     ref = O.top_map(g, ml.t, ml.d, -20.0, step, K, sx, sy, win)
     _check_map(got, ref, g, ml, -20.0, step, sx, sy, win)
+    # FP16 fields through the same path: S_w within the FP16 bound everywhere
+    # (a maximum over angles); S_1 where the angle agrees, else the oracle at
+    # the GPU's angle, which must tie the oracle's best within two bounds
+    tol16 = 2 * 2.0 ** -11 + 2e-5
+    pyr16 = P.Pyramid(sc.image, 1, 30.0, precision=P.TM_FP16)
+    sw, s1, k = [t.cpu().numpy() for t in P.score_map(gm, pyr16, 0, sp)]
+    mw, m1, mk = ref
+    same = k == mk
+    assert np.abs(sw - mw).max() <= tol16 and np.abs(s1 - m1)[same].max() <= tol16
+    for (j, i) in np.argwhere(~same):
+        a = O.score(g, ml.t, ml.d, int(i * sx), int(j * sy), O.theta(-20.0, step, int(k[j, i])), win)
+        assert abs(a[0] - mw[j, i]) <= 2 * tol16 and abs(a[1] - s1[j, i]) <= tol16, (i, j)
 
 
 # ------------------------------------------------------------ selection
