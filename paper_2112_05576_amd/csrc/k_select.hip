@@ -248,10 +248,13 @@ struct FinalArgs {
     int K0;  // angles of level 0; the key's last component is m = j K0 + k
     tm_pose* out;    // one pair: results here instead of at the pair's own buffers (null: the pair's)
     int32_t* n_out;
+    int pick;        // >= 0: take each candidate as the best of its 27 level-0 sums (the refinement's
+                     // last pick), centre from buffer ctr[pick]; < 0: candidates as they are
+    int full;        // angle grid wraps (for the pick)
 };
 
 // One workgroup per pair (blockIdx.y).
-__global__ __launch_bounds__(256) void k_final(FinalArgs fa, const PairDesc* __restrict__ pairs)
+__global__ __launch_bounds__(1024) void k_final(FinalArgs fa, const PairDesc* __restrict__ pairs)
 {
     const PairDesc& P = pairs[blockIdx.y];
     const tm_pose* __restrict__ cand = P.cand;
@@ -273,15 +276,35 @@ __global__ __launch_bounds__(256) void k_final(FinalArgs fa, const PairDesc* __r
     int nc = n_cand ? *n_cand : max_cand;
     nc = nc < max_cand ? nc : max_cand;
     nc = nc < kFinCap ? nc : kFinCap;
-    for (int i = threadIdx.x; i < nc; i += blockDim.x) {
-        const tm_pose c = cand[i];
-        if (!(c.score_w >= min_score)) continue;
-        const int idx = atomicAdd(&count, 1);
-        u_sw[idx] = c.score_w;
-        u_s1[idx] = c.score_1;
-        u_x[idx] = c.x;
-        u_y[idx] = c.y;
-        u_k[idx] = c.j * fa.K0 + c.k;
+    if (fa.pick >= 0) {
+        // one wave per candidate: the best of the 27 poses around its centre
+        const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        for (int i = wv; i < nc; i += nw) {
+            const tm_pose ctr = P.ctr[fa.pick][i];
+            float sw, s1;
+            int x, y, k;
+            pick27(P.part[0] + (size_t)i * 54, ctr.x, ctr.y, ctr.k, P.W[0], P.H[0], P.n[0], fa.K0, fa.full, &sw, &s1,
+                   &x, &y, &k);
+            if ((threadIdx.x & 63) == 0 && sw >= min_score) {
+                const int idx = atomicAdd(&count, 1);
+                u_sw[idx] = sw;
+                u_s1[idx] = s1;
+                u_x[idx] = x;
+                u_y[idx] = y;
+                u_k[idx] = ctr.j * fa.K0 + k;
+            }
+        }
+    } else {
+        for (int i = threadIdx.x; i < nc; i += blockDim.x) {
+            const tm_pose c = cand[i];
+            if (!(c.score_w >= min_score)) continue;
+            const int idx = atomicAdd(&count, 1);
+            u_sw[idx] = c.score_w;
+            u_s1[idx] = c.score_1;
+            u_x[idx] = c.x;
+            u_y[idx] = c.y;
+            u_k[idx] = c.j * fa.K0 + c.k;
+        }
     }
     __syncthreads();
     const int N = count;
@@ -338,9 +361,11 @@ hipError_t launch_select(const SearchDesc& s, const PairDesc* d, int npairs, int
 }
 
 hipError_t launch_final(const SearchDesc& s, const PairDesc* d, int npairs, hipStream_t st, tm_pose* out,
-                        int32_t* n_out)
+                        int32_t* n_out, int pick)
 {
     FinalArgs a;
+    a.pick = pick;
+    a.full = s.full;
     a.out = npairs == 1 ? out : nullptr;
     a.n_out = n_out;
     a.max_cand = s.max_cand;
@@ -349,7 +374,7 @@ hipError_t launch_final(const SearchDesc& s, const PairDesc* d, int npairs, hipS
     a.theta_min = s.theta_min;
     a.step0 = s.step[0];
     a.K0 = s.K[0] > 0 ? s.K[0] : 1;
-    hipLaunchKernelGGL(k_final, dim3(1, npairs), dim3(256), 0, st, a, d);
+    hipLaunchKernelGGL(k_final, dim3(1, npairs), dim3(1024), 0, st, a, d);
     return hipGetLastError();
 }
 

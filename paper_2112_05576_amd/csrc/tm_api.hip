@@ -848,9 +848,9 @@ TM_EXPORT tm_status tm_detect(const tm_model* m, tm_pyramid* p, const tm_search_
     if (refine) {
         const tmk::RefinePlan rp =
             refine_plan(&m, 1, p->L, sp->neighbourhood, p->precision, sp->max_candidates, g.sigma_max);
-        HIP_TRY(tmk::launch_refine(sd, dd, 1, top, rp, s));
+        HIP_TRY(tmk::launch_refine(sd, dd, 1, top, rp, s, false));
     }
-    HIP_TRY(tmk::launch_final(sd, dd, 1, s, out, n_out));
+    HIP_TRY(tmk::launch_final(sd, dd, 1, s, out, n_out, refine ? top % 2 : -1));
     return TM_OK;
 }
 
@@ -1186,8 +1186,8 @@ tm_status batch_enqueue(tm_batch* b, hipStream_t s, bool timed)
     }
     HIP_TRY(tmk::launch_dense(b->sd, b->plan, b->d_pairs, b->npairs, s, ev0, ev1));
     HIP_TRY(tmk::launch_select(b->sd, b->d_pairs, b->npairs, b->max_np, s));
-    if (b->L > 1) HIP_TRY(tmk::launch_refine(b->sd, b->d_pairs, b->npairs, top, b->rplan, s));
-    HIP_TRY(tmk::launch_final(b->sd, b->d_pairs, b->npairs, s));
+    if (b->L > 1) HIP_TRY(tmk::launch_refine(b->sd, b->d_pairs, b->npairs, top, b->rplan, s, false));
+    HIP_TRY(tmk::launch_final(b->sd, b->d_pairs, b->npairs, s, nullptr, nullptr, b->L > 1 ? top % 2 : -1));
     return TM_OK;
 }
 }  // namespace

@@ -187,4 +187,39 @@ __device__ __forceinline__ bool key_better(float aw, float a1, int ax, int ay, i
     return ak < bk;
 }
 
+// Best of the 27 poses around (x, y, k) (a pose of level l+1) at level l, from
+// the sums part[g][m] (m < 9: S_w of translation m, m >= 9: S_1).  Runs on
+// one wave; every lane returns the result.
+__device__ __forceinline__ void pick27(const float* __restrict__ part, int x, int y, int k, int W, int H, int n, int K, int full,
+                       float* bw, float* b1, int* bx, int* by, int* bk)
+{
+    const int lane = threadIdx.x & 63;
+    const int m = lane < 27 ? lane : 26;
+    const int g = m / 9, t = m % 9, b = t / 3, u = t % 3;
+    const int kg = angle_index(2 * k + g - 1, K, full);
+    const int xx = 2 * x + u - 1, yy = 2 * y + b - 1;
+    const float sw = part[g * 18 + t] / (float)n;
+    const float s1 = part[g * 18 + 9 + t] / (float)n;
+    const bool ok = lane < 27 && xx >= 0 && yy >= 0 && xx < W && yy < H;
+    float kw = ok ? sw : -INFINITY, k1 = ok ? s1 : -INFINITY;
+    int kx = ok ? xx : 0x7fffffff, ky = ok ? yy : 0x7fffffff, kk = ok ? kg : 0x7fffffff;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const float ow = __shfl_xor(kw, off, 64), o1 = __shfl_xor(k1, off, 64);
+        const int ox = __shfl_xor(kx, off, 64), oy = __shfl_xor(ky, off, 64), okk = __shfl_xor(kk, off, 64);
+        if (key_better(ow, o1, ox, oy, okk, kw, k1, kx, ky, kk)) {
+            kw = ow;
+            k1 = o1;
+            kx = ox;
+            ky = oy;
+            kk = okk;
+        }
+    }
+    *bw = kw;
+    *b1 = k1;
+    *bx = kx;
+    *by = ky;
+    *bk = kk;
+}
+
 }  // namespace tmk

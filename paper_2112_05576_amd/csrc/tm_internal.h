@@ -263,15 +263,20 @@ hipError_t launch_dense(const SearchDesc& s, const DensePlan& p, const PairDesc*
 // Candidates of every pair from its map: pair.cand / ncand (<= s.max_cand).
 hipError_t launch_select(const SearchDesc& s, const PairDesc* d, int npairs, int max_np, hipStream_t st);
 // Refine pair.cand (poses of level from_level) down to level 0, in place.
+// pick: end with the pick of the level-0 poses into pair.cand; without it the
+// level-0 sums and centres are left for launch_final (centre buffer
+// from_level % 2).
 hipError_t launch_refine(const SearchDesc& s, const PairDesc* d, int npairs, int from_level, const RefinePlan& rp,
-                         hipStream_t st);
+                         hipStream_t st, bool pick = true);
 // Kernel attributes of the staged refinement (call before capturing it).
 hipError_t prepare_refine();
 // Final selection of every pair: pair.cand -> pair.out / n_out.
 // out / n_out (one pair only, optional): write there instead of the pair's
 // own result buffers, so a descriptor need not change with the caller's output.
+// pick >= 0: the candidates are the best of their 27 level-0 sums, centres in
+// pair.ctr[pick] (a refinement launched without its own pick).
 hipError_t launch_final(const SearchDesc& s, const PairDesc* d, int npairs, hipStream_t st, tm_pose* out = nullptr,
-                        int32_t* n_out = nullptr);
+                        int32_t* n_out = nullptr, int pick = -1);
 
 // Continuous score (forward) or its backward of n poses; d: descriptor array
 // of npairs entries (batched: pose.pair selects, else descriptor 0).
