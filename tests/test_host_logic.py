@@ -1,0 +1,120 @@
+"""Host-side logic, on the CPU: the binding's structures against the C
+header's layout (compiled with gcc), the pose record dtypes, the benchmark's
+counter arithmetic, and the determinism of the seeded workloads."""
+import csv
+import ctypes
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _c_layout(tmp_path, struct, fields):
+    """sizeof and offsetof of `fields` in `struct`, from a gcc build of tm.h."""
+    src = tmp_path / f"{struct}.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "tm.h"', "int main(void) {",
+             f'  printf("%zu\\n", sizeof({struct}));']
+    lines += [f'  printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
+    lines += ["  return 0;", "}"]
+    src.write_text("\n".join(lines))
+    exe = tmp_path / struct
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split()
+    return int(out[0]), [int(v) for v in out[1:]]
+
+
+@pytest.mark.parametrize("cls,struct", [("PyrParamsC", "tm_pyr_params"), ("SearchParamsC", "tm_search_params")])
+def test_binding_structs_match_the_header(tmp_path, cls, struct):
+    from paper_2112_05576_amd import tm
+
+    c = getattr(tm, cls)
+    names = [f[0] for f in c._fields_]
+    size, offs = _c_layout(tmp_path, struct, names)
+    assert ctypes.sizeof(c) == size
+    assert [getattr(c, n).offset for n in names] == offs
+
+
+@pytest.mark.parametrize("dtype,struct,fields", [
+    ("POSE_DTYPE", "tm_pose", ["x", "y", "k", "level", "theta_deg", "score_w", "score_1", "j"]),
+    ("EVAL_DTYPE", "tm_eval_pose", ["x", "y", "theta_deg"]),
+])
+def test_pose_dtypes_match_the_header(tmp_path, dtype, struct, fields):
+    from paper_2112_05576_amd import tm
+
+    dt = getattr(tm, dtype)
+    size, offs = _c_layout(tmp_path, struct, fields)
+    assert dt.itemsize == size
+    assert [dt.fields[n][1] for n in dt.names] == offs
+
+
+def test_search_params_pack_every_field():
+    from paper_2112_05576_amd import tm
+
+    sp = tm.SearchParams(step_x=2, step_y=3, theta_min=-5.0, theta_range=90.0, theta_step_top=2.5,
+                         neighbourhood=5, min_score=0.25, nms_min_dist=7.0, max_candidates=17, max_matches=4,
+                         scale_min=0.9, scale_step=0.05, scale_count=5, vote=1)
+    c = sp.c()
+    assert (c.step_x, c.step_y, c.theta_min_deg, c.theta_range_deg, c.theta_step_top_deg) == (2, 3, -5.0, 90.0, 2.5)
+    assert (c.neighbourhood, c.max_candidates, c.max_matches, c.scale_count, c.vote) == (5, 17, 4, 5, 1)
+    assert abs(c.min_score - 0.25) == 0 and abs(c.nms_min_dist - 7.0) == 0
+    assert (c.scale_min, c.scale_step) == (0.9, 0.05)
+    assert abs(sp.scale(4) - 1.1) < 1e-12
+
+
+def _write_counters(path, counter, rows):
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value", "Grid_Size",
+                               "Workgroup_Size"])
+        w.writeheader()
+        for i, (name, value, grid, wg) in enumerate(rows):
+            w.writerow({"Dispatch_Id": i, "Kernel_Name": name, "Counter_Name": counter, "Counter_Value": value,
+                        "Grid_Size": grid, "Workgroup_Size": wg})
+
+
+def test_traffic_figures_from_counter_runs(tmp_path, monkeypatch):
+    """Per form (variant, waves per chunk): the median batched dispatch,
+    scaled by what the counter read for the 256 MiB copy; dispatches of a
+    smaller work list (single images) are left out; the figure is reported
+    only for the recorded source and the form in use."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    monkeypatch.setattr(bench, "TRAFFIC_JSON", str(tmp_path / "traffic.json"))
+    k = "void tmk::(anonymous namespace)::k_dense_fast<32, 8, 64, {}, {}, 0>(tmk::(anonymous namespace)::FastArgs)"
+    copy = "void at::native::vectorized_elementwise_kernel<4, at::native::neg_kernel>(int)"
+    fetch = [(k.format(0, 3), 99.0, 900 * 256, 256),           # a single image: fewer workgroups
+             (k.format(1, 4), 1000.0, 1280 * 256, 256), (k.format(1, 4), 1002.0, 1280 * 256, 256),
+             (k.format(1, 4), 90000.0, 1280 * 256, 256),       # a cold first launch: the median ignores it
+             (k.format(1, 2), 1500.0, 1280 * 512, 512),
+             (copy, 131072.0, 1 << 26, 256)]
+    write = [(n, v / 2, g, wg) for n, v, g, wg in fetch[:-1]] + [(copy, 262144.0, 1 << 26, 256)]
+    _write_counters(tmp_path / "f.csv", "FETCH_SIZE", fetch)
+    _write_counters(tmp_path / "w.csv", "WRITE_SIZE", write)
+    bench.traffic_from(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"))
+    forms = {(f["variant"], f["waves_per_chunk"]): f for f in
+             __import__("json").load(open(tmp_path / "traffic.json"))["forms"]}
+    assert set(forms) == {(4, 4), (2, 8)}
+    f44 = forms[(4, 4)]
+    assert f44["fetch_bytes"] == 1002.0 * 2048.0 and f44["write_bytes"] == 1002.0 / 2 * 1024.0
+    assert f44["launches"] == 3
+    assert bench.traffic_entry({"variant": 4, "waves_per_chunk": 4}) == f44["bytes_per_launch"]
+    assert bench.traffic_entry({"variant": 4, "waves_per_chunk": 16}) is None
+    monkeypatch.setattr(bench, "KERNEL_SRC", str(tmp_path / "f.csv"))  # another source: no figure
+    assert bench.traffic_entry({"variant": 4, "waves_per_chunk": 4}) is None
+
+
+def test_workloads_are_seeded():
+    import synth
+
+    a = synth.scene_for_config(2, 5)
+    b = synth.scene_for_config(2, 5)
+    c = synth.scene_for_config(2, 6)
+    assert a.image.dtype == np.uint8 and a.image.shape == (480, 640)
+    assert np.array_equal(a.image, b.image) and np.array_equal(a.model, b.model)
+    assert not np.array_equal(a.image, c.image)
+    assert [(i.x, i.y, i.theta) for i in a.instances] == [(i.x, i.y, i.theta) for i in b.instances]
+    assert len(a.instances) == 3
