@@ -87,12 +87,13 @@ __global__ __launch_bounds__(256) void k_cont(ContArgs a, const PairDesc* __rest
     const void* field = P.field[l];
     const int W = P.W[l], H = P.H[l], n = P.n[l];
     const ModelPoint* __restrict__ pts = P.pts[l];
+    const double2* __restrict__ dir = P.dir[l];  // g / |g| in FP64, stored with the model
     Acc sv = 0, gx = 0, gy = 0, gt = 0;
     for (int i = lane; i < n; i += 64) {
         const ModelPoint q = pts[i];
         const double tx = q.tx, ty = q.ty;
-        const double gm = sqrt((double)q.gx * q.gx + (double)q.gy * q.gy);
-        const double dx = q.gx / gm, dy = q.gy / gm;
+        const double2 d = dir[i];
+        const double dx = d.x, dy = d.y;
         const double px = c * tx - s * ty + x, py = s * tx + c * ty + y;
         const double x0 = floor(px), y0 = floor(py);
         const Acc fx = (Acc)(px - x0), fy = (Acc)(py - y0);
