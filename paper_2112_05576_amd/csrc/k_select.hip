@@ -180,20 +180,40 @@ __global__ __launch_bounds__(1024) void k_select(SelectArgs sa, const PairDesc* 
     __syncthreads();
     const int np = gw * gh;
     for (int p = threadIdx.x; p < np; p += blockDim.x) {
+        const float w = mw[p];
+        if (!(w >= min_score)) continue;  // most translations: below the floor, one load
         const int j = p / gw, i = p - j * gw;
-        const float w = mw[p], s = m1[p];
-        bool is_max = w >= min_score;
-        // all 8 neighbours are loaded at clamped addresses, then compared
+        const float s = m1[p];
+        // the 8 neighbours' S_w loaded at clamped addresses, then compared;
+        // a neighbour's S_1 only decides (and is only read) on an equal S_w
+        float nw[8];
+        int nq[8];
+        bool nin[8];
+        int c = 0;
 #pragma unroll
         for (int b = -1; b <= 1; ++b) {
 #pragma unroll
             for (int a = -1; a <= 1; ++a) {
                 if (a == 0 && b == 0) continue;
                 const int ii = i + a, jj = j + b;
-                const bool in = (unsigned)ii < (unsigned)gw && (unsigned)jj < (unsigned)gh;
-                const int q = min(max(jj, 0), gh - 1) * gw + min(max(ii, 0), gw - 1);
-                const float nw = mw[q], n1 = m1[q];
-                is_max = is_max && (!in || key_better(w, s, i, j, 0, nw, n1, ii, jj, 0));
+                nin[c] = (unsigned)ii < (unsigned)gw && (unsigned)jj < (unsigned)gh;
+                nq[c] = min(max(jj, 0), gh - 1) * gw + min(max(ii, 0), gw - 1);
+                nw[c] = mw[nq[c]];
+                ++c;
+            }
+        }
+        bool is_max = true;
+        c = 0;
+#pragma unroll
+        for (int b = -1; b <= 1; ++b) {
+#pragma unroll
+            for (int a = -1; a <= 1; ++a) {
+                if (a == 0 && b == 0) continue;
+                if (nin[c] && !(nw[c] < w)) {  // otherwise this pose is strictly better
+                    const float n1 = nw[c] == w ? m1[nq[c]] : 0.0f;
+                    is_max = is_max && key_better(w, s, i, j, 0, nw[c], n1, i + a, j + b, 0);
+                }
+                ++c;
             }
         }
         if (is_max) {
