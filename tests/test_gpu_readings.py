@@ -253,3 +253,25 @@ def test_batch_graph_with_readings_equals_single(precision):
         torch.cuda.synchronize()
         assert all(_poses_equal(x, y) for x, y in zip(b.results(), eager)), rep
     print(f"{sum(len(r) for r in eager)} detections over {len(eager)} pairs")
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_edge_vote_search_forms_bit_identical(prec, monkeypatch):
+    """The edge-taps search in every launch shape it has (orientation, waves
+    per chunk, angles per wave) gives the same bits; in FP16 its products
+    carry the per-pixel addend through v_dot2_f32_f16, whose result is read
+    only after the hazard wait, which a mismatch between shapes would show."""
+    P = _P()
+    sc = synth.scene_for_config(2, 3)
+    cfg = sc.config
+    case(f"edge-vote search forms prec={prec}")
+    gm = P.Model(sc.model, 4, cfg["tau_m"])
+    pyr = P.Pyramid(sc.image, 4, cfg["tau_s"], precision=prec)
+    sp = P.SearchParams(theta_step_top=1.0, vote=P.TM_VOTE_EDGE)
+    ref = [t.clone() for t in P.score_map(gm, pyr, 3, sp)]
+    for tr, wa, apw in [(0, 4, 1), (1, 16, 1), (0, 2, 3), (1, 8, 2), (1, 1, 1)]:
+        monkeypatch.setenv("TM_DENSE_TR", str(tr))
+        monkeypatch.setenv("TM_DENSE_WA", str(wa))
+        monkeypatch.setenv("TM_DENSE_APW", str(apw))
+        got = P.score_map(gm, pyr, 3, sp)
+        assert all(torch.equal(x, y) for x, y in zip(ref, got)), (tr, wa, apw)
