@@ -29,7 +29,8 @@ combinations of pyramid source (grey image or gradient maps) and window vote
 ends the run with one 256 MiB
 elementwise copy, the calibration of the HBM byte counters; --traffic-from
 turns two rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE) into the committed
-per-launch traffic figure of the search kernel.
+per-launch traffic figure of the search kernel; --trace-summary prints a
+rocprofv3 kernel trace as a table with one row per kernel and launch shape.
 """
 from __future__ import annotations
 
@@ -74,6 +75,8 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true", help="end with a 256 MiB elementwise copy (counter scale)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the search kernel's traffic entry from two rocprofv3 --pmc CSV files and exit")
+    ap.add_argument("--trace-summary", metavar="KERNEL_TRACE_CSV",
+                    help="print a per-kernel, per-launch-shape table of a rocprofv3 --kernel-trace CSV and exit")
     return ap.parse_args()
 
 
@@ -93,6 +96,30 @@ def _pmc_rows(path, counter):
                          int(r.get("Grid_Size", 0)), int(r.get("Workgroup_Size", 0))))
     rows.sort()
     return [(n, v, g, wg) for _, n, v, g, wg in rows]
+
+
+def trace_summary(path):
+    """Markdown table of a rocprofv3 --kernel-trace CSV: one row per kernel
+    and launch shape (workgroups x threads), so that launches of one kernel
+    made by different legs of the benchmark are told apart."""
+    import csv
+
+    groups = {}
+    total = 0
+    for r in csv.DictReader(open(path)):
+        name = r["Kernel_Name"]
+        name = re.sub(r"\(.*$", "", name.replace("(anonymous namespace)::", "").replace("tmk::", ""))
+        wg = int(r["Workgroup_Size_X"]) * int(r["Workgroup_Size_Y"]) * int(r["Workgroup_Size_Z"])
+        grid = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        ns = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        groups.setdefault((name[:70], grid // max(wg, 1), wg), []).append(ns)
+        total += ns
+    print("| kernel | workgroups x threads | calls | median us | min us | max us | share % |")
+    print("|---|---:|---:|---:|---:|---:|---:|")
+    for (name, nwg, wg), v in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+        v.sort()
+        print(f"| `{name}` | {nwg} x {wg} | {len(v)} | {v[len(v) // 2] / 1e3:.2f} | {v[0] / 1e3:.2f} | "
+              f"{v[-1] / 1e3:.2f} | {100.0 * sum(v) / max(total, 1):.2f} |")
 
 
 def traffic_from(fetch_csv, write_csv):
@@ -395,6 +422,9 @@ def paper_leg(P, torch, steps):
 
 def main():
     args = parse()
+    if args.trace_summary:
+        trace_summary(args.trace_summary)
+        return
     if args.traffic_from:
         traffic_from(*args.traffic_from)
         return

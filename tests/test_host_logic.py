@@ -107,6 +107,33 @@ def test_traffic_figures_from_counter_runs(tmp_path, monkeypatch):
     assert bench.traffic_entry({"variant": 4, "waves_per_chunk": 4}) is None
 
 
+def test_trace_summary_groups_by_launch_shape(tmp_path, capsys):
+    """One row per kernel and launch shape, with the median over its
+    dispatches; rows ordered by total time."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    cols = ["Kernel_Name", "Start_Timestamp", "End_Timestamp", "Workgroup_Size_X", "Workgroup_Size_Y",
+            "Workgroup_Size_Z", "Grid_Size_X", "Grid_Size_Y", "Grid_Size_Z"]
+    k = "void tmk::(anonymous namespace)::k_dense_fast<32, 8, 64, 1, 4, 0>(tmk::(anonymous namespace)::FastArgs)"
+    rows = [(k, 0, 3000, 256, 1, 1, 1280 * 256, 1, 1), (k, 5000, 9000, 256, 1, 1, 1280 * 256, 1, 1),
+            (k, 10000, 13200, 256, 1, 1, 1280 * 256, 1, 1),
+            (k, 20000, 20070, 256, 1, 1, 900 * 256, 1, 1),          # another shape: its own row
+            ("k_select(SelectArgs)", 30000, 30016, 1024, 1, 1, 1024, 1, 1)]
+    with open(tmp_path / "t.csv", "w") as f:
+        f.write(",".join(cols) + "\n")
+        for r in rows:
+            f.write(",".join(f'"{v}"' if isinstance(v, str) else str(v) for v in r) + "\n")
+    bench.trace_summary(str(tmp_path / "t.csv"))
+    lines = [ln for ln in capsys.readouterr().out.splitlines() if ln.startswith("| `")]
+    assert len(lines) == 3
+    cells = [[c.strip() for c in ln.strip("|").split("|")] for ln in lines]
+    assert cells[0][:4] == ["`void k_dense_fast<32, 8, 64, 1, 4, 0>`", "1280 x 256", "3", "3.20"]
+    assert cells[0][4:6] == ["3.00", "4.00"]
+    assert cells[1][:4] == ["`void k_dense_fast<32, 8, 64, 1, 4, 0>`", "900 x 256", "1", "0.07"]
+    assert cells[2][:4] == ["`k_select`", "1 x 1024", "1", "0.02"]
+
+
 def test_workloads_are_seeded():
     import synth
 
