@@ -169,6 +169,16 @@ def traffic_from(fetch_csv, write_csv):
     print(json.dumps(out))
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(scenes, cfg, budget_s, paper=False):
     """The FP64 oracle, as it is, on the host cores: full detections of the
     same images until the time budget is spent (and, with paper=True, one
@@ -190,7 +200,14 @@ def cpu_baseline(scenes, cfg, budget_s, paper=False):
             break
     dt = time.perf_counter() - t0
     res = {"value": poses / dt, "unit": "pose-evals/s", "cores": threads, "kind": "oracle",
-           "sample": f"{n_img} full detections of 640x480 images (4 levels, 360 top angles), {dt:.1f} s"}
+           "sample": f"{n_img} full detections of 640x480 images (4 levels, 360 top angles), {dt:.1f} s",
+           "cpu": _cpu_model()}
+    # one more detection of the first image on a single thread
+    sc = scenes[0]
+    t0 = time.perf_counter()
+    tr = O.detect(sc.image, sc.model, O.PyrParams(L, cfg["tau_s"]), O.PyrParams(L, cfg["tau_m"]), osp, nthreads=1)
+    res["single_core_value"] = tr.top[0].size * O.level_count(osp, O.level_step(osp, L, L - 1)) / (
+        time.perf_counter() - t0)
     if paper:
         import synth
 
