@@ -138,3 +138,32 @@ def test_model_with_few_top_level_points():
     img = synth.paste_rot90(model, 96, 96, 50, 41, 1)
     got, tr, osp = _detect_both(img, model, 3, 30.0, 30.0, theta_step_top=8.0)
     _match(got, tr, osp, 3)
+
+
+def test_zero_length_inputs_enqueue_nothing():
+    """Every call that takes a list of poses accepts an empty one and returns
+    an empty result; a map with nothing above the score floor selects nothing;
+    the library keeps working afterwards (no error is left behind)."""
+    P = _P()
+    case("zero-length inputs")
+    sc = synth.scene_for_config(1, 0)
+    cfg = sc.config
+    gm = P.Model(sc.model, 1, cfg["tau_m"])
+    pyr = P.Pyramid(sc.image, 1, cfg["tau_s"])
+    assert P.score_poses(gm, pyr, 0, [], [], []).shape == (0, 2)
+    assert len(P.refine(gm, pyr, P.SearchParams(theta_step_top=5.0), np.zeros(0, P.POSE_DTYPE), 0)) == 0
+    none = torch.zeros((0, 3), dtype=torch.float32)
+    assert P.cont_score(gm, pyr, 0, none).shape == (0,)
+    assert P.cont_score_backward(gm, pyr, 0, none).shape == (0, 3)
+    moved, scores = P.cont_line_search(gm, pyr, 0, none, none, [0.0, 1.0])
+    assert moved.shape == (0, 3) and scores.shape == (0,)
+    flat = torch.zeros((6, 8), dtype=torch.float32, device="cuda")
+    out, n = P.select(flat, flat, torch.zeros((6, 8), dtype=torch.int32, device="cuda"), 1, 1, 0, 0.5, 0.0, 16)
+    assert int(n.item()) == 0
+    # and a real call after them: one pose against the oracle
+    g = O.edge_field(sc.image, cfg["tau_s"])
+    ml = O.build_model(sc.model, O.PyrParams(1, cfg["tau_m"])).levels[0]
+    x, y, th = sc.instances[0].x, sc.instances[0].y, 10.0
+    want = O.score(g, ml.t, ml.d, int(round(x)), int(round(y)), th)
+    got = P.score_poses(gm, pyr, 0, [int(round(x))], [int(round(y))], [th]).cpu().numpy()[0]
+    assert abs(got[0] - want[0]) <= TOL and abs(got[1] - want[1]) <= TOL
