@@ -145,3 +145,12 @@ def test_workloads_are_seeded():
     assert not np.array_equal(a.image, c.image)
     assert [(i.x, i.y, i.theta) for i in a.instances] == [(i.x, i.y, i.theta) for i in b.instances]
     assert len(a.instances) == 3
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The measured path is one GPU's share: --gpus N > 1 exits with a message
+    before touching a device."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
