@@ -428,17 +428,18 @@ def test_score_poses_fp16():
     assert np.abs(got - ref).max() <= TOL16
 
 
-@pytest.mark.parametrize("index", [0, 1])
-def test_detect_fp16_matches_oracle(index):
+@pytest.mark.parametrize("ci,index", [(2, 0), (2, 1), (3, 0)])
+def test_detect_fp16_matches_oracle(ci, index):
     P = _P()
-    sc = synth.scene_for_config(2, index)
+    sc = synth.scene_for_config(ci, index)
     cfg = sc.config
-    case(f"detect FP16 C2 image {index}")
-    osp = O.SearchParams(theta_step_top=1.0)
-    tr = O.detect(sc.image, sc.model, O.PyrParams(4, cfg["tau_s"]), O.PyrParams(4, cfg["tau_m"]), osp)
-    gm = P.Model(sc.model, 4, cfg["tau_m"])
-    pyr = P.Pyramid(sc.image, 4, cfg["tau_s"], precision=P.TM_FP16)
-    got = P.detect(gm, pyr, P.SearchParams(theta_step_top=1.0))
+    L, st = cfg["levels"], cfg["theta_step_top"]
+    case(f"detect FP16 C{ci} image {index}")
+    osp = O.SearchParams(theta_step_top=st)
+    tr = O.detect(sc.image, sc.model, O.PyrParams(L, cfg["tau_s"]), O.PyrParams(L, cfg["tau_m"]), osp)
+    gm = P.Model(sc.model, L, cfg["tau_m"])
+    pyr = P.Pyramid(sc.image, L, cfg["tau_s"], precision=P.TM_FP16)
+    got = P.detect(gm, pyr, P.SearchParams(theta_step_top=st))
     ref = tr.detections
     print(f"FP16 {[(int(d['x']), int(d['y']), int(d['k']), round(float(d['sw']), 4)) for d in got]}")
     print(f"FP64 {[(d.x, d.y, d.k, round(d.sw, 4)) for d in ref]}")
@@ -446,7 +447,7 @@ def test_detect_fp16_matches_oracle(index):
     assert len(got) >= 1 and len(ref) >= 1
     g0, r0 = got[0], ref[0]
     if (int(g0["x"]), int(g0["y"]), int(g0["k"])) != (r0.x, r0.y, r0.k):
-        a = _oracle_key(tr.fields, tr.model, osp, 4, g0["x"], g0["y"], g0["k"])
+        a = _oracle_key(tr.fields, tr.model, osp, L, g0["x"], g0["y"], g0["k"])
         assert abs(a[0] - r0.sw) <= 2 * TOL16, (g0, r0)
     assert abs(float(g0["sw"]) - r0.sw) <= 2 * TOL16
 
