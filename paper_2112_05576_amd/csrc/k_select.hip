@@ -117,6 +117,18 @@ __device__ __forceinline__ bool too_close(int x, int y, int ax, int ay, int leve
 __device__ int greedy_wave0(const Keys& a, int N, int level, double dmin2, int cap, int* ax, int* ay, int* aidx)
 {
     const int lane = threadIdx.x & 63;
+    if (!(dmin2 > 0.0)) {
+        // no squared distance is below a bound <= 0: the first poses are
+        // accepted as they come
+        const int m = N < cap ? N : cap;
+        for (int c = lane; c < m; c += 64) {
+            ax[c] = a.x[c];
+            ay[c] = a.y[c];
+            aidx[c] = c;
+        }
+        __threadfence_block();
+        return m;
+    }
     int acc = 0;
     for (int c0 = 0; c0 < N && acc < cap; c0 += 64) {
         const int c = c0 + lane;
@@ -126,8 +138,8 @@ __device__ int greedy_wave0(const Keys& a, int N, int level, double dmin2, int c
         for (int q = 0; q < acc; ++q) sup = sup || too_close(x, y, ax[q], ay[q], level, dmin2);
         unsigned long long live = __ballot(!sup);
         while (live != 0ull && acc < cap) {
-            const int j = __builtin_ctzll(live);
-            const int xj = __shfl(x, j, 64), yj = __shfl(y, j, 64);
+            const int j = __builtin_ctzll(live);  // wave-uniform: read the lane directly
+            const int xj = __builtin_amdgcn_readlane(x, j), yj = __builtin_amdgcn_readlane(y, j);
             if (lane == 0) {
                 ax[acc] = xj;
                 ay[acc] = yj;
