@@ -100,11 +100,20 @@ __device__ void bucket_sort(const Keys& in, const Keys& out, int N, int* cnt, in
     __syncthreads();
 }
 
-__device__ __forceinline__ bool too_close(int x, int y, int ax, int ay, int level, double dmin2)
+// The squared distance d2 (scaled by 4^level) is an integer below 2^53 for
+// any image this library accepts, so d2 < dmin2 exactly when d2 < lim with
+// lim = ceil(dmin2) (dmin2 = dmin^2 is exact in FP64): the test runs in
+// integers.
+__device__ __forceinline__ long long dist_limit(double dmin2)
+{
+    return dmin2 >= 9.0e18 ? 0x7fffffffffffffffLL : (long long)ceil(dmin2);
+}
+
+__device__ __forceinline__ bool too_close(int x, int y, int ax, int ay, int level, long long lim)
 {
     const long long dx = (long long)x - ax, dy = (long long)y - ay;
     const long long d2 = (dx * dx + dy * dy) << (2 * level);
-    return (double)d2 < dmin2;
+    return d2 < lim;
 }
 
 // Greedy suppression over `a` sorted best first (N entries), run by wave 0:
@@ -129,13 +138,14 @@ __device__ int greedy_wave0(const Keys& a, int N, int level, double dmin2, int c
         __threadfence_block();
         return m;
     }
+    const long long lim = dist_limit(dmin2);
     int acc = 0;
     for (int c0 = 0; c0 < N && acc < cap; c0 += 64) {
         const int c = c0 + lane;
         const bool valid = c < N;
         const int x = valid ? a.x[c] : 0, y = valid ? a.y[c] : 0;
         bool sup = !valid;
-        for (int q = 0; q < acc; ++q) sup = sup || too_close(x, y, ax[q], ay[q], level, dmin2);
+        for (int q = 0; q < acc; ++q) sup |= too_close(x, y, ax[q], ay[q], level, lim);
         unsigned long long live = __ballot(!sup);
         while (live != 0ull && acc < cap) {
             const int j = __builtin_ctzll(live);  // wave-uniform: read the lane directly
@@ -146,7 +156,7 @@ __device__ int greedy_wave0(const Keys& a, int N, int level, double dmin2, int c
                 aidx[acc] = c0 + j;
             }
             ++acc;
-            live &= ~__ballot(too_close(x, y, xj, yj, level, dmin2));
+            live &= ~__ballot(too_close(x, y, xj, yj, level, lim));
             live &= (j == 63) ? 0ull : ~((2ull << j) - 1ull);
         }
         __threadfence_block();
