@@ -541,9 +541,11 @@ def main():
     P.timing_enable(False)
     dense_ms, launches = P.timing_read()
 
+    # the same top-1 pose, or no detection in either leg
     same_top1 = sum(1 for a, b in zip(plain_dets, bdets)
-                    if len(a) and len(b) and (int(a[0]["x"]), int(a[0]["y"]), int(a[0]["k"])) ==
-                    (int(b[0]["x"]), int(b[0]["y"]), int(b[0]["k"])))
+                    if (not len(a) and not len(b)) or
+                    (len(a) and len(b) and (int(a[0]["x"]), int(a[0]["y"]), int(a[0]["k"])) ==
+                     (int(b[0]["x"]), int(b[0]["y"]), int(b[0]["k"]))))
     hits_plain = sum(gt_hit(d, sc) for d, sc in zip(plain_dets, scenes))
     hits_batch = sum(gt_hit(d, sc) for d, sc in zip(bdets, scenes))
 
