@@ -356,6 +356,38 @@ def test_refine_matches_oracle():
     print(f"{len(cand)} candidates refined, {ties} ties")
 
 
+@pytest.mark.parametrize("index", [2, 25])
+def test_refine_fp16_step_matches_oracle(index):
+    """One refinement step in FP16 from the oracle's level-1 poses: each pick
+    is the oracle's pick or one whose oracle score is within two FP16 bounds
+    of it (the step's decision, taken on FP16 scores, can only differ where
+    the oracle's best two of the 27 poses are that close)."""
+    P = _P()
+    case(f"FP16 refinement step C2 image {index}")
+    sc = synth.scene_for_config(2, index)
+    cfg = sc.config
+    L = 4
+    osp = O.SearchParams(theta_step_top=1.0)
+    tr = O.detect(sc.image, sc.model, O.PyrParams(L, cfg["tau_s"]), O.PyrParams(L, cfg["tau_m"]), osp)
+    src, ref = tr.refined[-2], tr.refined[-1]  # level 1, level 0
+    poses = np.zeros(len(src.x), P.POSE_DTYPE)
+    poses["x"], poses["y"], poses["k"], poses["level"] = src.x, src.y, src.k, 1
+    poses["sw"], poses["s1"] = src.sw, src.s1
+    gm = P.Model(sc.model, L, cfg["tau_m"])
+    pyr = P.Pyramid(sc.image, L, cfg["tau_s"], precision=P.TM_FP16)
+    got = P.refine(gm, pyr, P.SearchParams(theta_step_top=1.0), poses, 1)
+    other = 0
+    for i in range(len(src.x)):
+        g = got[i]
+        if (int(g["x"]), int(g["y"]), int(g["k"])) == (ref.x[i], ref.y[i], ref.k[i]):
+            assert abs(g["sw"] - ref.sw[i]) <= TOL16
+            continue
+        a = _oracle_key(tr.fields, tr.model, osp, L, g["x"], g["y"], g["k"])
+        assert abs(a[0] - ref.sw[i]) <= 2 * TOL16, (i, g, ref.rows()[i])
+        other += 1
+    print(f"{len(src.x)} poses, {other} FP16 picks differ from the oracle's within two bounds")
+
+
 def test_detect_is_deterministic():
     P = _P()
     case("determinism")
