@@ -154,3 +154,22 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_integer_distance_test_equals_the_fp64_one():
+    """The suppression test d2 * 4^level < dmin^2 (FP64, as the oracle takes
+    it) and d2 * 4^level < ceil(dmin^2) (integers, as the GPU takes it) agree
+    for integer squared distances and FP32 distances, at the boundaries too."""
+    rng = np.random.default_rng(3)
+    dmin = np.concatenate([rng.uniform(0, 200, 20000).astype(np.float32),
+                           np.float32([0.0, 1.0, 2.5, 3.0, 7.0710678, 31.999998, 32.0, 1e6])])
+    dmin2 = dmin.astype(np.float64) ** 2
+    lim = np.ceil(dmin2).astype(np.int64)
+    for level in (0, 1, 3, 5):
+        for dx in range(-20, 21):
+            for dy in (0, 1, 7, 19):
+                d2 = (dx * dx + dy * dy) << (2 * level)
+                assert np.array_equal(float(d2) < dmin2, d2 < lim), (level, dx, dy)
+    # exact squares land on the boundary: not too close in either form
+    d = np.float32(5.0)
+    assert not (25.0 < float(d) ** 2) and not (25 < int(np.ceil(float(d) ** 2)))
