@@ -118,8 +118,8 @@ __device__ __forceinline__ bool too_close(int x, int y, int ax, int ay, int leve
 
 // Greedy suppression over `a` sorted best first (N entries), run by wave 0:
 // a pose is accepted iff its squared distance (scaled by 4^level) to every
-// accepted pose is >= dmin2.  The distance test is exact: integer squared
-// distance and a squared float, both exact in FP64.  The wave takes 64
+// accepted pose is >= dmin2.  The distance test is exact (integers against
+// dist_limit(dmin2)).  The wave takes 64
 // candidates at a time: each lane tests its candidate against the poses
 // accepted so far, then the survivors are accepted in key order, each one
 // removing the later lanes it is too close to.
