@@ -819,14 +819,20 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
         // (measured on one 640x480 FP32 detection: 70.6 us against 73.0 us
         // with four waves, and a quarter of the chunk partials to reduce)
         const bool small = units < 4096;
-        long long per_wave = small ? 4 : units / 4096;
+        long long per_wave = small ? 4 : units / 6144;
         if (per_wave < 1) per_wave = 1;
         per_wave = knob("TM_DENSE_APW", (int)per_wave, 1, 1 << 20);
-        // chunks sized for 4 waves a chunk, 4 waves sharing a chunk (measured
-        // best on the 64-image C2 batch, alone and with a second batch in
-        // flight beside it; the autotuner may choose otherwise per batch)
+        // chunks sized for about six waves per SIMD over the batch, then made
+        // equal (a multiple of 4 angles each), so that no chunk's workgroups
+        // finish far ahead of the others' (measured on the 64-image C2 batch:
+        // 360 angles in chunks of 224 + 136, 3.28 ms a launch and 3.02 ms a
+        // two-batch step; in 3 of 120, 3.05 ms and 2.88 ms; the autotuner
+        // varies the form, not the chunks)
+        const int K = poses_per_translation(s);
         p.A = (int)(per_wave * 4);
-        p.C = (poses_per_translation(s) + p.A - 1) / p.A;
+        p.C = (K + p.A - 1) / p.A;
+        p.A = ((K + p.C - 1) / p.C + 3) / 4 * 4;
+        p.C = (K + p.A - 1) / p.A;
         p.max_blocks = max_tiles * p.C;
         int wa = knob("TM_DENSE_WA", small ? 16 : 4, 1, 16);
         if (p.WY * wa > 16) wa = 16 / p.WY;
