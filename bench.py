@@ -17,7 +17,9 @@ x candidates x 3 per detection and is not counted); the plain leg,
 detections/s, taps/s and the agreement of top-1 poses between the legs are
 given beside it.  The search kernel's own duration (for the roofline entry)
 comes from HIP events around its launches in a few eager batched steps after
-the timed region, on the same stream.
+the timed region, on the same stream.  The search-kernel form is the
+autotuner's, or the default one if that gives the faster pipelined step
+(both give the same detections).
 
 --c4 adds the mixed batch (64 images of 640x480 to 2448x2048 against 8 models,
 one graph launch per step) and the continuous refinement of 4096 poses over
