@@ -130,3 +130,46 @@ def test_scaled_instance_is_found_at_its_scale(oracle_mod, sigma, theta):
     assert abs(d.x - 160) <= 1 and abs(d.y - 120) <= 1, d
     assert abs((d.theta - theta + 180) % 360 - 180) <= 1.0, d
     assert d.sw > 0.9
+
+
+@pytest.mark.parametrize("j", [0, 2])
+def test_refine_sim_picks_best_of_27_by_bruteforce(oracle_mod, j):
+    """O15 at a scale other than 1: each candidate (x, y, m = j K' + k) of the
+    level above moves to the best by the key of the 27 poses (2x + a, 2y + b,
+    2k + c) at its own scale sigma_j, the scores taken from the independent
+    NumPy brute force (tests/bruteforce.py) at that scale."""
+    O = oracle_mod
+    rng = _rng(60 + j)
+    img = rng.integers(0, 256, (30, 34), dtype=np.uint8)
+    mimg = np.full((9, 9), 40, np.uint8)
+    mimg[2:6, 2:7] = 210
+    mimg[6, 3:8] = 120
+    bt, bd = BF.model(mimg, 30.0)
+    M = O.build_model(mimg, O.PyrParams(1, 30.0))
+    g = BF.field(img, 50.0)
+    K, step = 48, 7.5            # this level's grid; the level above has K / 2 angles
+    K_above = K // 2
+    sigma_min, sigma_step = 0.8, 0.25
+    sigma = O.scale(sigma_min, sigma_step, j)
+    assert sigma != 1.0
+    cx = np.array([0, 8, 16], np.int32)
+    cy = np.array([0, 7, 14], np.int32)
+    ck = np.array([0, 11, 23], np.int32)
+    cands = O.Candidates(cx, cy, (j * K_above + ck).astype(np.int32), np.zeros(3), np.zeros(3))
+    out = O.refine_level_sim(g, M.levels[0], cands, 0.0, step, K, K_above, True, 3, sigma_min, sigma_step)
+    thetas = [O.theta(0.0, step, k) for k in range(K)]
+    Sw, S1 = BF.score_volume(g, bt, bd, thetas, sigma=sigma)
+    for c in range(3):
+        best = None
+        for dk in (-1, 0, 1):
+            k = (2 * int(ck[c]) + dk) % K
+            for b in (-1, 0, 1):
+                for a in (-1, 0, 1):
+                    x, y = 2 * int(cx[c]) + a, 2 * int(cy[c]) + b
+                    if not (0 <= x < 34 and 0 <= y < 30):
+                        continue
+                    key = (-Sw[k, y, x], -S1[k, y, x], x, y, k)
+                    best = key if best is None or key < best else best
+        assert (int(out.x[c]), int(out.y[c])) == best[2:4]
+        assert int(out.k[c]) == j * K + best[4]  # the key's last component: m = j K + k
+        assert abs(out.sw[c] + best[0]) <= 1e-12 and abs(out.s1[c] + best[1]) <= 1e-12
