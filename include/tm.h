@@ -22,10 +22,26 @@
  *  - Every call returns a tm_status.  On failure nothing has been enqueued
  *    (validation happens first) and tm_last_error() describes the problem in
  *    the calling thread.  A failed HIP runtime call returns TM_EDEVICE.
- *  - A model may be used by any number of streams at once as long as they use
- *    the same angle grid (its rotated-point table is cached per grid).  A
- *    pyramid carries the scratch space of tm_detect / tm_refine, so one
- *    pyramid is used by one stream at a time.
+ *  - A model may be used by any number of streams at once.  Its rotated-point
+ *    tables are cached per (level, angle grid, scale grid); the first call
+ *    with a new grid builds the table on its own stream and later calls on
+ *    other streams wait for it (an event).  Under graph capture a table must
+ *    already exist (run the call once before capturing).  A pyramid carries
+ *    the scratch space of tm_detect / tm_refine, so one pyramid is used by one
+ *    stream at a time.
+ *  - Device memory of handles (models, pyramids, batches and their scratch)
+ *    comes from the allocator registered with tm_set_allocator when the
+ *    handle is created (default: hipMalloc / hipFree); a handle keeps that
+ *    allocator for all its later allocations and frees.  Free a handle only
+ *    after the streams that used it have passed their last use of it.
+ *  - Result counts: a call that writes poses into a caller buffer of
+ *    `capacity` entries writes to *n_out_dev the number of poses the method
+ *    produced.  If that number exceeds `capacity`, only the first `capacity`
+ *    of them (the best by the selection key, so the truncation is
+ *    deterministic) are written: the result did not fit, which the caller
+ *    reads as TM_ECAPACITY (the call itself returns before the device has
+ *    counted, so this status travels in the count; the Python binding raises
+ *    it).
  *
  * Image layout: uint8, row-major, `pitch` bytes between rows (pitch >= width).
  * Coordinates: x to the right, y down; the model's reference point is its
@@ -142,6 +158,26 @@ typedef struct {
 typedef struct tm_model_s tm_model;
 typedef struct tm_pyramid_s tm_pyramid;
 
+/* Device-memory allocator for the handles (a caching allocator such as
+ * torch's, say).  alloc returns `bytes` of device memory of the current
+ * device, aligned to at least 256 bytes, or NULL on failure (the calling
+ * entry point then returns TM_ENOMEM); `stream` is the stream of the call
+ * that allocates (NULL when there is none).  free releases a block that
+ * alloc returned; the library frees a block only after the stream it was
+ * last used on has been synchronised, or at handle destruction (see the
+ * conventions above).  ctx is passed through unchanged. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* ctx, void* stream);
+    void (*free)(void* ptr, void* ctx, void* stream);
+    void* ctx;
+} tm_allocator;
+
+/* Register the allocator used by handles created from now on (NULL, or
+ * null function pointers: back to hipMalloc / hipFree).  Handles created
+ * before keep the allocator they were created with.  TM_EINVAL if exactly
+ * one of the two functions is null. */
+tm_status tm_set_allocator(const tm_allocator* allocator);
+
 /* Edge points of a model image on every pyramid level (Sec. II para. 2; the
  * points are the t_i of Eq. (2), row-major, relative to the reference pixel).
  * Waits on `stream` once to learn the point counts.  TM_EINVAL if the image
@@ -151,8 +187,11 @@ tm_status tm_build_model(const uint8_t* img_dev, int32_t width, int32_t height, 
                          const tm_pyr_params* params, void* stream, tm_model** out);
 
 /* Grey-level pyramid of a search image and its unit-gradient-direction field
- * on every level ((0, 0) off the edge set).  Allocates the pyramid; the image
- * is copied, not retained.  TM_EINVAL if the image is smaller than
+ * on every level ((0, 0) off the edge set): Sec. II para. 2, edge extraction
+ * (gradients and their magnitude against the threshold) and the image
+ * pyramid whose top image the search starts from; Eq. (1) compares the
+ * model's directions with this field.  Allocates the pyramid; the image is
+ * copied, not retained.  TM_EINVAL if the image is smaller than
  * 2^(levels-1) * 3 pixels a side. */
 tm_status tm_build_pyramid(const uint8_t* img_dev, int32_t width, int32_t height, int32_t pitch,
                            const tm_pyr_params* params, void* stream, tm_pyramid** out);
@@ -178,13 +217,17 @@ tm_status tm_score_map(const tm_model* model, tm_pyramid* pyr, int32_t level,
                        const tm_search_params* params, float* sw_dev, float* s1_dev, int32_t* k_dev,
                        void* stream);
 
-/* Candidate selection on a score map of `level` (layout as tm_score_map):
- * grid points with S_w >= min_score whose key (S_w desc, S_1 desc, x asc,
- * y asc) beats all 8 grid neighbours, sorted by the key, thinned greedily so
- * that accepted poses are >= dmin apart in level-0 pixels (distance scaled by
- * 2^level), at most `capacity`.  Writes the poses and their count (device
- * int).  Used inside tm_detect; exported so that it can be run on a given
- * map. */
+/* Candidate selection on a score map of `level` (layout as tm_score_map).
+ * Sec. II para. 3 records a pose whenever its score is better than the best
+ * so far, i.e. it keeps the single best pose; for several instances this is
+ * generalised to: grid points with S_w >= min_score whose key (S_w desc,
+ * S_1 desc, x asc, y asc) beats all 8 grid neighbours, sorted by the key,
+ * thinned greedily so that accepted poses are >= dmin apart in level-0 pixels
+ * (distance scaled by 2^level), at most `capacity` (1..1024, the method's cap
+ * on candidates, like max_candidates in a detection: reaching it is not an
+ * overflow).  Writes the poses and their count (device int).  Inputs: device
+ * maps of gw x gh (sw, s1 float; k int32); outputs: device buffers.  Used
+ * inside tm_detect; exported so that it can be run on a given map. */
 tm_status tm_select(const float* sw_dev, const float* s1_dev, const int32_t* k_dev, int32_t gw, int32_t gh,
                     int32_t step_x, int32_t step_y, int32_t level, float min_score, float dmin,
                     tm_pose* out_dev, int32_t capacity, int32_t* n_out_dev, void* stream);
@@ -192,16 +235,22 @@ tm_status tm_select(const float* sw_dev, const float* s1_dev, const int32_t* k_d
 /* Full detection (Sec. II): exhaustive search of the top level, candidate
  * selection (at most max_candidates), refinement down to level 0, then the
  * final selection: candidates with S_w >= min_score, key order, greedy
- * suppression within nms_min_dist, at most min(max_matches, capacity).
- * Poses are written to out_dev at level 0 and their count to *n_out_dev. */
+ * suppression within nms_min_dist, at most max_matches.  *n_out_dev gets
+ * their number and out_dev (capacity entries) the first min(number,
+ * capacity) of them at level 0; a number above capacity is the TM_ECAPACITY
+ * case of the conventions above. */
 tm_status tm_detect(const tm_model* model, tm_pyramid* pyr, const tm_search_params* params,
                     tm_pose* out_dev, int32_t capacity, int32_t* n_out_dev, void* stream);
 
 /* Coarse-to-fine refinement of n poses of level `from_level` (x, y, k on
- * that level's grid) down to level 0, in place: at each level below, the pose
- * is replaced by the best (by the selection key) of the 27 poses
- * (2x+a, 2y+b, 2k+c), a, b, c in {-1, 0, 1}, inside the level image.  Poses
- * must lie inside their level.  No selection is applied. */
+ * that level's grid) down to level 0, in place (Sec. II para. 2: the search
+ * starts with the pyramid's top image and is carried down to the full image;
+ * the paper gives no neighbourhood for the step, this uses the 3 x 3 x 3 one
+ * around the doubled pose): at each level below, the pose is replaced by the
+ * best (by the selection key) of the 27 poses (2x+a, 2y+b, 2k+c),
+ * a, b, c in {-1, 0, 1}, inside the level image, scored with Eq. (1) and the
+ * neighbouring window.  poses_dev: n device tm_pose records, read and
+ * written; poses must lie inside their level.  No selection is applied. */
 tm_status tm_refine(const tm_model* model, tm_pyramid* pyr, const tm_search_params* params, int32_t from_level,
                     tm_pose* poses_dev, int32_t n, void* stream);
 
@@ -236,8 +285,10 @@ tm_status tm_cont_line_search(const tm_model* model, tm_pyramid* pyr, int32_t le
 /* A batch binds n_images device images (each width x height, `pitch` bytes
  * per row) and n_models models to output buffers, for the detection of
  * every model in every image (Sec. II applied pair by pair).  Pair
- * p = image * n_models + model writes at most min(capacity, max_matches)
- * poses to out_dev[p * capacity ...] and their count to n_out_dev[p].
+ * p = image * n_models + model writes its matches (at most max_matches) to
+ * out_dev[p * capacity ...] and their number to n_out_dev[p]; a number above
+ * capacity is the TM_ECAPACITY case of the conventions above (the first
+ * capacity matches by key are written).
  * Creation allocates the pyramids, the rotated tables of the top level and
  * all scratch, and waits for the uploads; models must outlive the batch (their
  * points are read, their table cache is not used).  At most 65535 pairs.

@@ -282,9 +282,12 @@ __global__ __launch_bounds__(1024) void k_select(SelectArgs sa, const PairDesc* 
 }
 
 // Final selection of the refined level-0 poses: score floor, key order (rank
-// by counting, the list is short), greedy suppression, at most cap.
+// by counting, the list is short), greedy suppression, at most cap matches;
+// the first min(matches, buf) are written and the count of matches, so a
+// count above buf tells the caller that the result was truncated.
 struct FinalArgs {
     int max_cand, cap;
+    int buf;         // poses the result buffer holds
     float min_score;
     double theta_min, step0;
     int K0;  // angles of level 0; the key's last component is m = j K0 + k
@@ -365,7 +368,8 @@ __global__ __launch_bounds__(1024) void k_final(FinalArgs fa, const PairDesc* __
     }
     __syncthreads();
     const int m = n_acc;
-    for (int t = threadIdx.x; t < m; t += blockDim.x) {
+    const int mw = m < fa.buf ? m : fa.buf;  // written: the best by key first
+    for (int t = threadIdx.x; t < mw; t += blockDim.x) {
         const int c = acc_i[t];
         tm_pose o;
         const int mi = a.k[c];
@@ -411,7 +415,8 @@ hipError_t launch_final(const SearchDesc& s, const PairDesc* d, int npairs, hipS
     a.out = npairs == 1 ? out : nullptr;
     a.n_out = n_out;
     a.max_cand = s.max_cand;
-    a.cap = s.capacity;
+    a.cap = s.max_matches;
+    a.buf = s.capacity;
     a.min_score = s.min_score;
     a.theta_min = s.theta_min;
     a.step0 = s.step[0];

@@ -40,6 +40,17 @@ tm_status hip_fail(hipError_t e, const char* where)
 
 inline hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// ---------------------------------------------------------------- allocator
+// The allocator new handles take (tm_set_allocator); each handle keeps a copy.
+std::mutex g_alloc_mu;
+tm_allocator g_alloc = {nullptr, nullptr, nullptr};
+
+tm_allocator current_allocator()
+{
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    return g_alloc;
+}
+
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 tm_status check_image(const uint8_t* img, int w, int h, int pitch, const tm_pyr_params* p, const char* what)
@@ -183,43 +194,62 @@ tm_status ensure_ws(tm_pyramid* p, size_t bytes, hipStream_t s)
     if (p->ws.bytes >= bytes) return TM_OK;
     if (p->ws.ptr) {
         HIP_TRY(hipStreamSynchronize(s));
-        HIP_TRY(hipFree(p->ws.ptr));
+        tmk::dev_free(p->alloc, p->ws.ptr, s);
         p->ws.ptr = nullptr;
         p->ws.bytes = 0;
     }
     bytes = align_up(bytes, 1 << 20);
-    HIP_TRY(hipMalloc(&p->ws.ptr, bytes));
+    HIP_TRY(tmk::dev_alloc(p->alloc, &p->ws.ptr, bytes, s));
     p->ws.bytes = bytes;
     p->desc_valid = false;
     return TM_OK;
 }
 
-// Rotated table of the model's `level` for a grid; cached on the model.
+bool stream_capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
+// Rotated table of the model's `level` for a grid, cached on the model per
+// (level, grid): a new grid gets a table of its own (built on stream s, an
+// event recorded after it) and earlier tables stay valid for the streams
+// still reading them.  A stream other than the builder's waits for the event.
+constexpr size_t kMaxTables = 32;  // tables cached per model
+
 tm_status get_table(const tm_model* mc, int level, double theta_min, double step, int K, const Grid& g,
                     hipStream_t s, const tmk::TabEntry** out)
 {
     tm_model* m = const_cast<tm_model*>(mc);
-    tm_model_table_cache& c = m->cache;
     const tm_model_level& ml = m->lv[level];
     if (scaled_rad(ml, g.sigma_max) > 32000) return fail(TM_EINVAL, "model too large for the scale range");
-    if (c.tab && c.level == level && c.theta_min == theta_min && c.step == step && c.K == K && c.S == g.S &&
-        c.sigma_min == g.sigma_min && c.sigma_step == g.sigma_step) {
-        *out = c.tab;
-        return TM_OK;
-    }
-    size_t need = (size_t)K * g.S * ml.n_pad;
-    if (need > c.cap) {
-        if (c.tab) {
-            HIP_TRY(hipStreamSynchronize(s));
-            HIP_TRY(hipFree(c.tab));
-            c.tab = nullptr;
-            c.cap = 0;
+    std::lock_guard<std::mutex> lock(m->mu);
+    for (const tm_rot_table& c : m->tables) {
+        if (c.level == level && c.theta_min == theta_min && c.step == step && c.K == K && c.S == g.S &&
+            c.sigma_min == g.sigma_min && c.sigma_step == g.sigma_step) {
+            if (c.stream != s) {
+                if (!stream_capturing(s)) {
+                    HIP_TRY(hipStreamWaitEvent(s, c.ready, 0));
+                } else if (hipEventQuery(c.ready) != hipSuccess) {
+                    return fail(TM_EINVAL, "rotated table still being built on another stream; wait for it before "
+                                           "capturing");
+                }
+            }
+            *out = c.tab;
+            return TM_OK;
         }
-        HIP_TRY(hipMalloc(&c.tab, need * sizeof(tmk::TabEntry)));
-        c.cap = need;
     }
-    HIP_TRY(tmk::launch_tables(ml.pts, ml.n, ml.n_pad, theta_min, step, K, g.sigma_min, g.sigma_step, g.S, c.tab,
-                               s));
+    if (stream_capturing(s))
+        return fail(TM_EINVAL, "no rotated table for this grid yet; run the call once before capturing");
+    if (m->tables.size() >= kMaxTables) {
+        // evict the oldest table once the device has passed every use of it
+        HIP_TRY(hipDeviceSynchronize());
+        tm_rot_table& o = m->tables.front();
+        tmk::dev_free(m->alloc, o.tab, s);
+        (void)hipEventDestroy(o.ready);
+        m->tables.erase(m->tables.begin());
+    }
+    tm_rot_table c;
     c.level = level;
     c.theta_min = theta_min;
     c.step = step;
@@ -227,6 +257,20 @@ tm_status get_table(const tm_model* mc, int level, double theta_min, double step
     c.S = g.S;
     c.sigma_min = g.sigma_min;
     c.sigma_step = g.sigma_step;
+    c.stream = s;
+    void* tab = nullptr;
+    HIP_TRY(tmk::dev_alloc(m->alloc, &tab, (size_t)K * g.S * ml.n_pad * sizeof(tmk::TabEntry), s));
+    c.tab = reinterpret_cast<tmk::TabEntry*>(tab);
+    hipError_t e = hipEventCreateWithFlags(&c.ready, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = tmk::launch_tables(ml.pts, ml.n, ml.n_pad, theta_min, step, K, g.sigma_min, g.sigma_step, g.S, c.tab, s);
+    if (e == hipSuccess) e = hipEventRecord(c.ready, s);
+    if (e != hipSuccess) {
+        if (c.ready) (void)hipEventDestroy(c.ready);
+        tmk::dev_free(m->alloc, tab, s);
+        return hip_fail(e, "rotated table");
+    }
+    m->tables.push_back(c);
     *out = c.tab;
     return TM_OK;
 }
@@ -266,6 +310,7 @@ tmk::SearchDesc make_search(const tm_search_params* sp, const Grid& g, int level
     s.min_score = sp->min_score;
     s.max_cand = sp->max_candidates;
     s.capacity = capacity;
+    s.max_matches = sp->max_matches;
     s.S = g.S;
     s.sigma_min = g.sigma_min;
     s.sigma_step = g.sigma_step;
@@ -422,14 +467,52 @@ tmk::RefinePlan refine_plan(const tm_model* const* models, int n_models, int L, 
 
 TM_EXPORT const char* tm_last_error(void) { return g_err; }
 
+namespace tmk {
+hipError_t dev_alloc(const tm_allocator& a, void** p, size_t bytes, hipStream_t s)
+{
+    *p = nullptr;
+    if (!a.alloc) return hipMalloc(p, bytes);
+    void* q = a.alloc(bytes, a.ctx, reinterpret_cast<void*>(s));
+    if (!q) return hipErrorOutOfMemory;
+    if ((reinterpret_cast<uintptr_t>(q) & 255u) != 0) {  // the layouts assume 256-byte alignment
+        a.free(q, a.ctx, reinterpret_cast<void*>(s));
+        return hipErrorInvalidValue;
+    }
+    *p = q;
+    return hipSuccess;
+}
+
+void dev_free(const tm_allocator& a, void* p, hipStream_t s)
+{
+    if (!p) return;
+    if (a.free)
+        a.free(p, a.ctx, reinterpret_cast<void*>(s));
+    else
+        (void)hipFree(p);
+}
+}  // namespace tmk
+
+TM_EXPORT tm_status tm_set_allocator(const tm_allocator* a)
+{
+    if (a && ((a->alloc == nullptr) != (a->free == nullptr)))
+        return fail(TM_EINVAL, "tm_set_allocator: give both alloc and free, or neither");
+    std::lock_guard<std::mutex> g(g_alloc_mu);
+    if (a && a->alloc)
+        g_alloc = *a;
+    else
+        g_alloc = tm_allocator{nullptr, nullptr, nullptr};
+    return TM_OK;
+}
+
 TM_EXPORT const char* tm_version(void) { return "tm-hip 0.1 (gfx950)"; }
 
 namespace {
 // A pyramid of a w x h image with storage for all levels (not yet built).
-tm_status alloc_pyramid(int w, int h, const tm_pyr_params* pp, tm_pyramid** out)
+tm_status alloc_pyramid(int w, int h, const tm_pyr_params* pp, hipStream_t s, tm_pyramid** out)
 {
     tm_pyramid* p = new (std::nothrow) tm_pyramid_s();
     if (!p) return fail(TM_ENOMEM, "pyramid: host allocation");
+    p->alloc = current_allocator();
     p->L = pp->levels;
     p->precision = pp->precision;
     p->source = pp->source;
@@ -453,10 +536,10 @@ tm_status alloc_pyramid(int w, int h, const tm_pyr_params* pp, tm_pyramid** out)
         grd_off[l] = total;
         if (gradient) total = align_up(total + (size_t)ws[l] * hs[l] * 4, 256);
     }
-    hipError_t e = hipMalloc(&p->block, total);
+    hipError_t e = tmk::dev_alloc(p->alloc, &p->block, total, s);
     if (e != hipSuccess) {
         delete p;
-        return hip_fail(e, "pyramid: hipMalloc");
+        return hip_fail(e, "pyramid: device allocation");
     }
     for (int l = 0; l < p->L; ++l) {
         p->lv[l].w = ws[l];
@@ -480,7 +563,7 @@ TM_EXPORT tm_status tm_build_pyramid(const uint8_t* img, int32_t w, int32_t h, i
     tm_status st = check_image(img, w, h, pitch, pp, "tm_build_pyramid");
     if (st != TM_OK) return st;
     tm_pyramid* p = nullptr;
-    st = alloc_pyramid(w, h, pp, &p);
+    st = alloc_pyramid(w, h, pp, S(stream), &p);
     if (st != TM_OK) return st;
     st = tm_update_pyramid(p, img, pitch, stream);
     if (st != TM_OK) {
@@ -504,8 +587,8 @@ TM_EXPORT tm_status tm_update_pyramid(tm_pyramid* p, const uint8_t* img, int32_t
 TM_EXPORT void tm_pyramid_free(tm_pyramid* p)
 {
     if (!p) return;
-    if (p->block) (void)hipFree(p->block);
-    if (p->ws.ptr) (void)hipFree(p->ws.ptr);
+    tmk::dev_free(p->alloc, p->block, nullptr);
+    tmk::dev_free(p->alloc, p->ws.ptr, nullptr);
     delete p;
 }
 
@@ -537,8 +620,9 @@ TM_EXPORT tm_status tm_build_model(const uint8_t* img, int32_t w, int32_t h, int
     }
     const size_t cnt_off = total;
     total += 256;
+    const tm_allocator A = current_allocator();
     void* tmp = nullptr;
-    HIP_TRY(hipMalloc(&tmp, total));
+    HIP_TRY(tmk::dev_alloc(A, &tmp, total, s));
     tmk::ModelPoint* pts[TM_MAX_LEVELS];
     for (int l = 0; l < L; ++l) {
         lv[l].w = ws[l];
@@ -557,25 +641,26 @@ TM_EXPORT tm_status tm_build_model(const uint8_t* img, int32_t w, int32_t h, int
     if (e == hipSuccess) e = hipMemcpyAsync(hc, counts, sizeof(int) * L, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
-        (void)hipFree(tmp);
+        tmk::dev_free(A, tmp, s);
         return hip_fail(e, "tm_build_model");
     }
     for (int l = 0; l < L; ++l) {
         if (hc[l] < 1) {
-            (void)hipFree(tmp);
+            tmk::dev_free(A, tmp, s);
             return fail(TM_EINVAL, "tm_build_model: level %d has no edge point above the threshold", l);
         }
     }
     tm_model* m = new (std::nothrow) tm_model_s();
     if (!m) {
-        (void)hipFree(tmp);
+        tmk::dev_free(A, tmp, s);
         return fail(TM_ENOMEM, "tm_build_model: host allocation");
     }
+    m->alloc = A;
     m->L = L;
     m->tau = pp->edge_thresh;
     m->source = pp->source;
     if (hipGetDevice(&m->dev) != hipSuccess) {
-        (void)hipFree(tmp);
+        tmk::dev_free(A, tmp, s);
         delete m;
         return fail(TM_EDEVICE, "tm_build_model: hipGetDevice");
     }
@@ -587,14 +672,18 @@ TM_EXPORT tm_status tm_build_model(const uint8_t* img, int32_t w, int32_t h, int
         ml.n_pad = (ml.n + 7) / 8 * 8;
         std::vector<tmk::ModelPoint> hp(ml.n);
         e = hipMemcpy(hp.data(), pts[l], sizeof(tmk::ModelPoint) * ml.n, hipMemcpyDeviceToHost);
-        if (e == hipSuccess) e = hipMalloc(&ml.pts, sizeof(tmk::ModelPoint) * ml.n);
+        void* vp = nullptr;
+        if (e == hipSuccess) e = tmk::dev_alloc(A, &vp, sizeof(tmk::ModelPoint) * ml.n, s);
+        ml.pts = reinterpret_cast<tmk::ModelPoint*>(vp);
         if (e == hipSuccess)
             e = hipMemcpy(ml.pts, hp.data(), sizeof(tmk::ModelPoint) * ml.n, hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMalloc(&ml.dir, sizeof(double2) * ml.n);
+        vp = nullptr;
+        if (e == hipSuccess) e = tmk::dev_alloc(A, &vp, sizeof(double2) * ml.n, s);
+        ml.dir = reinterpret_cast<double2*>(vp);
         if (e == hipSuccess) e = tmk::launch_unit_dirs(ml.pts, ml.n, ml.dir, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) {
-            (void)hipFree(tmp);
+            tmk::dev_free(A, tmp, s);
             tm_model_free(m);
             return hip_fail(e, "tm_build_model: point copy");
         }
@@ -604,7 +693,7 @@ TM_EXPORT tm_status tm_build_model(const uint8_t* img, int32_t w, int32_t h, int
         // |round(R t)| <= |t| + 1 per component
         ml.rad = (int)ceil(sqrt((double)r2)) + 1;
     }
-    (void)hipFree(tmp);
+    tmk::dev_free(A, tmp, s);
     *out = m;
     return TM_OK;
 }
@@ -613,10 +702,13 @@ TM_EXPORT void tm_model_free(tm_model* m)
 {
     if (!m) return;
     for (int l = 0; l < m->L; ++l) {
-        if (m->lv[l].pts) (void)hipFree(m->lv[l].pts);
-        if (m->lv[l].dir) (void)hipFree(m->lv[l].dir);
+        tmk::dev_free(m->alloc, m->lv[l].pts, nullptr);
+        tmk::dev_free(m->alloc, m->lv[l].dir, nullptr);
     }
-    if (m->cache.tab) (void)hipFree(m->cache.tab);
+    for (tm_rot_table& c : m->tables) {
+        tmk::dev_free(m->alloc, c.tab, nullptr);
+        if (c.ready) (void)hipEventDestroy(c.ready);
+    }
     delete m;
 }
 
@@ -765,20 +857,23 @@ TM_EXPORT tm_status tm_select(const float* sw, const float* s1, const int32_t* k
     if ((long long)gw * gh > (1LL << 28)) return fail(TM_EINVAL, "tm_select: map too large");
     if (capacity < 1 || capacity > 1024) return fail(TM_EINVAL, "tm_select: capacity must be in [1, 1024]");
     if (!isfinite(min_score) || !isfinite(dmin)) return fail(TM_EINVAL, "tm_select: non-finite threshold");
-    // scratch: a private buffer of this thread (this entry point has no pyramid)
-    static thread_local void* scratch = nullptr;
-    static thread_local size_t scratch_bytes = 0;
+    // scratch: a private buffer of this thread (this entry point has no
+    // pyramid), with the allocator it came from
+    static thread_local void* sel_buf = nullptr;
+    static thread_local size_t sel_bytes = 0;
+    static thread_local tm_allocator sel_alloc = {nullptr, nullptr, nullptr};
     const size_t need = kDescBytes + tmk::select_scratch_bytes(gw * gh);
     hipStream_t s = S(stream);
-    if (need > scratch_bytes) {
-        if (scratch) {
+    if (need > sel_bytes) {
+        if (sel_buf) {
             HIP_TRY(hipStreamSynchronize(s));
-            HIP_TRY(hipFree(scratch));
-            scratch = nullptr;
-            scratch_bytes = 0;
+            tmk::dev_free(sel_alloc, sel_buf, s);
+            sel_buf = nullptr;
+            sel_bytes = 0;
         }
-        HIP_TRY(hipMalloc(&scratch, need));
-        scratch_bytes = need;
+        sel_alloc = current_allocator();
+        HIP_TRY(tmk::dev_alloc(sel_alloc, &sel_buf, need, s));
+        sel_bytes = need;
     }
     tmk::SearchDesc sd;
     memset(&sd, 0, sizeof(sd));
@@ -796,10 +891,10 @@ TM_EXPORT tm_status tm_select(const float* sw, const float* s1, const int32_t* k
     d.mw = const_cast<float*>(sw);
     d.m1 = const_cast<float*>(s1);
     d.mk = const_cast<int32_t*>(k);
-    d.sel = reinterpret_cast<float*>(reinterpret_cast<uint8_t*>(scratch) + kDescBytes);
+    d.sel = reinterpret_cast<float*>(reinterpret_cast<uint8_t*>(sel_buf) + kDescBytes);
     d.cand = out;
     d.ncand = n_out;
-    tmk::PairDesc* dd = reinterpret_cast<tmk::PairDesc*>(scratch);
+    tmk::PairDesc* dd = reinterpret_cast<tmk::PairDesc*>(sel_buf);
     hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, d, dd);
     HIP_TRY(hipGetLastError());
     HIP_TRY(tmk::launch_select(sd, dd, 1, gw * gh, s));
@@ -823,7 +918,7 @@ TM_EXPORT tm_status tm_detect(const tm_model* m, tm_pyramid* p, const tm_search_
     const tmk::TabEntry* tab = nullptr;
     st = get_table(m, top, sp->theta_min_deg, g.step[top], g.K[top], g, s, &tab);
     if (st != TM_OK) return st;
-    tmk::SearchDesc sd = make_search(sp, g, top, p->precision, std::min(capacity, sp->max_matches));
+    tmk::SearchDesc sd = make_search(sp, g, top, p->precision, capacity);
     tmk::PairGeom pg = pair_geom(m, p, top, sp->step_x, sp->step_y, g.sigma_max);
     tmk::DensePlan plan = tmk::plan_dense(sd, &pg, 1);
     tmk::PairDesc d;
@@ -983,8 +1078,8 @@ TM_EXPORT tm_status tm_cont_line_search(const tm_model* m, tm_pyramid* p, int32_
     tm_status st = cont_prepare(m, p, level, tmk::line_search_scratch_bytes(n, n_alphas), S(stream), &dd,
                                 "tm_cont_line_search");
     if (st != TM_OK) return st;
-    double* scratch = reinterpret_cast<double*>(reinterpret_cast<uint8_t*>(p->ws.ptr) + kDescBytes);
-    HIP_TRY(tmk::launch_line_search(dd, 0, 1, level, p->precision, poses, dirs, n, alphas, n_alphas, scores, scratch,
+    double* ls_scratch = reinterpret_cast<double*>(reinterpret_cast<uint8_t*>(p->ws.ptr) + kDescBytes);
+    HIP_TRY(tmk::launch_line_search(dd, 0, 1, level, p->precision, poses, dirs, n, alphas, n_alphas, scores, ls_scratch,
                                     S(stream)));
     return TM_OK;
 }
@@ -1007,15 +1102,29 @@ struct tm_batch_s {
     hipGraphExec_t graph = nullptr;  // captured tm_batch_run, made by the first tm_batch_run_graph
     void* ls_buf = nullptr;          // line-search scratch of the continuous score
     size_t ls_bytes = 0;
+    tm_allocator alloc = {};         // allocator of the batch's memory
+    hipEvent_t last_run = nullptr;   // recorded after each run enqueued outside a capture
 };
+
+namespace {
+// Wait until the device has passed the batch's last run (before its graph is
+// replaced, its scratch reused by the tuner, or its memory freed).
+tm_status batch_wait(tm_batch* b)
+{
+    if (b->last_run) HIP_TRY(hipEventSynchronize(b->last_run));
+    return TM_OK;
+}
+}  // namespace
 
 TM_EXPORT void tm_batch_free(tm_batch* b)
 {
     if (!b) return;
+    (void)batch_wait(b);
     if (b->graph) (void)hipGraphExecDestroy(b->graph);
-    if (b->ls_buf) (void)hipFree(b->ls_buf);
+    tmk::dev_free(b->alloc, b->ls_buf, nullptr);
     for (tm_pyramid* p : b->pyrs) tm_pyramid_free(p);
-    if (b->scratch) (void)hipFree(b->scratch);
+    tmk::dev_free(b->alloc, b->scratch, nullptr);
+    if (b->last_run) (void)hipEventDestroy(b->last_run);
     delete b;
 }
 
@@ -1050,6 +1159,12 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
     hipStream_t s = S(stream);
     tm_batch* b = new (std::nothrow) tm_batch_s();
     if (!b) return fail(TM_ENOMEM, "tm_batch_create: host allocation");
+    b->alloc = current_allocator();
+    if (hipEventCreateWithFlags(&b->last_run, hipEventDisableTiming) != hipSuccess) {
+        b->last_run = nullptr;
+        tm_batch_free(b);
+        return fail(TM_EDEVICE, "tm_batch_create: hipEventCreate");
+    }
     b->n_models = n_models;
     b->n_images = n_images;
     b->npairs = n_models * n_images;
@@ -1057,14 +1172,14 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
     b->models.assign(models, models + n_models);
     for (int i = 0; i < n_images; ++i) {
         tm_pyramid* p = nullptr;
-        st = alloc_pyramid(widths[i], heights[i], pp, &p);
+        st = alloc_pyramid(widths[i], heights[i], pp, s, &p);
         if (st != TM_OK) {
             tm_batch_free(b);
             return st;
         }
         b->pyrs.push_back(p);
     }
-    b->sd = make_search(sp, g, top, pp->precision, std::min(capacity, sp->max_matches));
+    b->sd = make_search(sp, g, top, pp->precision, capacity);
     std::vector<tmk::PairGeom> pg(b->npairs);
     for (int i = 0; i < n_images; ++i)
         for (int j = 0; j < n_models; ++j)
@@ -1110,10 +1225,10 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
                                      refine, nullptr),
                         256);
     }
-    hipError_t e = hipMalloc(&b->scratch, off);
+    hipError_t e = tmk::dev_alloc(b->alloc, &b->scratch, off, s);
     if (e != hipSuccess) {
         tm_batch_free(b);
-        return hip_fail(e, "tm_batch_create: hipMalloc");
+        return hip_fail(e, "tm_batch_create: device allocation");
     }
     uint8_t* base = reinterpret_cast<uint8_t*>(b->scratch);
     b->d_pairs = reinterpret_cast<tmk::PairDesc*>(base + desc_off);
@@ -1195,7 +1310,9 @@ tm_status batch_enqueue(tm_batch* b, hipStream_t s, bool timed)
 TM_EXPORT tm_status tm_batch_run(tm_batch* b, void* stream)
 {
     if (!b) return fail(TM_EINVAL, "tm_batch_run: null batch");
-    return batch_enqueue(b, S(stream), true);
+    const tm_status st = batch_enqueue(b, S(stream), true);
+    if (st == TM_OK && !stream_capturing(S(stream))) HIP_TRY(hipEventRecord(b->last_run, S(stream)));
+    return st;
 }
 
 TM_EXPORT tm_status tm_batch_run_graph(tm_batch* b, void* stream)
@@ -1229,6 +1346,7 @@ TM_EXPORT tm_status tm_batch_run_graph(tm_batch* b, void* stream)
         if (st != TM_OK) return st;
     }
     HIP_TRY(hipGraphLaunch(b->graph, S(stream)));
+    if (!stream_capturing(S(stream))) HIP_TRY(hipEventRecord(b->last_run, S(stream)));
     return TM_OK;
 }
 
@@ -1244,6 +1362,8 @@ TM_EXPORT tm_status tm_batch_set_form(tm_batch* b, int32_t variant, int32_t wave
         return fail(TM_EINVAL, "tm_batch_set_form: variant %d with %d waves per chunk does not apply to this batch",
                     variant, waves);
     HIP_TRY(tmk::prepare_dense(b->sd, p));
+    tm_status st = batch_wait(b);  // a run of the old graph may still be in flight
+    if (st != TM_OK) return st;
     b->plan = p;
     if (b->graph) {  // captured with the old form
         (void)hipGraphExecDestroy(b->graph);
@@ -1272,6 +1392,9 @@ TM_EXPORT tm_status tm_batch_tune(tm_batch* b, int32_t iterations, void* stream,
         if (us_out) *us_out = 0.f;
         return TM_OK;  // the generic search has no forms to choose from
     }
+    // the tuner's launches reuse the batch's scratch: no earlier run may still use it
+    tm_status wst = batch_wait(b);
+    if (wst != TM_OK) return wst;
     HIP_TRY(tmk::launch_pyramids_batch(b->d_pb, b->d_fa, b->n_images, b->L, b->level_w[0], b->level_h[0],
                                        b->max_field_blocks, b->level_w, b->level_h,
                                        b->pyrs[0]->source == TM_PYR_GRADIENT, s));
@@ -1373,10 +1496,13 @@ TM_EXPORT tm_status tm_batch_cont_line_search(tm_batch* b, int32_t level, tm_con
         return fail(TM_EINVAL, "tm_batch_cont_line_search: too many evaluations");
     const size_t need = tmk::line_search_scratch_bytes(n, n_alphas);
     if (need > b->ls_bytes) {
-        if (b->ls_buf) HIP_TRY(hipFree(b->ls_buf));  // waits for earlier users
+        if (b->ls_buf) {
+            HIP_TRY(hipDeviceSynchronize());  // earlier line searches may still use the buffer
+            tmk::dev_free(b->alloc, b->ls_buf, S(stream));
+        }
         b->ls_buf = nullptr;
         b->ls_bytes = 0;
-        HIP_TRY(hipMalloc(&b->ls_buf, need));
+        HIP_TRY(tmk::dev_alloc(b->alloc, &b->ls_buf, need, S(stream)));
         b->ls_bytes = need;
     }
     HIP_TRY(tmk::launch_line_search(b->d_pairs, 1, b->npairs, level, b->sd.precision, poses, dirs, n, alphas,

@@ -7,6 +7,7 @@
 #include <hip/hip_fp16.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <vector>
 
 #include "../../include/tm.h"
@@ -44,9 +45,15 @@ struct Workspace {
     size_t bytes = 0;
 };
 
+// Device memory through the allocator a handle was created with (null
+// functions: hipMalloc / hipFree).
+hipError_t dev_alloc(const tm_allocator& a, void** p, size_t bytes, hipStream_t s);
+void dev_free(const tm_allocator& a, void* p, hipStream_t s);
+
 }  // namespace tmk
 
 struct tm_pyramid_s {
+    tm_allocator alloc = {};  // allocator of this pyramid's memory
     int L = 0;
     int precision = TM_FP32;
     int source = TM_PYR_GREY;
@@ -68,23 +75,27 @@ struct tm_model_level {
     double2* dir = nullptr;          // device, n FP64 unit directions g/|g|
 };
 
-struct tm_model_table_cache {
+// One rotated table of a model level for one angle and scale grid.
+struct tm_rot_table {
     int level = -1;
     double theta_min = 0, step = 0;
     int K = 0;
     int S = 0;
     double sigma_min = 0, sigma_step = 0;
-    tmk::TabEntry* tab = nullptr;  // device, K * n_pad entries
-    size_t cap = 0;               // entries allocated
+    tmk::TabEntry* tab = nullptr;  // device, K * S * n_pad entries
+    hipEvent_t ready = nullptr;    // recorded after the table's kernel
+    hipStream_t stream = nullptr;  // stream the table was built on
 };
 
 struct tm_model_s {
+    tm_allocator alloc = {};  // allocator of this model's memory
     int L = 0;
     float tau = 0.f;
     int source = TM_PYR_GREY;
     int dev = 0;
     tm_model_level lv[tmk::kMaxLevels];
-    tm_model_table_cache cache;
+    std::mutex mu;                       // guards `tables`
+    std::vector<tm_rot_table> tables;  // one per (level, grid), kept until the model is freed
 };
 
 namespace tmk {
@@ -189,7 +200,9 @@ struct SearchDesc {
     int full, win, sx, sy, precision;
     int vote;                   // tm_vote: which taps of a window vote
     float min_score;
-    int max_cand, capacity;
+    int max_cand;               // candidates kept after the searched level
+    int capacity;               // poses the caller's result buffer holds
+    int max_matches;            // final matches kept (the method's cap)
     int S;                      // scales (1: rigid)
     double sigma_min, sigma_step;
 };

@@ -25,9 +25,19 @@ MAX_LEVELS = 8
 
 
 class TMError(RuntimeError):
-    def __init__(self, status: int, msg: str):
+    def __init__(self, status: int, msg: str, poses=None):
         super().__init__(f"tm status {status}: {msg}")
         self.status = status
+        self.poses = poses  # TM_ECAPACITY: the truncated result (the best `capacity` by key)
+
+
+class AllocatorC(ctypes.Structure):
+    pass
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+AllocatorC._fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", ctypes.c_void_p)]
 
 
 class PyrParamsC(ctypes.Structure):
@@ -95,6 +105,7 @@ def lib():
                                     _vp],
             "tm_batch_pyramid": [_vp, _i32, ctypes.POINTER(_vp)],
             "tm_timing_read": [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32)],
+            "tm_set_allocator": [ctypes.POINTER(AllocatorC)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -314,14 +325,25 @@ def detect_async(model: Model, pyr: Pyramid, sp: SearchParams, out: torch.Tensor
                            _vp(n_out.data_ptr()), _vp(_stream(stream))))
 
 
+def check_count(n: int, capacity: int, poses: np.ndarray | None = None) -> np.ndarray | None:
+    """TM_ECAPACITY when a call produced more poses than its buffer holds
+    (the count the library wrote exceeds the capacity); `poses` (the
+    truncated result) rides on the error."""
+    if n > capacity:
+        raise TMError(TM_ECAPACITY, f"{n} poses found, capacity {capacity}: the best {capacity} by key were kept",
+                      poses)
+    return poses
+
+
 def detect(model: Model, pyr: Pyramid, sp: SearchParams, capacity: int | None = None, stream=None) -> np.ndarray:
-    """Detections at level 0 as a numpy structured array (POSE_DTYPE)."""
+    """Detections at level 0 as a numpy structured array (POSE_DTYPE);
+    TMError(TM_ECAPACITY) if there were more than `capacity`."""
     cap = capacity or sp.max_matches
     out = torch.empty((cap, POSE_WORDS), dtype=torch.int32, device="cuda")
     n = torch.zeros(1, dtype=torch.int32, device="cuda")
     detect_async(model, pyr, sp, out, n, stream)
     m = int(n.item())
-    return poses_to_numpy(out, m)
+    return check_count(m, cap, poses_to_numpy(out, min(m, cap)))
 
 
 def refine(model: Model, pyr: Pyramid, sp: SearchParams, poses: np.ndarray, from_level: int,
@@ -407,10 +429,17 @@ class Batch:
         return _ascend(_ContBatch(self), _cont_poses(poses, pairs), steps, level, step_xy, step_theta, decay)
 
     def results(self):
-        """Per pair, the detections as a numpy structured array (waits for the device)."""
+        """Per pair, the detections as a numpy structured array (waits for the
+        device); TMError(TM_ECAPACITY), with the truncated lists, if a pair had
+        more matches than the capacity."""
         n = self.n_out.cpu().numpy()
         o = self.out.cpu().numpy()
-        return [o[p].view(POSE_DTYPE).reshape(-1)[:n[p]] for p in range(len(n))]
+        res = [o[p].view(POSE_DTYPE).reshape(-1)[:min(int(n[p]), self.capacity)] for p in range(len(n))]
+        over = [p for p in range(len(n)) if n[p] > self.capacity]
+        if over:
+            raise TMError(TM_ECAPACITY, f"pairs {over[:8]} found more than {self.capacity} matches: the best "
+                                        f"{self.capacity} by key were kept", res)
+        return res
 
     def free(self):
         if self._h:
@@ -566,6 +595,34 @@ def refine_continuous(model: Model, pyr: Pyramid, poses: torch.Tensor, steps: in
     down.  Step lengths shrink by `decay` per step.  Returns (poses, scores),
     the scores those of the FP64 line search (FP32-rounded)."""
     return _ascend(_ContSingle(model, pyr), _cont_poses(poses), steps, level, step_xy, step_theta, decay)
+
+
+_allocator_keep = None  # the registered callbacks stay referenced while the library may call them
+
+
+def _torch_alloc(nbytes, ctx, stream):
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+    except Exception:  # out of memory: the library returns TM_ENOMEM
+        return None
+
+
+def _torch_free(ptr, ctx, stream):
+    torch.cuda.caching_allocator_delete(int(ptr))
+
+
+def use_torch_allocator(on: bool = True):
+    """Handles created from now on take their device memory from torch's
+    caching allocator (on=False: back to hipMalloc / hipFree).  Handles keep
+    the allocator they were created with."""
+    global _allocator_keep
+    if on:
+        a = AllocatorC(_ALLOC_FN(_torch_alloc), _FREE_FN(_torch_free), None)
+        _check(lib().tm_set_allocator(ctypes.byref(a)))
+        # the old callbacks stay alive too: handles made with them free through them
+        _allocator_keep = (a, _allocator_keep)
+    else:
+        _check(lib().tm_set_allocator(None))
 
 
 def timing_enable(on: bool = True):

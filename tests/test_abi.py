@@ -137,3 +137,26 @@ def test_search_params_validation(L):
     assert L.tm_timing_enable(0) == tm.TM_OK
     ms, n = C.c_double(), C.c_int32()
     assert L.tm_timing_read(C.byref(ms), C.byref(n)) == tm.TM_OK and n.value == 0
+
+
+def test_allocator_registration_is_validated(L):
+    from paper_2112_05576_amd import tm
+
+    half = tm.AllocatorC(tm._ALLOC_FN(lambda n, c, s: None), tm._FREE_FN(), None)  # alloc without free
+    assert L.tm_set_allocator(ctypes.byref(half)) == tm.TM_EINVAL
+    assert b"alloc and free" in L.tm_last_error()
+    assert L.tm_set_allocator(None) == tm.TM_OK  # back to hipMalloc / hipFree
+
+
+def test_capacity_count_maps_to_ecapacity():
+    """A count above the caller's capacity is the TM_ECAPACITY case: the
+    binding raises it with the truncated result attached."""
+    import numpy as np
+
+    from paper_2112_05576_amd import tm
+
+    poses = np.zeros(2, tm.POSE_DTYPE)
+    assert tm.check_count(2, 2, poses) is poses
+    with pytest.raises(tm.TMError) as e:
+        tm.check_count(5, 2, poses)
+    assert e.value.status == tm.TM_ECAPACITY and e.value.poses is poses

@@ -1,0 +1,139 @@
+"""The C-ABI conventions on the GPU: results that do not fit the caller's
+capacity (the TM_ECAPACITY case: the count says how many there were, the
+best `capacity` by key are written), device memory from a registered
+allocator (torch's caching allocator), and rotated tables cached per angle
+grid on one model used with several grids in turn."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def case(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2112_05576_amd as P
+
+    P.lib()
+    return P
+
+
+def _c2(index=0):
+    import paper_2112_05576_amd as P
+
+    sc = synth.scene_for_config(2, index)
+    cfg = sc.config
+    L = cfg["levels"]
+    return P, sc, cfg, L
+
+
+def test_detect_capacity_overflow():
+    P, sc, cfg, L = _c2(0)
+    case("capacity overflow C2 image 0")
+    gm = P.Model(sc.model, L, cfg["tau_m"])
+    pyr = P.Pyramid(sc.image, L, cfg["tau_s"])
+    sp = P.SearchParams(theta_step_top=cfg["theta_step_top"])
+    full = P.detect(gm, pyr, sp)
+    assert len(full) >= 2, len(full)
+    for cap in (1, len(full) - 1):
+        with pytest.raises(P.TMError) as e:
+            P.detect(gm, pyr, sp, capacity=cap)
+        assert e.value.status == P.TM_ECAPACITY
+        # deterministic truncation: the best `cap` of the full result, bit for bit
+        assert e.value.poses.tobytes() == full[:cap].tobytes()
+    # the raw count: every match is counted, only `cap` are written
+    out = torch.full((3, P.tm.POSE_WORDS), -7, dtype=torch.int32, device="cuda")
+    n = torch.zeros(1, dtype=torch.int32, device="cuda")
+    P.detect_async(gm, pyr, sp, out[:1], n)
+    assert int(n.item()) == len(full)
+    assert int(out[1, 0].item()) == -7  # nothing written past the capacity
+    # exactly at the capacity: no error
+    assert P.detect(gm, pyr, sp, capacity=len(full)).tobytes() == full.tobytes()
+    # batches: the same per pair
+    imgs = [torch.from_numpy(synth.scene_for_config(2, i).image).cuda() for i in range(3)]
+    b = P.Batch([gm], imgs, L, cfg["tau_s"], sp, capacity=1)
+    b.run()
+    with pytest.raises(P.TMError) as e:
+        b.results()
+    assert e.value.status == P.TM_ECAPACITY
+    for i, im in enumerate(imgs):
+        pyr.update(im)
+        ref = P.detect(gm, pyr, sp)
+        assert e.value.poses[i].tobytes() == ref[:1].tobytes()
+
+
+def test_torch_allocator():
+    P, sc, cfg, L = _c2(1)
+    case("torch caching allocator")
+    sp = P.SearchParams(theta_step_top=cfg["theta_step_top"])
+    gm0 = P.Model(sc.model, L, cfg["tau_m"])
+    pyr0 = P.Pyramid(sc.image, L, cfg["tau_s"])
+    ref = P.detect(gm0, pyr0, sp)
+    img = torch.from_numpy(sc.image).cuda()
+    torch.cuda.synchronize()
+    P.use_torch_allocator(True)
+    try:
+        a0 = torch.cuda.memory_allocated()
+        gm = P.Model(sc.model, L, cfg["tau_m"])
+        a1 = torch.cuda.memory_allocated()
+        pyr = P.Pyramid(img, L, cfg["tau_s"])
+        a2 = torch.cuda.memory_allocated()
+        # the handles' memory is torch's: the model's points, the pyramid's levels
+        assert a1 > a0 and a2 - a1 >= 640 * 480 * 9, (a0, a1, a2)
+        got = P.detect(gm, pyr, sp)
+        assert got.tobytes() == ref.tobytes()
+        b = P.Batch([gm], [img], L, cfg["tau_s"], sp)
+        b.run(graph=True)
+        assert b.results()[0].tobytes() == ref.tobytes()
+        torch.cuda.synchronize()
+        held = torch.cuda.memory_allocated()
+        b.free()
+        pyr.free()
+        gm.free()
+        assert torch.cuda.memory_allocated() < held
+        assert torch.cuda.memory_allocated() <= a0 + 4096
+    finally:
+        P.use_torch_allocator(False)
+    # handles made after switching back use hipMalloc again
+    a3 = torch.cuda.memory_allocated()
+    pyr2 = P.Pyramid(img, L, cfg["tau_s"])
+    assert torch.cuda.memory_allocated() == a3
+    assert P.detect(gm0, pyr2, sp).tobytes() == ref.tobytes()
+
+
+def test_tables_cached_per_grid():
+    """One model searched with two angle grids in turn, and on two streams at
+    once: every result equals that of a fresh model with one grid."""
+    P, sc, cfg, L = _c2(2)
+    case("rotated tables per grid")
+    gm = P.Model(sc.model, L, cfg["tau_m"])
+    pyr = P.Pyramid(sc.image, L, cfg["tau_s"])
+    pyr_b = P.Pyramid(sc.image, L, cfg["tau_s"])
+    grids = [P.SearchParams(theta_step_top=1.0), P.SearchParams(theta_step_top=2.0),
+             P.SearchParams(theta_step_top=1.0, theta_min=-30.0, theta_range=60.0)]
+    ref = []
+    for sp in grids:
+        fresh = P.Model(sc.model, L, cfg["tau_m"])
+        ref.append(P.detect(fresh, pyr, sp))
+    for rep in range(2):
+        for sp, r in zip(grids, ref):
+            assert P.detect(gm, pyr, sp).tobytes() == r.tobytes()
+    # two streams, two grids, one model
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = [torch.empty((8, P.tm.POSE_WORDS), dtype=torch.int32, device="cuda") for _ in range(2)]
+    ns = [torch.zeros(1, dtype=torch.int32, device="cuda") for _ in range(2)]
+    for it in range(4):
+        P.detect_async(gm, pyr, grids[it % 2], outs[0], ns[0], stream=s1)
+        P.detect_async(gm, pyr_b, grids[(it + 1) % 2], outs[1], ns[1], stream=s2)
+    torch.cuda.synchronize()
+    got0 = P.poses_to_numpy(outs[0], int(ns[0].item()))
+    got1 = P.poses_to_numpy(outs[1], int(ns[1].item()))
+    assert got0.tobytes() == ref[1].tobytes() and got1.tobytes() == ref[0].tobytes()
