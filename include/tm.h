@@ -242,6 +242,28 @@ tm_status tm_select(const float* sw_dev, const float* s1_dev, const int32_t* k_d
 tm_status tm_detect(const tm_model* model, tm_pyramid* pyr, const tm_search_params* params,
                     tm_pose* out_dev, int32_t capacity, int32_t* n_out_dev, void* stream);
 
+/* Bytes of the static device array behind tm_detect_static (one per GPU). */
+#define TM_STATIC_SCRATCH_BYTES (64u << 20)
+
+/* tm_detect for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * same detection, with the same results as tm_detect, but every scratch
+ * buffer (the pair descriptor, the top level's rotated table, rebuilt on
+ * each call, the search partials and score map, the selection and
+ * refinement scratch) lives in a static device array of
+ * TM_STATIC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends, instead of the pyramid's workspace and the model's
+ * table cache.  Allocates nothing (no hipMalloc, no registered allocator)
+ * and reads the model and pyramid without changing them.  Returns
+ * TM_ECAPACITY, with nothing enqueued, if the detection needs more than
+ * TM_STATIC_SCRATCH_BYTES (large top levels, many angles); otherwise the
+ * arguments and the result count are those of tm_detect.  Every call on one
+ * GPU shares that GPU's array, which keeps the last call's contents: calls
+ * that overlap on one GPU (on other streams or threads) race, so serialise
+ * them. */
+tm_status tm_detect_static(const tm_model* model, const tm_pyramid* pyr, const tm_search_params* params,
+                           tm_pose* out_dev, int32_t capacity, int32_t* n_out_dev, void* stream);
+
 /* Coarse-to-fine refinement of n poses of level `from_level` (x, y, k on
  * that level's grid) down to level 0, in place (Sec. II para. 2: the search
  * starts with the pyramid's top image and is carried down to the full image;

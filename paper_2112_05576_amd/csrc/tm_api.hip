@@ -949,6 +949,88 @@ TM_EXPORT tm_status tm_detect(const tm_model* m, tm_pyramid* p, const tm_search_
     return TM_OK;
 }
 
+// ---------------------------------------------------------------- no allocation
+// tm_detect_static: every scratch buffer of a detection in this array, one
+// copy per GPU, held until the process ends.  Host code never uses the name
+// (on the host it is a stand-in, not a device address): each device's
+// address comes from hipGetSymbolAddress, once, and is kept in g_static_ptr.
+static __device__ __align__(256) unsigned char scratch[TM_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};
+
+tm_status static_scratch(void** out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(TM_EDEVICE, "tm_detect_static: device %d out of range", dev);
+    std::lock_guard<std::mutex> g(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                     "tm_detect_static: hipGetSymbolAddress");
+        g_static_ptr[dev] = ptr;
+    }
+    *out = g_static_ptr[dev];
+    return TM_OK;
+}
+}  // namespace
+
+TM_EXPORT tm_status tm_detect_static(const tm_model* m, const tm_pyramid* p, const tm_search_params* sp,
+                                     tm_pose* out, int32_t capacity, int32_t* n_out, void* stream)
+{
+    tm_status st = check_pair(m, p, "tm_detect_static");
+    if (st != TM_OK) return st;
+    st = check_search(sp, "tm_detect_static");
+    if (st != TM_OK) return st;
+    if (!out || !n_out) return fail(TM_EINVAL, "tm_detect_static: null output");
+    if (capacity < 1) return fail(TM_EINVAL, "tm_detect_static: capacity < 1");
+    Grid g;
+    st = make_grid(sp, p->L, &g);
+    if (st != TM_OK) return st;
+    hipStream_t s = S(stream);
+    const int top = p->L - 1;
+    const tm_model_level& mt = m->lv[top];
+    if (scaled_rad(mt, g.sigma_max) > 32000) return fail(TM_EINVAL, "tm_detect_static: model too large for the scale range");
+    tmk::SearchDesc sd = make_search(sp, g, top, p->precision, capacity);
+    tmk::PairGeom pg = pair_geom(m, p, top, sp->step_x, sp->step_y, g.sigma_max);
+    tmk::DensePlan plan = tmk::plan_dense(sd, &pg, 1);
+    tmk::PairDesc d;
+    memset(&d, 0, sizeof(d));
+    const bool refine = p->L > 1;
+    // layout: descriptor, rotated table of the top level, pair scratch
+    const size_t tab_bytes = align_up((size_t)g.K[top] * g.S * mt.n_pad * sizeof(tmk::TabEntry), 256);
+    const size_t need =
+        kDescBytes + tab_bytes + pair_scratch(&d, m, pg, plan, p->L, sp->max_candidates, true, true, refine, nullptr);
+    if (need > (size_t)TM_STATIC_SCRATCH_BYTES)
+        return fail(TM_ECAPACITY, "tm_detect_static: the detection needs %zu bytes of scratch, the static array "
+                                  "holds %zu", need, (size_t)TM_STATIC_SCRATCH_BYTES);
+    void* base = nullptr;
+    st = static_scratch(&base);
+    if (st != TM_OK) return st;
+    uint8_t* b = reinterpret_cast<uint8_t*>(base);
+    tmk::TabEntry* tab = reinterpret_cast<tmk::TabEntry*>(b + kDescBytes);
+    HIP_TRY(tmk::launch_tables(mt.pts, mt.n, mt.n_pad, sp->theta_min_deg, g.step[top], g.K[top], g.sigma_min,
+                               g.sigma_step, g.S, tab, s));
+    pair_static(&d, m, p, tab, top, pg, plan, default_dmin(m, sp), sp->neighbourhood, g.sigma_max);
+    pair_scratch(&d, m, pg, plan, p->L, sp->max_candidates, true, true, refine, b + kDescBytes + tab_bytes);
+    tmk::PairDesc* dd = reinterpret_cast<tmk::PairDesc*>(b);
+    hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, d, dd);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(tmk::launch_dense(sd, plan, dd, 1, s));
+    HIP_TRY(tmk::launch_select(sd, dd, 1, pg.gw * pg.gh, s));
+    if (refine) {
+        const tmk::RefinePlan rp =
+            refine_plan(&m, 1, p->L, sp->neighbourhood, p->precision, sp->max_candidates, g.sigma_max);
+        HIP_TRY(tmk::launch_refine(sd, dd, 1, top, rp, s, false));
+    }
+    HIP_TRY(tmk::launch_final(sd, dd, 1, s, out, n_out, refine ? top % 2 : -1));
+    return TM_OK;
+}
+
 TM_EXPORT tm_status tm_timing_enable(int32_t on)
 {
     Timing& t = timing();

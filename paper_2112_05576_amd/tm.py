@@ -80,6 +80,7 @@ def lib():
             "tm_select": [_vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, ctypes.c_float, ctypes.c_float, _vp, _i32,
                           _vp, _vp],
             "tm_detect": [_vp, _vp, ctypes.POINTER(SearchParamsC), _vp, _i32, _vp, _vp],
+            "tm_detect_static": [_vp, _vp, ctypes.POINTER(SearchParamsC), _vp, _i32, _vp, _vp],
             "tm_refine": [_vp, _vp, ctypes.POINTER(SearchParamsC), _i32, _vp, _i32, _vp],
             "tm_model_level_info": [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
             "tm_model_points": [_vp, _i32, _vp, _vp, _vp],
@@ -333,6 +334,15 @@ def check_count(n: int, capacity: int, poses: np.ndarray | None = None) -> np.nd
         raise TMError(TM_ECAPACITY, f"{n} poses found, capacity {capacity}: the best {capacity} by key were kept",
                       poses)
     return poses
+
+
+def detect_static_async(model: Model, pyr: Pyramid, sp: SearchParams, out: torch.Tensor, n_out: torch.Tensor,
+                        stream=None):
+    """As detect_async, through tm_detect_static: the detection's scratch
+    in the library's static device array, nothing allocated."""
+    c = sp.c()
+    _check(lib().tm_detect_static(model.handle, pyr.handle, ctypes.byref(c), _vp(out.data_ptr()), out.shape[0],
+                                  _vp(n_out.data_ptr()), _vp(_stream(stream))))
 
 
 def detect(model: Model, pyr: Pyramid, sp: SearchParams, capacity: int | None = None, stream=None) -> np.ndarray:
