@@ -169,7 +169,7 @@ __global__ __launch_bounds__(256) void k_grad_level(FieldsArg one, const FieldsA
 
 // Unit gradient direction of every pixel of every level: (gx, gy)/|g| formed
 // in FP64 and rounded once to the storage precision where gx^2 + gy^2 > T2,
-// (0, 0) elsewhere.  Each thread covers 4 consecutive pixels of a row; their
+// (0, 0) elsewhere (an FP16 pyramid also gets the FP32 rounding, its twin).  Each thread covers 4 consecutive pixels of a row; their
 // 3 x 6 neighbourhood (or their 4 gradient pairs) is loaded at once, before
 // any of the four is computed, so a thread waits for memory once.
 template <bool BATCH>
@@ -232,6 +232,8 @@ __global__ __launch_bounds__(256) void k_sobel_fields(FieldsArg one, const Field
         const size_t o = (size_t)y * W + x;
         if (precision == TM_FP16) {
             reinterpret_cast<__half2*>(a.field[l])[o] = __floats2half2_rn((float)dx, (float)dy);
+            // the FP32 twin the decisions after the FP16 search read
+            if (a.field32[l]) reinterpret_cast<float2*>(a.field32[l])[o] = make_float2((float)dx, (float)dy);
         } else {
             reinterpret_cast<float2*>(a.field[l])[o] = make_float2((float)dx, (float)dy);
         }
@@ -318,6 +320,7 @@ FieldsArg fields_arg(const PyrLevel* lv, int L, long long T2, int precision)
         a.img[l] = lv[l].img;
         a.grad[l] = lv[l].grad;
         a.field[l] = lv[l].field;
+        a.field32[l] = precision == TM_FP16 ? lv[l].field32 : nullptr;
         a.w[l] = lv[l].w;
         a.h[l] = lv[l].h;
         a.block0[l] = blocks;

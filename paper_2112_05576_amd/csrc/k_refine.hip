@@ -43,11 +43,9 @@ struct LevelArgs {
 };
 // (the window reading, tm_vote, is the kernels' VOTE template argument)
 
-// Field element as stored (FP32 pair, or the half2 bits), the rotated model
-// direction in the form its product takes (FP32 pair, or half2), and the
-// product: FP32 products and sum, or v_dot2_f32_f16 (FP32 result) as in the
-// FP16 search.
-typedef _Float16 rh2_t __attribute__((ext_vector_type(2)));
+// Field element (an FP32 pair), the rotated model direction in the form its
+// product takes, and the product (FP32 products and sum).  The refinement
+// always reads FP32 fields: an FP16 pyramid keeps an FP32 twin for it.
 template <int PREC>
 struct Raw;
 template <>
@@ -59,24 +57,6 @@ struct Raw<TM_FP32> {
     static __device__ __forceinline__ R dir(double rx, double ry) { return make_float2((float)rx, (float)ry); }
     static __device__ __forceinline__ float dot(R r, T g) { return r.x * g.x + r.y * g.y; }
     static __device__ __forceinline__ bool edge(T g) { return g.x != 0.0f || g.y != 0.0f; }
-};
-template <>
-struct Raw<TM_FP16> {
-    using T = uint32_t;
-    using R = uint32_t;
-    static __device__ __forceinline__ T zero() { return 0u; }
-    static __device__ __forceinline__ T load(const void* f, size_t o) { return reinterpret_cast<const uint32_t*>(f)[o]; }
-    static __device__ __forceinline__ R dir(double rx, double ry)
-    {
-        const __half2 h = __floats2half2_rn((float)rx, (float)ry);
-        return __builtin_bit_cast(uint32_t, h);
-    }
-    static __device__ __forceinline__ float dot(R r, T g)
-    {
-        return __builtin_amdgcn_fdot2(__builtin_bit_cast(rh2_t, r), __builtin_bit_cast(rh2_t, g), 0.0f, false);
-    }
-    // non-edges are stored as the half2 (+0, +0), bit pattern 0
-    static __device__ __forceinline__ bool edge(T g) { return g != 0u; }
 };
 
 // The 9 windowed votes and 9 centre votes of one point from the 5x5 block of
@@ -437,9 +417,7 @@ hipError_t prepare_refine()
     static bool done = false;
     if (done) return hipSuccess;
     const void* k[] = {reinterpret_cast<const void*>(&k_refine_tile<TM_FP32, 0>),
-                       reinterpret_cast<const void*>(&k_refine_tile<TM_FP16, 0>),
-                       reinterpret_cast<const void*>(&k_refine_tile<TM_FP32, 1>),
-                       reinterpret_cast<const void*>(&k_refine_tile<TM_FP16, 1>)};
+                       reinterpret_cast<const void*>(&k_refine_tile<TM_FP32, 1>)};
     for (const void* f : k) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileMax);
         if (e != hipSuccess) return e;
@@ -453,21 +431,16 @@ template <int VOTE>
 void launch_level_kernels(const SearchDesc& s, const PairDesc* d, int npairs, const RefinePlan& rp, int l,
                           const LevelArgs& a, hipStream_t st)
 {
+    // the descriptors' fields are FP32 (an FP16 pyramid's twin): the
+    // refinement's picks are decisions, taken at FP32 accuracy
     if (!rp.staged || rp.gather[l]) {
         dim3 grid((unsigned)(s.max_cand * 3), npairs);
-        if (s.precision == TM_FP16)
-            hipLaunchKernelGGL((k_refine_level<TM_FP16, VOTE>), grid, dim3(kThreads), 0, st, a, d);
-        else
-            hipLaunchKernelGGL((k_refine_level<TM_FP32, VOTE>), grid, dim3(kThreads), 0, st, a, d);
+        hipLaunchKernelGGL((k_refine_level<TM_FP32, VOTE>), grid, dim3(kThreads), 0, st, a, d);
     }
     if (rp.staged && rp.tile_bytes[l] > 0) {
         dim3 grid((unsigned)s.max_cand, npairs);
-        if (s.precision == TM_FP16)
-            hipLaunchKernelGGL((k_refine_tile<TM_FP16, VOTE>), grid, dim3(kThreads * kTileGroups), rp.tile_bytes[l],
-                               st, a, d);
-        else
-            hipLaunchKernelGGL((k_refine_tile<TM_FP32, VOTE>), grid, dim3(kThreads * kTileGroups), rp.tile_bytes[l],
-                               st, a, d);
+        hipLaunchKernelGGL((k_refine_tile<TM_FP32, VOTE>), grid, dim3(kThreads * kTileGroups), rp.tile_bytes[l], st,
+                           a, d);
     }
 }
 }  // namespace

@@ -114,7 +114,10 @@ struct Px<TM_FP32> {
     using T = float2;
     static __device__ __forceinline__ T zero() { return make_float2(0.f, 0.f); }
     static __device__ __forceinline__ T load(const void* f, size_t o) { return reinterpret_cast<const float2*>(f)[o]; }
-    static __device__ __forceinline__ float dot(const TabEntry& e, T g) { return e.rx * g.x + e.ry * g.y; }
+    // one product and one fused multiply-add, written out so that every kernel
+    // that scores in FP32 (the searches and the re-scoring of an FP16 search)
+    // rounds it identically
+    static __device__ __forceinline__ float dot(const TabEntry& e, T g) { return __builtin_fmaf(e.ry, g.y, e.rx * g.x); }
     // on the edge set: the field and the tile padding hold non-edges as (+0, +0)
     static __device__ __forceinline__ bool edge(T g) { return (__float_as_uint(g.x) | __float_as_uint(g.y)) != 0u; }
     template <bool ASM>
@@ -244,7 +247,7 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc*
     const int tid = bx % n_tiles;
     const int U0 = (tid % P.tiles_x) * TW, V0 = (tid / P.tiles_x) * TH;
     const int W = P.W[a.level], H = P.H[a.level];
-    const void* field = P.field[a.level];
+    const void* field = P.sfield;
     const int halo = P.rad + 1;
     const int LR = TH + 2 * halo;
     const int fc = TW + 2 * halo;
@@ -278,12 +281,17 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc*
     const int n_pad = P.n_pad;
     const float n_f = (float)P.n[a.level];
 
-    float bw[R], b1[R];
+    // per row: the best angle by the key and, in FP16, the best S_w over the
+    // other angles (b2), which tells the certification of the FP16 search
+    // whether another angle could win in FP32
+    constexpr bool SECOND = PREC == TM_FP16;
+    float bw[R], b1[R], b2[R];
     int bk[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         bw[r] = -INFINITY;
         b1[r] = -INFINITY;
+        b2[r] = -INFINITY;
         bk[r] = -1;
     }
     const int k0 = chunk * a.A, k1 = min(a.K, k0 + a.A);
@@ -408,19 +416,24 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc*
         for (int r = 0; r < R; ++r) {
             const float sw = tw[r] / n_f, s1 = t1[r] / n_f;
             if (sw > bw[r] || (sw == bw[r] && s1 > b1[r])) {
+                if constexpr (SECOND) b2[r] = bw[r];  // >= every earlier other angle's S_w
                 bw[r] = sw;
                 b1[r] = s1;
                 bk[r] = k;
+            } else if constexpr (SECOND) {
+                b2[r] = fmaxf(b2[r], sw);
             }
         }
     }
 
-    // combine the WA waves that share this tile, in key order
+    // combine the WA waves that share this tile, in key order (the second
+    // best: the larger of the kept one's second best and the other's best)
     __syncthreads();
     const int npos = TH * TW;
     float* cw = reinterpret_cast<float*>(smem);
     float* c1 = cw + a.WA * npos;
     int* ck = reinterpret_cast<int*>(c1 + a.WA * npos);
+    float* c2 = reinterpret_cast<float*>(ck + a.WA * npos);
     if (li >= 1 && li <= G - 2) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -428,6 +441,7 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc*
             cw[idx] = bw[r];
             c1[idx] = b1[r];
             ck[idx] = bk[r];
+            if constexpr (SECOND) c2[idx] = b2[r];
         }
     }
     __syncthreads();
@@ -435,20 +449,24 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc*
         const int pv = p / TW, pu = p - pv * TW;
         const int X = tr ? V0 + pv : U0 + pu, Y = tr ? U0 + pu : V0 + pv;
         if (X >= W || Y >= H) continue;
-        float w0 = cw[p], s0 = c1[p];
+        float w0 = cw[p], s0 = c1[p], q0 = SECOND ? c2[p] : 0.f;
         int kk = ck[p];
         for (int w = 1; w < a.WA; ++w) {
             const int q = w * npos + p;
             if (key_better(cw[q], c1[q], 0, 0, ck[q], w0, s0, 0, 0, kk)) {
+                if constexpr (SECOND) q0 = fmaxf(c2[q], w0);
                 w0 = cw[q];
                 s0 = c1[q];
                 kk = ck[q];
+            } else if constexpr (SECOND) {
+                q0 = fmaxf(q0, cw[q]);
             }
         }
         const size_t o = ((size_t)chunk * H + Y) * W + X;
         P.pw[o] = w0;
         P.p1[o] = s0;
         P.pk[o] = kk;
+        if constexpr (SECOND) P.p2[o] = q0;
     }
 }
 
@@ -470,7 +488,7 @@ __global__ __launch_bounds__(256) void k_pad_field(int level, const PairDesc* __
     const int yy = idx / P.pW, xx = idx - yy * P.pW;
     const int x = xx - P.pad, y = yy - P.pad, W = P.W[level], H = P.H[level];
     T v = Px<PREC>::zero();
-    if (x >= 0 && x < W && y >= 0 && y < H) v = Px<PREC>::load(P.field[level], (size_t)y * W + x);
+    if (x >= 0 && x < W && y >= 0 && y < H) v = Px<PREC>::load(P.sfield, (size_t)y * W + x);
     reinterpret_cast<T*>(P.pfield)[idx] = v;
 }
 
@@ -505,7 +523,8 @@ __global__ __launch_bounds__(256) void k_dense_generic(GenericArgs a, const Pair
         else
             return d;
     };
-    float bw = -INFINITY, b1 = -INFINITY;
+    constexpr bool SECOND = PREC == TM_FP16;  // as in k_dense_fast
+    float bw = -INFINITY, b1 = -INFINITY, b2 = -INFINITY;
     int bk = -1;
     const int k0 = chunk * a.A, k1 = min(a.K, k0 + a.A);
     for (int k = k0; k < k1; ++k) {
@@ -558,15 +577,19 @@ __global__ __launch_bounds__(256) void k_dense_generic(GenericArgs a, const Pair
         }
         const float sw = tw / n_f, s1 = t1 / n_f;
         if (sw > bw || (sw == bw && s1 > b1)) {
+            if constexpr (SECOND) b2 = bw;
             bw = sw;
             b1 = s1;
             bk = k;
+        } else if constexpr (SECOND) {
+            b2 = fmaxf(b2, sw);
         }
     }
     const size_t o = ((size_t)chunk * gh + gy) * gw + gx;
     P.pw[o] = bw;
     P.p1[o] = b1;
     P.pk[o] = bk;
+    if constexpr (SECOND) P.p2[o] = b2;
 }
 
 // Best angle per translation over the C chunk partials, in key order.  A
@@ -681,6 +704,298 @@ __global__ __launch_bounds__(256) void k_sparse(const void* __restrict__ field, 
     }
 }
 
+// ---------------------------------------------------------------- certification of an FP16 search
+//
+// An FP16 search scores every pose with half2 directions and FP32 sums.  Its
+// score of a pose differs from the FP32 search's (the same sums over the FP32
+// directions) by at most E(n), n the level's model points (cert_eps below).
+// The selection decides on the map: the best angle per translation, which
+// translations are strict local maxima above the floor, their key order.
+// These decisions are made identical to the ones taken on the FP32 map, with
+// M the FP16 map value and hi = M + E, lo = M - E bounding the FP32 one:
+//  * u may be a candidate in FP32 iff hi(u) >= min_score and no grid
+//    neighbour v has lo(v) > hi(u) (such a v beats u in FP32 as well);
+//  * every such u, and every neighbour v of one with hi(v) >= lo(u), is given
+//    its FP32 value: the FP32 search's own arithmetic (Px<TM_FP32>::dot,
+//    blocks of 32 points, the same divisions and key) over the angles that
+//    can hold the FP32 best, i.e. the angle chunks whose FP16 best reaches
+//    M - 2E; when that is a single chunk whose other angles all stay below
+//    M - 2E (its second best), the FP16 best angle alone is scored;
+//  * every other translation keeps its FP16 value: it is below the floor in
+//    both maps, or strictly beaten by a neighbour in both, and next to a
+//    possible candidate it is strictly below that candidate in both.
+// The selection on the patched map therefore returns the FP32 search's
+// candidates with their FP32 values, and a detection continues exactly as an
+// FP32 one does (the refinement reads the FP32 twin).
+//
+// E(n): per product, the FP16 rounding of both unit vectors (2^-11 relative
+// per component) moves r . g by at most 2^-11 (|r||g_h| + |r||g|) <= 2^-10 +
+// 2^-22, and the two FP32 roundings of each product add 2^-23; a window
+// maximum moves by no more than its operands; each blocked FP32 sum of n
+// votes of size <= 1 + 2^-10 is within (31 + ceil(n/32)) 2^-24 per vote of
+// the exact sum, twice (both searches), plus the two divisions.  A unit
+// field direction from integer gradients has no component below 1/1443, so
+// none is an FP16 subnormal; a rotated model direction may have one (below
+// 2^-14), and were the product to flush it, the product would move by at most
+// 2^-14 more.  cert_eps takes 2^-10 + 2^-14 + 2^-18 + (66 + 2 ceil(n/32))
+// 2^-23, above all of it.
+__device__ __forceinline__ double cert_eps(int n)
+{
+    return ldexp(1.0, -10) + ldexp(1.0, -14) + ldexp(1.0, -18) +
+           (66.0 + 2.0 * (double)((n + 31) / 32)) * ldexp(1.0, -23);
+}
+
+struct CertArgs {
+    int level, C, A, K, win, sx, sy;
+    float min_score;
+    CertBufs cb;
+    int lds_bytes;  // k_rescore_multi: bytes of its staged field block (0: gathers only)
+};
+
+__global__ __launch_bounds__(64) void k_cert_zero(int* count)
+{
+    if (threadIdx.x < 2) count[threadIdx.x] = 0;
+}
+
+// One thread per translation of every pair: the translations whose FP32
+// values the selection needs, queued with the angles to score.
+__global__ __launch_bounds__(256) void k_certify(CertArgs a, const PairDesc* __restrict__ pairs)
+{
+    const int pr = blockIdx.y;
+    const PairDesc& P = pairs[pr];
+    const int gw = P.gw, gh = P.gh, np = gw * gh;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const int x = p % gw, y = p / gw;
+    const double E = cert_eps(P.n[a.level]);
+    double M[5][5];
+    bool in[5][5];
+#pragma unroll
+    for (int b = 0; b < 5; ++b)
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            const int xx = x + c - 2, yy = y + b - 2;
+            in[b][c] = (unsigned)xx < (unsigned)gw && (unsigned)yy < (unsigned)gh;
+            M[b][c] = in[b][c] ? (double)P.mw[yy * gw + xx] : 0.0;
+        }
+    // may the translation at block position (b, c) (1..3) be a candidate in FP32?
+    auto possible = [&](int b, int c) -> bool {
+        if (!in[b][c]) return false;
+        const double hi = M[b][c] + E;
+        if (!(hi >= (double)a.min_score)) return false;
+        bool ok = true;
+#pragma unroll
+        for (int v = -1; v <= 1; ++v)
+#pragma unroll
+            for (int u = -1; u <= 1; ++u)
+                if ((u || v) && in[b + v][c + u] && M[b + v][c + u] - E > hi) ok = false;
+        return ok;
+    };
+    bool need = possible(2, 2);
+    const double hi_u = M[2][2] + E;
+#pragma unroll
+    for (int v = -1; v <= 1; ++v)
+#pragma unroll
+        for (int u = -1; u <= 1; ++u)
+            if ((u || v) && !need && possible(2 + v, 2 + u) && hi_u >= M[2 + v][2 + u] - E) need = true;
+    if (!need) return;
+    const double lim = M[2][2] - 2.0 * E;
+    unsigned long long mask = 0ull;
+    int nc = 0, c1 = -1;
+    for (int c = 0; c < a.C; ++c)
+        if ((double)P.pw[(size_t)c * np + p] >= lim) {
+            if (c < 64) mask |= 1ull << c;
+            if (nc++ == 0) c1 = c;
+        }
+    if (nc == 1 && a.C <= 64 && (double)P.p2[(size_t)c1 * np + p] < lim) {
+        const int i = atomicAdd(&a.cb.count[1], 1);
+        a.cb.single[i] = make_int2(pr, p);
+    } else {
+        if (a.C > 64) mask = ~0ull;  // all angles
+        const int i = atomicAdd(&a.cb.count[0], 1);
+        a.cb.multi[i] = make_int4(pr, p, (int)(unsigned)(mask & 0xffffffffull), (int)(unsigned)(mask >> 32));
+    }
+}
+
+// Eq. (1) of one pose in FP32 with the FP32 search's arithmetic: window
+// maximum of the products of each (padded) table entry, votes added in
+// blocks of 32 points in point order, block sums in order, one division.
+// g(qx, qy): the FP32 field at the translation plus (qx, qy), zero outside
+// the image.
+template <int VOTE, class Fetch>
+__device__ __forceinline__ void score_fp32(const TabEntry* __restrict__ Tb, int n_pad, float n_f, int h, Fetch g,
+                                           float* sw, float* s1)
+{
+    float tw = 0.f, t1 = 0.f;
+    for (int i0 = 0; i0 < n_pad; i0 += kBlock) {
+        float pw = 0.f, p1 = 0.f;
+        const int i1 = min(n_pad, i0 + kBlock);
+        for (int i = i0; i < i1; ++i) {
+            const TabEntry e = Tb[i];
+            float best = -INFINITY;
+            for (int dy = -h; dy <= h; ++dy)
+                for (int dx = -h; dx <= h; ++dx) {
+                    const float2 v = g((int)e.qx + dx, (int)e.qy + dy);
+                    const float d = Px<TM_FP32>::dot(e, v);
+                    if constexpr (VOTE == 1)
+                        best = fmaxf(best, Px<TM_FP32>::edge(v) ? d : kOffEdge);
+                    else
+                        best = fmaxf(best, d);
+                }
+            pw += win_finish<VOTE>(best);
+            p1 += Px<TM_FP32>::dot(e, g((int)e.qx, (int)e.qy));
+        }
+        tw += pw;
+        t1 += p1;
+    }
+    *sw = tw / n_f;
+    *s1 = t1 / n_f;
+}
+
+// The queued translations with several open angle chunks: one workgroup per
+// translation (looping over the queue), the FP32 field block around it
+// staged in LDS when it fits, one thread per angle of the open chunks, the
+// best by the key (S_w desc, S_1 desc, angle asc) written to the map.
+template <int VOTE>
+__global__ __launch_bounds__(256) void k_rescore_multi(CertArgs a, const PairDesc* __restrict__ pairs)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    float2* blk = reinterpret_cast<float2*>(smem);
+    __shared__ float rw[4], r1[4];
+    __shared__ int rk[4];
+    __shared__ int ch_lo[64], ch_n[64], n_ch, n_ang;
+    const int count = a.cb.count[0];
+    const int h = (a.win - 1) / 2;
+    for (int e = blockIdx.x; e < count; e += gridDim.x) {
+        const int4 en = a.cb.multi[e];
+        const PairDesc& P = pairs[en.x];
+        const int p = en.y;
+        const unsigned long long mask = (unsigned long long)(unsigned)en.z | ((unsigned long long)(unsigned)en.w << 32);
+        const int x = (p % P.gw) * a.sx, y = (p / P.gw) * a.sy;
+        const int W = P.W[a.level], H = P.H[a.level];
+        const float2* __restrict__ f32 = reinterpret_cast<const float2*>(P.field[a.level]);
+        const int B = P.rad + h, S = 2 * B + 1;
+        const bool staged = (long long)S * S * 8 <= a.lds_bytes;
+        if (threadIdx.x == 0) {
+            int m = 0, t = 0;
+            for (int c = 0; c < a.C; ++c)
+                if (a.C > 64 || ((mask >> c) & 1ull)) {
+                    if (m < 64) {
+                        ch_lo[m] = c * a.A;
+                        ch_n[m] = min(a.K, (c + 1) * a.A) - c * a.A;
+                        t += ch_n[m];
+                    }
+                    ++m;
+                }
+            if (m > 64) {  // more than 64 chunks: every angle as one range
+                ch_lo[0] = 0;
+                ch_n[0] = a.K;
+                m = 1;
+                t = a.K;
+            }
+            n_ch = m;
+            n_ang = t;
+        }
+        if (staged)
+            for (int i = threadIdx.x; i < S * S; i += blockDim.x) {
+                const int r = i / S, c = i - r * S;
+                const int gx = x - B + c, gy = y - B + r;
+                blk[i] = ((unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H) ? f32[(size_t)gy * W + gx]
+                                                                                      : make_float2(0.f, 0.f);
+            }
+        __syncthreads();
+        float kw = -INFINITY, k1 = -INFINITY;
+        int kk = 0x7fffffff;
+        const float n_f = (float)P.n[a.level];
+        for (int j = threadIdx.x; j < n_ang; j += blockDim.x) {
+            int c = 0, r = j;
+            while (r >= ch_n[c]) r -= ch_n[c++];
+            const int k = ch_lo[c] + r;
+            const TabEntry* Tb = P.tab + (size_t)k * P.n_pad;
+            float sw, s1;
+            if (staged) {
+                const float2* ctr = blk + B * S + B;
+                score_fp32<VOTE>(Tb, P.n_pad, n_f, h, [&](int qx, int qy) { return ctr[qy * S + qx]; }, &sw, &s1);
+            } else {
+                score_fp32<VOTE>(Tb, P.n_pad, n_f, h,
+                                 [&](int qx, int qy) {
+                                     const int gx = x + qx, gy = y + qy;
+                                     return ((unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H)
+                                                ? f32[(size_t)gy * W + gx]
+                                                : make_float2(0.f, 0.f);
+                                 },
+                                 &sw, &s1);
+            }
+            if (key_better(sw, s1, 0, 0, k, kw, k1, 0, 0, kk)) {
+                kw = sw;
+                k1 = s1;
+                kk = k;
+            }
+        }
+        // the best of the workgroup by the key (a total order: any merge order gives it)
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const float ow = __shfl_xor(kw, off, 64), o1 = __shfl_xor(k1, off, 64);
+            const int ok = __shfl_xor(kk, off, 64);
+            if (key_better(ow, o1, 0, 0, ok, kw, k1, 0, 0, kk)) {
+                kw = ow;
+                k1 = o1;
+                kk = ok;
+            }
+        }
+        const int wv = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) {
+            rw[wv] = kw;
+            r1[wv] = k1;
+            rk[wv] = kk;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+                if (key_better(rw[w], r1[w], 0, 0, rk[w], kw, k1, 0, 0, kk)) {
+                    kw = rw[w];
+                    k1 = r1[w];
+                    kk = rk[w];
+                }
+            P.mw[p] = kw;
+            P.m1[p] = k1;
+            P.mk[p] = kk;
+        }
+        __syncthreads();  // before the next translation's block and lists
+    }
+}
+
+// The queued translations whose FP32 best is the FP16 best angle: one thread
+// each, taps gathered from the FP32 field.
+template <int VOTE>
+__global__ __launch_bounds__(256) void k_rescore_single(CertArgs a, const PairDesc* __restrict__ pairs)
+{
+    const int count = a.cb.count[1];
+    const int h = (a.win - 1) / 2;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < count; e += gridDim.x * blockDim.x) {
+        const int2 en = a.cb.single[e];
+        const PairDesc& P = pairs[en.x];
+        const int p = en.y;
+        const int x = (p % P.gw) * a.sx, y = (p / P.gw) * a.sy;
+        const int W = P.W[a.level], H = P.H[a.level];
+        const float2* __restrict__ f32 = reinterpret_cast<const float2*>(P.field[a.level]);
+        const int k = P.mk[p];
+        float sw, s1;
+        score_fp32<VOTE>(P.tab + (size_t)k * P.n_pad, P.n_pad, (float)P.n[a.level], h,
+                         [&](int qx, int qy) {
+                             const int gx = x + qx, gy = y + qy;
+                             return ((unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H)
+                                        ? f32[(size_t)gy * W + gx]
+                                        : make_float2(0.f, 0.f);
+                         },
+                         &sw, &s1);
+        P.mw[p] = sw;
+        P.m1[p] = s1;
+    }
+}
+
+constexpr int kCertLds = 64 * 1024;  // largest staged block of k_rescore_multi
+
 // ---------------------------------------------------------------- planning
 constexpr int kLC[] = {64, 96, 128, 192, 256};
 
@@ -761,9 +1076,11 @@ void plan_tiles(const DensePlan& p, const PairGeom& g, int* tiles_x, int* tiles_
 DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
 {
     DensePlan p = {};
+    p.prec = s.precision;
     int max_halo = 0;
     for (int i = 0; i < npairs; ++i) {
         max_halo = max(max_halo, g[i].rad + 1);
+        p.max_rad = max(p.max_rad, g[i].rad);
         p.max_np = max(p.max_np, g[i].gw * g[i].gh);
     }
     p.fast = s.sx == 1 && s.sy == 1 && s.win == 3;
@@ -786,7 +1103,7 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
         // FP16 pixels take 4 bytes (8 with the edge-taps addend), FP32 8
         const size_t px_bytes = s.precision == TM_FP16 ? (p.vote ? 8 : 4) : 8;
         p.tile_lds = (size_t)(TH + 2 * max_halo) * p.LC * px_bytes;
-        const size_t comb_bytes = (size_t)12 * p.WA * TH * TW;
+        const size_t comb_bytes = (size_t)(s.precision == TM_FP16 ? 16 : 12) * p.WA * TH * TW;
         p.lds = p.tile_lds > comb_bytes ? p.tile_lds : comb_bytes;
         if (p.LC == 0 || p.lds > 160 * 1024) p.fast = false;
     }
@@ -863,7 +1180,7 @@ bool retune_dense(DensePlan& p, int variant, int WA)
     if (!p.fast || variant < 0 || variant > 5 || WA < 1 || p.WY * WA > 16) return false;
     if (p.vote && variant != p.variant) return false;
     const int TW = p.G - 2, TH = p.WY * (64 / p.G) * p.R;
-    const size_t comb_bytes = (size_t)12 * WA * TH * TW;
+    const size_t comb_bytes = (size_t)(p.prec == TM_FP16 ? 16 : 12) * WA * TH * TW;
     const size_t lds = p.tile_lds > comb_bytes ? p.tile_lds : comb_bytes;
     if (lds > 160 * 1024) return false;
     p.variant = variant;
@@ -926,7 +1243,7 @@ bool build_work(const DensePlan& p, const PairGeom* g, int npairs, std::vector<i
     return true;
 }
 
-size_t dense_partials_bytes(const DensePlan& p, int np) { return (size_t)p.C * np * 12; }
+size_t dense_partials_bytes(const DensePlan& p, int np) { return (size_t)p.C * np * (p.prec == TM_FP16 ? 16 : 12); }
 
 hipError_t prepare_dense(const SearchDesc& s, const DensePlan& p)
 {
@@ -1018,6 +1335,59 @@ hipError_t launch_sparse(const void* field, int W, int H, int precision, const M
             launch_sparse_t<TM_FP32, 1>(field, W, H, pts, n, win, poses, np, scores, s);
         else
             launch_sparse_t<TM_FP32, 0>(field, W, H, pts, n, win, poses, np, scores, s);
+    }
+    return hipGetLastError();
+}
+
+size_t cert_bytes(int total_np) { return 256 + (size_t)total_np * (sizeof(int4) + sizeof(int2)) + 256; }
+
+CertBufs cert_bufs(void* base, int total_np)
+{
+    CertBufs b;
+    uint8_t* q = reinterpret_cast<uint8_t*>(base);
+    b.count = reinterpret_cast<int*>(q);
+    b.multi = reinterpret_cast<int4*>(q + 256);
+    b.single = reinterpret_cast<int2*>(q + 256 + (size_t)total_np * sizeof(int4));
+    b.cap = total_np;
+    return b;
+}
+
+hipError_t launch_certify(const SearchDesc& s, const DensePlan& p, const PairDesc* d, int npairs, const CertBufs& cb,
+                          hipStream_t st)
+{
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rescore_multi<0>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, kCertLds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rescore_multi<1>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, kCertLds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    if (!d) return hipSuccess;
+    CertArgs a;
+    a.level = s.level;
+    a.C = p.C;
+    a.A = p.A;
+    a.K = poses_per_translation(s);
+    a.win = s.win;
+    a.sx = s.sx;
+    a.sy = s.sy;
+    a.min_score = s.min_score;
+    a.cb = cb;
+    const int B = p.max_rad + (s.win - 1) / 2, S = 2 * B + 1;
+    // pairs whose block fits are staged, larger ones gather from memory
+    a.lds_bytes = (long long)S * S * 8 <= kCertLds ? S * S * 8 : kCertLds;
+    hipLaunchKernelGGL(k_cert_zero, dim3(1), dim3(64), 0, st, cb.count);
+    hipLaunchKernelGGL(k_certify, dim3((p.max_np + 255) / 256, npairs), dim3(256), 0, st, a, d);
+    const int gm = min(cb.cap, 2048), gs = min((cb.cap + 255) / 256, 64);
+    if (s.vote) {
+        hipLaunchKernelGGL(k_rescore_multi<1>, dim3(gm), dim3(256), a.lds_bytes, st, a, d);
+        hipLaunchKernelGGL(k_rescore_single<1>, dim3(gs), dim3(256), 0, st, a, d);
+    } else {
+        hipLaunchKernelGGL(k_rescore_multi<0>, dim3(gm), dim3(256), a.lds_bytes, st, a, d);
+        hipLaunchKernelGGL(k_rescore_single<0>, dim3(gs), dim3(256), 0, st, a, d);
     }
     return hipGetLastError();
 }

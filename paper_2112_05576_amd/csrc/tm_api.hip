@@ -335,15 +335,16 @@ void pair_static(tmk::PairDesc* d, const tm_model* m, const tm_pyramid* p, const
                  const tmk::PairGeom& g, const tmk::DensePlan& plan, float dmin, int win, double sigma_max)
 {
     for (int l = 0; l < p->L; ++l) {
-        d->field[l] = p->lv[l].field;
+        d->field[l] = p->lv[l].field32;  // the refinement and the re-scoring work in FP32
         d->W[l] = p->lv[l].w;
         d->H[l] = p->lv[l].h;
         d->pts[l] = m->lv[l].pts;
         d->dir[l] = m->lv[l].dir;
         d->n[l] = m->lv[l].n;
         d->rad_l[l] = scaled_rad(m->lv[l], sigma_max);
-        d->rtile[l] = tmk::refine_tile_fits(d->rad_l[l], p->precision, win) ? 1 : 0;
+        d->rtile[l] = tmk::refine_tile_fits(d->rad_l[l], TM_FP32, win) ? 1 : 0;
     }
+    d->sfield = p->lv[level].field;  // the exhaustive search reads the storage precision
     d->tab = tab;
     d->n_pad = m->lv[level].n_pad;
     d->rad = g.rad;
@@ -386,6 +387,7 @@ size_t pair_scratch(tmk::PairDesc* d, const tm_model* m, const tmk::PairGeom& g,
             d->pw = pw;
             d->p1 = pw + C * np;
             d->pk = reinterpret_cast<int32_t*>(pw + 2 * C * np);
+            d->p2 = plan.prec == TM_FP16 ? pw + 3 * C * np : nullptr;
             d->mw = mw;
             d->m1 = mw + np;
             d->mk = reinterpret_cast<int32_t*>(mw + 2 * np);
@@ -444,9 +446,10 @@ tm_status put_desc(tm_pyramid* p, const tmk::PairDesc& d, hipStream_t s, tmk::Pa
 // is used once a launch refines at least kStagedMin candidates.
 constexpr int kStagedMin = 512;
 
-tmk::RefinePlan refine_plan(const tm_model* const* models, int n_models, int L, int win, int precision,
-                            long long candidates, double sigma_max)
+tmk::RefinePlan refine_plan(const tm_model* const* models, int n_models, int L, int win, long long candidates,
+                            double sigma_max)
 {
+    const int precision = TM_FP32;  // the refinement reads the FP32 fields (an FP16 pyramid's twin)
     tmk::RefinePlan rp;
     memset(&rp, 0, sizeof(rp));
     rp.staged = candidates >= kStagedMin;
@@ -524,15 +527,20 @@ tm_status alloc_pyramid(int w, int h, const tm_pyr_params* pp, hipStream_t s, tm
     }
     int ws[TM_MAX_LEVELS], hs[TM_MAX_LEVELS];
     level_sizes(w, h, p->L, ws, hs);
-    const size_t fsz = pp->precision == TM_FP16 ? 4 : 8;
+    // per level: the uint8 image, the direction field in the storage
+    // precision, for FP16 its FP32 twin, and the gradient maps if asked for
+    const bool fp16 = pp->precision == TM_FP16;
+    const size_t fsz = fp16 ? 4 : 8;
     size_t total = 0;
-    size_t img_off[TM_MAX_LEVELS], fld_off[TM_MAX_LEVELS], grd_off[TM_MAX_LEVELS];
+    size_t img_off[TM_MAX_LEVELS], fld_off[TM_MAX_LEVELS], f32_off[TM_MAX_LEVELS], grd_off[TM_MAX_LEVELS];
     const bool gradient = pp->source == TM_PYR_GRADIENT;
     for (int l = 0; l < p->L; ++l) {
         img_off[l] = total;
         total = align_up(total + (size_t)ws[l] * hs[l], 256);
         fld_off[l] = total;
         total = align_up(total + (size_t)ws[l] * hs[l] * fsz, 256);
+        f32_off[l] = fp16 ? total : fld_off[l];
+        if (fp16) total = align_up(total + (size_t)ws[l] * hs[l] * 8, 256);
         grd_off[l] = total;
         if (gradient) total = align_up(total + (size_t)ws[l] * hs[l] * 4, 256);
     }
@@ -546,6 +554,7 @@ tm_status alloc_pyramid(int w, int h, const tm_pyr_params* pp, hipStream_t s, tm
         p->lv[l].h = hs[l];
         p->lv[l].img = reinterpret_cast<uint8_t*>(p->block) + img_off[l];
         p->lv[l].field = reinterpret_cast<uint8_t*>(p->block) + fld_off[l];
+        p->lv[l].field32 = reinterpret_cast<uint8_t*>(p->block) + f32_off[l];
         p->lv[l].grad = gradient ? reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(p->block) + grd_off[l])
                                  : nullptr;
     }
@@ -925,8 +934,9 @@ TM_EXPORT tm_status tm_detect(const tm_model* m, tm_pyramid* p, const tm_search_
     memset(&d, 0, sizeof(d));
     pair_static(&d, m, p, tab, top, pg, plan, default_dmin(m, sp), sp->neighbourhood, g.sigma_max);
     const bool refine = p->L > 1;
-    st = ensure_ws(p, kDescBytes + pair_scratch(&d, m, pg, plan, p->L, sp->max_candidates, true, true, refine, nullptr),
-                   s);
+    const bool certify = p->precision == TM_FP16;
+    const size_t pair_bytes = pair_scratch(&d, m, pg, plan, p->L, sp->max_candidates, true, true, refine, nullptr);
+    st = ensure_ws(p, kDescBytes + pair_bytes + (certify ? tmk::cert_bytes(pg.gw * pg.gh) : 0), s);
     if (st != TM_OK) return st;
     pair_scratch(&d, m, pg, plan, p->L, sp->max_candidates, true, true, refine,
                  reinterpret_cast<uint8_t*>(p->ws.ptr) + kDescBytes);
@@ -939,10 +949,15 @@ TM_EXPORT tm_status tm_detect(const tm_model* m, tm_pyramid* p, const tm_search_
     st = timing_pair(&ev0, &ev1);
     if (st != TM_OK) return st;
     HIP_TRY(tmk::launch_dense(sd, plan, dd, 1, s, ev0, ev1));
+    if (certify)
+        HIP_TRY(tmk::launch_certify(sd, plan, dd, 1,
+                                    tmk::cert_bufs(reinterpret_cast<uint8_t*>(p->ws.ptr) + kDescBytes + pair_bytes,
+                                                   pg.gw * pg.gh),
+                                    s));
     HIP_TRY(tmk::launch_select(sd, dd, 1, pg.gw * pg.gh, s));
     if (refine) {
         const tmk::RefinePlan rp =
-            refine_plan(&m, 1, p->L, sp->neighbourhood, p->precision, sp->max_candidates, g.sigma_max);
+            refine_plan(&m, 1, p->L, sp->neighbourhood, sp->max_candidates, g.sigma_max);
         HIP_TRY(tmk::launch_refine(sd, dd, 1, top, rp, s, false));
     }
     HIP_TRY(tmk::launch_final(sd, dd, 1, s, out, n_out, refine ? top % 2 : -1));
@@ -1003,8 +1018,9 @@ TM_EXPORT tm_status tm_detect_static(const tm_model* m, const tm_pyramid* p, con
     const bool refine = p->L > 1;
     // layout: descriptor, rotated table of the top level, pair scratch
     const size_t tab_bytes = align_up((size_t)g.K[top] * g.S * mt.n_pad * sizeof(tmk::TabEntry), 256);
-    const size_t need =
-        kDescBytes + tab_bytes + pair_scratch(&d, m, pg, plan, p->L, sp->max_candidates, true, true, refine, nullptr);
+    const bool certify = p->precision == TM_FP16;
+    const size_t pair_bytes = pair_scratch(&d, m, pg, plan, p->L, sp->max_candidates, true, true, refine, nullptr);
+    const size_t need = kDescBytes + tab_bytes + pair_bytes + (certify ? tmk::cert_bytes(pg.gw * pg.gh) : 0);
     if (need > (size_t)TM_STATIC_SCRATCH_BYTES)
         return fail(TM_ECAPACITY, "tm_detect_static: the detection needs %zu bytes of scratch, the static array "
                                   "holds %zu", need, (size_t)TM_STATIC_SCRATCH_BYTES);
@@ -1021,10 +1037,13 @@ TM_EXPORT tm_status tm_detect_static(const tm_model* m, const tm_pyramid* p, con
     hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, d, dd);
     HIP_TRY(hipGetLastError());
     HIP_TRY(tmk::launch_dense(sd, plan, dd, 1, s));
+    if (certify)
+        HIP_TRY(tmk::launch_certify(sd, plan, dd, 1,
+                                    tmk::cert_bufs(b + kDescBytes + tab_bytes + pair_bytes, pg.gw * pg.gh), s));
     HIP_TRY(tmk::launch_select(sd, dd, 1, pg.gw * pg.gh, s));
     if (refine) {
         const tmk::RefinePlan rp =
-            refine_plan(&m, 1, p->L, sp->neighbourhood, p->precision, sp->max_candidates, g.sigma_max);
+            refine_plan(&m, 1, p->L, sp->neighbourhood, sp->max_candidates, g.sigma_max);
         HIP_TRY(tmk::launch_refine(sd, dd, 1, top, rp, s, false));
     }
     HIP_TRY(tmk::launch_final(sd, dd, 1, s, out, n_out, refine ? top % 2 : -1));
@@ -1088,7 +1107,7 @@ TM_EXPORT tm_status tm_refine(const tm_model* m, tm_pyramid* p, const tm_search_
     tmk::PairDesc* dd = nullptr;
     st = put_desc(p, d, s, &dd);
     if (st != TM_OK) return st;
-    const tmk::RefinePlan rp = refine_plan(&m, 1, p->L, sp->neighbourhood, p->precision, n, g.sigma_max);
+    const tmk::RefinePlan rp = refine_plan(&m, 1, p->L, sp->neighbourhood, n, g.sigma_max);
     HIP_TRY(tmk::launch_refine(sd, dd, 1, from_level, rp, s));
     return TM_OK;
 }
@@ -1186,6 +1205,8 @@ struct tm_batch_s {
     size_t ls_bytes = 0;
     tm_allocator alloc = {};         // allocator of the batch's memory
     hipEvent_t last_run = nullptr;   // recorded after each run enqueued outside a capture
+    bool certify = false;            // FP16 search: its decisions are certified in FP32
+    tmk::CertBufs cert = {};
 };
 
 namespace {
@@ -1272,7 +1293,7 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
         tm_batch_free(b);
         return fail(TM_EDEVICE, "tm_batch_create: internal error in the search work list");
     }
-    b->rplan = refine_plan(models, n_models, L, sp->neighbourhood, pp->precision,
+    b->rplan = refine_plan(models, n_models, L, sp->neighbourhood,
                            (long long)b->npairs * sp->max_candidates, g.sigma_max);
     for (auto& q : pg) b->max_np = std::max(b->max_np, q.gw * q.gh);
 
@@ -1297,6 +1318,15 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
     off = align_up(off + (size_t)n_images * sizeof(tmk::FieldsArg), 256);
     const size_t work_off = off;
     off = align_up(off + work.size() * sizeof(int2), 256);
+    long long total_np = 0;
+    for (auto& q : pg) total_np += (long long)q.gw * q.gh;
+    if (total_np > (1LL << 30)) {
+        tm_batch_free(b);
+        return fail(TM_EINVAL, "tm_batch_create: too many translations");
+    }
+    b->certify = pp->precision == TM_FP16;
+    const size_t cert_off = off;
+    if (b->certify) off = align_up(off + tmk::cert_bytes((int)total_np), 256);
     std::vector<size_t> pair_off(b->npairs);
     const bool refine = L > 1;
     for (int q = 0; q < b->npairs; ++q) {
@@ -1314,6 +1344,7 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
     }
     uint8_t* base = reinterpret_cast<uint8_t*>(b->scratch);
     b->d_pairs = reinterpret_cast<tmk::PairDesc*>(base + desc_off);
+    if (b->certify) b->cert = tmk::cert_bufs(base + cert_off, (int)total_np);
     b->d_pb = reinterpret_cast<tmk::PyrBuildArg*>(base + pb_off);
     b->d_fa = reinterpret_cast<tmk::FieldsArg*>(base + fa_off);
     for (int j = 0; j < n_models; ++j) {
@@ -1382,6 +1413,7 @@ tm_status batch_enqueue(tm_batch* b, hipStream_t s, bool timed)
         if (st != TM_OK) return st;
     }
     HIP_TRY(tmk::launch_dense(b->sd, b->plan, b->d_pairs, b->npairs, s, ev0, ev1));
+    if (b->certify) HIP_TRY(tmk::launch_certify(b->sd, b->plan, b->d_pairs, b->npairs, b->cert, s));
     HIP_TRY(tmk::launch_select(b->sd, b->d_pairs, b->npairs, b->max_np, s));
     if (b->L > 1) HIP_TRY(tmk::launch_refine(b->sd, b->d_pairs, b->npairs, top, b->rplan, s, false));
     HIP_TRY(tmk::launch_final(b->sd, b->d_pairs, b->npairs, s, nullptr, nullptr, b->L > 1 ? top % 2 : -1));
@@ -1404,6 +1436,7 @@ TM_EXPORT tm_status tm_batch_run_graph(tm_batch* b, void* stream)
         // Capture on a private stream: nothing runs, the launches become nodes.
         HIP_TRY(tmk::prepare_dense(b->sd, b->plan));
         HIP_TRY(tmk::prepare_refine());
+        HIP_TRY(tmk::launch_certify(b->sd, b->plan, nullptr, 0, b->cert, nullptr));  // kernel attributes only
         hipStream_t cs = nullptr;
         HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
         hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
@@ -1550,7 +1583,7 @@ TM_EXPORT tm_status tm_batch_cont_score(tm_batch* b, int32_t level, const tm_con
 {
     tm_status st = batch_cont_check(b, level, n, poses, scores, "tm_batch_cont_score");
     if (st != TM_OK) return st;
-    HIP_TRY(tmk::launch_cont(b->d_pairs, 1, b->npairs, level, b->sd.precision, poses, n, nullptr, scores, false,
+    HIP_TRY(tmk::launch_cont(b->d_pairs, 1, b->npairs, level, TM_FP32, poses, n, nullptr, scores, false,
                              S(stream)));
     return TM_OK;
 }
@@ -1560,7 +1593,7 @@ TM_EXPORT tm_status tm_batch_cont_score_backward(tm_batch* b, int32_t level, con
 {
     tm_status st = batch_cont_check(b, level, n, poses, gout, "tm_batch_cont_score_backward");
     if (st != TM_OK) return st;
-    HIP_TRY(tmk::launch_cont(b->d_pairs, 1, b->npairs, level, b->sd.precision, poses, n, gin, gout, true, S(stream)));
+    HIP_TRY(tmk::launch_cont(b->d_pairs, 1, b->npairs, level, TM_FP32, poses, n, gin, gout, true, S(stream)));
     return TM_OK;
 }
 
@@ -1587,7 +1620,7 @@ TM_EXPORT tm_status tm_batch_cont_line_search(tm_batch* b, int32_t level, tm_con
         HIP_TRY(tmk::dev_alloc(b->alloc, &b->ls_buf, need, S(stream)));
         b->ls_bytes = need;
     }
-    HIP_TRY(tmk::launch_line_search(b->d_pairs, 1, b->npairs, level, b->sd.precision, poses, dirs, n, alphas,
+    HIP_TRY(tmk::launch_line_search(b->d_pairs, 1, b->npairs, level, TM_FP32, poses, dirs, n, alphas,
                                     n_alphas, scores, reinterpret_cast<double*>(b->ls_buf), S(stream)));
     return TM_OK;
 }

@@ -36,7 +36,9 @@ struct alignas(16) TabEntry {
 struct PyrLevel {
     int w, h;
     uint8_t* img;   // w*h bytes, row-major
-    void* field;    // w*h float2 (FP32) or half2 (FP16), row-major
+    void* field;    // w*h float2 (FP32) or half2 (FP16), row-major: the storage the searches read
+    void* field32;  // w*h float2: the FP32 field (the same buffer as `field` in an FP32 pyramid; an FP16
+                    // pyramid keeps this twin for the decisions taken after its FP16 search)
     uint32_t* grad; // gradient-map pyramid only: w*h packed int16 pairs (gx low, gy high); else null
 };
 
@@ -118,6 +120,7 @@ struct FieldsArg {
     const uint8_t* img[kMaxLevels];
     uint32_t* grad[kMaxLevels];  // gradient-map pyramid (all null: gradients of each grey level)
     void* field[kMaxLevels];
+    void* field32[kMaxLevels];   // FP16 pyramids: the FP32 twin, written beside the half2 field (else null)
     int w[kMaxLevels];
     int h[kMaxLevels];
     int block0[kMaxLevels + 1];  // first workgroup of each level
@@ -161,7 +164,8 @@ hipError_t launch_table_export(const TabEntry* tab, int n, int n_pad, int K, int
 // scratch and result buffers.  Lives in device memory; kernels take the pair
 // from blockIdx.y.
 struct PairDesc {
-    const void* field[kMaxLevels];   // direction field per level
+    const void* field[kMaxLevels];   // FP32 direction field per level (refinement, re-scoring)
+    const void* sfield;              // field the exhaustive search reads (the searched level, storage precision)
     int W[kMaxLevels], H[kMaxLevels];
     const ModelPoint* pts[kMaxLevels];
     const double2* dir[kMaxLevels];  // FP64 unit directions of the points
@@ -173,7 +177,8 @@ struct PairDesc {
     float dmin;                      // suppression distance, level-0 pixels
     float* pw;                       // chunk partials [C][gh][gw]: best S_w,
     float* p1;                       //   S_1,
-    int32_t* pk;                     //   angle
+    int32_t* pk;                     //   angle,
+    float* p2;                       //   FP16 search: the best S_w over the chunk's other angles
     float* mw;                       // best angle per translation [gh][gw]: S_w,
     float* m1;                       //   S_1,
     int32_t* mk;                     //   angle
@@ -214,6 +219,7 @@ inline int poses_per_translation(const SearchDesc& s) { return s.K[s.level] * s.
 // Launch plan of the exhaustive search, common to all pairs.
 struct DensePlan {
     bool fast;
+    int prec;                   // precision of the searched field (FP16 plans also keep the second best)
     int vote;                   // tm_vote (the edge-taps reading has one kernel form)
     int variant;                // search kernel form (k_dense_fast VAR)
     int tr;                     // 1: lanes along y, strips along x (FastArgs.tr)
@@ -223,6 +229,7 @@ struct DensePlan {
     size_t tile_lds;            // the field tile's share of lds
     int max_blocks;             // workgroups of the largest pair (fast path)
     int max_np;                 // translations of the largest pair
+    int max_rad;                // largest bound on |q| components over the pairs
     const int2* work = nullptr; // optional device work list (fast path, build_work)
     int n_work = 0;
     // generic path: bytes per field pixel, window half-width, and the largest
@@ -273,6 +280,25 @@ hipError_t prepare_dense(const SearchDesc& s, const DensePlan& p);
 // (optional) are recorded around the search kernel only.
 hipError_t launch_dense(const SearchDesc& s, const DensePlan& p, const PairDesc* d, int npairs, hipStream_t st,
                         hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Certification of an FP16 search (see k_score.hip): translations whose
+// FP32 scores could decide the candidate selection are re-scored in FP32 from
+// the FP32 twin, with the FP32 search's arithmetic, over the angles their FP16
+// scores leave open, and the map takes those values.  Buffers (device): two
+// counters (multi, single) and two lists with room for every translation of
+// every pair.
+struct CertBufs {
+    int* count;       // [2]: entries in `multi`, in `single`
+    int4* multi;      // (pair, translation, chunk mask low, high): angles of the masked chunks
+    int2* single;     // (pair, translation): the FP16 best angle alone
+    int cap;          // entries each list holds
+};
+size_t cert_bytes(int total_np);
+CertBufs cert_bufs(void* base, int total_np);
+// Enqueues: the counters cleared (a kernel, not a memset), the flagging of
+// the translations, and the two re-scoring kernels.
+hipError_t launch_certify(const SearchDesc& s, const DensePlan& p, const PairDesc* d, int npairs, const CertBufs& cb,
+                          hipStream_t st);
+
 // Candidates of every pair from its map: pair.cand / ncand (<= s.max_cand).
 hipError_t launch_select(const SearchDesc& s, const PairDesc* d, int npairs, int max_np, hipStream_t st);
 // Refine pair.cand (poses of level from_level) down to level 0, in place.

@@ -6,10 +6,10 @@ times), and the continuous refinement of 4096 poses over the same pairs.
 At this size the oracle cannot redo every search, so the checks are:
   * for three 640x480 images with the two models of C2's size (about 750
     and 1100 points), the oracle's full detection, whose top match the batch
-    must reproduce (equal, or a tie within two FP16 bounds under the
-    oracle's own key);
+    must reproduce (equal, or a tie within 1e-5 under the oracle's own key:
+    the FP16 search is certified and the refinement runs in FP32);
   * for every pair, every reported detection's S_w and S_1 recomputed by the
-    oracle at the reported pose, within the FP16 bound;
+    oracle at the reported pose, within 1e-5;
   * for the continuous score, sampled poses against the oracle's FP64 value
     and gradient, and the refinement never lowering a pose's score."""
 import numpy as np
@@ -21,7 +21,7 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
-TOL16 = 2 * 2.0 ** -11 + 2e-5
+TOL = 1e-5
 
 
 def case(msg):
@@ -71,7 +71,7 @@ def test_c4_batch_graph_fp16(c4):
             for d in dets:
                 assert int(d["level"]) == 0
                 sw, s1 = O.score(g0, ml.t, ml.d, int(d["x"]), int(d["y"]), float(d["theta"]))
-                assert abs(float(d["sw"]) - sw) <= TOL16 and abs(float(d["s1"]) - s1) <= TOL16, (i, j, d, sw, s1)
+                assert abs(float(d["sw"]) - sw) <= TOL and abs(float(d["s1"]) - s1) <= TOL, (i, j, d, sw, s1)
                 checked += 1
     print(f"checked {checked} detections of {sum(len(r) for r in got)}")
     assert checked > 100
@@ -87,14 +87,13 @@ def test_c4_batch_graph_fp16(c4):
             print(f"  oracle {[(d.x, d.y, d.k, round(d.sw, 4)) for d in ref[:3]]}")
             print(f"  gpu    {[(int(d['x']), int(d['y']), int(d['k']), round(float(d['sw']), 4)) for d in dets[:3]]}")
             if len(ref) == 0 or len(dets) == 0:  # only a top score at the threshold may be missing on one side
-                top = float(dets[0]["sw"]) if len(dets) else (ref[0].sw if ref else sp.min_score)
-                assert abs(top - sp.min_score) <= 2 * TOL16, (i, j, len(ref), len(dets))
+                assert len(ref) == len(dets), (i, j, len(ref), len(dets))
                 continue
             r0, g0 = ref[0], dets[0]
             if (int(g0["x"]), int(g0["y"]), int(g0["k"])) != (r0.x, r0.y, r0.k):
                 ml = tr.model.levels[0]
-                sw, _ = O.score(tr.fields[0], ml.t, ml.d, int(g0["x"]), int(g0["y"]), float(g0["theta"]))
-                assert abs(sw - r0.sw) <= 2 * TOL16, (i, j, g0, r0)
+                sw, s1 = O.score(tr.fields[0], ml.t, ml.d, int(g0["x"]), int(g0["y"]), float(g0["theta"]))
+                assert abs(sw - r0.sw) <= TOL and abs(s1 - r0.s1) <= TOL, (i, j, g0, r0)
 
 
 def test_c5_continuous_refinement(c4):
