@@ -61,13 +61,20 @@ def parse():
     ap.add_argument("--batch", type=int, default=64, help="images per batched step")
     ap.add_argument("--precision", choices=["fp32", "fp16"], default="fp16",
                     help="direction storage of the batched leg (fp16: FP32 accumulation)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="time budget of the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=30.0,
+                    help="time budget of the oracle CPU baseline (it stops earlier once every image is done)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--eager", action="store_true", help="batched leg as plain enqueues instead of a graph launch")
     ap.add_argument("--streams", type=int, default=2,
                     help="batches in flight on their own streams in the batched leg (steps alternate between them)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default search-kernel form (no autotuning)")
     ap.add_argument("--c4", action="store_true", help="also time the 64 x 8 mixed batch and the C5 refinement")
+    ap.add_argument("--c3", action="store_true",
+                    help="also time the 2048x2048 five-level FP16 detection with its per-score error against FP32")
+    ap.add_argument("--no-other", action="store_true", help="skip the batched leg of the other precision")
+    ap.add_argument("--valu-from", metavar="VALU_CSV",
+                    help="write the search kernel's VALU-instruction entry from a rocprofv3 --pmc SQ_INSTS_VALU CSV "
+                         "and exit")
     ap.add_argument("--similarity", action="store_true",
                     help="also time the similarity-pose search (x, y, theta, scale) on 64 scaled 640x480 scenes")
     ap.add_argument("--paper", action="store_true",
@@ -183,31 +190,37 @@ def _cpu_model():
 
 def cpu_baseline(scenes, cfg, budget_s, paper=False):
     """The FP64 oracle, as it is, on the host cores: full detections of the
-    same images until the time budget is spent (and, with paper=True, one
-    detection of the paper-shaped search, timed on its own)."""
+    benchmark's images, each once, in order, until all are done or the time
+    budget is spent (and, with paper=True, one detection of the paper-shaped
+    search, timed on its own).  Returns the baseline entry and the oracle's
+    detections by image index, which the top-1 comparison of the GPU legs
+    uses."""
     import oracle as O
 
     threads = O.default_threads()
     osp = O.SearchParams(theta_step_top=cfg["theta_step_top"])
     L = cfg["levels"]
-    n_img, poses = 0, 0
+    model = O.build_model(scenes[0].model, O.PyrParams(L, cfg["tau_m"]))
+    dets = {}
+    poses = 0
     t0 = time.perf_counter()
-    while True:
-        sc = scenes[n_img % len(scenes)]
+    for i, sc in enumerate(scenes):
         tr = O.detect(sc.image, sc.model, O.PyrParams(L, cfg["tau_s"]), O.PyrParams(L, cfg["tau_m"]), osp,
-                      nthreads=threads)
-        n_img += 1
+                      nthreads=threads, model=model)
+        dets[i] = (tr.detections, tr.fields[0])
         poses += tr.top[0].size * O.level_count(osp, O.level_step(osp, L, L - 1))
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
     res = {"value": poses / dt, "unit": "pose-evals/s", "cores": threads, "kind": "oracle",
-           "sample": f"{n_img} full detections of 640x480 images (4 levels, 360 top angles), {dt:.1f} s",
+           "sample": f"{len(dets)} full detections of distinct 640x480 images (4 levels, 360 top angles), "
+                     f"{dt:.1f} s",
            "cpu": _cpu_model()}
     # one more detection of the first image on a single thread
     sc = scenes[0]
     t0 = time.perf_counter()
-    tr = O.detect(sc.image, sc.model, O.PyrParams(L, cfg["tau_s"]), O.PyrParams(L, cfg["tau_m"]), osp, nthreads=1)
+    tr = O.detect(sc.image, sc.model, O.PyrParams(L, cfg["tau_s"]), O.PyrParams(L, cfg["tau_m"]), osp, nthreads=1,
+                  model=model)
     res["single_core_value"] = tr.top[0].size * O.level_count(osp, O.level_step(osp, L, L - 1)) / (
         time.perf_counter() - t0)
     if paper:
@@ -219,7 +232,35 @@ def cpu_baseline(scenes, cfg, budget_s, paper=False):
         t0 = time.perf_counter()
         O.detect(sc.image, sc.model, O.PyrParams(1, pc["tau_s"]), O.PyrParams(1, pc["tau_m"]), osp, nthreads=threads)
         res["paper_shape_ms_per_detection"] = (time.perf_counter() - t0) * 1e3
-    return res
+    return res, (model, dets)
+
+
+def top1_vs_oracle(gpu_dets, oracle, cfg):
+    """Top-1 of a GPU leg against the oracle's, image by image: the same pose
+    ("identical"), a pose whose oracle S_w and S_1 are within 1e-5 of the
+    oracle's top match ("tie"), or neither ("differs"); images where neither
+    side detects anything are counted apart ("both_empty"), not as
+    agreement."""
+    import oracle as O
+
+    model, dets = oracle
+    ml = model.levels[0]
+    L = cfg["levels"]
+    osp = O.SearchParams(theta_step_top=cfg["theta_step_top"])
+    step0 = O.level_step(osp, L, 0)
+    out = {"identical": 0, "tie": 0, "differs": 0, "both_empty": 0, "images": len(dets)}
+    for i, (ref, f0) in dets.items():
+        g = gpu_dets[i]
+        if len(ref) == 0 and len(g) == 0:
+            out["both_empty"] += 1
+        elif len(ref) == 0 or len(g) == 0:
+            out["differs"] += 1
+        elif (int(g[0]["x"]), int(g[0]["y"]), int(g[0]["k"])) == (ref[0].x, ref[0].y, ref[0].k):
+            out["identical"] += 1
+        else:
+            sw, s1 = O.score(f0, ml.t, ml.d, int(g[0]["x"]), int(g[0]["y"]), O.theta(0.0, step0, int(g[0]["k"])))
+            out["tie" if abs(sw - ref[0].sw) <= 1e-5 and abs(s1 - ref[0].s1) <= 1e-5 else "differs"] += 1
+    return out
 
 
 def traffic_entry(form):
@@ -439,72 +480,110 @@ def paper_leg(P, torch, steps):
     return res
 
 
-def main():
-    args = parse()
-    if args.trace_summary:
-        trace_summary(args.trace_summary)
-        return
-    if args.traffic_from:
-        traffic_from(*args.traffic_from)
-        return
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is single-GPU by design.",
-              file=sys.stderr)
-        sys.exit(2)
-    import torch
+VALU_JSON = os.path.join(ROOT, "profiles", "dense_c2_valu.json")
 
-    import paper_2112_05576_amd as P
+
+def valu_from(csv_path):
+    """Executed VALU instructions per launch of the search kernel, from a
+    rocprofv3 --pmc SQ_INSTS_VALU CSV of this benchmark (tuning on, so that
+    every form of the batched search is dispatched): the median over the
+    batched launches of each form (variant, waves per chunk, precision,
+    screen), with the SHA-256 of k_score.hip they were counted on."""
+    out = {"kernel_sha256": hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest(), "forms": []}
+    rows = _pmc_rows(csv_path, "SQ_INSTS_VALU")
+    blocks = [g // wg for n, _, g, wg in rows if "k_dense_fast" in n]
+    per = {}
+    for n, v, g, wg in rows:
+        if "k_dense_fast" not in n or g // wg != max(blocks):
+            continue
+        targs = re.search(r"k_dense_fast<([^>]*)>", n).group(1).split(",")
+        prec, var = int(targs[3]), int(targs[4])
+        screen = len(targs) > 6 and targs[6].strip() == "true"
+        per.setdefault((var, wg // 64, prec, screen), []).append(v)
+    for (var, wa, prec, screen), v in sorted(per.items()):
+        out["forms"].append({"variant": var, "waves_per_chunk": wa, "precision": "fp16" if prec else "fp32",
+                             "screen": screen, "valu_instr_per_launch": float(np.median(v)), "launches": len(v)})
+    with open(VALU_JSON, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
+def valu_entry(form, precision):
+    """The counted VALU instructions per launch of the form in use, if they
+    were counted on the current k_score.hip."""
+    if not os.path.exists(VALU_JSON):
+        return None
+    d = json.load(open(VALU_JSON))
+    if d.get("kernel_sha256") != hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest():
+        return None
+    for f in d.get("forms", []):
+        if (f["variant"], f["waves_per_chunk"], f["precision"]) == (form.get("variant"), form.get("waves_per_chunk"),
+                                                                     precision) and f["screen"] == (precision == "fp16"):
+            return {"valu_instr_per_launch": f["valu_instr_per_launch"], "counted_in": os.path.relpath(VALU_JSON, ROOT)}
+    return None
+
+
+def c3_leg(P, torch, steps):
+    """The large-frame precision configuration: 2048x2048 scenes with 5
+    instances of a 256x256 model, 5 levels, 8 degrees at the top (0.5 at
+    level 0).  One tm_detect per frame in FP16 (certified search, FP32
+    refinement) and in FP32, timed; their detections compared bit for bit;
+    and the per-score error of the FP16 top-level map against the FP32 map
+    (both at the top level, every translation's best angle)."""
     import synth
 
-    cfg = dict(synth.CONFIGS[2])
+    scenes = [synth.scene_for_config(3, i) for i in range(2)]
+    cfg = scenes[0].config
     L = cfg["levels"]
-    nb = args.batch
-    scenes = [synth.scene_for_config(2, i) for i in range(nb)]
-    imgs = [torch.from_numpy(s.image).cuda() for s in scenes]
-    model = P.Model(scenes[0].model, L, cfg["tau_m"])
     sp = P.SearchParams(theta_step_top=cfg["theta_step_top"])
-    stream = torch.cuda.current_stream()
-    prec_b = P.TM_FP16 if args.precision == "fp16" else P.TM_FP32
-    K = int(np.ceil(360.0 / cfg["theta_step_top"]))
-    n_top = model.level_info(L - 1)[2]
+    model = P.Model(scenes[0].model, L, cfg["tau_m"])
+    imgs = [torch.from_numpy(s.image).cuda() for s in scenes]
+    out = {"workload": "2048x2048, 5 instances of a 256x256 model, 5 levels, 8 deg top step (45 angles, 0.5 deg at "
+                       "level 0), one detection per call"}
+    dets = {}
+    maps = {}
+    for name, prec in (("fp16", P.TM_FP16), ("fp32", P.TM_FP32)):
+        pyr = P.Pyramid(imgs[0], L, cfg["tau_s"], precision=prec)
+        o = torch.empty((sp.max_matches, P.tm.POSE_WORDS), dtype=torch.int32, device="cuda")
+        n = torch.zeros(1, dtype=torch.int32, device="cuda")
+        for i in range(2):
+            pyr.update(imgs[i % 2])
+            P.detect_async(model, pyr, sp, o, n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            pyr.update(imgs[i % 2])
+            P.detect_async(model, pyr, sp, o, n)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        dets[name] = []
+        for im in imgs:
+            pyr.update(im)
+            dets[name].append(P.detect(model, pyr, sp))
+        pyr.update(imgs[0])
+        maps[name] = [t.float().cpu().numpy() for t in P.score_map(model, pyr, L - 1, sp)]
+        out[name] = {"ms_per_detection": dt * 1e3, "detections_per_sec": 1.0 / dt,
+                     "detections": [len(d) for d in dets[name]]}
+        pyr.free()
+    out["fp16_equals_fp32_bit_for_bit"] = all(a.tobytes() == b.tobytes() for a, b in zip(dets["fp16"], dets["fp32"]))
+    e = np.abs(maps["fp16"][0].astype(np.float64) - maps["fp32"][0])
+    out["fp16_map_error_vs_fp32"] = {"max": float(e.max()), "mean": float(e.mean()),
+                                     "p99": float(np.percentile(e, 99)), "translations": int(e.size),
+                                     "angle_differs": int((maps["fp16"][2] != maps["fp32"][2]).sum())}
+    return out
 
-    # ---- leg 1: FP32 plain, one detection (pyramid + search) per call
-    pyr = P.Pyramid(imgs[0], L, cfg["tau_s"], precision=P.TM_FP32)
-    H3, W3 = pyr.level_shape(L - 1)
-    poses_per_det = H3 * W3 * K
-    taps_per_det = poses_per_det * n_top * 9
-    cap = sp.max_matches
-    outs = torch.empty((nb, cap, P.tm.POSE_WORDS), dtype=torch.int32, device="cuda")
-    nout = torch.zeros((nb,), dtype=torch.int32, device="cuda")
 
-    def plain(i):
-        j = i % nb
-        pyr.update(imgs[j])
-        P.detect_async(model, pyr, sp, outs[j], nout[j:j + 1])
-
-    for i in range(max(args.warmup, nb)):
-        plain(i)
-    torch.cuda.synchronize()
-    P.timing_read()
-    P.timing_enable(True)
-    plain_steps = max(args.steps, 1) * 4
-    t0 = time.perf_counter()
-    for i in range(plain_steps):
-        plain(i)
-    torch.cuda.synchronize()
-    plain_s = time.perf_counter() - t0
-    P.timing_enable(False)
-    plain_dense_ms, plain_launches = P.timing_read()
-    plain_dets = [P.poses_to_numpy(outs[j], int(nout[j].item())) for j in range(nb)]
-
-    # ---- leg 2 (the timed steps): all images in one batched enqueue.  With
-    # --streams S > 1, S batches over the same images (each with its own
-    # pyramids and scratch, the same search form) run on S streams of default
-    # priority and the steps alternate between them, so that one batch's
-    # latency-bound stages (selection, refinement) overlap the next one's
-    # search; every step is still one whole pass over its batch.
+def batched_leg(P, torch, model, imgs, L, cfg, sp, prec, args, stream):
+    """One batched leg as the headline times it: --streams batches over the
+    same images (each with its own pyramids and scratch, the same search
+    form) on their own streams of default priority, the steps alternating
+    between them, every step one whole pass over its batch.  Returns its
+    timing, detections and search form, and the search kernel's launch time
+    from HIP events around its launches in eager steps after the timed
+    region (one batch, same stream, nothing overlapping it)."""
     ns = max(1, args.streams)
-    batches = [P.Batch([model], imgs, L, cfg["tau_s"], sp, precision=prec_b) for _ in range(ns)]
+    nb = len(imgs)
+    batches = [P.Batch([model], imgs, L, cfg["tau_s"], sp, precision=prec) for _ in range(ns)]
     batch = batches[0]
     default_form = batch.search_form()
     tuned = batch.tune(iterations=3) if not args.no_tune else None
@@ -555,10 +634,9 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     elapsed = max(wall, ev0.elapsed_time(ev1) / 1e3)
-    bdets = batch.results()
+    dets = batch.results()
     for b in batches[1:]:  # the same images give the same detections on every batch
-        assert all(len(x) == len(y) and (x.tobytes() == y.tobytes()) for x, y in zip(b.results(), bdets))
-    # the search kernel's duration: HIP events around its launches (same stream)
+        assert all(len(x) == len(y) and (x.tobytes() == y.tobytes()) for x, y in zip(b.results(), dets))
     P.timing_read()
     P.timing_enable(True)
     for _ in range(max(5, min(args.steps, 20))):
@@ -566,19 +644,123 @@ def main():
     torch.cuda.synchronize()
     P.timing_enable(False)
     dense_ms, launches = P.timing_read()
+    for b in batches:
+        b.free()
+    return {"elapsed": elapsed, "dets": dets, "form": dict(form, tuned=tuned is not None, chosen_by=chosen_by),
+            "launch_s": dense_ms / max(launches, 1) / 1e3, "ns": ns}
 
-    # the same top-1 pose, or no detection in either leg
-    same_top1 = sum(1 for a, b in zip(plain_dets, bdets)
-                    if (not len(a) and not len(b)) or
-                    (len(a) and len(b) and (int(a[0]["x"]), int(a[0]["y"]), int(a[0]["k"])) ==
-                     (int(b[0]["x"]), int(b[0]["y"]), int(b[0]["k"]))))
-    hits_plain = sum(gt_hit(d, sc) for d, sc in zip(plain_dets, scenes))
-    hits_batch = sum(gt_hit(d, sc) for d, sc in zip(bdets, scenes))
 
-    dense_avg_s = dense_ms / max(launches, 1) / 1e3
+def ceilings(P):
+    """Measured ceilings of the search kernel's roofs (tm_probe): its VALU
+    instruction mix, each instruction class of it, plain FP32 adds, its LDS
+    read pattern and an HBM copy."""
+    return {"valu_mix_wave_instr_per_s": P.probe_rate(P.tm.PROBE_VALU_MIX, 4000),
+            "valu_dot2_wave_instr_per_s": P.probe_rate(P.tm.PROBE_DOT2, 4000),
+            "valu_max_dpp_wave_instr_per_s": P.probe_rate(P.tm.PROBE_MAX_DPP, 4000),
+            "valu_max3_wave_instr_per_s": P.probe_rate(P.tm.PROBE_MAX3, 4000),
+            "valu_add_wave_instr_per_s": P.probe_rate(P.tm.PROBE_VALU_ADD, 4000),
+            "lds_bytes_per_s": P.probe_rate(P.tm.PROBE_LDS, 4000),
+            "hbm_bytes_per_s": P.probe_rate(P.tm.PROBE_HBM, 1)}
+
+
+def main():
+    args = parse()
+    if args.trace_summary:
+        trace_summary(args.trace_summary)
+        return
+    if args.traffic_from:
+        traffic_from(*args.traffic_from)
+        return
+    if args.valu_from:
+        valu_from(args.valu_from)
+        return
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is single-GPU by design.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_2112_05576_amd as P
+    import synth
+
+    cfg = dict(synth.CONFIGS[2])
+    L = cfg["levels"]
+    nb = args.batch
+    scenes = [synth.scene_for_config(2, i) for i in range(nb)]
+    imgs = [torch.from_numpy(s.image).cuda() for s in scenes]
+    model = P.Model(scenes[0].model, L, cfg["tau_m"])
+    sp = P.SearchParams(theta_step_top=cfg["theta_step_top"])
+    stream = torch.cuda.current_stream()
+    prec_b = P.TM_FP16 if args.precision == "fp16" else P.TM_FP32
+    K = int(np.ceil(360.0 / cfg["theta_step_top"]))
+    n_top = model.level_info(L - 1)[2]
+
+    # ---- FP32 plain, one detection (pyramid + search) per call
+    pyr = P.Pyramid(imgs[0], L, cfg["tau_s"], precision=P.TM_FP32)
+    H3, W3 = pyr.level_shape(L - 1)
+    poses_per_det = H3 * W3 * K
+    taps_per_det = poses_per_det * n_top * 9
+    cap = sp.max_matches
+    outs = torch.empty((nb, cap, P.tm.POSE_WORDS), dtype=torch.int32, device="cuda")
+    nout = torch.zeros((nb,), dtype=torch.int32, device="cuda")
+
+    def plain(i):
+        j = i % nb
+        pyr.update(imgs[j])
+        P.detect_async(model, pyr, sp, outs[j], nout[j:j + 1])
+
+    for i in range(max(args.warmup, nb)):
+        plain(i)
+    torch.cuda.synchronize()
+    P.timing_read()
+    P.timing_enable(True)
+    plain_steps = max(args.steps, 1) * 4
+    t0 = time.perf_counter()
+    for i in range(plain_steps):
+        plain(i)
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    P.timing_enable(False)
+    plain_dense_ms, plain_launches = P.timing_read()
+    plain_dets = [P.poses_to_numpy(outs[j], int(nout[j].item())) for j in range(nb)]
+    pyr.free()
+
+    # ---- the headline: the batched leg in the asked precision (FP16 by
+    # default); beside it the other precision's batched leg
+    head = batched_leg(P, torch, model, imgs, L, cfg, sp, prec_b, args, stream)
+    other_prec = P.TM_FP32 if prec_b == P.TM_FP16 else P.TM_FP16
+    other_name = "fp32" if other_prec == P.TM_FP32 else "fp16"
+    other = batched_leg(P, torch, model, imgs, L, cfg, sp, other_prec, args, stream) if not args.no_other else None
+    bdets = head["dets"]
+    elapsed = head["elapsed"]
+    hits = {"fp32_plain": sum(gt_hit(d, sc) for d, sc in zip(plain_dets, scenes)),
+            f"{args.precision}_batched": sum(gt_hit(d, sc) for d, sc in zip(bdets, scenes))}
+    same_bits = {f"{args.precision}_batched_vs_fp32_plain":
+                 sum(a.tobytes() == b.tobytes() for a, b in zip(bdets, plain_dets))}
+    if other is not None:
+        hits[f"{other_name}_batched"] = sum(gt_hit(d, sc) for d, sc in zip(other["dets"], scenes))
+        same_bits[f"{args.precision}_batched_vs_{other_name}_batched"] = sum(
+            a.tobytes() == b.tobytes() for a, b in zip(bdets, other["dets"]))
+
+    dense_avg_s = head["launch_s"]
     flops = taps_per_det * nb * FLOP_PER_TAP
     achieved = flops / dense_avg_s / 1e12
     dets_per_s = nb * args.steps / elapsed
+    ceil = ceilings(P)
+    roof = {"kernel": "k_dense_fast (exhaustive top-level search, all images of the step)", "bound": "alu",
+            "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_entry(head["form"]),
+            "launch_us": dense_avg_s * 1e6, "flop_per_launch": flops,
+            "taps_per_s": taps_per_det * nb / dense_avg_s,
+            "lds_tap_ceiling_taps_per_s": ceil["lds_bytes_per_s"] / (4 if prec_b == P.TM_FP16 else 8),
+            "measured_ceilings": ceil}
+    valu = valu_entry(head["form"], args.precision)
+    if valu is not None:
+        rate = valu["valu_instr_per_launch"] / dense_avg_s
+        roof["executed_valu"] = dict(valu, wave_instr_per_s=rate,
+                                     frac_of_mix_probe=rate / ceil["valu_mix_wave_instr_per_s"],
+                                     issue_floor_us=valu["valu_instr_per_launch"] /
+                                     ceil["valu_mix_wave_instr_per_s"] * 1e6)
     res = {
         "metric": "pose-evals/sec and detections/sec at 640x480 (FP32 plain vs FP16 batched, equal top-1)",
         "value": poses_per_det * dets_per_s,
@@ -596,23 +778,28 @@ def main():
                                "4 levels, 1 deg top step (80x60x360 top poses per image), full detection",
                    "images_per_step": nb, "levels": L, "top_angles": K, "model_points_top": n_top,
                    "path": f"{args.precision}-batched" + ("" if args.eager else ", graph launch")
-                           + (f", {ns} batches in flight on {ns} streams" if ns > 1 else ""),
-                   "search_form": dict(form, tuned=tuned is not None, chosen_by=chosen_by)},
+                           + (f", {head['ns']} batches in flight on {head['ns']} streams" if head["ns"] > 1 else "")
+                           + (", certified FP16 search, FP32 refinement" if args.precision == "fp16" else ""),
+                   "search_form": head["form"]},
         "detections_per_sec": dets_per_s,
         "taps_per_sec": taps_per_det * dets_per_s,
         "fp32_plain": {"pose_evals_per_sec": poses_per_det * plain_steps / plain_s,
                        "detections_per_sec": plain_steps / plain_s,
                        "us_per_detection": plain_s / plain_steps * 1e6,
                        "search_kernel_us": plain_dense_ms / max(plain_launches, 1) * 1e3},
-        "equal_top1": f"{same_top1}/{nb}",
-        "top1_ground_truth_hits": {"fp32_plain": f"{hits_plain}/{nb}", "batched": f"{hits_batch}/{nb}"},
-        "roofline": {"kernel": "k_dense_fast (exhaustive top-level search, all images of the step)", "bound": "alu",
-                     "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_entry(form),
-                     "launch_us": dense_avg_s * 1e6, "flop_per_launch": flops},
+        "same_detections_bit_for_bit": same_bits,
+        "top1_ground_truth_hits": {k: f"{v}/{nb}" for k, v in hits.items()},
+        "roofline": roof,
     }
+    if other is not None:
+        res[f"{other_name}_batched"] = {"ms_per_step": other["elapsed"] * 1e3 / args.steps,
+                                        "detections_per_sec": nb * args.steps / other["elapsed"],
+                                        "pose_evals_per_sec": poses_per_det * nb * args.steps / other["elapsed"],
+                                        "search_launch_us": other["launch_s"] * 1e6, "search_form": other["form"]}
     if args.c4:
         res["c4"], res["c5"] = c4_legs(P, torch, max(2, args.steps // 10), 1)
+    if args.c3:
+        res["c3"] = c3_leg(P, torch, max(5, args.steps // 5))
     if args.paper:
         res["paper_shape"] = paper_leg(P, torch, max(8, args.steps))
     if args.similarity:
@@ -620,7 +807,11 @@ def main():
     if args.readings:
         res["readings"] = readings_leg(P, torch, max(5, args.steps // 4))
     if not args.no_cpu_baseline:
-        res["cpu_baseline"] = cpu_baseline(scenes[:8], cfg, args.cpu_seconds, paper=args.paper)
+        res["cpu_baseline"], oracle = cpu_baseline(scenes, cfg, args.cpu_seconds, paper=args.paper)
+        res["top1_vs_oracle"] = {"fp32_plain": top1_vs_oracle(plain_dets, oracle, cfg),
+                                 f"{args.precision}_batched": top1_vs_oracle(bdets, oracle, cfg)}
+        if other is not None:
+            res["top1_vs_oracle"][f"{other_name}_batched"] = top1_vs_oracle(other["dets"], oracle, cfg)
     if args.copy_probe:
         x = torch.ones(COPY_PROBE_BYTES // 4, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)

@@ -418,6 +418,25 @@ tm_status tm_pyramid_read(const tm_pyramid* pyr, int32_t level, uint8_t* img_dev
 tm_status tm_timing_enable(int32_t on);
 tm_status tm_timing_read(double* dense_ms, int32_t* launches);
 
+/* Ceiling probes for the roofline of the exhaustive search (measurement
+ * infrastructure, not part of the method): one launch that runs a single
+ * instruction mix of the search at full occupancy, enqueued on `stream`; the
+ * caller times it (events around the call) and divides *work_out by the time.
+ *  kind 0: the search's per-point arithmetic (10 v_dot2_f32_f16, 8 v_max3_f32,
+ *          16 DPP maxima, 8 sums): *work_out = wave-level VALU instructions;
+ *  kind 1: independent v_add_f32: *work_out = wave-level VALU instructions;
+ *  kind 2: the search's LDS reads (10 rows of a strip a lane, 4 bytes each,
+ *          at a moving wave-uniform offset): *work_out = bytes read;
+ *  kind 3: streaming copy of the first half of buf_dev into the second:
+ *          *work_out = bytes read plus written (HBM stream);
+ *  kinds 4, 5, 6: one instruction class of the mix at a time (v_dot2_f32_f16,
+ *          DPP v_max_f32, v_max3_f32): *work_out = wave-level VALU instructions.
+ * iterations (1 .. 10^6) sets the length of kinds 0-2; buf_dev is device
+ * memory of buf_bytes bytes (>= 256; kinds 0-2 only write it if a result
+ * that never occurs comes out).  TM_EINVAL on a bad kind or size. */
+tm_status tm_probe(int32_t kind, int32_t iterations, void* buf_dev, int64_t buf_bytes, void* stream,
+                   double* work_out);
+
 void tm_model_free(tm_model* model);
 void tm_pyramid_free(tm_pyramid* pyr);
 

@@ -208,6 +208,76 @@ struct FastArgs {
     const int2* work;   // optional work list: block b runs (pair, block) work[b]; pair < 0: nothing
 };
 
+// What a certified FP16 search keeps per translation and angle range: the
+// best angle by the key (S_w desc, S_1 desc, k asc; the fast kernel's screen
+// has no S_1 and keeps 0), the runner-up by S_w (its angle), and the best S_w
+// of all the remaining angles.  Invariant: w3 <= w2 <= w.
+struct Top3 {
+    float w, s;
+    int k;
+    float w2;
+    int k2;
+    float w3;
+};
+
+// Add one angle's (S_w, S_1, k) to a summary.
+__device__ __forceinline__ void top3_add(Top3& t, float w, float s, int k)
+{
+    if (key_better(w, s, 0, 0, k, t.w, t.s, 0, 0, t.k)) {
+        t.w3 = fmaxf(t.w3, t.w2);
+        t.w2 = t.w;
+        t.k2 = t.k;
+        t.w = w;
+        t.s = s;
+        t.k = k;
+    } else if (w > t.w2) {
+        t.w3 = fmaxf(t.w3, t.w2);
+        t.w2 = w;
+        t.k2 = k;
+    } else {
+        t.w3 = fmaxf(t.w3, w);
+    }
+}
+
+// Merge the summary of another set of angles into a.
+__device__ __forceinline__ void top3_merge(Top3& a, const Top3& b)
+{
+    if (key_better(b.w, b.s, 0, 0, b.k, a.w, a.s, 0, 0, a.k)) {
+        Top3 r = b;
+        if (a.w > b.w2) {  // a's best is the runner-up
+            r.w2 = a.w;
+            r.k2 = a.k;
+            r.w3 = fmaxf(b.w2, a.w2);
+        } else {
+            r.w3 = fmaxf(b.w3, a.w);
+        }
+        a = r;
+    } else if (b.w > a.w2) {  // b's best is the runner-up
+        a.w3 = fmaxf(a.w2, b.w2);
+        a.w2 = b.w;
+        a.k2 = b.k;
+    } else {
+        a.w3 = fmaxf(a.w3, b.w);
+    }
+}
+
+// Chunk partials of a certified search: best (S_w, S_1, k), runner-up (S_w,
+// k), rest's best S_w.
+__device__ __forceinline__ void top3_store(const PairDesc& P, size_t o, const Top3& t)
+{
+    P.pw[o] = t.w;
+    P.p1[o] = t.s;
+    P.pk[o] = t.k;
+    P.p2[o] = t.w2;
+    P.pk2[o] = t.k2;
+    P.p3[o] = t.w3;
+}
+
+__device__ __forceinline__ Top3 top3_load(const PairDesc& P, size_t o)
+{
+    return Top3{P.pw[o], P.p1[o], P.pk[o], P.p2[o], P.pk2[o], P.p3[o]};
+}
+
 // VAR: 0 compiler-built products and window maxima; 1 the same with the
 // VOP3P dot and the DPP-folded maxima written out; 2, 3, 4 as 1 with 2, 4, 8
 // table entries fetched per loop step (one scalar-load wait per step); 5 as 3
@@ -218,7 +288,11 @@ struct FastArgs {
 // the addend stored with each tile pixel (TileOf), and the centre sum takes
 // vote_finish of the product, which is the plain product on the edge set and
 // -0 elsewhere.
-template <int G, int R, int LC, int PREC, int VAR, int VOTE>
+// SCREEN (an FP16 search whose decisions are certified): no centre sum; per
+// row the best angle by (S_w desc, k asc), the runner-up's S_w and angle, and
+// the best S_w of the remaining angles (Top3 below), which is what the
+// certification needs to know which angles could win in FP32.
+template <int G, int R, int LC, int PREC, int VAR, int VOTE, bool SCREEN = false>
 __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc* __restrict__ pairs)
 {
     using Tile = TileOf<PREC, VOTE>;
@@ -281,18 +355,17 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc*
     const int n_pad = P.n_pad;
     const float n_f = (float)P.n[a.level];
 
-    // per row: the best angle by the key and, in FP16, the best S_w over the
-    // other angles (b2), which tells the certification of the FP16 search
-    // whether another angle could win in FP32
-    constexpr bool SECOND = PREC == TM_FP16;
-    float bw[R], b1[R], b2[R];
-    int bk[R];
+    static_assert(!SCREEN || PREC == TM_FP16, "only the FP16 search is certified");
+    float bw[R], b1[R], w2[R], w3[R];
+    int bk[R], k2[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         bw[r] = -INFINITY;
         b1[r] = -INFINITY;
-        b2[r] = -INFINITY;
+        w2[r] = -INFINITY;
+        w3[r] = -INFINITY;
         bk[r] = -1;
+        k2[r] = -1;
     }
     const int k0 = chunk * a.A, k1 = min(a.K, k0 + a.A);
     for (int k = k0 + wa; k < k1; k += a.WA) {
@@ -353,13 +426,13 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc*
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         pw[r] += win_finish<VOTE>(M[r]);
-                        p1[r] += D[r + 1];
+                        if constexpr (!SCREEN) p1[r] += D[r + 1];
                     }
                 } else {
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         pw[r] += win_finish<VOTE>(hmax3<ASM>(V[r]));
-                        p1[r] += D[r + 1];
+                        if constexpr (!SCREEN) p1[r] += D[r + 1];
                     }
                 }
             };
@@ -409,39 +482,60 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc*
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 tw[r] += pw[r];
-                t1[r] += p1[r];
+                if constexpr (!SCREEN) t1[r] += p1[r];
             }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const float sw = tw[r] / n_f, s1 = t1[r] / n_f;
-            if (sw > bw[r] || (sw == bw[r] && s1 > b1[r])) {
-                if constexpr (SECOND) b2[r] = bw[r];  // >= every earlier other angle's S_w
-                bw[r] = sw;
-                b1[r] = s1;
-                bk[r] = k;
-            } else if constexpr (SECOND) {
-                b2[r] = fmaxf(b2[r], sw);
+            const float sw = tw[r] / n_f;
+            if constexpr (SCREEN) {
+                // angles arrive in increasing order: a strictly larger S_w wins
+                if (sw > bw[r]) {
+                    w3[r] = fmaxf(w3[r], w2[r]);
+                    w2[r] = bw[r];
+                    k2[r] = bk[r];
+                    bw[r] = sw;
+                    bk[r] = k;
+                } else if (sw > w2[r]) {
+                    w3[r] = fmaxf(w3[r], w2[r]);
+                    w2[r] = sw;
+                    k2[r] = k;
+                } else {
+                    w3[r] = fmaxf(w3[r], sw);
+                }
+            } else {
+                const float s1 = t1[r] / n_f;
+                if (sw > bw[r] || (sw == bw[r] && s1 > b1[r])) {
+                    bw[r] = sw;
+                    b1[r] = s1;
+                    bk[r] = k;
+                }
             }
         }
     }
 
-    // combine the WA waves that share this tile, in key order (the second
-    // best: the larger of the kept one's second best and the other's best)
+    // combine the WA waves that share this tile, in key order
     __syncthreads();
     const int npos = TH * TW;
+    const int nq = a.WA * npos;
     float* cw = reinterpret_cast<float*>(smem);
-    float* c1 = cw + a.WA * npos;
-    int* ck = reinterpret_cast<int*>(c1 + a.WA * npos);
-    float* c2 = reinterpret_cast<float*>(ck + a.WA * npos);
+    float* c1 = cw + nq;  // S_1; in SCREEN the runner-up's S_w
+    int* ck = reinterpret_cast<int*>(c1 + nq);
+    int* ck2 = ck + nq;   // SCREEN: the runner-up's angle
+    float* c3 = reinterpret_cast<float*>(ck2 + nq);  // SCREEN: the best S_w of the rest
     if (li >= 1 && li <= G - 2) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int idx = (wa * TH + row0 + r) * TW + (li - 1);
             cw[idx] = bw[r];
-            c1[idx] = b1[r];
             ck[idx] = bk[r];
-            if constexpr (SECOND) c2[idx] = b2[r];
+            if constexpr (SCREEN) {
+                c1[idx] = w2[r];
+                ck2[idx] = k2[r];
+                c3[idx] = w3[r];
+            } else {
+                c1[idx] = b1[r];
+            }
         }
     }
     __syncthreads();
@@ -449,24 +543,29 @@ __global__ __launch_bounds__(1024) void k_dense_fast(FastArgs a, const PairDesc*
         const int pv = p / TW, pu = p - pv * TW;
         const int X = tr ? V0 + pv : U0 + pu, Y = tr ? U0 + pu : V0 + pv;
         if (X >= W || Y >= H) continue;
-        float w0 = cw[p], s0 = c1[p], q0 = SECOND ? c2[p] : 0.f;
-        int kk = ck[p];
-        for (int w = 1; w < a.WA; ++w) {
-            const int q = w * npos + p;
-            if (key_better(cw[q], c1[q], 0, 0, ck[q], w0, s0, 0, 0, kk)) {
-                if constexpr (SECOND) q0 = fmaxf(c2[q], w0);
-                w0 = cw[q];
-                s0 = c1[q];
-                kk = ck[q];
-            } else if constexpr (SECOND) {
-                q0 = fmaxf(q0, cw[q]);
-            }
-        }
         const size_t o = ((size_t)chunk * H + Y) * W + X;
-        P.pw[o] = w0;
-        P.p1[o] = s0;
-        P.pk[o] = kk;
-        if constexpr (SECOND) P.p2[o] = q0;
+        if constexpr (SCREEN) {
+            Top3 t{cw[p], 0.f, ck[p], c1[p], ck2[p], c3[p]};
+            for (int w = 1; w < a.WA; ++w) {
+                const int q = w * npos + p;
+                top3_merge(t, Top3{cw[q], 0.f, ck[q], c1[q], ck2[q], c3[q]});
+            }
+            top3_store(P, o, t);
+        } else {
+            float w0 = cw[p], s0 = c1[p];
+            int kk = ck[p];
+            for (int w = 1; w < a.WA; ++w) {
+                const int q = w * npos + p;
+                if (key_better(cw[q], c1[q], 0, 0, ck[q], w0, s0, 0, 0, kk)) {
+                    w0 = cw[q];
+                    s0 = c1[q];
+                    kk = ck[q];
+                }
+            }
+            P.pw[o] = w0;
+            P.p1[o] = s0;
+            P.pk[o] = kk;
+        }
     }
 }
 
@@ -498,7 +597,8 @@ __global__ __launch_bounds__(256) void k_pad_field(int level, const PairDesc* __
 // per step over the padded table (padding entries, q = 0 and r = 0, add
 // exactly 0; blocks keep their bounds since 8 divides 32).  VOTE as in
 // k_dense_fast.  grid: (translations, chunk, pair).
-template <int PREC, int VOTE>
+// SCREEN: also the runner-up and the rest's best (Top3) for the certification.
+template <int PREC, int VOTE, bool SCREEN = false>
 __global__ __launch_bounds__(256) void k_dense_generic(GenericArgs a, const PairDesc* __restrict__ pairs)
 {
     using T = typename Px<PREC>::T;
@@ -523,9 +623,7 @@ __global__ __launch_bounds__(256) void k_dense_generic(GenericArgs a, const Pair
         else
             return d;
     };
-    constexpr bool SECOND = PREC == TM_FP16;  // as in k_dense_fast
-    float bw = -INFINITY, b1 = -INFINITY, b2 = -INFINITY;
-    int bk = -1;
+    Top3 t{-INFINITY, -INFINITY, -1, -INFINITY, -1, -INFINITY};
     const int k0 = chunk * a.A, k1 = min(a.K, k0 + a.A);
     for (int k = k0; k < k1; ++k) {
         CTabEntry* Tb = (CTabEntry*)P.tab + (size_t)k * P.n_pad;  // wave-uniform: scalar loads
@@ -576,20 +674,22 @@ __global__ __launch_bounds__(256) void k_dense_generic(GenericArgs a, const Pair
             t1 += p1;
         }
         const float sw = tw / n_f, s1 = t1 / n_f;
-        if (sw > bw || (sw == bw && s1 > b1)) {
-            if constexpr (SECOND) b2 = bw;
-            bw = sw;
-            b1 = s1;
-            bk = k;
-        } else if constexpr (SECOND) {
-            b2 = fmaxf(b2, sw);
+        if constexpr (SCREEN) {
+            top3_add(t, sw, s1, k);
+        } else if (sw > t.w || (sw == t.w && s1 > t.s)) {
+            t.w = sw;
+            t.s = s1;
+            t.k = k;
         }
     }
     const size_t o = ((size_t)chunk * gh + gy) * gw + gx;
-    P.pw[o] = bw;
-    P.p1[o] = b1;
-    P.pk[o] = bk;
-    if constexpr (SECOND) P.p2[o] = b2;
+    if constexpr (SCREEN) {
+        top3_store(P, o, t);
+    } else {
+        P.pw[o] = t.w;
+        P.p1[o] = t.s;
+        P.pk[o] = t.k;
+    }
 }
 
 // Best angle per translation over the C chunk partials, in key order.  A
@@ -660,6 +760,25 @@ __global__ __launch_bounds__(256) void k_reduce_chunks(int C, const PairDesc* __
         P.m1[p] = s0;
         P.mk[p] = k;
     }
+}
+
+// Per translation of a certified search: the chunks' Top3 summaries merged
+// (the key is a total order, so the merge order does not matter), written to
+// the map with the runner-up and the rest's best.
+__global__ __launch_bounds__(256) void k_reduce_screen(int C, const PairDesc* __restrict__ pairs)
+{
+    const PairDesc& P = pairs[blockIdx.y];
+    const int np = P.gw * P.gh;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    Top3 t = top3_load(P, p);
+    for (int c = 1; c < C; ++c) top3_merge(t, top3_load(P, (size_t)c * np + p));
+    P.mw[p] = t.w;
+    P.m1[p] = t.s;
+    P.mk[p] = t.k;
+    P.m2[p] = t.w2;
+    P.mk2[p] = t.k2;
+    P.m3[p] = t.w3;
 }
 
 // One wave per pose: lanes take points i = lane, lane + 64, ...; each point's
@@ -749,16 +868,20 @@ struct CertArgs {
     int level, C, A, K, win, sx, sy;
     float min_score;
     CertBufs cb;
-    int lds_bytes;  // k_rescore_multi: bytes of its staged field block (0: gathers only)
+    int lds_bytes;  // k_rescore: bytes of its staged field block (0: gathers only)
 };
 
 __global__ __launch_bounds__(64) void k_cert_zero(int* count)
 {
-    if (threadIdx.x < 2) count[threadIdx.x] = 0;
+    if (threadIdx.x == 0) count[0] = 0;
 }
 
 // One thread per translation of every pair: the translations whose FP32
-// values the selection needs, queued with the angles to score.
+// values the selection needs, queued with the angles to score.  Entry
+// (pair, translation, a, b): the angles a and b (b < 0: none) when every
+// other angle is below M - 2E (the map's runner-up and rest's best say so);
+// otherwise (-1 - pair, translation, mask low, mask high): the angle chunks
+// whose FP16 best reaches M - 2E.
 __global__ __launch_bounds__(256) void k_certify(CertArgs a, const PairDesc* __restrict__ pairs)
 {
     const int pr = blockIdx.y;
@@ -800,50 +923,100 @@ __global__ __launch_bounds__(256) void k_certify(CertArgs a, const PairDesc* __r
             if ((u || v) && !need && possible(2 + v, 2 + u) && hi_u >= M[2 + v][2 + u] - E) need = true;
     if (!need) return;
     const double lim = M[2][2] - 2.0 * E;
-    unsigned long long mask = 0ull;
-    int nc = 0, c1 = -1;
-    for (int c = 0; c < a.C; ++c)
-        if ((double)P.pw[(size_t)c * np + p] >= lim) {
-            if (c < 64) mask |= 1ull << c;
-            if (nc++ == 0) c1 = c;
-        }
-    if (nc == 1 && a.C <= 64 && (double)P.p2[(size_t)c1 * np + p] < lim) {
-        const int i = atomicAdd(&a.cb.count[1], 1);
-        a.cb.single[i] = make_int2(pr, p);
+    int4 en;
+    if ((double)P.m3[p] < lim) {
+        // the FP32 best is the FP16 best angle, or the runner-up if it reaches M - 2E
+        en = make_int4(pr, p, P.mk[p], (double)P.m2[p] >= lim ? P.mk2[p] : -1);
     } else {
+        unsigned long long mask = 0ull;
+        for (int c = 0; c < a.C && c < 64; ++c)
+            if ((double)P.pw[(size_t)c * np + p] >= lim) mask |= 1ull << c;
         if (a.C > 64) mask = ~0ull;  // all angles
-        const int i = atomicAdd(&a.cb.count[0], 1);
-        a.cb.multi[i] = make_int4(pr, p, (int)(unsigned)(mask & 0xffffffffull), (int)(unsigned)(mask >> 32));
+        en = make_int4(-1 - pr, p, (int)(unsigned)(mask & 0xffffffffull), (int)(unsigned)(mask >> 32));
     }
+    a.cb.list[atomicAdd(&a.cb.count[0], 1)] = en;
+}
+
+// One model point's windowed vote (the maximum of its window's products,
+// finished for the edge-taps reading) and its centre product, in FP32 with
+// the FP32 search's arithmetic.  g(qx, qy): the FP32 field at the
+// translation plus (qx, qy), zero outside the image.  HW: the window's half
+// side when it is 1 (the loops unrolled), else -1 (h at run time).
+template <int VOTE, int HW, class Fetch>
+__device__ __forceinline__ void vote_fp32(const TabEntry& e, int h, Fetch g, float* vote, float* centre)
+{
+    float best = -INFINITY, c = 0.f;
+    auto tap = [&](int dx, int dy) {
+        const float2 v = g((int)e.qx + dx, (int)e.qy + dy);
+        const float d = Px<TM_FP32>::dot(e, v);
+        if (dx == 0 && dy == 0) c = d;
+        if constexpr (VOTE == 1)
+            best = fmaxf(best, Px<TM_FP32>::edge(v) ? d : kOffEdge);
+        else
+            best = fmaxf(best, d);
+    };
+    if constexpr (HW == 1) {
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) tap(dx, dy);
+    } else {
+        for (int dy = -h; dy <= h; ++dy)
+            for (int dx = -h; dx <= h; ++dx) tap(dx, dy);
+    }
+    *vote = win_finish<VOTE>(best);
+    *centre = c;
+}
+
+// One pose scored by a whole wave, lane t taking points t, t + 64, ...: the
+// votes are computed side by side and then added in point order (blocks of
+// 32, block sums in order) by reading them lane by lane, so the sums are
+// those of score_fp32 bit for bit.  Every lane returns the result.
+template <int VOTE, int HW, class Fetch>
+__device__ __forceinline__ void score_fp32_wave(const TabEntry* __restrict__ Tb, int n_pad, float n_f, int h, Fetch g,
+                                                float* sw, float* s1)
+{
+    const int lane = threadIdx.x & 63;
+    float tw = 0.f, t1 = 0.f, pw = 0.f, p1 = 0.f;
+    for (int i0 = 0; i0 < n_pad; i0 += 64) {
+        float v = 0.f, c = 0.f;
+        if (i0 + lane < n_pad) vote_fp32<VOTE, HW>(Tb[i0 + lane], h, g, &v, &c);
+        const int m = min(64, n_pad - i0);  // a multiple of 8, so block ends fall on lanes 31 and 63
+        for (int j = 0; j < m; ++j) {
+            pw += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
+            p1 += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c), j));
+            if (((i0 + j) & (kBlock - 1)) == kBlock - 1 || i0 + j == n_pad - 1) {
+                tw += pw;
+                t1 += p1;
+                pw = 0.f;
+                p1 = 0.f;
+            }
+        }
+    }
+    *sw = tw / n_f;
+    *s1 = t1 / n_f;
 }
 
 // Eq. (1) of one pose in FP32 with the FP32 search's arithmetic: window
 // maximum of the products of each (padded) table entry, votes added in
 // blocks of 32 points in point order, block sums in order, one division.
 // g(qx, qy): the FP32 field at the translation plus (qx, qy), zero outside
-// the image.
-template <int VOTE, class Fetch>
-__device__ __forceinline__ void score_fp32(const TabEntry* __restrict__ Tb, int n_pad, float n_f, int h, Fetch g,
+// the image.  HW: the window's half side when it is 1 (the loops unrolled),
+// else -1 (h at run time).
+template <int VOTE, int HW, class Fetch>
+__device__ __forceinline__ void score_fp32(const TabEntry* __restrict__ Tb, int n_pad, float n_f, int h_rt, Fetch g,
                                            float* sw, float* s1)
 {
+    const int h = HW >= 0 ? HW : h_rt;
     float tw = 0.f, t1 = 0.f;
     for (int i0 = 0; i0 < n_pad; i0 += kBlock) {
         float pw = 0.f, p1 = 0.f;
         const int i1 = min(n_pad, i0 + kBlock);
         for (int i = i0; i < i1; ++i) {
-            const TabEntry e = Tb[i];
-            float best = -INFINITY;
-            for (int dy = -h; dy <= h; ++dy)
-                for (int dx = -h; dx <= h; ++dx) {
-                    const float2 v = g((int)e.qx + dx, (int)e.qy + dy);
-                    const float d = Px<TM_FP32>::dot(e, v);
-                    if constexpr (VOTE == 1)
-                        best = fmaxf(best, Px<TM_FP32>::edge(v) ? d : kOffEdge);
-                    else
-                        best = fmaxf(best, d);
-                }
-            pw += win_finish<VOTE>(best);
-            p1 += Px<TM_FP32>::dot(e, g((int)e.qx, (int)e.qy));
+            float v, c;
+            vote_fp32<VOTE, HW>(Tb[i], h, g, &v, &c);
+            pw += v;
+            p1 += c;
         }
         tw += pw;
         t1 += p1;
@@ -852,25 +1025,25 @@ __device__ __forceinline__ void score_fp32(const TabEntry* __restrict__ Tb, int 
     *s1 = t1 / n_f;
 }
 
-// The queued translations with several open angle chunks: one workgroup per
-// translation (looping over the queue), the FP32 field block around it
-// staged in LDS when it fits, one thread per angle of the open chunks, the
-// best by the key (S_w desc, S_1 desc, angle asc) written to the map.
-template <int VOTE>
-__global__ __launch_bounds__(256) void k_rescore_multi(CertArgs a, const PairDesc* __restrict__ pairs)
+// The queued translations: one workgroup per translation (looping over the
+// queue), the FP32 field block around it staged in LDS when it fits, one
+// thread per angle to score, the best by the key (S_w desc, S_1 desc, angle
+// asc) written to the map.
+template <int VOTE, int HW>
+__global__ __launch_bounds__(256) void k_rescore(CertArgs a, const PairDesc* __restrict__ pairs)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     float2* blk = reinterpret_cast<float2*>(smem);
     __shared__ float rw[4], r1[4];
     __shared__ int rk[4];
-    __shared__ int ch_lo[64], ch_n[64], n_ch, n_ang;
+    __shared__ int ch_lo[64], ch_n[64], n_ang;
     const int count = a.cb.count[0];
     const int h = (a.win - 1) / 2;
     for (int e = blockIdx.x; e < count; e += gridDim.x) {
-        const int4 en = a.cb.multi[e];
-        const PairDesc& P = pairs[en.x];
+        const int4 en = a.cb.list[e];
+        const bool chunks = en.x < 0;
+        const PairDesc& P = pairs[chunks ? -1 - en.x : en.x];
         const int p = en.y;
-        const unsigned long long mask = (unsigned long long)(unsigned)en.z | ((unsigned long long)(unsigned)en.w << 32);
         const int x = (p % P.gw) * a.sx, y = (p / P.gw) * a.sy;
         const int W = P.W[a.level], H = P.H[a.level];
         const float2* __restrict__ f32 = reinterpret_cast<const float2*>(P.field[a.level]);
@@ -878,22 +1051,31 @@ __global__ __launch_bounds__(256) void k_rescore_multi(CertArgs a, const PairDes
         const bool staged = (long long)S * S * 8 <= a.lds_bytes;
         if (threadIdx.x == 0) {
             int m = 0, t = 0;
-            for (int c = 0; c < a.C; ++c)
-                if (a.C > 64 || ((mask >> c) & 1ull)) {
-                    if (m < 64) {
-                        ch_lo[m] = c * a.A;
-                        ch_n[m] = min(a.K, (c + 1) * a.A) - c * a.A;
-                        t += ch_n[m];
-                    }
-                    ++m;
+            if (!chunks) {
+                ch_lo[0] = en.z;
+                ch_n[0] = 1;
+                m = 1;
+                t = 1;
+                if (en.w >= 0) {
+                    ch_lo[1] = en.w;
+                    ch_n[1] = 1;
+                    m = 2;
+                    t = 2;
                 }
-            if (m > 64) {  // more than 64 chunks: every angle as one range
+            } else if (a.C > 64) {  // every angle as one range
                 ch_lo[0] = 0;
                 ch_n[0] = a.K;
-                m = 1;
                 t = a.K;
+            } else {
+                const unsigned long long mask =
+                    (unsigned long long)(unsigned)en.z | ((unsigned long long)(unsigned)en.w << 32);
+                for (int c = 0; c < a.C; ++c)
+                    if ((mask >> c) & 1ull) {
+                        ch_lo[m] = c * a.A;
+                        ch_n[m] = min(a.K, (c + 1) * a.A) - c * a.A;
+                        t += ch_n[m++];
+                    }
             }
-            n_ch = m;
             n_ang = t;
         }
         if (staged)
@@ -907,29 +1089,47 @@ __global__ __launch_bounds__(256) void k_rescore_multi(CertArgs a, const PairDes
         float kw = -INFINITY, k1 = -INFINITY;
         int kk = 0x7fffffff;
         const float n_f = (float)P.n[a.level];
-        for (int j = threadIdx.x; j < n_ang; j += blockDim.x) {
-            int c = 0, r = j;
-            while (r >= ch_n[c]) r -= ch_n[c++];
-            const int k = ch_lo[c] + r;
-            const TabEntry* Tb = P.tab + (size_t)k * P.n_pad;
-            float sw, s1;
-            if (staged) {
-                const float2* ctr = blk + B * S + B;
-                score_fp32<VOTE>(Tb, P.n_pad, n_f, h, [&](int qx, int qy) { return ctr[qy * S + qx]; }, &sw, &s1);
-            } else {
-                score_fp32<VOTE>(Tb, P.n_pad, n_f, h,
-                                 [&](int qx, int qy) {
-                                     const int gx = x + qx, gy = y + qy;
-                                     return ((unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H)
-                                                ? f32[(size_t)gy * W + gx]
-                                                : make_float2(0.f, 0.f);
-                                 },
-                                 &sw, &s1);
+        const float2* ctr = blk + B * S + B;
+        auto staged_at = [&](int qx, int qy) { return ctr[qy * S + qx]; };
+        auto gathered_at = [&](int qx, int qy) {
+            const int gx = x + qx, gy = y + qy;
+            return ((unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H) ? f32[(size_t)gy * W + gx]
+                                                                              : make_float2(0.f, 0.f);
+        };
+        if (!chunks) {
+            // one or two angles: a wave each, its lanes taking the points
+            const int wv = threadIdx.x >> 6;
+            if (wv < n_ang) {
+                const int k = ch_lo[wv];
+                const TabEntry* Tb = P.tab + (size_t)k * P.n_pad;
+                float sw, s1;
+                if (staged)
+                    score_fp32_wave<VOTE, HW>(Tb, P.n_pad, n_f, h, staged_at, &sw, &s1);
+                else
+                    score_fp32_wave<VOTE, HW>(Tb, P.n_pad, n_f, h, gathered_at, &sw, &s1);
+                if ((threadIdx.x & 63) == 0) {
+                    kw = sw;
+                    k1 = s1;
+                    kk = k;
+                }
             }
-            if (key_better(sw, s1, 0, 0, k, kw, k1, 0, 0, kk)) {
-                kw = sw;
-                k1 = s1;
-                kk = k;
+        } else {
+            // open chunks: a thread per angle, its points in order
+            for (int j = threadIdx.x; j < n_ang; j += blockDim.x) {
+                int c = 0, r = j;
+                while (r >= ch_n[c]) r -= ch_n[c++];
+                const int k = ch_lo[c] + r;
+                const TabEntry* Tb = P.tab + (size_t)k * P.n_pad;
+                float sw, s1;
+                if (staged)
+                    score_fp32<VOTE, HW>(Tb, P.n_pad, n_f, h, staged_at, &sw, &s1);
+                else
+                    score_fp32<VOTE, HW>(Tb, P.n_pad, n_f, h, gathered_at, &sw, &s1);
+                if (key_better(sw, s1, 0, 0, k, kw, k1, 0, 0, kk)) {
+                    kw = sw;
+                    k1 = s1;
+                    kk = k;
+                }
             }
         }
         // the best of the workgroup by the key (a total order: any merge order gives it)
@@ -965,35 +1165,6 @@ __global__ __launch_bounds__(256) void k_rescore_multi(CertArgs a, const PairDes
     }
 }
 
-// The queued translations whose FP32 best is the FP16 best angle: one thread
-// each, taps gathered from the FP32 field.
-template <int VOTE>
-__global__ __launch_bounds__(256) void k_rescore_single(CertArgs a, const PairDesc* __restrict__ pairs)
-{
-    const int count = a.cb.count[1];
-    const int h = (a.win - 1) / 2;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < count; e += gridDim.x * blockDim.x) {
-        const int2 en = a.cb.single[e];
-        const PairDesc& P = pairs[en.x];
-        const int p = en.y;
-        const int x = (p % P.gw) * a.sx, y = (p / P.gw) * a.sy;
-        const int W = P.W[a.level], H = P.H[a.level];
-        const float2* __restrict__ f32 = reinterpret_cast<const float2*>(P.field[a.level]);
-        const int k = P.mk[p];
-        float sw, s1;
-        score_fp32<VOTE>(P.tab + (size_t)k * P.n_pad, P.n_pad, (float)P.n[a.level], h,
-                         [&](int qx, int qy) {
-                             const int gx = x + qx, gy = y + qy;
-                             return ((unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H)
-                                        ? f32[(size_t)gy * W + gx]
-                                        : make_float2(0.f, 0.f);
-                         },
-                         &sw, &s1);
-        P.mw[p] = sw;
-        P.m1[p] = s1;
-    }
-}
-
 constexpr int kCertLds = 64 * 1024;  // largest staged block of k_rescore_multi
 
 // ---------------------------------------------------------------- planning
@@ -1013,32 +1184,44 @@ int knob(const char* name, int dflt, int lo, int hi)
 
 // d == nullptr: only raise the kernel's LDS limit (done once, before any
 // launch, so that no attribute call happens while a stream is captured).
-template <int G, int R, int LC, int PREC, int VAR, int VOTE>
+template <int G, int R, int LC, int PREC, int VAR, int VOTE, bool SCREEN>
 hipError_t launch_fast_t(const DensePlan& p, const FastArgs& a, const PairDesc* d, int npairs, hipStream_t s)
 {
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dense_fast<G, R, LC, PREC, VAR, VOTE>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipError_t e =
+            hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dense_fast<G, R, LC, PREC, VAR, VOTE, SCREEN>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
     if (!d) return hipSuccess;
     const dim3 grid = a.work ? dim3(p.n_work) : dim3(p.max_blocks, npairs);
-    hipLaunchKernelGGL((k_dense_fast<G, R, LC, PREC, VAR, VOTE>), grid, dim3(64 * p.WY * p.WA), p.lds, s, a, d);
+    hipLaunchKernelGGL((k_dense_fast<G, R, LC, PREC, VAR, VOTE, SCREEN>), grid, dim3(64 * p.WY * p.WA), p.lds, s, a,
+                       d);
     return hipGetLastError();
 }
 
+template <int PREC, int VAR, int VOTE, bool SCREEN>
+hipError_t launch_fast_lc(const DensePlan& p, const FastArgs& a, const PairDesc* d, int npairs, hipStream_t s)
+{
+    switch (p.LC) {
+        case 64: return launch_fast_t<32, 8, 64, PREC, VAR, VOTE, SCREEN>(p, a, d, npairs, s);
+        case 96: return launch_fast_t<32, 8, 96, PREC, VAR, VOTE, SCREEN>(p, a, d, npairs, s);
+        case 128: return launch_fast_t<32, 8, 128, PREC, VAR, VOTE, SCREEN>(p, a, d, npairs, s);
+        case 192: return launch_fast_t<32, 8, 192, PREC, VAR, VOTE, SCREEN>(p, a, d, npairs, s);
+        default: return launch_fast_t<32, 8, 256, PREC, VAR, VOTE, SCREEN>(p, a, d, npairs, s);
+    }
+}
+
+// the FP16 screen of a certified detection, or the plain search
 template <int PREC, int VAR, int VOTE = 0>
 hipError_t launch_fast_p(const DensePlan& p, const FastArgs& a, const PairDesc* d, int npairs, hipStream_t s)
 {
-    switch (p.LC) {
-        case 64: return launch_fast_t<32, 8, 64, PREC, VAR, VOTE>(p, a, d, npairs, s);
-        case 96: return launch_fast_t<32, 8, 96, PREC, VAR, VOTE>(p, a, d, npairs, s);
-        case 128: return launch_fast_t<32, 8, 128, PREC, VAR, VOTE>(p, a, d, npairs, s);
-        case 192: return launch_fast_t<32, 8, 192, PREC, VAR, VOTE>(p, a, d, npairs, s);
-        default: return launch_fast_t<32, 8, 256, PREC, VAR, VOTE>(p, a, d, npairs, s);
+    if constexpr (PREC == TM_FP16) {
+        if (p.screen) return launch_fast_lc<PREC, VAR, VOTE, true>(p, a, d, npairs, s);
     }
+    return launch_fast_lc<PREC, VAR, VOTE, false>(p, a, d, npairs, s);
 }
 
 // The edge-taps reading is built in one form per precision, the default one
@@ -1077,6 +1260,7 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
 {
     DensePlan p = {};
     p.prec = s.precision;
+    p.screen = s.screen && s.precision == TM_FP16;
     int max_halo = 0;
     for (int i = 0; i < npairs; ++i) {
         max_halo = max(max_halo, g[i].rad + 1);
@@ -1103,7 +1287,7 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
         // FP16 pixels take 4 bytes (8 with the edge-taps addend), FP32 8
         const size_t px_bytes = s.precision == TM_FP16 ? (p.vote ? 8 : 4) : 8;
         p.tile_lds = (size_t)(TH + 2 * max_halo) * p.LC * px_bytes;
-        const size_t comb_bytes = (size_t)(s.precision == TM_FP16 ? 16 : 12) * p.WA * TH * TW;
+        const size_t comb_bytes = (size_t)(p.screen ? 20 : 12) * p.WA * TH * TW;
         p.lds = p.tile_lds > comb_bytes ? p.tile_lds : comb_bytes;
         if (p.LC == 0 || p.lds > 160 * 1024) p.fast = false;
     }
@@ -1180,7 +1364,7 @@ bool retune_dense(DensePlan& p, int variant, int WA)
     if (!p.fast || variant < 0 || variant > 5 || WA < 1 || p.WY * WA > 16) return false;
     if (p.vote && variant != p.variant) return false;
     const int TW = p.G - 2, TH = p.WY * (64 / p.G) * p.R;
-    const size_t comb_bytes = (size_t)(p.prec == TM_FP16 ? 16 : 12) * WA * TH * TW;
+    const size_t comb_bytes = (size_t)(p.screen ? 20 : 12) * WA * TH * TW;
     const size_t lds = p.tile_lds > comb_bytes ? p.tile_lds : comb_bytes;
     if (lds > 160 * 1024) return false;
     p.variant = variant;
@@ -1243,7 +1427,7 @@ bool build_work(const DensePlan& p, const PairGeom* g, int npairs, std::vector<i
     return true;
 }
 
-size_t dense_partials_bytes(const DensePlan& p, int np) { return (size_t)p.C * np * (p.prec == TM_FP16 ? 16 : 12); }
+size_t dense_partials_bytes(const DensePlan& p, int np) { return (size_t)p.C * np * (p.screen ? 24 : 12); }
 
 hipError_t prepare_dense(const SearchDesc& s, const DensePlan& p)
 {
@@ -1290,7 +1474,12 @@ hipError_t launch_dense(const SearchDesc& s, const DensePlan& p, const PairDesc*
         else
             hipLaunchKernelGGL(k_pad_field<TM_FP32>, pgrid, dim3(256), 0, st, s.level, d);
         dim3 grid((p.max_np + 255) / 256, p.C, npairs);
-        if (s.precision == TM_FP16) {
+        if (s.precision == TM_FP16 && p.screen) {
+            if (s.vote)
+                hipLaunchKernelGGL((k_dense_generic<TM_FP16, 1, true>), grid, dim3(256), 0, st, a, d);
+            else
+                hipLaunchKernelGGL((k_dense_generic<TM_FP16, 0, true>), grid, dim3(256), 0, st, a, d);
+        } else if (s.precision == TM_FP16) {
             if (s.vote)
                 hipLaunchKernelGGL((k_dense_generic<TM_FP16, 1>), grid, dim3(256), 0, st, a, d);
             else
@@ -1308,8 +1497,11 @@ hipError_t launch_dense(const SearchDesc& s, const DensePlan& p, const PairDesc*
         e = hipEventRecord(ev1, st);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_reduce_chunks, dim3((p.max_np + kRedPos - 1) / kRedPos, npairs), dim3(kRedPos * kRedLanes),
-                       0, st, p.C, d);
+    if (p.screen)
+        hipLaunchKernelGGL(k_reduce_screen, dim3((p.max_np + 255) / 256, npairs), dim3(256), 0, st, p.C, d);
+    else
+        hipLaunchKernelGGL(k_reduce_chunks, dim3((p.max_np + kRedPos - 1) / kRedPos, npairs),
+                           dim3(kRedPos * kRedLanes), 0, st, p.C, d);
     return hipGetLastError();
 }
 
@@ -1339,29 +1531,36 @@ hipError_t launch_sparse(const void* field, int W, int H, int precision, const M
     return hipGetLastError();
 }
 
-size_t cert_bytes(int total_np) { return 256 + (size_t)total_np * (sizeof(int4) + sizeof(int2)) + 256; }
+size_t cert_bytes(int total_np) { return 256 + (size_t)total_np * sizeof(int4) + 256; }
 
 CertBufs cert_bufs(void* base, int total_np)
 {
     CertBufs b;
     uint8_t* q = reinterpret_cast<uint8_t*>(base);
     b.count = reinterpret_cast<int*>(q);
-    b.multi = reinterpret_cast<int4*>(q + 256);
-    b.single = reinterpret_cast<int2*>(q + 256 + (size_t)total_np * sizeof(int4));
+    b.list = reinterpret_cast<int4*>(q + 256);
     b.cap = total_np;
     return b;
 }
+
+namespace {
+template <int VOTE, int HW>
+hipError_t rescore_attr()
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rescore<VOTE, HW>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, kCertLds);
+}
+}  // namespace
 
 hipError_t launch_certify(const SearchDesc& s, const DensePlan& p, const PairDesc* d, int npairs, const CertBufs& cb,
                           hipStream_t st)
 {
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rescore_multi<0>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, kCertLds);
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_rescore_multi<1>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, kCertLds);
+        hipError_t e = rescore_attr<0, 1>();
+        if (e == hipSuccess) e = rescore_attr<1, 1>();
+        if (e == hipSuccess) e = rescore_attr<0, -1>();
+        if (e == hipSuccess) e = rescore_attr<1, -1>();
         if (e != hipSuccess) return e;
         attr_set = true;
     }
@@ -1376,18 +1575,22 @@ hipError_t launch_certify(const SearchDesc& s, const DensePlan& p, const PairDes
     a.sy = s.sy;
     a.min_score = s.min_score;
     a.cb = cb;
-    const int B = p.max_rad + (s.win - 1) / 2, S = 2 * B + 1;
     // pairs whose block fits are staged, larger ones gather from memory
+    const int B = p.max_rad + (s.win - 1) / 2, S = 2 * B + 1;
     a.lds_bytes = (long long)S * S * 8 <= kCertLds ? S * S * 8 : kCertLds;
     hipLaunchKernelGGL(k_cert_zero, dim3(1), dim3(64), 0, st, cb.count);
     hipLaunchKernelGGL(k_certify, dim3((p.max_np + 255) / 256, npairs), dim3(256), 0, st, a, d);
-    const int gm = min(cb.cap, 2048), gs = min((cb.cap + 255) / 256, 64);
-    if (s.vote) {
-        hipLaunchKernelGGL(k_rescore_multi<1>, dim3(gm), dim3(256), a.lds_bytes, st, a, d);
-        hipLaunchKernelGGL(k_rescore_single<1>, dim3(gs), dim3(256), 0, st, a, d);
+    const dim3 grid(min(cb.cap, 4096)), block(256);
+    if (s.win == 3) {
+        if (s.vote)
+            hipLaunchKernelGGL((k_rescore<1, 1>), grid, block, a.lds_bytes, st, a, d);
+        else
+            hipLaunchKernelGGL((k_rescore<0, 1>), grid, block, a.lds_bytes, st, a, d);
     } else {
-        hipLaunchKernelGGL(k_rescore_multi<0>, dim3(gm), dim3(256), a.lds_bytes, st, a, d);
-        hipLaunchKernelGGL(k_rescore_single<0>, dim3(gs), dim3(256), 0, st, a, d);
+        if (s.vote)
+            hipLaunchKernelGGL((k_rescore<1, -1>), grid, block, a.lds_bytes, st, a, d);
+        else
+            hipLaunchKernelGGL((k_rescore<0, -1>), grid, block, a.lds_bytes, st, a, d);
     }
     return hipGetLastError();
 }

@@ -370,7 +370,7 @@ size_t pair_scratch(tmk::PairDesc* d, const tm_model* m, const tmk::PairGeom& g,
     if (search) {
         const size_t C = (size_t)plan.C;
         float* pw = reinterpret_cast<float*>(take(tmk::dense_partials_bytes(plan, (int)np)));
-        float* mw = reinterpret_cast<float*>(take(np * 12));
+        float* mw = reinterpret_cast<float*>(take(np * (plan.screen ? 24 : 12)));
         if (!plan.fast) {
             // the generic search's zero-bordered copy of the searched field
             const int pad = g.rad + plan.win_h + 1;
@@ -387,10 +387,17 @@ size_t pair_scratch(tmk::PairDesc* d, const tm_model* m, const tmk::PairGeom& g,
             d->pw = pw;
             d->p1 = pw + C * np;
             d->pk = reinterpret_cast<int32_t*>(pw + 2 * C * np);
-            d->p2 = plan.prec == TM_FP16 ? pw + 3 * C * np : nullptr;
             d->mw = mw;
             d->m1 = mw + np;
             d->mk = reinterpret_cast<int32_t*>(mw + 2 * np);
+            if (plan.screen) {
+                d->p2 = pw + 3 * C * np;
+                d->pk2 = reinterpret_cast<int32_t*>(pw + 4 * C * np);
+                d->p3 = pw + 5 * C * np;
+                d->m2 = mw + 3 * np;
+                d->mk2 = reinterpret_cast<int32_t*>(mw + 4 * np);
+                d->m3 = mw + 5 * np;
+            }
         }
     }
     if (select) {
@@ -928,13 +935,14 @@ TM_EXPORT tm_status tm_detect(const tm_model* m, tm_pyramid* p, const tm_search_
     st = get_table(m, top, sp->theta_min_deg, g.step[top], g.K[top], g, s, &tab);
     if (st != TM_OK) return st;
     tmk::SearchDesc sd = make_search(sp, g, top, p->precision, capacity);
+    sd.screen = p->precision == TM_FP16;  // an FP16 search is a screen whose decisions are certified
     tmk::PairGeom pg = pair_geom(m, p, top, sp->step_x, sp->step_y, g.sigma_max);
     tmk::DensePlan plan = tmk::plan_dense(sd, &pg, 1);
     tmk::PairDesc d;
     memset(&d, 0, sizeof(d));
     pair_static(&d, m, p, tab, top, pg, plan, default_dmin(m, sp), sp->neighbourhood, g.sigma_max);
     const bool refine = p->L > 1;
-    const bool certify = p->precision == TM_FP16;
+    const bool certify = plan.screen;
     const size_t pair_bytes = pair_scratch(&d, m, pg, plan, p->L, sp->max_candidates, true, true, refine, nullptr);
     st = ensure_ws(p, kDescBytes + pair_bytes + (certify ? tmk::cert_bytes(pg.gw * pg.gh) : 0), s);
     if (st != TM_OK) return st;
@@ -1011,6 +1019,7 @@ TM_EXPORT tm_status tm_detect_static(const tm_model* m, const tm_pyramid* p, con
     const tm_model_level& mt = m->lv[top];
     if (scaled_rad(mt, g.sigma_max) > 32000) return fail(TM_EINVAL, "tm_detect_static: model too large for the scale range");
     tmk::SearchDesc sd = make_search(sp, g, top, p->precision, capacity);
+    sd.screen = p->precision == TM_FP16;
     tmk::PairGeom pg = pair_geom(m, p, top, sp->step_x, sp->step_y, g.sigma_max);
     tmk::DensePlan plan = tmk::plan_dense(sd, &pg, 1);
     tmk::PairDesc d;
@@ -1018,7 +1027,7 @@ TM_EXPORT tm_status tm_detect_static(const tm_model* m, const tm_pyramid* p, con
     const bool refine = p->L > 1;
     // layout: descriptor, rotated table of the top level, pair scratch
     const size_t tab_bytes = align_up((size_t)g.K[top] * g.S * mt.n_pad * sizeof(tmk::TabEntry), 256);
-    const bool certify = p->precision == TM_FP16;
+    const bool certify = plan.screen;
     const size_t pair_bytes = pair_scratch(&d, m, pg, plan, p->L, sp->max_candidates, true, true, refine, nullptr);
     const size_t need = kDescBytes + tab_bytes + pair_bytes + (certify ? tmk::cert_bytes(pg.gw * pg.gh) : 0);
     if (need > (size_t)TM_STATIC_SCRATCH_BYTES)
@@ -1047,6 +1056,16 @@ TM_EXPORT tm_status tm_detect_static(const tm_model* m, const tm_pyramid* p, con
         HIP_TRY(tmk::launch_refine(sd, dd, 1, top, rp, s, false));
     }
     HIP_TRY(tmk::launch_final(sd, dd, 1, s, out, n_out, refine ? top % 2 : -1));
+    return TM_OK;
+}
+
+TM_EXPORT tm_status tm_probe(int32_t kind, int32_t iterations, void* buf, int64_t buf_bytes, void* stream,
+                             double* work)
+{
+    if (kind < 0 || kind > 6) return fail(TM_EINVAL, "tm_probe: kind must be 0..6");
+    if (iterations < 1 || iterations > 1000000) return fail(TM_EINVAL, "tm_probe: iterations must be 1..10^6");
+    if (!buf || buf_bytes < 256 || !work) return fail(TM_EINVAL, "tm_probe: need a buffer of >= 256 bytes");
+    HIP_TRY(tmk::launch_probe(kind, iterations, buf, buf_bytes, S(stream), work));
     return TM_OK;
 }
 
@@ -1283,6 +1302,7 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
         b->pyrs.push_back(p);
     }
     b->sd = make_search(sp, g, top, pp->precision, capacity);
+    b->sd.screen = pp->precision == TM_FP16;
     std::vector<tmk::PairGeom> pg(b->npairs);
     for (int i = 0; i < n_images; ++i)
         for (int j = 0; j < n_models; ++j)
@@ -1324,7 +1344,7 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
         tm_batch_free(b);
         return fail(TM_EINVAL, "tm_batch_create: too many translations");
     }
-    b->certify = pp->precision == TM_FP16;
+    b->certify = b->plan.screen;
     const size_t cert_off = off;
     if (b->certify) off = align_up(off + tmk::cert_bytes((int)total_np), 256);
     std::vector<size_t> pair_off(b->npairs);

@@ -177,11 +177,16 @@ struct PairDesc {
     float dmin;                      // suppression distance, level-0 pixels
     float* pw;                       // chunk partials [C][gh][gw]: best S_w,
     float* p1;                       //   S_1,
-    int32_t* pk;                     //   angle,
-    float* p2;                       //   FP16 search: the best S_w over the chunk's other angles
+    int32_t* pk;                     //   angle; a certified (screen) search also keeps
+    float* p2;                       //   the runner-up's S_w,
+    int32_t* pk2;                    //   its angle,
+    float* p3;                       //   and the best S_w of the chunk's remaining angles
     float* mw;                       // best angle per translation [gh][gw]: S_w,
     float* m1;                       //   S_1,
-    int32_t* mk;                     //   angle
+    int32_t* mk;                     //   angle; a certified search also keeps
+    float* m2;                       //   the runner-up's S_w,
+    int32_t* mk2;                    //   its angle,
+    float* m3;                       //   and the best S_w of the remaining angles
     float* sel;                      // selection scratch, select_scratch_bytes(gw*gh)
     tm_pose* cand;                   // candidates [max_cand] (refined in place)
     int32_t* ncand;                  // their count (device); null: max_cand
@@ -210,6 +215,7 @@ struct SearchDesc {
     int max_matches;            // final matches kept (the method's cap)
     int S;                      // scales (1: rigid)
     double sigma_min, sigma_step;
+    int screen;                 // FP16 detection: the search is a screen whose decisions are certified
 };
 
 // Poses per translation at the searched level: angles x scales, indexed
@@ -219,7 +225,8 @@ inline int poses_per_translation(const SearchDesc& s) { return s.K[s.level] * s.
 // Launch plan of the exhaustive search, common to all pairs.
 struct DensePlan {
     bool fast;
-    int prec;                   // precision of the searched field (FP16 plans also keep the second best)
+    int prec;                   // precision of the searched field
+    bool screen;                // FP16 screen of a certified detection (no S_1; runner-up kept)
     int vote;                   // tm_vote (the edge-taps reading has one kernel form)
     int variant;                // search kernel form (k_dense_fast VAR)
     int tr;                     // 1: lanes along y, strips along x (FastArgs.tr)
@@ -283,19 +290,18 @@ hipError_t launch_dense(const SearchDesc& s, const DensePlan& p, const PairDesc*
 // Certification of an FP16 search (see k_score.hip): translations whose
 // FP32 scores could decide the candidate selection are re-scored in FP32 from
 // the FP32 twin, with the FP32 search's arithmetic, over the angles their FP16
-// scores leave open, and the map takes those values.  Buffers (device): two
-// counters (multi, single) and two lists with room for every translation of
-// every pair.
+// scores leave open, and the map takes those values.  Buffers (device): a
+// counter and a list with room for every translation of every pair.
 struct CertBufs {
-    int* count;       // [2]: entries in `multi`, in `single`
-    int4* multi;      // (pair, translation, chunk mask low, high): angles of the masked chunks
-    int2* single;     // (pair, translation): the FP16 best angle alone
-    int cap;          // entries each list holds
+    int* count;       // entries in `list`
+    int4* list;       // (pair, translation, angle a, angle b or -1), or (-1 - pair, translation,
+                      // chunk mask low, high): the angles to score in FP32
+    int cap;          // entries the list holds (every translation of every pair)
 };
 size_t cert_bytes(int total_np);
 CertBufs cert_bufs(void* base, int total_np);
-// Enqueues: the counters cleared (a kernel, not a memset), the flagging of
-// the translations, and the two re-scoring kernels.
+// Enqueues: the counter cleared (a kernel, not a memset), the flagging of
+// the translations, and the re-scoring kernel.
 hipError_t launch_certify(const SearchDesc& s, const DensePlan& p, const PairDesc* d, int npairs, const CertBufs& cb,
                           hipStream_t st);
 
@@ -325,6 +331,11 @@ size_t line_search_scratch_bytes(int n, int n_alpha);
 hipError_t launch_line_search(const PairDesc* d, int batched, int npairs, int level, int precision,
                               tm_cont_pose* poses, const float* dirs, int n, const double* alphas, int n_alpha,
                               float* scores, double* scratch, hipStream_t s);
+
+// Ceiling probes (k_roof.hip): kind 0 the search's VALU mix, 1 plain VALU
+// adds, 2 LDS reads of the search's pattern, 3 an HBM copy within buf; work:
+// VALU instructions (waves), LDS bytes, or HBM bytes enqueued.
+hipError_t launch_probe(int kind, int iters, void* buf, long long buf_bytes, hipStream_t s, double* work);
 
 // One wave per pose: S_w and S_1 of arbitrary poses.
 hipError_t launch_sparse(const void* field, int W, int H, int precision, const ModelPoint* pts, int n, int win,

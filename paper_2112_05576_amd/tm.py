@@ -107,6 +107,7 @@ def lib():
             "tm_batch_pyramid": [_vp, _i32, ctypes.POINTER(_vp)],
             "tm_timing_read": [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i32)],
             "tm_set_allocator": [ctypes.POINTER(AllocatorC)],
+            "tm_probe": [_i32, _i32, _vp, ctypes.c_int64, _vp, ctypes.POINTER(ctypes.c_double)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -633,6 +634,30 @@ def use_torch_allocator(on: bool = True):
         _allocator_keep = (a, _allocator_keep)
     else:
         _check(lib().tm_set_allocator(None))
+
+
+PROBE_VALU_MIX, PROBE_VALU_ADD, PROBE_LDS, PROBE_HBM, PROBE_DOT2, PROBE_MAX_DPP, PROBE_MAX3 = 0, 1, 2, 3, 4, 5, 6
+
+
+def probe_rate(kind: int, iterations: int = 2000, hbm_bytes: int = 1 << 30, repeats: int = 5) -> float:
+    """Rate of a ceiling probe (tm_probe): work per second of the best of
+    `repeats` launches, timed with events on the current stream (VALU:
+    wave-level instructions/s; LDS and HBM: bytes/s)."""
+    nbytes = hbm_bytes if kind == PROBE_HBM else 4096
+    buf = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    work = ctypes.c_double()
+    st = torch.cuda.current_stream()
+    _check(lib().tm_probe(kind, iterations, _vp(buf.data_ptr()), nbytes, _vp(st.cuda_stream), ctypes.byref(work)))
+    best = float("inf")
+    for _ in range(repeats):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        _check(lib().tm_probe(kind, iterations, _vp(buf.data_ptr()), nbytes, _vp(st.cuda_stream),
+                              ctypes.byref(work)))
+        e1.record(st)
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    return work.value / best
 
 
 def timing_enable(on: bool = True):

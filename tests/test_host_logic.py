@@ -173,3 +173,32 @@ def test_integer_distance_test_equals_the_fp64_one():
     # exact squares land on the boundary: not too close in either form
     d = np.float32(5.0)
     assert not (25.0 < float(d) ** 2) and not (25 < int(np.ceil(float(d) ** 2)))
+
+
+def test_valu_counts_per_form(tmp_path, monkeypatch):
+    """The search kernel's executed VALU instructions per launch come from a
+    SQ_INSTS_VALU counter run: the median over the batched launches of each
+    form (variant, waves, precision, screen); reported only for the recorded
+    source and the form and precision in use (an FP16 detection runs the
+    screen form)."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    monkeypatch.setattr(bench, "VALU_JSON", str(tmp_path / "valu.json"))
+    k = ("void tmk::(anonymous namespace)::k_dense_fast<32, 8, 64, {}, {}, 0, {}>"
+         "(tmk::(anonymous namespace)::FastArgs)")
+    rows = [(k.format(0, 3, "false"), 5.0, 900 * 256, 256),        # a single image: fewer workgroups
+            (k.format(1, 4, "true"), 1.5e9, 1920 * 256, 256), (k.format(1, 4, "true"), 1.6e9, 1920 * 256, 256),
+            (k.format(1, 4, "true"), 1.4e9, 1920 * 256, 256),
+            (k.format(0, 4, "false"), 2.0e9, 1920 * 512, 512)]
+    _write_counters(tmp_path / "v.csv", "SQ_INSTS_VALU", rows)
+    bench.valu_from(str(tmp_path / "v.csv"))
+    forms = __import__("json").load(open(tmp_path / "valu.json"))["forms"]
+    by = {(f["variant"], f["waves_per_chunk"], f["precision"], f["screen"]): f for f in forms}
+    assert set(by) == {(4, 4, "fp16", True), (4, 8, "fp32", False)}
+    assert by[(4, 4, "fp16", True)]["valu_instr_per_launch"] == 1.5e9
+    assert bench.valu_entry({"variant": 4, "waves_per_chunk": 4}, "fp16")["valu_instr_per_launch"] == 1.5e9
+    assert bench.valu_entry({"variant": 4, "waves_per_chunk": 8}, "fp32")["valu_instr_per_launch"] == 2.0e9
+    assert bench.valu_entry({"variant": 4, "waves_per_chunk": 8}, "fp16") is None
+    monkeypatch.setattr(bench, "KERNEL_SRC", str(tmp_path / "v.csv"))  # another source: no figure
+    assert bench.valu_entry({"variant": 4, "waves_per_chunk": 4}, "fp16") is None
