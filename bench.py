@@ -582,39 +582,24 @@ def batched_leg(P, torch, model, imgs, L, cfg, sp, prec, args, stream):
     from HIP events around its launches in eager steps after the timed
     region (one batch, same stream, nothing overlapping it)."""
     ns = max(1, args.streams)
-    nb = len(imgs)
     batches = [P.Batch([model], imgs, L, cfg["tau_s"], sp, precision=prec) for _ in range(ns)]
     batch = batches[0]
-    default_form = batch.search_form()
-    tuned = batch.tune(iterations=3) if not args.no_tune else None
-    form = batch.search_form()
     streams = [stream] + [torch.cuda.Stream() for _ in range(ns - 1)]
     graph = not args.eager
-
-    def pipelined(f, n=20):
-        """Wall time of n steps with every batch in form f (after one warm step each)."""
-        for b in batches:
-            b.set_form(f["variant"], f["waves_per_chunk"])
-        for i in range(ns):
-            batches[i].run(streams[i], graph=graph)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for i in range(n):
-            batches[i % ns].run(streams[i % ns], graph=graph)
-        torch.cuda.synchronize()
-        return time.perf_counter() - t
-
-    # the tuner times one batch alone; with batches in flight side by side the
-    # default form can do better, so the two are compared on the pipelined
-    # step and the faster is kept (both give the same detections)
-    chosen_by = "single-batch launch" if tuned is not None else "default"
-    key = lambda f: (f["variant"], f["waves_per_chunk"])
-    if tuned is not None and ns > 1 and key(form) != key(default_form):
-        if pipelined(default_form) < pipelined(form):
-            form = default_form
-        chosen_by = "pipelined step"
-    for b in batches:
-        b.set_form(form["variant"], form["waves_per_chunk"])
+    # the autotuner picks the search's schedule (variant, waves per chunk,
+    # angles per chunk); with two batches in flight it times the chunkings on
+    # their pipelined step, and both keep its choice (all schedules give the
+    # same detections)
+    tuned = None
+    if not args.no_tune:
+        if ns >= 2:
+            tuned = batch.tune(iterations=3, partner=batches[1], partner_stream=streams[1])
+            for b in batches[2:]:
+                b.set_form(tuned["variant"], tuned["waves_per_chunk"], tuned["chunk_angles"])
+        else:
+            tuned = batch.tune(iterations=3)
+    form = batch.search_form()
+    chosen_by = "default" if tuned is None else ("autotuner, pipelined step" if ns >= 2 else "autotuner, search launch")
     for i in range(max(args.warmup, ns)):
         batches[i % ns].run(streams[i % ns], graph=graph)
     torch.cuda.synchronize()
@@ -647,7 +632,7 @@ def batched_leg(P, torch, model, imgs, L, cfg, sp, prec, args, stream):
     for b in batches:
         b.free()
     return {"elapsed": elapsed, "dets": dets, "form": dict(form, tuned=tuned is not None, chosen_by=chosen_by),
-            "launch_s": dense_ms / max(launches, 1) / 1e3, "ns": ns}
+            "launch_s": dense_ms / max(launches, 1) / 1e3, "ns": ns, "nb": len(imgs)}
 
 
 def ceilings(P):

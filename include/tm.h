@@ -336,33 +336,43 @@ tm_status tm_batch_run(tm_batch* batch, void* stream);
  * Search-kernel timing (tm_timing_enable) does not apply to graph launches. */
 tm_status tm_batch_run_graph(tm_batch* batch, void* stream);
 
-/* Autotuner of a batch's exhaustive search: runs the pyramid stage, then
- * times every form of the search kernel (6 instruction-level variants × 2,
- * 4, 8 or 16 waves sharing an angle chunk, where they fit in LDS) for
- * `iterations` launches each (1 to 1000) on the bound images, twice over
- * (a form's time is the smaller of its two rounds), and keeps the fastest
- * for the batch's later runs (a captured graph is discarded and
- * captured again by the next tm_batch_run_graph).  All forms give
- * bit-identical results; tuning changes only time.  Waits for the device.
- * variant_out, waves_out, us_out (each may be NULL): the choice and its mean
- * time per launch (variant -1 when the batch uses the generic search, which
- * has no forms to choose from). */
-tm_status tm_batch_tune(tm_batch* batch, int32_t iterations, void* stream, int32_t* variant_out, int32_t* waves_out,
-                        float* us_out);
+/* Autotuner of a batch's exhaustive search (the search is 99 % of the work;
+ * its schedule is what the tuner picks).  The schedule has three
+ * dimensions: the instruction-level variant of the search kernel (0..5), the
+ * waves sharing an angle chunk (2, 4, 8, 16; a workgroup stages one field
+ * tile for them) and the angle chunk (how many angles one workgroup scores:
+ * the batch holds up to four times its planned number of chunks, at most
+ * 12).  First every (variant, waves) form that fits in LDS is timed on the
+ * search alone at the planned chunking, `iterations` launches each, twice
+ * over (a form's time is the smaller of its two rounds); then the two
+ * fastest forms are timed at every chunking.  With a partner (a batch of the
+ * same shape, run on its own partner_stream) the second stage times the
+ * pipelined step of the two batches as graph launches alternating on the two
+ * streams, which is what a caller keeping two batches in flight runs, and
+ * both batches end with the choice; without one it times the search alone.
+ * Runs the pyramid stage first; waits for the device.  All schedules give
+ * bit-identical results; tuning changes only time.  variant_out, waves_out,
+ * chunk_out (angles per chunk), us_out (each may be NULL): the choice and its
+ * time (per step with a partner, per search launch without).  For a batch on
+ * the generic search there is nothing to choose: -1, 0, 0, 0. */
+tm_status tm_batch_tune(tm_batch* batch, tm_batch* partner, int32_t iterations, void* stream, void* partner_stream,
+                        int32_t* variant_out, int32_t* waves_out, int32_t* chunk_out, float* us_out);
 
-/* Use the given form of the search kernel for the batch's later runs (a
- * form reported by tm_batch_tune or tm_batch_search_form of a batch of the
- * same shape, say): TM_EINVAL if it does not apply (variant 0..5, 1..16
- * waves sharing a chunk, within LDS; the edge-taps vote has one variant per
- * precision; -1 is accepted, and changes nothing, for a batch on the generic
- * search).  Results do not depend on the form.  A captured graph is
+/* Use the given schedule of the search for the batch's later runs (one
+ * reported by tm_batch_tune or tm_batch_search_form of a batch of the same
+ * shape, say): TM_EINVAL if it does not apply (variant 0..5, 1..16 waves
+ * sharing a chunk, within LDS; the edge-taps vote has one variant per
+ * precision; chunk: angles per chunk, 0 keeps the current chunking, and the
+ * chunks must not outnumber what the batch holds; -1 is accepted, and
+ * changes nothing, for a batch on the generic search).  Results do not depend
+ * on the schedule.  Waits for the batch's last run; a captured graph is
  * discarded and captured again by the next tm_batch_run_graph. */
-tm_status tm_batch_set_form(tm_batch* batch, int32_t variant, int32_t waves);
+tm_status tm_batch_set_form(tm_batch* batch, int32_t variant, int32_t waves, int32_t chunk);
 
-/* The form of the batch's exhaustive search now in use (default or tuned):
- * kernel variant and waves sharing an angle chunk (-1 and 0 for the generic
- * search). */
-tm_status tm_batch_search_form(const tm_batch* batch, int32_t* variant, int32_t* waves);
+/* The schedule of the batch's exhaustive search now in use (default or
+ * tuned): kernel variant, waves sharing an angle chunk and angles per chunk
+ * (chunk may be NULL; -1, 0, 0 for the generic search). */
+tm_status tm_batch_search_form(const tm_batch* batch, int32_t* variant, int32_t* waves, int32_t* chunk);
 
 /* The continuous score, its backward and the FP64 line search (as
  * tm_cont_score, tm_cont_score_backward and tm_cont_line_search) over the

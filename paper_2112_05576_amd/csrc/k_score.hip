@@ -1373,6 +1373,35 @@ bool retune_dense(DensePlan& p, int variant, int WA)
     return true;
 }
 
+bool rechunk_dense(DensePlan& p, const SearchDesc& s, const PairGeom* g, int npairs, int A)
+{
+    const int K = poses_per_translation(s);
+    if (!p.fast || A < 1) return false;
+    A = std::min((A + 3) / 4 * 4, (K + 3) / 4 * 4);  // a multiple of 4 angles, at most all of them
+    p.A = A;
+    p.C = (K + A - 1) / A;
+    int max_tiles = 0;
+    for (int i = 0; i < npairs; ++i) {
+        int tx, ty;
+        plan_tiles(p, g[i], &tx, &ty);
+        max_tiles = max(max_tiles, tx * ty);
+    }
+    p.max_blocks = max_tiles * p.C;
+    return true;
+}
+
+std::vector<int> chunk_candidates(const DensePlan& p, const SearchDesc& s, int c_max)
+{
+    std::vector<int> out;
+    const int K = poses_per_translation(s);
+    if (!p.fast) return out;
+    for (int C = 1; C <= c_max; ++C) {
+        const int A = std::min(((K + C - 1) / C + 3) / 4 * 4, (K + 3) / 4 * 4);
+        if ((K + A - 1) / A <= c_max && std::find(out.begin(), out.end(), A) == out.end()) out.push_back(A);
+    }
+    return out;
+}
+
 bool build_work(const DensePlan& p, const PairGeom* g, int npairs, std::vector<int2>& out)
 {
     out.clear();

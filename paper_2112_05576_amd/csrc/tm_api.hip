@@ -1226,6 +1226,18 @@ struct tm_batch_s {
     hipEvent_t last_run = nullptr;   // recorded after each run enqueued outside a capture
     bool certify = false;            // FP16 search: its decisions are certified in FP32
     tmk::CertBufs cert = {};
+    // what a change of the search's angle chunking needs: the pairs' geometry,
+    // the host copies of their descriptors, their scratch regions (sized for
+    // the largest chunking offered), and the work list's room
+    std::vector<tmk::PairGeom> pg;
+    std::vector<tmk::PairDesc> hd;
+    std::vector<size_t> pair_off;
+    uint8_t* base = nullptr;
+    int2* work_dev = nullptr;
+    size_t work_cap = 0;
+    int c_max = 1;                   // most angle chunks the scratch holds
+    int max_cand = 0;
+    bool refine = false;
 };
 
 namespace {
@@ -1313,6 +1325,26 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
         tm_batch_free(b);
         return fail(TM_EDEVICE, "tm_batch_create: internal error in the search work list");
     }
+    // the autotuner may choose another angle chunking: up to four times the
+    // planned number of chunks (at most 12), whose scratch and work list are
+    // sized here
+    tmk::DensePlan plan_max = b->plan;
+    b->c_max = b->plan.C;
+    size_t work_cap = work.size();
+    if (b->plan.fast) {
+        b->c_max = std::max(b->plan.C, std::min(12, 4 * b->plan.C));
+        for (int A : tmk::chunk_candidates(b->plan, b->sd, b->c_max)) {
+            tmk::DensePlan q = b->plan;
+            std::vector<int2> w;
+            if (!tmk::rechunk_dense(q, b->sd, pg.data(), b->npairs, A) || !tmk::build_work(q, pg.data(), b->npairs, w)) {
+                tm_batch_free(b);
+                return fail(TM_EDEVICE, "tm_batch_create: internal error in the search work list");
+            }
+            work_cap = std::max(work_cap, w.size());
+            if (q.C > plan_max.C) plan_max = q;
+        }
+    }
+    b->work_cap = work_cap;
     b->rplan = refine_plan(models, n_models, L, sp->neighbourhood,
                            (long long)b->npairs * sp->max_candidates, g.sigma_max);
     for (auto& q : pg) b->max_np = std::max(b->max_np, q.gw * q.gh);
@@ -1337,7 +1369,7 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
     const size_t fa_off = off;
     off = align_up(off + (size_t)n_images * sizeof(tmk::FieldsArg), 256);
     const size_t work_off = off;
-    off = align_up(off + work.size() * sizeof(int2), 256);
+    off = align_up(off + work_cap * sizeof(int2), 256);
     long long total_np = 0;
     for (auto& q : pg) total_np += (long long)q.gw * q.gh;
     if (total_np > (1LL << 30)) {
@@ -1353,7 +1385,7 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
         tmk::PairDesc tmp;
         memset(&tmp, 0, sizeof(tmp));
         pair_off[q] = off;
-        off += align_up(pair_scratch(&tmp, models[q % n_models], pg[q], b->plan, L, sp->max_candidates, true, true,
+        off += align_up(pair_scratch(&tmp, models[q % n_models], pg[q], plan_max, L, sp->max_candidates, true, true,
                                      refine, nullptr),
                         256);
     }
@@ -1406,8 +1438,9 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
         e = hipMemcpyAsync(b->d_pb, hpb.data(), hpb.size() * sizeof(tmk::PyrBuildArg), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_fa, hfa.data(), hfa.size() * sizeof(tmk::FieldsArg), hipMemcpyHostToDevice, s);
+    b->work_dev = reinterpret_cast<int2*>(base + work_off);
     if (e == hipSuccess && !work.empty()) {
-        b->plan.work = reinterpret_cast<const int2*>(base + work_off);
+        b->plan.work = b->work_dev;
         b->plan.n_work = (int)work.size();
         e = hipMemcpyAsync(base + work_off, work.data(), work.size() * sizeof(int2), hipMemcpyHostToDevice, s);
     }
@@ -1416,9 +1449,50 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
         tm_batch_free(b);
         return hip_fail(e, "tm_batch_create: upload");
     }
+    b->pg = pg;
+    b->hd = hd;
+    b->pair_off = pair_off;
+    b->base = base;
+    b->max_cand = sp->max_candidates;
+    b->refine = refine;
     *outb = b;
     return TM_OK;
 }
+
+namespace {
+// Give the batch a plan with another angle chunking (and form): the pairs'
+// scratch pointers and the work list follow it.  Waits for the batch's last
+// run and for the uploads; the captured graph is discarded.
+tm_status batch_apply_plan(tm_batch* b, tmk::DensePlan p, hipStream_t s)
+{
+    if (p.C > b->c_max) return fail(TM_EINVAL, "angle chunking beyond the batch's scratch (%d chunks, at most %d)",
+                                    p.C, b->c_max);
+    std::vector<int2> work;
+    if (!tmk::build_work(p, b->pg.data(), b->npairs, work) || work.size() > b->work_cap)
+        return fail(TM_EDEVICE, "internal error in the search work list");
+    tm_status st = batch_wait(b);
+    if (st != TM_OK) return st;
+    for (int q = 0; q < b->npairs; ++q)
+        pair_scratch(&b->hd[q], b->models[q % b->n_models], b->pg[q], p, b->L, b->max_cand, true, true, b->refine,
+                     b->base + b->pair_off[q]);
+    HIP_TRY(hipMemcpyAsync(b->d_pairs, b->hd.data(), b->hd.size() * sizeof(tmk::PairDesc), hipMemcpyHostToDevice, s));
+    p.work = nullptr;
+    p.n_work = 0;
+    if (!work.empty()) {
+        HIP_TRY(hipMemcpyAsync(b->work_dev, work.data(), work.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+        p.work = b->work_dev;
+        p.n_work = (int)work.size();
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(tmk::prepare_dense(b->sd, p));
+    b->plan = p;
+    if (b->graph) {  // captured with the old plan
+        (void)hipGraphExecDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    return TM_OK;
+}
+}  // namespace
 
 namespace {
 tm_status batch_enqueue(tm_batch* b, hipStream_t s, bool timed)
@@ -1485,7 +1559,7 @@ TM_EXPORT tm_status tm_batch_run_graph(tm_batch* b, void* stream)
     return TM_OK;
 }
 
-TM_EXPORT tm_status tm_batch_set_form(tm_batch* b, int32_t variant, int32_t waves)
+TM_EXPORT tm_status tm_batch_set_form(tm_batch* b, int32_t variant, int32_t waves, int32_t chunk)
 {
     if (!b) return fail(TM_EINVAL, "tm_batch_set_form: null batch");
     if (!b->plan.fast) {
@@ -1496,53 +1570,108 @@ TM_EXPORT tm_status tm_batch_set_form(tm_batch* b, int32_t variant, int32_t wave
     if (!tmk::retune_dense(p, variant, waves))
         return fail(TM_EINVAL, "tm_batch_set_form: variant %d with %d waves per chunk does not apply to this batch",
                     variant, waves);
-    HIP_TRY(tmk::prepare_dense(b->sd, p));
-    tm_status st = batch_wait(b);  // a run of the old graph may still be in flight
-    if (st != TM_OK) return st;
-    b->plan = p;
-    if (b->graph) {  // captured with the old form
-        (void)hipGraphExecDestroy(b->graph);
-        b->graph = nullptr;
-    }
-    return TM_OK;
+    if (chunk < 0) return fail(TM_EINVAL, "tm_batch_set_form: chunk must be >= 0");
+    if (chunk > 0 && !tmk::rechunk_dense(p, b->sd, b->pg.data(), b->npairs, chunk))
+        return fail(TM_EINVAL, "tm_batch_set_form: chunk %d does not apply", chunk);
+    if (p.C > b->c_max)
+        return fail(TM_EINVAL, "tm_batch_set_form: %d angles a chunk makes %d chunks, the batch holds at most %d", chunk,
+                    p.C, b->c_max);
+    return batch_apply_plan(b, p, nullptr);
 }
 
-TM_EXPORT tm_status tm_batch_search_form(const tm_batch* b, int32_t* variant, int32_t* waves)
+TM_EXPORT tm_status tm_batch_search_form(const tm_batch* b, int32_t* variant, int32_t* waves, int32_t* chunk)
 {
     if (!b || !variant || !waves) return fail(TM_EINVAL, "tm_batch_search_form: null argument");
     *variant = b->plan.fast ? b->plan.variant : -1;
     *waves = b->plan.fast ? b->plan.WA : 0;
+    if (chunk) *chunk = b->plan.A;
     return TM_OK;
 }
 
-TM_EXPORT tm_status tm_batch_tune(tm_batch* b, int32_t iterations, void* stream, int32_t* variant_out,
-                                  int32_t* waves_out, float* us_out)
+namespace {
+// Mean milliseconds of one search launch of plan p over the batch.
+hipError_t time_search(tm_batch* b, const tmk::DensePlan& p, int iterations, hipStream_t s, hipEvent_t e0,
+                       hipEvent_t e1, float* ms)
+{
+    hipError_t e = tmk::prepare_dense(b->sd, p);
+    if (e == hipSuccess) e = tmk::launch_dense(b->sd, p, b->d_pairs, b->npairs, s);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int it = 0; it < iterations && e == hipSuccess; ++it) e = tmk::launch_dense(b->sd, p, b->d_pairs, b->npairs, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    if (e == hipSuccess) *ms /= iterations;
+    return e;
+}
+
+// Mean milliseconds of one step of two batches run side by side as graph
+// launches, the steps alternating between b on s and c on cs (as a caller
+// keeping two batches in flight runs them).
+tm_status time_pipelined(tm_batch* b, tm_batch* c, int steps, hipStream_t s, hipStream_t cs, hipEvent_t e0,
+                         hipEvent_t e1, hipEvent_t ej, float* ms)
+{
+    tm_status st = tm_batch_run_graph(b, s);  // captures the graphs (outside the timed steps)
+    if (st == TM_OK) st = tm_batch_run_graph(c, cs);
+    if (st != TM_OK) return st;
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipStreamSynchronize(cs));
+    HIP_TRY(hipEventRecord(e0, s));
+    HIP_TRY(hipStreamWaitEvent(cs, e0, 0));
+    for (int i = 0; i < steps && st == TM_OK; ++i) st = tm_batch_run_graph(i % 2 ? c : b, i % 2 ? cs : s);
+    if (st != TM_OK) return st;
+    HIP_TRY(hipEventRecord(ej, cs));
+    HIP_TRY(hipStreamWaitEvent(s, ej, 0));
+    HIP_TRY(hipEventRecord(e1, s));
+    HIP_TRY(hipEventSynchronize(e1));
+    HIP_TRY(hipEventElapsedTime(ms, e0, e1));
+    *ms /= steps;
+    return TM_OK;
+}
+}  // namespace
+
+TM_EXPORT tm_status tm_batch_tune(tm_batch* b, tm_batch* partner, int32_t iterations, void* stream,
+                                  void* partner_stream, int32_t* variant_out, int32_t* waves_out, int32_t* chunk_out,
+                                  float* us_out)
 {
     if (!b) return fail(TM_EINVAL, "tm_batch_tune: null batch");
     if (iterations < 1 || iterations > 1000) return fail(TM_EINVAL, "tm_batch_tune: iterations must be 1..1000");
+    if (partner) {
+        bool same = partner != b && partner->npairs == b->npairs && partner->plan.fast == b->plan.fast &&
+                    partner->c_max == b->c_max &&
+                    tmk::poses_per_translation(partner->sd) == tmk::poses_per_translation(b->sd);
+        for (int q = 0; same && q < b->npairs; ++q)
+            same = memcmp(&partner->pg[q], &b->pg[q], sizeof(tmk::PairGeom)) == 0;
+        if (!same) return fail(TM_EINVAL, "tm_batch_tune: the partner batch is not of the same shape");
+        if (S(partner_stream) == S(stream)) return fail(TM_EINVAL, "tm_batch_tune: the partner needs its own stream");
+    }
     hipStream_t s = S(stream);
     if (!b->plan.fast) {
         if (variant_out) *variant_out = -1;
         if (waves_out) *waves_out = 0;
+        if (chunk_out) *chunk_out = 0;
         if (us_out) *us_out = 0.f;
         return TM_OK;  // the generic search has no forms to choose from
     }
     // the tuner's launches reuse the batch's scratch: no earlier run may still use it
-    tm_status wst = batch_wait(b);
-    if (wst != TM_OK) return wst;
+    tm_status st = batch_wait(b);
+    if (st == TM_OK && partner) st = batch_wait(partner);
+    if (st != TM_OK) return st;
     HIP_TRY(tmk::launch_pyramids_batch(b->d_pb, b->d_fa, b->n_images, b->L, b->level_w[0], b->level_h[0],
                                        b->max_field_blocks, b->level_w, b->level_h,
                                        b->pyrs[0]->source == TM_PYR_GRADIENT, s));
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    HIP_TRY(hipEventCreate(&e0));
-    hipError_t e = hipEventCreate(&e1);
-    if (e != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return hip_fail(e, "tm_batch_tune: hipEventCreate");
-    }
-    // every form that fits, timed in two rounds (each form's time is the
-    // smaller of its two), so that a drift of the clock during the first
-    // round does not decide the choice
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipEventCreate(&ev[i]);
+    auto done = [&](tm_status r) {
+        for (hipEvent_t x : ev)
+            if (x) (void)hipEventDestroy(x);
+        return r;
+    };
+    if (e != hipSuccess) return done(hip_fail(e, "tm_batch_tune: hipEventCreate"));
+    // 1. every (variant, waves per chunk) form that fits, its search launches
+    //    timed at the planned chunking in two rounds (a form's time is the
+    //    smaller of its two), so that a clock drift during the first round
+    //    does not decide
     static const int kWaves[] = {2, 4, 8, 16};
     constexpr int kRounds = 2;
     std::vector<tmk::DensePlan> forms;
@@ -1554,37 +1683,50 @@ TM_EXPORT tm_status tm_batch_tune(tm_batch* b, int32_t iterations, void* stream,
     std::vector<float> form_ms(forms.size(), INFINITY);
     for (int round = 0; round < kRounds && e == hipSuccess; ++round)
         for (size_t f = 0; f < forms.size() && e == hipSuccess; ++f) {
-            const tmk::DensePlan& p = forms[f];
-            e = tmk::prepare_dense(b->sd, p);
-            if (e == hipSuccess) e = tmk::launch_dense(b->sd, p, b->d_pairs, b->npairs, s);  // warm-up
-            if (e == hipSuccess) e = hipEventRecord(e0, s);
-            for (int it = 0; it < iterations && e == hipSuccess; ++it)
-                e = tmk::launch_dense(b->sd, p, b->d_pairs, b->npairs, s);
-            if (e == hipSuccess) e = hipEventRecord(e1, s);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            e = time_search(b, forms[f], iterations, s, ev[0], ev[1], &ms);
             if (e == hipSuccess) form_ms[f] = std::min(form_ms[f], ms);
         }
-    tmk::DensePlan best = b->plan;
+    if (e != hipSuccess) return done(hip_fail(e, "tm_batch_tune"));
+    // 2. the two fastest forms at every angle chunking the batch holds,
+    //    timed on the pipelined step of the two batches when a partner is
+    //    given (the step is what such a caller sees), else on the search
+    std::vector<size_t> order(forms.size());
+    for (size_t f = 0; f < order.size(); ++f) order[f] = f;
+    std::sort(order.begin(), order.end(), [&](size_t x, size_t y) { return form_ms[x] < form_ms[y]; });
+    const std::vector<int> chunks = tmk::chunk_candidates(b->plan, b->sd, b->c_max);
+    tmk::DensePlan best = forms[order[0]];
     float best_ms = INFINITY;
-    for (size_t f = 0; f < forms.size(); ++f)
-        if (form_ms[f] < best_ms) {
-            best_ms = form_ms[f];
-            best = forms[f];
+    for (size_t oi = 0; oi < std::min<size_t>(2, order.size()); ++oi)
+        for (int A : chunks) {
+            tmk::DensePlan p = forms[order[oi]];
+            if (!tmk::rechunk_dense(p, b->sd, b->pg.data(), b->npairs, A) || p.C > b->c_max) continue;
+            float ms = 0.f;
+            if (partner) {
+                st = batch_apply_plan(b, p, s);
+                if (st == TM_OK) st = batch_apply_plan(partner, p, S(partner_stream));
+                if (st == TM_OK)
+                    st = time_pipelined(b, partner, 2 * iterations + 2, s, S(partner_stream), ev[0], ev[1], ev[2], &ms);
+                if (st != TM_OK) return done(st);
+            } else {
+                st = batch_apply_plan(b, p, s);
+                if (st != TM_OK) return done(st);
+                e = time_search(b, b->plan, iterations, s, ev[0], ev[1], &ms);
+                if (e != hipSuccess) return done(hip_fail(e, "tm_batch_tune"));
+            }
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = b->plan;
+            }
         }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (e != hipSuccess) return hip_fail(e, "tm_batch_tune");
-    b->plan = best;
-    if (b->graph) {  // captured with the old form
-        (void)hipGraphExecDestroy(b->graph);
-        b->graph = nullptr;
-    }
+    st = batch_apply_plan(b, best, s);
+    if (st == TM_OK && partner) st = batch_apply_plan(partner, best, S(partner_stream));
+    if (st != TM_OK) return done(st);
     if (variant_out) *variant_out = best.variant;
     if (waves_out) *waves_out = best.WA;
-    if (us_out) *us_out = best_ms * 1000.f / iterations;
-    return TM_OK;
+    if (chunk_out) *chunk_out = best.A;
+    if (us_out) *us_out = best_ms * 1000.f;
+    return done(TM_OK);
 }
 
 namespace {

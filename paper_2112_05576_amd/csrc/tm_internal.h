@@ -255,6 +255,11 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs);
 // same scratch and work list): kernel variant and waves sharing a chunk.
 // false if the plan is not the fast path or the form does not fit.
 bool retune_dense(DensePlan& p, int variant, int WA);
+// Another angle chunking of a fast plan (A angles a chunk, rounded up to a
+// multiple of 4; the same tiles and form): chunks and workgroups follow.
+bool rechunk_dense(DensePlan& p, const SearchDesc& s, const PairGeom* g, int npairs, int A);
+// The distinct chunk sizes (angles) that give at most c_max chunks.
+std::vector<int> chunk_candidates(const DensePlan& p, const SearchDesc& s, int c_max);
 // Tile counts of a pair under a plan (fast path).
 void plan_tiles(const DensePlan& p, const PairGeom& g, int* tiles_x, int* tiles_y);
 size_t dense_partials_bytes(const DensePlan& p, int np);

@@ -94,9 +94,10 @@ def lib():
                                 ctypes.POINTER(SearchParamsC), _vp, _i32, _vp, _vp, ctypes.POINTER(_vp)],
             "tm_batch_run": [_vp, _vp],
             "tm_batch_run_graph": [_vp, _vp],
-            "tm_batch_tune": [_vp, _i32, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_float)],
-            "tm_batch_search_form": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
-            "tm_batch_set_form": [_vp, _i32, _i32],
+            "tm_batch_tune": [_vp, _vp, _i32, _vp, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                              ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_float)],
+            "tm_batch_search_form": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
+            "tm_batch_set_form": [_vp, _i32, _i32, _i32],
             "tm_batch_cont_score": [_vp, _i32, _vp, _i32, _vp, _vp],
             "tm_batch_cont_score_backward": [_vp, _i32, _vp, _i32, _vp, _vp, _vp],
             "tm_batch_cont_line_search": [_vp, _i32, _vp, _vp, _i32, ctypes.POINTER(ctypes.c_double), _i32, _vp, _vp],
@@ -405,23 +406,30 @@ class Batch:
     def handle(self):
         return self._h
 
-    def tune(self, iterations: int = 3, stream=None) -> dict:
-        """Time every form of the search kernel on the bound images and keep
-        the fastest (results are bit-identical whichever runs)."""
-        v, w, us = _i32(), _i32(), ctypes.c_float()
-        _check(lib().tm_batch_tune(self._h, iterations, _vp(_stream(stream)), ctypes.byref(v), ctypes.byref(w),
-                                   ctypes.byref(us)))
-        return {"variant": v.value, "waves_per_chunk": w.value, "search_us": us.value}
+    def tune(self, iterations: int = 3, stream=None, partner: "Batch | None" = None, partner_stream=None) -> dict:
+        """Autotune the search's schedule (variant, waves per chunk, angles per
+        chunk) on the bound images and keep the fastest (results are
+        bit-identical whichever runs).  With a partner batch of the same
+        shape on its own stream, the chunkings are timed on the pipelined
+        step of the two and both keep the choice."""
+        v, w, c, us = _i32(), _i32(), _i32(), ctypes.c_float()
+        ph = partner.handle if partner is not None else None
+        ps = _vp(_stream(partner_stream)) if partner is not None else None
+        _check(lib().tm_batch_tune(self._h, ph, iterations, _vp(_stream(stream)), ps, ctypes.byref(v), ctypes.byref(w),
+                                   ctypes.byref(c), ctypes.byref(us)))
+        return {"variant": v.value, "waves_per_chunk": w.value, "chunk_angles": c.value,
+                ("step_us" if partner is not None else "search_us"): us.value}
 
-    def set_form(self, variant: int, waves_per_chunk: int):
-        """Use this search-kernel form (e.g. another batch's tuned one) from now on."""
-        _check(lib().tm_batch_set_form(self._h, int(variant), int(waves_per_chunk)))
+    def set_form(self, variant: int, waves_per_chunk: int, chunk_angles: int = 0):
+        """Use this search schedule (e.g. another batch's tuned one) from now on
+        (chunk_angles 0: keep the chunking)."""
+        _check(lib().tm_batch_set_form(self._h, int(variant), int(waves_per_chunk), int(chunk_angles)))
 
     def search_form(self) -> dict:
-        """The search-kernel form in use: variant and waves sharing a chunk."""
-        v, w = _i32(), _i32()
-        _check(lib().tm_batch_search_form(self._h, ctypes.byref(v), ctypes.byref(w)))
-        return {"variant": v.value, "waves_per_chunk": w.value}
+        """The search schedule in use: variant, waves sharing a chunk, angles per chunk."""
+        v, w, c = _i32(), _i32(), _i32()
+        _check(lib().tm_batch_search_form(self._h, ctypes.byref(v), ctypes.byref(w), ctypes.byref(c)))
+        return {"variant": v.value, "waves_per_chunk": w.value, "chunk_angles": c.value}
 
     def cont_score(self, level: int, poses: torch.Tensor, pairs, stream=None) -> torch.Tensor:
         """S_c of (n, 3) poses on pairs[i] (image * n_models + model)."""

@@ -71,6 +71,14 @@ def test_detect_capacity_overflow():
 
 
 def test_torch_allocator():
+    """Handles take their memory from torch's caching allocator once it is
+    registered: a counting wrapper around it sees every handle allocate and
+    free all it took; results are those of hipMalloc'd handles; handles made
+    after switching back take nothing from it."""
+    import ctypes
+
+    from paper_2112_05576_amd import tm
+
     P, sc, cfg, L = _c2(1)
     case("torch caching allocator")
     sp = P.SearchParams(theta_step_top=cfg["theta_step_top"])
@@ -78,34 +86,50 @@ def test_torch_allocator():
     pyr0 = P.Pyramid(sc.image, L, cfg["tau_s"])
     ref = P.detect(gm0, pyr0, sp)
     img = torch.from_numpy(sc.image).cuda()
-    torch.cuda.synchronize()
-    P.use_torch_allocator(True)
+    live = {}
+
+    def alloc(nbytes, ctx, stream):
+        p = torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+        live[p] = int(nbytes)
+        return p
+
+    def free(ptr, ctx, stream):
+        live.pop(int(ptr))
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    a = tm.AllocatorC(tm._ALLOC_FN(alloc), tm._FREE_FN(free), None)
+    assert P.lib().tm_set_allocator(ctypes.byref(a)) == 0
     try:
-        a0 = torch.cuda.memory_allocated()
         gm = P.Model(sc.model, L, cfg["tau_m"])
-        a1 = torch.cuda.memory_allocated()
+        m_bytes = sum(live.values())
+        assert m_bytes > 0  # the model's points and directions
         pyr = P.Pyramid(img, L, cfg["tau_s"])
-        a2 = torch.cuda.memory_allocated()
-        # the handles' memory is torch's: the model's points, the pyramid's levels
-        assert a1 > a0 and a2 - a1 >= 640 * 480 * 9, (a0, a1, a2)
+        assert sum(live.values()) - m_bytes >= 640 * 480 * 9  # the pyramid's levels and fields
         got = P.detect(gm, pyr, sp)
         assert got.tobytes() == ref.tobytes()
         b = P.Batch([gm], [img], L, cfg["tau_s"], sp)
         b.run(graph=True)
         assert b.results()[0].tobytes() == ref.tobytes()
         torch.cuda.synchronize()
-        held = torch.cuda.memory_allocated()
         b.free()
         pyr.free()
         gm.free()
-        assert torch.cuda.memory_allocated() < held
-        assert torch.cuda.memory_allocated() <= a0 + 4096
+        assert not live, live  # every block handed back
+    finally:
+        assert P.lib().tm_set_allocator(None) == 0
+    # the binding's own registration: torch's caching allocator as it is
+    P.use_torch_allocator(True)
+    try:
+        gm = P.Model(sc.model, L, cfg["tau_m"])
+        pyr = P.Pyramid(img, L, cfg["tau_s"])
+        assert P.detect(gm, pyr, sp).tobytes() == ref.tobytes()
+        pyr.free()
+        gm.free()
     finally:
         P.use_torch_allocator(False)
-    # handles made after switching back use hipMalloc again
-    a3 = torch.cuda.memory_allocated()
+    # handles made after switching back take nothing from the wrapper
     pyr2 = P.Pyramid(img, L, cfg["tau_s"])
-    assert torch.cuda.memory_allocated() == a3
+    assert not live
     assert P.detect(gm0, pyr2, sp).tobytes() == ref.tobytes()
 
 

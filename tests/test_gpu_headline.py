@@ -44,9 +44,9 @@ def test_headline_batch_two_streams_matches_oracle():
     sp = P.SearchParams(theta_step_top=cfg["theta_step_top"])
     b0 = P.Batch([model], imgs, L, cfg["tau_s"], sp, precision=P.TM_FP16)
     b1 = P.Batch([model], imgs, L, cfg["tau_s"], sp, precision=P.TM_FP16)
-    form = b0.tune(iterations=1)
-    b1.set_form(form["variant"], form["waves_per_chunk"])
     streams = [torch.cuda.current_stream(), torch.cuda.Stream()]
+    form = b0.tune(iterations=1, partner=b1, partner_stream=streams[1])  # both keep the pipelined step's choice
+    assert b1.search_form() == b0.search_form()
     for i in range(6):
         (b0, b1)[i % 2].run(streams[i % 2], graph=True)
     torch.cuda.synchronize()

@@ -658,9 +658,11 @@ def test_paper_shaped_search_matches_oracle(index):
 
 
 def test_batch_tune_keeps_results():
-    """The autotuner only picks among bit-identical forms of the search: the
-    tuned batch returns exactly the detections of the untuned one, eager and
-    as a graph."""
+    """The autotuner only picks among bit-identical schedules of the search
+    (variant, waves per chunk, angles per chunk): the tuned batch returns
+    exactly the detections of the untuned one, eager and as a graph, alone
+    and tuned on the pipelined step with a partner; every chunking the batch
+    holds gives the same detections."""
     P = _P()
     case("batch autotune")
     cfg = synth.CONFIGS[2]
@@ -672,22 +674,46 @@ def test_batch_tune_keeps_results():
         b = P.Batch(models, images, 4, cfg["tau_s"], sp, precision=precision)
         b.run()
         ref = b.results()
+        planned = b.search_form()
         b.run(graph=True)  # a graph of the untuned form, to be discarded by tune()
         torch.cuda.synchronize()
         choice = b.tune(iterations=1)
         print(f"precision {precision}: {choice}")
         assert 0 <= choice["variant"] <= 5 and choice["waves_per_chunk"] in (2, 4, 8, 16)
-        assert choice["search_us"] > 0
+        assert choice["search_us"] > 0 and 4 <= choice["chunk_angles"] <= 360
         b.run()
         assert all(_poses_equal(a, c) for a, c in zip(b.results(), ref))
         b.run(graph=True)
         assert all(_poses_equal(a, c) for a, c in zip(b.results(), ref))
-        # another batch of the same shape takes the tuned form as it is, and
-        # a form that does not apply is refused
+        # every chunking the batch holds, in the planned form: the same detections
+        for chunk in (8, 16, 40, 120, 360):
+            try:
+                b.set_form(planned["variant"], planned["waves_per_chunk"], chunk)
+            except P.TMError:  # more chunks than the batch holds
+                assert 360 // chunk > 12
+                continue
+            assert b.search_form()["chunk_angles"] == chunk
+            b.run(graph=True)
+            assert all(_poses_equal(a, c) for a, c in zip(b.results(), ref)), chunk
+        # tuned on the pipelined step with a partner of the same shape: both keep the choice
         b2 = P.Batch(models, images, 4, cfg["tau_s"], sp, precision=precision)
-        b2.set_form(choice["variant"], choice["waves_per_chunk"])
-        assert b2.search_form() == {"variant": choice["variant"], "waves_per_chunk": choice["waves_per_chunk"]}
-        b2.run(graph=True)
+        s2 = torch.cuda.Stream()
+        pc = b.tune(iterations=1, partner=b2, partner_stream=s2)
+        assert pc["step_us"] > 0 and b2.search_form() == b.search_form()
+        b.run(graph=True)
+        b2.run(s2, graph=True)
+        torch.cuda.synchronize()
+        assert all(_poses_equal(a, c) for a, c in zip(b.results(), ref))
         assert all(_poses_equal(a, c) for a, c in zip(b2.results(), ref))
+        # another batch of the same shape takes the tuned schedule as it is, and
+        # a form that does not apply is refused
+        b3 = P.Batch(models, images, 4, cfg["tau_s"], sp, precision=precision)
+        b3.set_form(choice["variant"], choice["waves_per_chunk"], choice["chunk_angles"])
+        assert b3.search_form() == {"variant": choice["variant"], "waves_per_chunk": choice["waves_per_chunk"],
+                                    "chunk_angles": choice["chunk_angles"]}
+        b3.run(graph=True)
+        assert all(_poses_equal(a, c) for a, c in zip(b3.results(), ref))
         with pytest.raises(P.TMError):
-            b2.set_form(9, 4)
+            b3.set_form(9, 4)
+        with pytest.raises(P.TMError):
+            b3.set_form(planned["variant"], planned["waves_per_chunk"], 1)  # 360 chunks: beyond the scratch
