@@ -4,21 +4,26 @@
 // (2x + a, 2y + b, 2k + c), a, b, c in {-1, 0, 1}, with the same windowed
 // score (Eq. 1) and keeping the best by the selection key.
 //
-// One pass per level, by one of two kernels with the same arithmetic:
-//  * k_refine_level, one workgroup per (candidate, angle c): each thread takes
-//    every 256th model point, forms q_i and r_i in FP64, reads the 5x5 field
+// One pass per level, by one of two kernels with the same arithmetic.  The
+// points of a pose are shared by kThreads threads (thread t takes the points
+// t, t + kThreads, ...), and the sums are kept per wave of them:
+//  * k_refine_level, one workgroup of one wave per (candidate, angle, wave):
+//    each lane forms q_i and r_i of its points in FP64, reads the 5x5 field
 //    block covering the 3x3 windows of the 9 translations straight from
 //    memory (two points' 50 loads in flight), and accumulates 9 windowed and
 //    9 centre votes;
 //  * k_refine_tile, one workgroup per candidate: the candidate's whole field
 //    block (side 2 rad + 5 around (2x, 2y)) is first staged in LDS with
-//    coalesced loads, then three groups of 256 threads score the three
+//    coalesced loads, then three groups of kThreads threads score the three
 //    angles as above with the taps read from LDS.
-// A thread adds its points in increasing order and the workgroup combines the
-// threads by a fixed butterfly per wave and the waves in order, in both
-// kernels, so their sums are bit-identical and a launch may take either (the
-// staged one pays off once a launch holds many candidates).  The next level
-// (or the final pick) picks the best of the 27 sums.
+// A thread adds its points in increasing order and each wave combines its
+// lanes by a fixed butterfly, in both kernels, so their per-wave sums are
+// bit-identical and a launch may take either; whoever picks from them adds
+// the waves in order.  The gathers are bound by the address rate of each
+// CU's vector memory unit (every lane's block lies elsewhere), so they are
+// spread one wave per workgroup over as many CUs as the candidates allow;
+// the staged kernel pays off once a launch holds many candidates.  The next
+// level (or the final pick) picks the best of the 27 sums.
 #include "tm_device.h"
 
 namespace tmk {
@@ -27,6 +32,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
+static_assert(kWaves == kRefineWaves, "sums are kept per wave of a pose's threads");
 constexpr size_t kTileMax = 128 * 1024;  // largest staged field block
 
 struct LevelArgs {
@@ -93,13 +99,10 @@ __device__ __forceinline__ void votes5x5(const typename Raw<PREC>::T (&gv)[5][5]
         }
 }
 
-// The 18 sums of a group of kThreads threads (t: the thread's index in its
-// group): a fixed butterfly per wave, then the group's waves in order;
-// written to out[0..17].  Every thread of the workgroup must call it (it
-// holds two workgroup barriers; red may be reused afterwards).
-__device__ __forceinline__ void block_sum18(float (&aw)[9], float (&a1)[9], float (*red)[18], float* out, int t)
+// The 18 sums of one wave (a fixed butterfly), written to out[0..17] by its
+// first lane.
+__device__ __forceinline__ void wave_sum18(float (&aw)[9], float (&a1)[9], float* out)
 {
-    const int lane = t & 63, wv = t >> 6;
 #pragma unroll
     for (int m = 0; m < 9; ++m) {
 #pragma unroll
@@ -108,20 +111,13 @@ __device__ __forceinline__ void block_sum18(float (&aw)[9], float (&a1)[9], floa
             a1[m] += __shfl_xor(a1[m], off, 64);
         }
     }
-    if (lane == 0) {
+    if ((threadIdx.x & 63) == 0) {
 #pragma unroll
         for (int m = 0; m < 9; ++m) {
-            red[wv][m] = aw[m];
-            red[wv][9 + m] = a1[m];
+            out[m] = aw[m];
+            out[9 + m] = a1[m];
         }
     }
-    __syncthreads();
-    if (t < 18) {
-        float s = 0.f;
-        for (int w = 0; w < kWaves; ++w) s += red[w][t];
-        out[t] = s;
-    }
-    __syncthreads();
 }
 
 // The candidate's pose at the level above: picked by the first wave from that
@@ -139,8 +135,8 @@ __device__ void take_centre(const LevelArgs& a, const PairDesc& P, int c, bool w
         if (a.pick) {
             const tm_pose ctr = P.ctr[a.src][c];
             const int la = l + 1;
-            pick27(P.part[la] + (size_t)c * 54, ctr.x, ctr.y, ctr.k, P.W[la], P.H[la], P.n[la], a.K_above, a.full,
-                   &sw, &s1, &x, &y, &k);
+            pick27(P.part[la] + (size_t)c * kPartPerCand, ctr.x, ctr.y, ctr.k, P.W[la], P.H[la], P.n[la], a.K_above,
+                   a.full, &sw, &s1, &x, &y, &k);
             j = ctr.j;
         } else {
             const tm_pose p = P.cand[c];
@@ -193,41 +189,22 @@ __device__ __forceinline__ void block5(int px, int py, int W, int H, Block5& b)
     }
 }
 
+// The 9 windowed and 9 centre votes of the points t, t + kThreads, ... of
+// level l for the pose (2x + ., 2y + ., angle with cosine/sine cs, sn, scale
+// sigma), added to aw / a1 in point order; field taps gathered from memory.
 template <int PREC, int VOTE>
-__global__ __launch_bounds__(kThreads) void k_refine_level(LevelArgs a, const PairDesc* __restrict__ pairs)
+__device__ __forceinline__ void gather_votes(const PairDesc& P, int l, int win, int x, int y, double cs, double sn,
+                                             double sigma, int t, float (&aw)[9], float (&a1)[9])
 {
-    __shared__ float red[kWaves][18];
-    __shared__ int cur[4];
-    const PairDesc& P = pairs[blockIdx.y];
-    const int l = a.level;
-    if (a.staged && P.rtile[l]) return;  // this pair's level is refined by k_refine_tile
-    const int g = blockIdx.x % 3;
-    const int c = blockIdx.x / 3;
-    int count = a.max_cand;
-    if (P.ncand) count = min(count, *P.ncand);
-    if (c >= count) return;
-    take_centre(a, P, c, g == 0, cur);
-    __syncthreads();
-    const int x = cur[0], y = cur[1], k = cur[2];
-    const double sigma = scale_of(a.sigma_min, a.sigma_step, cur[3]);
     const void* field = P.field[l];
     const int W = P.W[l], H = P.H[l], n = P.n[l];
     const ModelPoint* __restrict__ pts = P.pts[l];
     const double2* __restrict__ dir = P.dir[l];
-    const int kc = angle_index(2 * k + g - 1, a.K, a.full);
-    double cs, sn;
-    sincos_deg(level_theta(a.theta_min, a.step, kc), &cs, &sn);
-    float aw[9], a1[9];
-#pragma unroll
-    for (int m = 0; m < 9; ++m) {
-        aw[m] = 0.f;
-        a1[m] = 0.f;
-    }
-    const int wh = (a.win - 1) / 2;
+    const int wh = (win - 1) / 2;
     if (wh == 1) {
         // two points per step (this thread's next two), their 50 loads issued
         // before any is used; votes added in point order
-        for (int i = threadIdx.x; i < n; i += 2 * kThreads) {
+        for (int i = t; i < n; i += 2 * kThreads) {
             const int j = i + kThreads;
             const bool two = j < n;
             int qx0, qy0, qx1 = 0, qy1 = 0;
@@ -252,7 +229,7 @@ __global__ __launch_bounds__(kThreads) void k_refine_level(LevelArgs a, const Pa
         }
     } else {
         // any odd window: direct evaluation of each translation
-        for (int i = threadIdx.x; i < n; i += kThreads) {
+        for (int i = t; i < n; i += kThreads) {
             int qx, qy;
             double rx, ry;
             const double2 d = dir[i];
@@ -273,7 +250,35 @@ __global__ __launch_bounds__(kThreads) void k_refine_level(LevelArgs a, const Pa
                 }
         }
     }
-    block_sum18(aw, a1, red, P.part[l] + ((size_t)c * 3 + g) * 18, threadIdx.x);
+}
+
+template <int PREC, int VOTE>
+__global__ __launch_bounds__(64) void k_refine_level(LevelArgs a, const PairDesc* __restrict__ pairs)
+{
+    __shared__ int cur[4];
+    const PairDesc& P = pairs[blockIdx.y];
+    const int l = a.level;
+    if (a.staged && P.rtile[l]) return;  // this pair's level is refined by k_refine_tile
+    const int c = blockIdx.x / (3 * kWaves);
+    const int g = blockIdx.x / kWaves % 3, w = blockIdx.x % kWaves;
+    int count = a.max_cand;
+    if (P.ncand) count = min(count, *P.ncand);
+    if (c >= count) return;
+    take_centre(a, P, c, g == 0 && w == 0, cur);
+    __syncthreads();
+    const int x = cur[0], y = cur[1], k = cur[2];
+    const double sigma = scale_of(a.sigma_min, a.sigma_step, cur[3]);
+    const int kc = angle_index(2 * k + g - 1, a.K, a.full);
+    double cs, sn;
+    sincos_deg(level_theta(a.theta_min, a.step, kc), &cs, &sn);
+    float aw[9], a1[9];
+#pragma unroll
+    for (int m = 0; m < 9; ++m) {
+        aw[m] = 0.f;
+        a1[m] = 0.f;
+    }
+    gather_votes<PREC, VOTE>(P, l, a.win, x, y, cs, sn, sigma, w * 64 + (int)threadIdx.x, aw, a1);
+    wave_sum18(aw, a1, P.part[l] + (size_t)c * kPartPerCand + (g * kWaves + w) * 18);
 }
 
 // One workgroup per candidate, three groups of kThreads threads, group g
@@ -288,7 +293,6 @@ __global__ __launch_bounds__(kThreads * kTileGroups) void k_refine_tile(LevelArg
 {
     using T = typename Raw<PREC>::T;
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ float red[kTileGroups][kWaves][18];
     __shared__ int cur[4];
     const PairDesc& P = pairs[blockIdx.y];
     const int l = a.level;
@@ -362,7 +366,7 @@ __global__ __launch_bounds__(kThreads * kTileGroups) void k_refine_tile(LevelArg
                 for (int u = 0; u < 5; ++u) gv[v][u] = b[v * S + u];
             votes5x5<PREC, VOTE>(gv, rin, cin, Raw<PREC>::dir(rx, ry), aw, a1);
         }
-        block_sum18(aw, a1, red[g], P.part[l] + ((size_t)c * 3 + g) * 18, t);
+        wave_sum18(aw, a1, P.part[l] + (size_t)c * kPartPerCand + (g * kWaves + (t >> 6)) * 18);
     }
 }
 
@@ -383,7 +387,7 @@ __global__ __launch_bounds__(64) void k_refine_pick(PickArgs a, const PairDesc* 
     const tm_pose ctr = P.ctr[a.src][c];
     float sw, s1;
     int x, y, k;
-    pick27(P.part[0] + (size_t)c * 54, ctr.x, ctr.y, ctr.k, P.W[0], P.H[0], P.n[0], a.K0, a.full, &sw, &s1, &x, &y,
+    pick27(P.part[0] + (size_t)c * kPartPerCand, ctr.x, ctr.y, ctr.k, P.W[0], P.H[0], P.n[0], a.K0, a.full, &sw, &s1, &x, &y,
            &k);
     if (threadIdx.x == 0) {
         tm_pose o;
@@ -434,8 +438,8 @@ void launch_level_kernels(const SearchDesc& s, const PairDesc* d, int npairs, co
     // the descriptors' fields are FP32 (an FP16 pyramid's twin): the
     // refinement's picks are decisions, taken at FP32 accuracy
     if (!rp.staged || rp.gather[l]) {
-        dim3 grid((unsigned)(s.max_cand * 3), npairs);
-        hipLaunchKernelGGL((k_refine_level<TM_FP32, VOTE>), grid, dim3(kThreads), 0, st, a, d);
+        dim3 grid((unsigned)(s.max_cand * 3 * kWaves), npairs);
+        hipLaunchKernelGGL((k_refine_level<TM_FP32, VOTE>), grid, dim3(64), 0, st, a, d);
     }
     if (rp.staged && rp.tile_bytes[l] > 0) {
         dim3 grid((unsigned)s.max_cand, npairs);

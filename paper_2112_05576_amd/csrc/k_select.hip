@@ -328,7 +328,7 @@ __global__ __launch_bounds__(1024) void k_final(FinalArgs fa, const PairDesc* __
             const tm_pose ctr = P.ctr[fa.pick][i];
             float sw, s1;
             int x, y, k;
-            pick27(P.part[0] + (size_t)i * 54, ctr.x, ctr.y, ctr.k, P.W[0], P.H[0], P.n[0], fa.K0, fa.full, &sw, &s1,
+            pick27(P.part[0] + (size_t)i * kPartPerCand, ctr.x, ctr.y, ctr.k, P.W[0], P.H[0], P.n[0], fa.K0, fa.full, &sw, &s1,
                    &x, &y, &k);
             if ((threadIdx.x & 63) == 0 && sw >= min_score) {
                 const int idx = atomicAdd(&count, 1);

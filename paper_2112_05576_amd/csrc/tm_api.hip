@@ -418,7 +418,7 @@ size_t pair_scratch(tmk::PairDesc* d, const tm_model* m, const tmk::PairGeom& g,
         }
         for (int l = 0; l < L; ++l) {
             float* pl = reinterpret_cast<float*>(
-                take((size_t)max_cand * 3 * 18 * sizeof(float)));
+                take((size_t)max_cand * tmk::kPartPerCand * sizeof(float)));
             if (base) d->part[l] = pl;
         }
     }

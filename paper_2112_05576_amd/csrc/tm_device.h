@@ -188,8 +188,8 @@ __device__ __forceinline__ bool key_better(float aw, float a1, int ax, int ay, i
 }
 
 // Best of the 27 poses around (x, y, k) (a pose of level l+1) at level l, from
-// the sums part[g][m] (m < 9: S_w of translation m, m >= 9: S_1).  Runs on
-// one wave; every lane returns the result.
+// the per-wave sums part[g][w][m] (m < 9: S_w of translation m, m >= 9: S_1),
+// the waves added in order.  Runs on one wave; every lane returns the result.
 __device__ __forceinline__ void pick27(const float* __restrict__ part, int x, int y, int k, int W, int H, int n, int K, int full,
                        float* bw, float* b1, int* bx, int* by, int* bk)
 {
@@ -198,8 +198,14 @@ __device__ __forceinline__ void pick27(const float* __restrict__ part, int x, in
     const int g = m / 9, t = m % 9, b = t / 3, u = t % 3;
     const int kg = angle_index(2 * k + g - 1, K, full);
     const int xx = 2 * x + u - 1, yy = 2 * y + b - 1;
-    const float sw = part[g * 18 + t] / (float)n;
-    const float s1 = part[g * 18 + 9 + t] / (float)n;
+    float aw = 0.f, a1 = 0.f;
+#pragma unroll
+    for (int w = 0; w < kRefineWaves; ++w) {
+        aw += part[(g * kRefineWaves + w) * 18 + t];
+        a1 += part[(g * kRefineWaves + w) * 18 + 9 + t];
+    }
+    const float sw = aw / (float)n;
+    const float s1 = a1 / (float)n;
     const bool ok = lane < 27 && xx >= 0 && yy >= 0 && xx < W && yy < H;
     float kw = ok ? sw : -INFINITY, k1 = ok ? s1 : -INFINITY;
     int kx = ok ? xx : 0x7fffffff, ky = ok ? yy : 0x7fffffff, kk = ok ? kg : 0x7fffffff;

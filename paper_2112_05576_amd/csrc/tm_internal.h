@@ -15,6 +15,12 @@
 namespace tmk {
 
 constexpr int kMaxLevels = TM_MAX_LEVELS;
+// The refinement's sums of one candidate and level: for each of its 3 angles,
+// the 18 sums (9 windowed, 9 centre) of each of the kRefineWaves waves that
+// share the angle's points; a sum over the angle's points is the waves' sums
+// added in wave order.
+constexpr int kRefineWaves = 4;
+constexpr int kPartPerCand = 3 * kRefineWaves * 18;
 
 // One model edge point: offset t from the level's reference pixel and the
 // integer Sobel gradient (the unit direction d = g/|g| is formed in FP64
@@ -191,7 +197,7 @@ struct PairDesc {
     tm_pose* cand;                   // candidates [max_cand] (refined in place)
     int32_t* ncand;                  // their count (device); null: max_cand
     tm_pose* ctr[2];                 // refinement centres [max_cand]
-    float* part[kMaxLevels];         // refinement sums [max_cand][3][18]
+    float* part[kMaxLevels];         // refinement sums [max_cand][3][kRefineWaves][18]
     int rad_l[kMaxLevels];           // bound on |q| components at each level
     int rtile[kMaxLevels];           // 1: level refined by the staged kernel (partials: one chunk)
     void* pfield;                    // generic search: the searched field with a zero border
