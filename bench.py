@@ -72,6 +72,10 @@ def parse():
     ap.add_argument("--c3", action="store_true",
                     help="also time the 2048x2048 five-level FP16 detection with its per-score error against FP32")
     ap.add_argument("--no-other", action="store_true", help="skip the batched leg of the other precision")
+    ap.add_argument("--plain-only", action="store_true",
+                    help="time the FP32 plain leg alone and print its figures (a profiling aid, not the bench line)")
+    ap.add_argument("--loop-mix-from", metavar="K_SCORE_ASM",
+                    help="record the search loop's VALU issue mix from the AMD assembly of k_score.hip")
     ap.add_argument("--valu-from", metavar="VALU_CSV",
                     help="write the search kernel's VALU-instruction entry from a rocprofv3 --pmc SQ_INSTS_VALU CSV "
                          "and exit")
@@ -132,13 +136,14 @@ def trace_summary(path):
 
 
 def traffic_from(fetch_csv, write_csv):
-    """HBM bytes per launch of the search kernel: its FETCH_SIZE and
+    """HBM bytes per launch of the batched search kernel: its FETCH_SIZE and
     WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads
     for the final 256 MiB elementwise copy of --copy-probe (read 256 MiB,
     write 256 MiB).  Run the counter passes with tuning on: the tuner
-    dispatches every form of the search kernel over the same batch, so one
-    pass per counter gives the figure of each form (variant, waves per
-    chunk), and the bench line takes the one of the form it runs."""
+    dispatches every schedule of the search over the same batch, so one pass
+    per counter gives the figure of each schedule, told apart by kernel
+    variant, waves per chunk and workgroups per launch; the bench line takes
+    the one of the schedule it runs."""
     out = {"kernel_sha256": hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()}
     per = {}
     for key, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
@@ -149,18 +154,21 @@ def traffic_from(fetch_csv, write_csv):
         scale = COPY_PROBE_BYTES / probe  # bytes per counted KiB
         out[f"{key}_probe_kib"] = probe
         out[f"{key}_scale_bytes_per_kib"] = scale
-        # the batched launches: the search dispatches with the most
-        # workgroups (every form of the batch runs the same work list)
-        blocks = [g // wg for n, _, g, wg in rows if "k_dense_fast" in n]
-        if not blocks:
-            raise SystemExit(f"no k_dense_fast dispatch in {path}")
-        for n, v, g, wg in rows:
-            if "k_dense_fast" not in n or g // wg != max(blocks):
+        n = 0
+        for name, v, g, wg in rows:
+            m = re.search(r"k_dense_fast<([^>]*)>", name)
+            if not m:
                 continue
-            # template arguments: G, R, LC, PREC, VAR (the variant), VOTE
-            targs = [int(t) for t in re.search(r"k_dense_fast<([^>]*)>", n).group(1).split(",")]
-            f = per.setdefault((targs[4], wg // 64), {"variant": targs[4], "waves_per_chunk": wg // 64})
+            # template arguments: G, R, LC, PREC, VAR (the variant), VOTE[, SCREEN]; the FP16 batch's launches
+            targs = [t.strip() for t in m.group(1).split(",")]
+            if int(targs[3]) != 1:
+                continue
+            k = (int(targs[4]), wg // 64, g // wg)
+            f = per.setdefault(k, {"variant": k[0], "waves_per_chunk": k[1], "workgroups": k[2]})
             f.setdefault(key, []).append(v * scale)
+            n += 1
+        if not n:
+            raise SystemExit(f"no FP16 k_dense_fast dispatch in {path}")
     forms = []
     for f in per.values():
         if "fetch" not in f or "write" not in f:
@@ -168,13 +176,12 @@ def traffic_from(fetch_csv, write_csv):
         # the median launch: a batch's first launch after its creation reads
         # its inputs from cold caches and is not the steady state
         fb, wb = float(np.median(f["fetch"])), float(np.median(f["write"]))
-        forms.append({"variant": f["variant"], "waves_per_chunk": f["waves_per_chunk"], "fetch_bytes": fb,
-                      "write_bytes": wb, "bytes_per_launch": fb + wb, "launches": len(f["fetch"]),
-                      "fetch_bytes_max": max(f["fetch"])})
-    out["forms"] = sorted(forms, key=lambda f: (f["variant"], f["waves_per_chunk"]))
+        forms.append({"variant": f["variant"], "waves_per_chunk": f["waves_per_chunk"], "workgroups": f["workgroups"],
+                      "fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
+                      "launches": len(f["fetch"]), "fetch_bytes_max": max(f["fetch"])})
+    out["forms"] = sorted(forms, key=lambda f: (f["variant"], f["waves_per_chunk"], f["workgroups"]))
     os.makedirs(os.path.dirname(TRAFFIC_JSON), exist_ok=True)
-    with open(TRAFFIC_JSON, "w") as fh:
-        json.dump(out, fh, indent=1)
+    _dump_forms(TRAFFIC_JSON, out)
     print(json.dumps(out))
 
 
@@ -223,9 +230,16 @@ def cpu_baseline(scenes, cfg, budget_s, paper=False):
                   model=model)
     res["single_core_value"] = tr.top[0].size * O.level_count(osp, O.level_step(osp, L, L - 1)) / (
         time.perf_counter() - t0)
-    if paper:
-        import synth
+    # the single-instance configuration (128x128, one level, 72 angles), one
+    # full detection
+    import synth
 
+    c1 = synth.CONFIGS[1]
+    sc1 = synth.scene_for_config(1, 0)
+    dt1, poses1, _, _, _ = oracle_detection(sc1.image, sc1.model, c1, c1["levels"], threads)
+    res["configs"] = {"128x128 single instance, 1 level, 72 angles": {
+        "ms_per_detection": dt1 * 1e3, "pose_evals_per_sec": poses1 / dt1, "sample": "1 full detection"}}
+    if paper:
         sc = synth.scene_for_config(6, 0)
         pc = sc.config
         osp = O.SearchParams(step_x=3, step_y=3, theta_min=0.0, theta_range=90.0, theta_step_top=3.0, max_matches=1)
@@ -233,6 +247,39 @@ def cpu_baseline(scenes, cfg, budget_s, paper=False):
         O.detect(sc.image, sc.model, O.PyrParams(1, pc["tau_s"]), O.PyrParams(1, pc["tau_m"]), osp, nthreads=threads)
         res["paper_shape_ms_per_detection"] = (time.perf_counter() - t0) * 1e3
     return res, (model, dets)
+
+
+def oracle_detection(image, model_img, cfg, L, threads):
+    """One full oracle detection (pyramid, exhaustive top level, refinement,
+    selection) timed on `threads` host threads: (seconds, top-level poses,
+    detections, level-0 field, oracle model)."""
+    import oracle as O
+
+    osp = O.SearchParams(theta_step_top=cfg["theta_step_top"])
+    om = O.build_model(model_img, O.PyrParams(L, cfg["tau_m"]))
+    t0 = time.perf_counter()
+    tr = O.detect(image, model_img, O.PyrParams(L, cfg["tau_s"]), O.PyrParams(L, cfg["tau_m"]), osp, nthreads=threads,
+                  model=om)
+    dt = time.perf_counter() - t0
+    return dt, tr.top[0].size * O.level_count(osp, O.level_step(osp, L, L - 1)), tr.detections, tr.fields[0], om
+
+
+def top1_one(g, ref, f0, om, cfg, L):
+    """"identical", "tie" (the GPU top match's oracle S_w and S_1 within 1e-5
+    of the oracle's top match), "differs" or "both_empty" for one image."""
+    import oracle as O
+
+    if len(ref) == 0 and len(g) == 0:
+        return "both_empty"
+    if len(ref) == 0 or len(g) == 0:
+        return "differs"
+    if (int(g[0]["x"]), int(g[0]["y"]), int(g[0]["k"])) == (ref[0].x, ref[0].y, ref[0].k):
+        return "identical"
+    osp = O.SearchParams(theta_step_top=cfg["theta_step_top"])
+    ml = om.levels[0]
+    sw, s1 = O.score(f0, ml.t, ml.d, int(g[0]["x"]), int(g[0]["y"]),
+                     O.theta(0.0, O.level_step(osp, L, 0), int(g[0]["k"])))
+    return "tie" if abs(sw - ref[0].sw) <= 1e-5 and abs(s1 - ref[0].s1) <= 1e-5 else "differs"
 
 
 def top1_vs_oracle(gpu_dets, oracle, cfg):
@@ -273,7 +320,8 @@ def traffic_entry(form):
     if d.get("kernel_sha256") != h:
         return None
     for f in d.get("forms", []):
-        if (f["variant"], f["waves_per_chunk"]) == (form.get("variant"), form.get("waves_per_chunk")):
+        if (f["variant"], f["waves_per_chunk"], f.get("workgroups")) == (
+                form.get("variant"), form.get("waves_per_chunk"), form.get("workgroups")):
             return f["bytes_per_launch"]
     return None
 
@@ -287,8 +335,11 @@ def _ang(a, b):
     return np.abs((a - b + 180.0) % 360.0 - 180.0)
 
 
-def c4_legs(P, torch, steps, warmup):
-    """The mixed batch (FP16, graph launch) and the continuous refinement."""
+def c4_legs(P, torch, steps, warmup, oracle_threads=0):
+    """The mixed batch (FP16, graph launch) and the continuous refinement.
+    With oracle_threads, the oracle's full detections of a 2-image x 8-model
+    subset of the batch are timed on that many host threads and the batch's
+    top-1 of those pairs compared with them."""
     import synth
 
     cfg = synth.C4
@@ -325,6 +376,21 @@ def c4_legs(P, torch, steps, warmup):
                       f"({', '.join(str(m.level_info(0)[2]) for m in models)} level-0 points), FP16, graph launch",
           "ms_per_step": dt * 1e3, "detections_per_sec": len(scenes) * nm / dt, "pose_evals_per_sec": poses / dt,
           "taps_per_sec": taps / dt, "instances_found": f"{found}/{total}", "search_form": tuned}
+    if oracle_threads:
+        secs, n_o, top1 = 0.0, 0, {}
+        for i in range(2):
+            for k in range(nm):
+                dt_o, poses_o, ref, f0, om = oracle_detection(scenes[i].image, mods[k][1], cfg, L, oracle_threads)
+                secs += dt_o
+                n_o += poses_o
+                r = top1_one(res[i * nm + k], ref, f0, om, cfg, L)
+                top1[r] = top1.get(r, 0) + 1
+        c4["cpu_oracle"] = {"ms_per_detection": secs / (2 * nm) * 1e3, "pose_evals_per_sec": n_o / secs,
+                            "cores": oracle_threads,
+                            "sample": f"images 0-1 ({scenes[0].image.shape[1]}x{scenes[0].image.shape[0]}, "
+                                      f"{scenes[1].image.shape[1]}x{scenes[1].image.shape[0]}) x {nm} models, "
+                                      f"full detections"}
+        c4["top1_vs_oracle_subset"] = top1
     # C5: 4096 poses near the truth, 10 ascent steps on FP32 fields
     b32 = P.Batch(models, imgs, L, cfg["tau_s"], sp, precision=P.TM_FP32)
     b32.run()
@@ -481,30 +547,145 @@ def paper_leg(P, torch, steps):
 
 
 VALU_JSON = os.path.join(ROOT, "profiles", "dense_c2_valu.json")
+LOOP_MIX_JSON = os.path.join(ROOT, "profiles", "dense_c2_loop_mix.json")
+SIMDS = 1024                 # 256 CUs x 4 SIMDs
+CLOCK_HZ = 2.4e9             # MI355X peak engine clock (published)
+# Issue cycles of one wave64 VALU instruction by class: the packed-half dot
+# product, DPP-modified and three-operand max instructions take 4 (the class
+# probes measure 4.1 to 4.6 at the clock they run at), the rest 2 (plain
+# adds measure 2.2).
+SLOW_VALU = ("v_dot2", "v_max3", "v_min3", "v_med3")
+
+
+def _dump_forms(path, out):
+    """A record with its forms one per line (short files for profiles/)."""
+    head = {k: v for k, v in out.items() if k != "forms"}
+    with open(path, "w") as fh:
+        fh.write(json.dumps(head)[:-1] + ', "forms": [\n')
+        fh.write(",\n".join(json.dumps(f, separators=(",", ":")) for f in out["forms"]))
+        fh.write("\n]}\n")
+
+
+def _valu_cycles(mnemonic, operands):
+    return 4 if mnemonic.startswith(SLOW_VALU) or mnemonic.endswith("_dpp") or "row_" in operands or \
+        "wave_sh" in operands or "quad_perm" in operands else 2
+
+
+def loop_mix_from(asm_path):
+    """The VALU mix of the search kernel's innermost loop, per instantiation
+    of k_dense_fast, from the AMD assembly of k_score.hip (hipcc
+    --cuda-device-only -S): instructions by issue class and the mean issue
+    cycles per instruction, which with the SIMD count and the engine clock
+    give the issue peak of that loop; recorded with the SHA-256 of the
+    source."""
+    lines = open(asm_path).read().splitlines()
+    fn_re = re.compile(r"^(_ZN3tmk\S*k_dense_fastILi(\d+)ELi(\d+)ELi(\d+)ELi(\d+)ELi(\d+)ELi(\d+)ELb([01])E\S*):")
+    out = {"kernel_sha256": hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest(), "clock_hz": CLOCK_HZ,
+           "simds": SIMDS, "forms": []}
+    i = 0
+    while i < len(lines):
+        m = fn_re.match(lines[i])
+        if not m:
+            i += 1
+            continue
+        j = i + 1
+        while j < len(lines) and "s_endpgm" not in lines[j]:
+            j += 1
+        body = lines[i + 1:j]
+        labels = {}
+        loops = []
+        for k, ln in enumerate(body):
+            lm = re.match(r"^(\.LBB\w+):", ln)
+            if lm:
+                labels[lm.group(1)] = k
+            bm = re.match(r"^\s*s_c?branch\w*\s+(\.LBB\w+)", ln)
+            if bm and bm.group(1) in labels and labels[bm.group(1)] < k:
+                loops.append((labels[bm.group(1)], k))
+        # innermost loops (no other loop inside); the search loop is the one
+        # with the most cross-lane (DPP) window maxima, then products (dot2,
+        # fma, mul), then VALU instructions
+        inner = [(a, b) for a, b in loops if not any(a < c and d < b for c, d in loops if (c, d) != (a, b))]
+        best = None
+        for a, b in inner:
+            cls = {}
+            n = cyc = lds = prod = dpp = 0
+            for ln in body[a:b + 1]:
+                t = ln.strip().split(None, 1)
+                if t and t[0].startswith("ds_read"):
+                    lds += 1
+                if not t or not t[0].startswith("v_"):
+                    continue
+                if t[0].startswith(("v_dot2", "v_fma", "v_mul_f32", "v_pk_fma", "v_pk_mul")):
+                    prod += 1
+                c = _valu_cycles(t[0], t[1] if len(t) > 1 else "")
+                if "dpp" in t[0] or "row_" in ln or "wave_sh" in ln or "quad_perm" in ln:
+                    dpp += 1
+                cls[t[0]] = cls.get(t[0], 0) + 1
+                n += 1
+                cyc += c
+            if n and (best is None or (dpp, prod, n) > (best["dpp"], best["products"], best["valu"])):
+                best = {"valu": n, "cycles": cyc, "lds_reads": lds, "products": prod, "dpp": dpp,
+                        "by_mnemonic": dict(sorted(cls.items(), key=lambda kv: -kv[1]))}
+        if best:
+            G, R, LC, prec, var, vote, screen = (int(x) for x in m.groups()[1:])
+            out["forms"].append({"precision": "fp16" if prec else "fp32", "variant": var, "vote": vote,
+                                 "screen": bool(screen), "lc": LC, "loop_valu": best["valu"],
+                                 "loop_issue_cycles": best["cycles"], "loop_lds_reads": best["lds_reads"],
+                                 "cycles_per_instr": best["cycles"] / best["valu"],
+                                 "by_mnemonic": best["by_mnemonic"]})
+        i = j
+    # one entry per form: the smallest field-tile width (the 640x480 batches'), its six most frequent mnemonics
+    keep = {}
+    for f in out["forms"]:
+        k = (f["precision"], f["variant"], f["vote"], f["screen"])
+        if k not in keep or f["lc"] < keep[k]["lc"]:
+            keep[k] = dict(f, by_mnemonic=dict(list(f["by_mnemonic"].items())[:6]))
+    out["forms"] = [keep[k] for k in sorted(keep)]
+    _dump_forms(LOOP_MIX_JSON, out)
+    print(json.dumps({k: v for k, v in out.items() if k != "forms"} | {"forms": len(out["forms"])}))
+
+
+def loop_mix_entry(form, precision, vote=0):
+    """Mean issue cycles per VALU instruction of the search loop of the form
+    in use, if recorded on the current k_score.hip (the loop of the smallest
+    field-tile width, the one the 640x480 batches use, is the one recorded)."""
+    if not os.path.exists(LOOP_MIX_JSON):
+        return None
+    d = json.load(open(LOOP_MIX_JSON))
+    if d.get("kernel_sha256") != hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest():
+        return None
+    fs = [f for f in d.get("forms", []) if (f["precision"], f["variant"], f["vote"], f["screen"]) ==
+          (precision, form.get("variant"), vote, precision == "fp16")]
+    if not fs:
+        return None
+    f = fs[0]
+    return {"cycles_per_instr": f["cycles_per_instr"], "loop_valu": f["loop_valu"],
+            "counted_in": os.path.relpath(LOOP_MIX_JSON, ROOT)}
 
 
 def valu_from(csv_path):
     """Executed VALU instructions per launch of the search kernel, from a
     rocprofv3 --pmc SQ_INSTS_VALU CSV of this benchmark (tuning on, so that
-    every form of the batched search is dispatched): the median over the
-    batched launches of each form (variant, waves per chunk, precision,
-    screen), with the SHA-256 of k_score.hip they were counted on."""
+    every schedule of the batched search is dispatched): the median over the
+    launches of each schedule (variant, waves per chunk, workgroups per
+    launch, precision, screen), with the SHA-256 of k_score.hip they were
+    counted on."""
     out = {"kernel_sha256": hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest(), "forms": []}
     rows = _pmc_rows(csv_path, "SQ_INSTS_VALU")
-    blocks = [g // wg for n, _, g, wg in rows if "k_dense_fast" in n]
     per = {}
     for n, v, g, wg in rows:
-        if "k_dense_fast" not in n or g // wg != max(blocks):
+        m = re.search(r"k_dense_fast<([^>]*)>", n)
+        if not m:
             continue
-        targs = re.search(r"k_dense_fast<([^>]*)>", n).group(1).split(",")
+        targs = m.group(1).split(",")
         prec, var = int(targs[3]), int(targs[4])
         screen = len(targs) > 6 and targs[6].strip() == "true"
-        per.setdefault((var, wg // 64, prec, screen), []).append(v)
-    for (var, wa, prec, screen), v in sorted(per.items()):
-        out["forms"].append({"variant": var, "waves_per_chunk": wa, "precision": "fp16" if prec else "fp32",
-                             "screen": screen, "valu_instr_per_launch": float(np.median(v)), "launches": len(v)})
-    with open(VALU_JSON, "w") as fh:
-        json.dump(out, fh, indent=1)
+        per.setdefault((var, wg // 64, g // wg, prec, screen), []).append(v)
+    for (var, wa, nwg, prec, screen), v in sorted(per.items()):
+        out["forms"].append({"variant": var, "waves_per_chunk": wa, "workgroups": nwg,
+                             "precision": "fp16" if prec else "fp32", "screen": screen,
+                             "valu_instr_per_launch": float(np.median(v)), "launches": len(v)})
+    _dump_forms(VALU_JSON, out)
     print(json.dumps(out))
 
 
@@ -517,19 +698,22 @@ def valu_entry(form, precision):
     if d.get("kernel_sha256") != hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest():
         return None
     for f in d.get("forms", []):
-        if (f["variant"], f["waves_per_chunk"], f["precision"]) == (form.get("variant"), form.get("waves_per_chunk"),
-                                                                     precision) and f["screen"] == (precision == "fp16"):
+        if (f["variant"], f["waves_per_chunk"], f.get("workgroups"), f["precision"]) == (
+                form.get("variant"), form.get("waves_per_chunk"), form.get("workgroups"), precision) and \
+                f["screen"] == (precision == "fp16"):
             return {"valu_instr_per_launch": f["valu_instr_per_launch"], "counted_in": os.path.relpath(VALU_JSON, ROOT)}
     return None
 
 
-def c3_leg(P, torch, steps):
+def c3_leg(P, torch, steps, oracle_threads=0):
     """The large-frame precision configuration: 2048x2048 scenes with 5
     instances of a 256x256 model, 5 levels, 8 degrees at the top (0.5 at
     level 0).  One tm_detect per frame in FP16 (certified search, FP32
     refinement) and in FP32, timed; their detections compared bit for bit;
     and the per-score error of the FP16 top-level map against the FP32 map
-    (both at the top level, every translation's best angle)."""
+    (both at the top level, every translation's best angle).  With
+    oracle_threads, the oracle's full detection of each frame is timed on
+    that many host threads and both legs' top-1 compared with it."""
     import synth
 
     scenes = [synth.scene_for_config(3, i) for i in range(2)]
@@ -566,6 +750,20 @@ def c3_leg(P, torch, steps):
                      "detections": [len(d) for d in dets[name]]}
         pyr.free()
     out["fp16_equals_fp32_bit_for_bit"] = all(a.tobytes() == b.tobytes() for a, b in zip(dets["fp16"], dets["fp32"]))
+    if oracle_threads:
+        # the oracle's full detection of each frame, timed, and the top-1 of both legs against it
+        secs, poses = 0.0, 0
+        top1 = {"fp16": {}, "fp32": {}}
+        for i, sc in enumerate(scenes):
+            dt_o, n_o, ref, f0, om = oracle_detection(sc.image, sc.model, cfg, L, oracle_threads)
+            secs += dt_o
+            poses += n_o
+            for name in ("fp16", "fp32"):
+                r = top1_one(dets[name][i], ref, f0, om, cfg, L)
+                top1[name][r] = top1[name].get(r, 0) + 1
+        out["cpu_oracle"] = {"ms_per_detection": secs / len(scenes) * 1e3, "pose_evals_per_sec": poses / secs,
+                             "cores": oracle_threads, "sample": f"{len(scenes)} full detections"}
+        out["top1_vs_oracle"] = top1
     e = np.abs(maps["fp16"][0].astype(np.float64) - maps["fp32"][0])
     out["fp16_map_error_vs_fp32"] = {"max": float(e.max()), "mean": float(e.mean()),
                                      "p99": float(np.percentile(e, 99)), "translations": int(e.size),
@@ -598,7 +796,7 @@ def batched_leg(P, torch, model, imgs, L, cfg, sp, prec, args, stream):
                 b.set_form(tuned["variant"], tuned["waves_per_chunk"], tuned["chunk_angles"])
         else:
             tuned = batch.tune(iterations=3)
-    form = batch.search_form()
+    form = dict(batch.search_form(), workgroups=batch.search_launch()["workgroups"])
     chosen_by = "default" if tuned is None else ("autotuner, pipelined step" if ns >= 2 else "autotuner, search launch")
     for i in range(max(args.warmup, ns)):
         batches[i % ns].run(streams[i % ns], graph=graph)
@@ -635,6 +833,11 @@ def batched_leg(P, torch, model, imgs, L, cfg, sp, prec, args, stream):
             "launch_s": dense_ms / max(launches, 1) / 1e3, "ns": ns, "nb": len(imgs)}
 
 
+def progress(msg):
+    """A progress line on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def ceilings(P):
     """Measured ceilings of the search kernel's roofs (tm_probe): its VALU
     instruction mix, each instruction class of it, plain FP32 adds, its LDS
@@ -659,6 +862,9 @@ def main():
     if args.valu_from:
         valu_from(args.valu_from)
         return
+    if args.loop_mix_from:
+        loop_mix_from(args.loop_mix_from)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path is single-GPU by design.",
               file=sys.stderr)
@@ -681,6 +887,7 @@ def main():
     n_top = model.level_info(L - 1)[2]
 
     # ---- FP32 plain, one detection (pyramid + search) per call
+    progress("FP32 plain leg")
     pyr = P.Pyramid(imgs[0], L, cfg["tau_s"], precision=P.TM_FP32)
     H3, W3 = pyr.level_shape(L - 1)
     poses_per_det = H3 * W3 * K
@@ -697,24 +904,40 @@ def main():
     for i in range(max(args.warmup, nb)):
         plain(i)
     torch.cuda.synchronize()
-    P.timing_read()
-    P.timing_enable(True)
     plain_steps = max(args.steps, 1) * 4
     t0 = time.perf_counter()
     for i in range(plain_steps):
         plain(i)
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - t0
+    # the search kernel's duration from events around it, in calls of their
+    # own (the events stay out of the timed detections above)
+    P.timing_read()
+    P.timing_enable(True)
+    for i in range(nb):
+        plain(i)
+    torch.cuda.synchronize()
     P.timing_enable(False)
     plain_dense_ms, plain_launches = P.timing_read()
     plain_dets = [P.poses_to_numpy(outs[j], int(nout[j].item())) for j in range(nb)]
     pyr.free()
+    plain_res = {"pose_evals_per_sec": poses_per_det * plain_steps / plain_s,
+                 "detections_per_sec": plain_steps / plain_s,
+                 "us_per_detection": plain_s / plain_steps * 1e6,
+                 "search_kernel_us": plain_dense_ms / max(plain_launches, 1) * 1e3}
+    if args.plain_only:
+        print(json.dumps({"fp32_plain": plain_res, "detections": plain_steps,
+                          "workload": "one 640x480 image per call, pyramid + detection, FP32"}), flush=True)
+        return
 
     # ---- the headline: the batched leg in the asked precision (FP16 by
     # default); beside it the other precision's batched leg
+    progress(f"{args.precision} batched leg")
     head = batched_leg(P, torch, model, imgs, L, cfg, sp, prec_b, args, stream)
     other_prec = P.TM_FP32 if prec_b == P.TM_FP16 else P.TM_FP16
     other_name = "fp32" if other_prec == P.TM_FP32 else "fp16"
+    if not args.no_other:
+        progress(f"{other_name} batched leg")
     other = batched_leg(P, torch, model, imgs, L, cfg, sp, other_prec, args, stream) if not args.no_other else None
     bdets = head["dets"]
     elapsed = head["elapsed"]
@@ -731,21 +954,39 @@ def main():
     flops = taps_per_det * nb * FLOP_PER_TAP
     achieved = flops / dense_avg_s / 1e12
     dets_per_s = nb * args.steps / elapsed
+    progress("ceiling probes")
     ceil = ceilings(P)
+    # the search is bound by VALU issue: the roofline is its executed VALU
+    # instructions per second (counted by SQ_INSTS_VALU for the schedule in
+    # use) against the issue peak of its inner loop's instruction mix (SIMDs x
+    # engine clock / issue cycles per instruction of that loop); the FLOP and
+    # tap figures are given beside it (they count the method's 9 n taps per
+    # pose, which the kernel shares between neighbouring translations, so they
+    # can exceed the vector peak)
     roof = {"kernel": "k_dense_fast (exhaustive top-level search, all images of the step)", "bound": "alu",
             "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic_entry(head["form"]),
-            "launch_us": dense_avg_s * 1e6, "flop_per_launch": flops,
-            "taps_per_s": taps_per_det * nb / dense_avg_s,
-            "lds_tap_ceiling_taps_per_s": ceil["lds_bytes_per_s"] / (4 if prec_b == P.TM_FP16 else 8),
-            "measured_ceilings": ceil}
+            "launch_us": dense_avg_s * 1e6}
     valu = valu_entry(head["form"], args.precision)
-    if valu is not None:
+    mix = loop_mix_entry(head["form"], args.precision)
+    if valu is not None and mix is not None:
         rate = valu["valu_instr_per_launch"] / dense_avg_s
-        roof["executed_valu"] = dict(valu, wave_instr_per_s=rate,
-                                     frac_of_mix_probe=rate / ceil["valu_mix_wave_instr_per_s"],
-                                     issue_floor_us=valu["valu_instr_per_launch"] /
-                                     ceil["valu_mix_wave_instr_per_s"] * 1e6)
+        peak = SIMDS * CLOCK_HZ / mix["cycles_per_instr"]
+        roof.update({"achieved": rate / 1e12, "peak": peak / 1e12, "unit": "T VALU wave-instr/s", "frac": rate / peak,
+                     "peak_basis": f"{SIMDS} SIMDs x {CLOCK_HZ / 1e9:.1f} GHz / {mix['cycles_per_instr']:.3f} issue "
+                                   f"cycles per instruction of the search loop ({mix['loop_valu']} VALU: dot2, DPP "
+                                   f"and 3-operand max at 4 cycles, the rest at 2)",
+                     "valu_instr_per_launch": valu["valu_instr_per_launch"],
+                     "counted_in": [valu["counted_in"], mix["counted_in"]]})
+    roof.update({"flop": {"achieved_tflops": achieved, "peak_tflops": PEAK_FP32_TFLOPS,
+                          "frac": achieved / PEAK_FP32_TFLOPS, "flop_per_launch": flops,
+                          "note": "3 FLOP per algorithmic tap (9 n per pose)"},
+                 "taps_per_s": taps_per_det * nb / dense_avg_s,
+                 "lds_tap_ceiling_taps_per_s": ceil["lds_bytes_per_s"] / (4 if prec_b == P.TM_FP16 else 8),
+                 "measured_ceilings": ceil})
+    if valu is not None:
+        roof["executed_valu_vs_mix_probe"] = valu["valu_instr_per_launch"] / dense_avg_s / ceil[
+            "valu_mix_wave_instr_per_s"]
     res = {
         "metric": "pose-evals/sec and detections/sec at 640x480 (FP32 plain vs FP16 batched, equal top-1)",
         "value": poses_per_det * dets_per_s,
@@ -768,10 +1009,7 @@ def main():
                    "search_form": head["form"]},
         "detections_per_sec": dets_per_s,
         "taps_per_sec": taps_per_det * dets_per_s,
-        "fp32_plain": {"pose_evals_per_sec": poses_per_det * plain_steps / plain_s,
-                       "detections_per_sec": plain_steps / plain_s,
-                       "us_per_detection": plain_s / plain_steps * 1e6,
-                       "search_kernel_us": plain_dense_ms / max(plain_launches, 1) * 1e3},
+        "fp32_plain": plain_res,
         "same_detections_bit_for_bit": same_bits,
         "top1_ground_truth_hits": {k: f"{v}/{nb}" for k, v in hits.items()},
         "roofline": roof,
@@ -781,17 +1019,28 @@ def main():
                                         "detections_per_sec": nb * args.steps / other["elapsed"],
                                         "pose_evals_per_sec": poses_per_det * nb * args.steps / other["elapsed"],
                                         "search_launch_us": other["launch_s"] * 1e6, "search_form": other["form"]}
+    oracle_threads = 0
+    if not args.no_cpu_baseline:
+        import oracle as O
+
+        oracle_threads = O.default_threads()
     if args.c4:
-        res["c4"], res["c5"] = c4_legs(P, torch, max(2, args.steps // 10), 1)
+        progress("c4 leg")
+        res["c4"], res["c5"] = c4_legs(P, torch, max(2, args.steps // 10), 1, oracle_threads)
     if args.c3:
-        res["c3"] = c3_leg(P, torch, max(5, args.steps // 5))
+        progress("c3 leg")
+        res["c3"] = c3_leg(P, torch, max(5, args.steps // 5), oracle_threads)
     if args.paper:
+        progress("paper leg")
         res["paper_shape"] = paper_leg(P, torch, max(8, args.steps))
     if args.similarity:
+        progress("similarity leg")
         res["similarity"] = similarity_leg(P, torch, max(5, args.steps // 4))
     if args.readings:
+        progress("readings leg")
         res["readings"] = readings_leg(P, torch, max(5, args.steps // 4))
     if not args.no_cpu_baseline:
+        progress("oracle on the host")
         res["cpu_baseline"], oracle = cpu_baseline(scenes, cfg, args.cpu_seconds, paper=args.paper)
         res["top1_vs_oracle"] = {"fp32_plain": top1_vs_oracle(plain_dets, oracle, cfg),
                                  f"{args.precision}_batched": top1_vs_oracle(bdets, oracle, cfg)}

@@ -374,6 +374,11 @@ tm_status tm_batch_set_form(tm_batch* batch, int32_t variant, int32_t waves, int
  * (chunk may be NULL; -1, 0, 0 for the generic search). */
 tm_status tm_batch_search_form(const tm_batch* batch, int32_t* variant, int32_t* waves, int32_t* chunk);
 
+/* Launch shape of the batch's search kernel in its current schedule:
+ * workgroups per launch and threads per workgroup (inspection: matches a
+ * profiler's dispatch records to a schedule). */
+tm_status tm_batch_search_launch(const tm_batch* batch, int32_t* workgroups, int32_t* threads);
+
 /* The continuous score, its backward and the FP64 line search (as
  * tm_cont_score, tm_cont_score_backward and tm_cont_line_search) over the
  * pairs of a batch, against the fields its last run built: pose.pair names

@@ -1588,6 +1588,20 @@ TM_EXPORT tm_status tm_batch_search_form(const tm_batch* b, int32_t* variant, in
     return TM_OK;
 }
 
+TM_EXPORT tm_status tm_batch_search_launch(const tm_batch* b, int32_t* workgroups, int32_t* threads)
+{
+    if (!b || !workgroups || !threads) return fail(TM_EINVAL, "tm_batch_search_launch: null argument");
+    const tmk::DensePlan& p = b->plan;
+    if (p.fast) {
+        *workgroups = p.work ? p.n_work : p.max_blocks * b->npairs;
+        *threads = 64 * p.WY * p.WA;
+    } else {
+        *workgroups = (p.max_np + 255) / 256 * p.C * b->npairs;
+        *threads = 256;
+    }
+    return TM_OK;
+}
+
 namespace {
 // Mean milliseconds of one search launch of plan p over the batch.
 hipError_t time_search(tm_batch* b, const tmk::DensePlan& p, int iterations, hipStream_t s, hipEvent_t e0,

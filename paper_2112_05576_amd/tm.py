@@ -97,6 +97,7 @@ def lib():
             "tm_batch_tune": [_vp, _vp, _i32, _vp, _vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                               ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_float)],
             "tm_batch_search_form": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
+            "tm_batch_search_launch": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)],
             "tm_batch_set_form": [_vp, _i32, _i32, _i32],
             "tm_batch_cont_score": [_vp, _i32, _vp, _i32, _vp, _vp],
             "tm_batch_cont_score_backward": [_vp, _i32, _vp, _i32, _vp, _vp, _vp],
@@ -430,6 +431,12 @@ class Batch:
         v, w, c = _i32(), _i32(), _i32()
         _check(lib().tm_batch_search_form(self._h, ctypes.byref(v), ctypes.byref(w), ctypes.byref(c)))
         return {"variant": v.value, "waves_per_chunk": w.value, "chunk_angles": c.value}
+
+    def search_launch(self) -> dict:
+        """Launch shape of the search kernel in the current schedule."""
+        g, t = _i32(), _i32()
+        _check(lib().tm_batch_search_launch(self._h, ctypes.byref(g), ctypes.byref(t)))
+        return {"workgroups": g.value, "threads": t.value}
 
     def cont_score(self, level: int, poses: torch.Tensor, pairs, stream=None) -> torch.Tensor:
         """S_c of (n, 3) poses on pairs[i] (image * n_models + model)."""

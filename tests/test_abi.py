@@ -102,6 +102,7 @@ def test_continuous_and_batch_entries_validate_first(L):
     assert L.tm_batch_run_graph(None, None) == tm.TM_EINVAL
     assert L.tm_batch_tune(None, None, 3, None, None, None, None, None, None) == tm.TM_EINVAL
     assert L.tm_batch_set_form(None, 4, 4, 0) == tm.TM_EINVAL
+    assert L.tm_batch_search_launch(None, None, None) == tm.TM_EINVAL
     assert L.tm_batch_cont_score(None, 0, fake, 1, fake, None) == tm.TM_EINVAL
     assert L.tm_batch_cont_score_backward(None, 0, fake, 1, None, fake, None) == tm.TM_EINVAL
     assert L.tm_batch_cont_line_search(None, 0, fake, fake, 1, al, 3, None, None) == tm.TM_EINVAL

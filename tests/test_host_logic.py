@@ -76,35 +76,41 @@ def _write_counters(path, counter, rows):
 
 
 def test_traffic_figures_from_counter_runs(tmp_path, monkeypatch):
-    """Per form (variant, waves per chunk): the median batched dispatch,
-    scaled by what the counter read for the 256 MiB copy; dispatches of a
-    smaller work list (single images) are left out; the figure is reported
-    only for the recorded source and the form in use."""
+    """Per schedule of the FP16 batched search (variant, waves per chunk,
+    workgroups per launch): the median dispatch, scaled by what the counter
+    read for the 256 MiB copy; FP32 dispatches (single images, the other
+    leg) are left out; the figure is reported only for the recorded source
+    and the schedule in use."""
     sys.path.insert(0, ROOT)
     import bench
 
     monkeypatch.setattr(bench, "TRAFFIC_JSON", str(tmp_path / "traffic.json"))
-    k = "void tmk::(anonymous namespace)::k_dense_fast<32, 8, 64, {}, {}, 0>(tmk::(anonymous namespace)::FastArgs)"
+    k = ("void tmk::(anonymous namespace)::k_dense_fast<32, 8, 64, {}, {}, 0, true>"
+         "(tmk::(anonymous namespace)::FastArgs)")
     copy = "void at::native::vectorized_elementwise_kernel<4, at::native::neg_kernel>(int)"
-    fetch = [(k.format(0, 3), 99.0, 900 * 256, 256),           # a single image: fewer workgroups
+    fetch = [(k.format(0, 3), 99.0, 900 * 256, 256),           # FP32: not the batched FP16 search
              (k.format(1, 4), 1000.0, 1280 * 256, 256), (k.format(1, 4), 1002.0, 1280 * 256, 256),
              (k.format(1, 4), 90000.0, 1280 * 256, 256),       # a cold first launch: the median ignores it
+             (k.format(1, 4), 700.0, 1920 * 256, 256),         # another chunking: its own figure
              (k.format(1, 2), 1500.0, 1280 * 512, 512),
              (copy, 131072.0, 1 << 26, 256)]
     write = [(n, v / 2, g, wg) for n, v, g, wg in fetch[:-1]] + [(copy, 262144.0, 1 << 26, 256)]
     _write_counters(tmp_path / "f.csv", "FETCH_SIZE", fetch)
     _write_counters(tmp_path / "w.csv", "WRITE_SIZE", write)
     bench.traffic_from(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"))
-    forms = {(f["variant"], f["waves_per_chunk"]): f for f in
+    forms = {(f["variant"], f["waves_per_chunk"], f["workgroups"]): f for f in
              __import__("json").load(open(tmp_path / "traffic.json"))["forms"]}
-    assert set(forms) == {(4, 4), (2, 8)}
-    f44 = forms[(4, 4)]
+    assert set(forms) == {(4, 4, 1280), (4, 4, 1920), (2, 8, 1280)}
+    f44 = forms[(4, 4, 1280)]
     assert f44["fetch_bytes"] == 1002.0 * 2048.0 and f44["write_bytes"] == 1002.0 / 2 * 1024.0
     assert f44["launches"] == 3
-    assert bench.traffic_entry({"variant": 4, "waves_per_chunk": 4}) == f44["bytes_per_launch"]
-    assert bench.traffic_entry({"variant": 4, "waves_per_chunk": 16}) is None
+    assert forms[(4, 4, 1920)]["fetch_bytes"] == 700.0 * 2048.0
+    form = {"variant": 4, "waves_per_chunk": 4, "workgroups": 1280}
+    assert bench.traffic_entry(form) == f44["bytes_per_launch"]
+    assert bench.traffic_entry(dict(form, workgroups=640)) is None
+    assert bench.traffic_entry(dict(form, waves_per_chunk=16)) is None
     monkeypatch.setattr(bench, "KERNEL_SRC", str(tmp_path / "f.csv"))  # another source: no figure
-    assert bench.traffic_entry({"variant": 4, "waves_per_chunk": 4}) is None
+    assert bench.traffic_entry(form) is None
 
 
 def test_trace_summary_groups_by_launch_shape(tmp_path, capsys):
@@ -177,28 +183,65 @@ def test_integer_distance_test_equals_the_fp64_one():
 
 def test_valu_counts_per_form(tmp_path, monkeypatch):
     """The search kernel's executed VALU instructions per launch come from a
-    SQ_INSTS_VALU counter run: the median over the batched launches of each
-    form (variant, waves, precision, screen); reported only for the recorded
-    source and the form and precision in use (an FP16 detection runs the
-    screen form)."""
+    SQ_INSTS_VALU counter run: the median over the launches of each schedule
+    (variant, waves, workgroups per launch, precision, screen); reported
+    only for the recorded source and the schedule and precision in use (an
+    FP16 detection runs the screen form)."""
     sys.path.insert(0, ROOT)
     import bench
 
     monkeypatch.setattr(bench, "VALU_JSON", str(tmp_path / "valu.json"))
     k = ("void tmk::(anonymous namespace)::k_dense_fast<32, 8, 64, {}, {}, 0, {}>"
          "(tmk::(anonymous namespace)::FastArgs)")
-    rows = [(k.format(0, 3, "false"), 5.0, 900 * 256, 256),        # a single image: fewer workgroups
+    rows = [(k.format(0, 3, "false"), 5.0, 900 * 256, 256),        # a single image: its own schedule
             (k.format(1, 4, "true"), 1.5e9, 1920 * 256, 256), (k.format(1, 4, "true"), 1.6e9, 1920 * 256, 256),
             (k.format(1, 4, "true"), 1.4e9, 1920 * 256, 256),
             (k.format(0, 4, "false"), 2.0e9, 1920 * 512, 512)]
     _write_counters(tmp_path / "v.csv", "SQ_INSTS_VALU", rows)
     bench.valu_from(str(tmp_path / "v.csv"))
     forms = __import__("json").load(open(tmp_path / "valu.json"))["forms"]
-    by = {(f["variant"], f["waves_per_chunk"], f["precision"], f["screen"]): f for f in forms}
-    assert set(by) == {(4, 4, "fp16", True), (4, 8, "fp32", False)}
-    assert by[(4, 4, "fp16", True)]["valu_instr_per_launch"] == 1.5e9
-    assert bench.valu_entry({"variant": 4, "waves_per_chunk": 4}, "fp16")["valu_instr_per_launch"] == 1.5e9
-    assert bench.valu_entry({"variant": 4, "waves_per_chunk": 8}, "fp32")["valu_instr_per_launch"] == 2.0e9
-    assert bench.valu_entry({"variant": 4, "waves_per_chunk": 8}, "fp16") is None
+    by = {(f["variant"], f["waves_per_chunk"], f["workgroups"], f["precision"], f["screen"]): f for f in forms}
+    assert set(by) == {(3, 4, 900, "fp32", False), (4, 4, 1920, "fp16", True), (4, 8, 1920, "fp32", False)}
+    assert by[(4, 4, 1920, "fp16", True)]["valu_instr_per_launch"] == 1.5e9
+    f16 = {"variant": 4, "waves_per_chunk": 4, "workgroups": 1920}
+    assert bench.valu_entry(f16, "fp16")["valu_instr_per_launch"] == 1.5e9
+    assert bench.valu_entry({"variant": 4, "waves_per_chunk": 8, "workgroups": 1920}, "fp32")[
+        "valu_instr_per_launch"] == 2.0e9
+    assert bench.valu_entry({"variant": 4, "waves_per_chunk": 8, "workgroups": 1920}, "fp16") is None
+    assert bench.valu_entry(dict(f16, workgroups=1280), "fp16") is None
     monkeypatch.setattr(bench, "KERNEL_SRC", str(tmp_path / "v.csv"))  # another source: no figure
-    assert bench.valu_entry({"variant": 4, "waves_per_chunk": 4}, "fp16") is None
+    assert bench.valu_entry(f16, "fp16") is None
+
+
+def test_loop_mix_from_assembly(tmp_path, monkeypatch):
+    """The search loop of each k_dense_fast instantiation is its innermost
+    loop with the most DPP window maxima; its VALU instructions are costed 4
+    issue cycles (dot2, DPP, 3-operand max) or 2 (the rest)."""
+    sys.path.insert(0, ROOT)
+    import bench
+
+    monkeypatch.setattr(bench, "LOOP_MIX_JSON", str(tmp_path / "mix.json"))
+    asm = "\n".join([
+        "_ZN3tmk12_GLOBAL__N_112k_dense_fastILi32ELi8ELi64ELi1ELi4ELi0ELb1EEEvNS0_8FastArgsEPKNS_8PairDescE:",
+        "\ts_load_dwordx2 s[0:1], s[4:5], 0x0",
+        ".LBB0_1:",                                       # the epilogue-like loop: products, no DPP
+        "\tv_fma_f32 v1, v2, v3, v4",
+        "\tv_fma_f32 v1, v2, v3, v4",
+        "\tv_fma_f32 v1, v2, v3, v4",
+        "\ts_cbranch_scc0 .LBB0_1",
+        ".LBB0_2:",                                       # the search loop
+        "\tds_read2st64_b32 v[0:1], v5 offset1:1",
+        "\tv_dot2_f32_f16 v6, s0, v0, 0",
+        "\tv_max_f32_dpp v7, v6, v6 wave_shr:1 row_mask:0xf bank_mask:0xf bound_ctrl:1",
+        "\tv_max3_f32 v8, v7, v6, v9",
+        "\tv_add_f32_e32 v10, v10, v8",
+        "\ts_cbranch_scc0 .LBB0_2",
+        "\ts_endpgm",
+    ])
+    (tmp_path / "k.s").write_text(asm + "\n")
+    bench.loop_mix_from(str(tmp_path / "k.s"))
+    f = __import__("json").load(open(tmp_path / "mix.json"))["forms"]
+    assert len(f) == 1 and (f[0]["precision"], f[0]["variant"], f[0]["screen"]) == ("fp16", 4, True)
+    assert f[0]["loop_valu"] == 4 and f[0]["loop_issue_cycles"] == 4 + 4 + 4 + 2
+    assert bench.loop_mix_entry({"variant": 4}, "fp16")["cycles_per_instr"] == 14 / 4
+    assert bench.loop_mix_entry({"variant": 3}, "fp16") is None
