@@ -393,7 +393,12 @@ tm_status tm_batch_cont_line_search(tm_batch* batch, int32_t level, tm_cont_pose
                                     int32_t n, const double* alphas, int32_t n_alphas, float* scores_dev,
                                     void* stream);
 
-/* The pyramid the batch built for one image (owned by the batch). */
+/* The pyramid the batch built for one image (owned by the batch).  An FP16
+ * batch keeps FP16 directions at its searched (top) level only: below it the
+ * pyramid holds the uint8 levels and the FP32 directions its refinement
+ * reads, so tm_pyramid_level gives a null field there and tm_pyramid_read
+ * (field), tm_score_poses and tm_score_map of those levels fail with
+ * TM_EINVAL. */
 tm_status tm_batch_pyramid(const tm_batch* batch, int32_t image, const tm_pyramid** out);
 
 void tm_batch_free(tm_batch* batch);

@@ -18,39 +18,57 @@ __global__ __launch_bounds__(256) void k_pyr_build(PyrBuildArg one, const PyrBui
                                                     int top, int copy_base)
 {
     __shared__ uint8_t cells[16 * 16];
-    const PyrBuildArg& lv = BATCH ? many[blockIdx.z] : one;
+    const uint3 B = xcd_block();  // (block column, block row, image)
+    const PyrBuildArg& lv = BATCH ? many[B.z] : one;
     top = min(top, lv.L - 1);
-    if ((int)blockIdx.x * 64 >= lv.w[base] || (int)blockIdx.y * 64 >= lv.h[base]) return;
+    if ((int)B.x * 64 >= lv.w[base] || (int)B.y * 64 >= lv.h[base]) return;
     const uint8_t* __restrict__ src = base == 0 ? lv.src : lv.img[base];
     const int src_pitch = base == 0 ? lv.pitch : lv.w[base];
     const int t = threadIdx.x;
     const int cx = t & 15, cy = t >> 4;
     const int W = lv.w[base], H = lv.h[base];
-    const int x0 = blockIdx.x * 64 + cx * 4;
-    const int y0 = blockIdx.y * 64 + cy * 4;
+    const int x0 = B.x * 64 + cx * 4;
+    const int y0 = B.y * 64 + cy * 4;
     int v[4][4];
+    // a row's four bytes as one word where they are whole and aligned
+    const bool words = x0 + 3 < W && ((reinterpret_cast<uintptr_t>(src) | (uintptr_t)src_pitch) & 3) == 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
+        const int y = y0 + j;
+        if (words) {
+            const uint32_t w = y < H ? *reinterpret_cast<const uint32_t*>(src + (size_t)y * src_pitch + x0) : 0u;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            int x = x0 + i, y = y0 + j;
-            v[j][i] = (x < W && y < H) ? (int)src[(size_t)y * src_pitch + x] : 0;
+            for (int i = 0; i < 4; ++i) v[j][i] = (int)((w >> (8 * i)) & 0xffu);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int x = x0 + i;
+                v[j][i] = (x < W && y < H) ? (int)src[(size_t)y * src_pitch + x] : 0;
+            }
         }
     }
     if (copy_base) {
         uint8_t* dst = lv.img[base];
+        const bool wdst = words && (W & 3) == 0 && (reinterpret_cast<uintptr_t>(dst) & 3) == 0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 4; ++j) {
+            if (y0 + j >= H) continue;
+            if (wdst) {
+                *reinterpret_cast<uint32_t*>(dst + (size_t)(y0 + j) * W + x0) =
+                    (uint32_t)v[j][0] | ((uint32_t)v[j][1] << 8) | ((uint32_t)v[j][2] << 16) | ((uint32_t)v[j][3] << 24);
+            } else {
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                if (x0 + i < W && y0 + j < H) dst[(size_t)(y0 + j) * W + x0 + i] = (uint8_t)v[j][i];
+                for (int i = 0; i < 4; ++i)
+                    if (x0 + i < W) dst[(size_t)(y0 + j) * W + x0 + i] = (uint8_t)v[j][i];
+            }
+        }
     }
     if (top <= base) return;
     // level base+1: a 2x2 patch per thread
     int l1[2][2];
     {
         const int l = base + 1, W1 = lv.w[l], H1 = lv.h[l];
-        const int bx = blockIdx.x * 32 + cx * 2, by = blockIdx.y * 32 + cy * 2;
+        const int bx = B.x * 32 + cx * 2, by = B.y * 32 + cy * 2;
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -66,7 +84,7 @@ __global__ __launch_bounds__(256) void k_pyr_build(PyrBuildArg one, const PyrBui
         const int l = base + 2, W2 = lv.w[l], H2 = lv.h[l];
         int s = l1[0][0] + l1[0][1] + l1[1][0] + l1[1][1];
         int p = (s + 2) >> 2;
-        int x = blockIdx.x * 16 + cx, y = blockIdx.y * 16 + cy;
+        int x = B.x * 16 + cx, y = B.y * 16 + cy;
         if (x < W2 && y < H2) lv.img[l][(size_t)y * W2 + x] = (uint8_t)p;
         cells[cy * 16 + cx] = (uint8_t)p;
     }
@@ -82,7 +100,7 @@ __global__ __launch_bounds__(256) void k_pyr_build(PyrBuildArg one, const PyrBui
                     cells[(2 * iy + 1) * side + 2 * ix] + cells[(2 * iy + 1) * side + 2 * ix + 1];
             p = (s + 2) >> 2;
             const int Wl = lv.w[l], Hl = lv.h[l];
-            int x = blockIdx.x * ns + ix, y = blockIdx.y * ns + iy;
+            int x = B.x * ns + ix, y = B.y * ns + iy;
             if (x < Wl && y < Hl) lv.img[l][(size_t)y * Wl + x] = (uint8_t)p;
         }
         __syncthreads();
@@ -175,15 +193,16 @@ __global__ __launch_bounds__(256) void k_grad_level(FieldsArg one, const FieldsA
 template <bool BATCH>
 __global__ __launch_bounds__(256) void k_sobel_fields(FieldsArg one, const FieldsArg* __restrict__ many)
 {
-    const FieldsArg& a = BATCH ? many[blockIdx.y] : one;
-    if ((int)blockIdx.x >= a.block0[a.L]) return;
+    const uint3 B = xcd_block();  // (block, image)
+    const FieldsArg& a = BATCH ? many[B.y] : one;
+    if ((int)B.x >= a.block0[a.L]) return;
     const long long T2 = a.T2;
     const int precision = a.precision;
     int l = 0;
-    while (l + 1 < a.L && (int)blockIdx.x >= a.block0[l + 1]) ++l;
+    while (l + 1 < a.L && (int)B.x >= a.block0[l + 1]) ++l;
     const int W = a.w[l], H = a.h[l];
     const int qw = (W + 3) / 4;
-    const int idx = ((int)blockIdx.x - a.block0[l]) * 256 + (int)threadIdx.x;
+    const int idx = ((int)B.x - a.block0[l]) * 256 + (int)threadIdx.x;
     const int y = idx / qw, x0 = (idx % qw) * 4;
     if (y >= H) return;
     const uint8_t* __restrict__ img = a.img[l];
@@ -217,10 +236,9 @@ __global__ __launch_bounds__(256) void k_sobel_fields(FieldsArg one, const Field
             gyv[i] = in ? gy : 0;
         }
     }
+    float fx[4], fy[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int x = x0 + i;
-        if (x >= W) break;
         const int gx = gxv[i], gy = gyv[i];
         const long long m2 = (long long)gx * gx + (long long)gy * gy;
         double dx = 0.0, dy = 0.0;
@@ -229,14 +247,30 @@ __global__ __launch_bounds__(256) void k_sobel_fields(FieldsArg one, const Field
             dx = (double)gx / m;
             dy = (double)gy / m;
         }
-        const size_t o = (size_t)y * W + x;
-        if (precision == TM_FP16) {
-            reinterpret_cast<__half2*>(a.field[l])[o] = __floats2half2_rn((float)dx, (float)dy);
-            // the FP32 twin the decisions after the FP16 search read
-            if (a.field32[l]) reinterpret_cast<float2*>(a.field32[l])[o] = make_float2((float)dx, (float)dy);
+        fx[i] = (float)dx;
+        fy[i] = (float)dy;
+    }
+    const size_t o = (size_t)y * W + x0;
+    // FP32 pairs: two pixels per 16-byte store where the four are whole and
+    // the row offset keeps the alignment
+    float* f32 = reinterpret_cast<float*>(precision == TM_FP16 ? a.field32[l] : a.field[l]);
+    if (f32) {
+        if (x0 + 3 < W && (o & 1) == 0) {
+            float4* q = reinterpret_cast<float4*>(f32 + 2 * o);
+            q[0] = make_float4(fx[0], fy[0], fx[1], fy[1]);
+            q[1] = make_float4(fx[2], fy[2], fx[3], fy[3]);
         } else {
-            reinterpret_cast<float2*>(a.field[l])[o] = make_float2((float)dx, (float)dy);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (x0 + i < W) reinterpret_cast<float2*>(f32)[o + i] = make_float2(fx[i], fy[i]);
         }
+    }
+    // the FP16 field (a batch's pyramid keeps it at its searched level only);
+    // an FP16 pyramid's FP32 pairs above are the twin its decisions read
+    if (precision == TM_FP16 && a.field[l]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (x0 + i < W) reinterpret_cast<__half2*>(a.field[l])[o + i] = __floats2half2_rn(fx[i], fy[i]);
     }
 }
 

@@ -518,7 +518,11 @@ TM_EXPORT const char* tm_version(void) { return "tm-hip 0.1 (gfx950)"; }
 
 namespace {
 // A pyramid of a w x h image with storage for all levels (not yet built).
-tm_status alloc_pyramid(int w, int h, const tm_pyr_params* pp, hipStream_t s, tm_pyramid** out)
+// top_only_fp16: an FP16 pyramid of a batch, whose levels below the top are
+// only ever read in FP32 (by the refinement): their FP16 field is neither
+// allocated nor written (lv[l].field is null there).
+tm_status alloc_pyramid(int w, int h, const tm_pyr_params* pp, hipStream_t s, tm_pyramid** out,
+                        bool top_only_fp16 = false)
 {
     tm_pyramid* p = new (std::nothrow) tm_pyramid_s();
     if (!p) return fail(TM_ENOMEM, "pyramid: host allocation");
@@ -541,11 +545,13 @@ tm_status alloc_pyramid(int w, int h, const tm_pyr_params* pp, hipStream_t s, tm
     size_t total = 0;
     size_t img_off[TM_MAX_LEVELS], fld_off[TM_MAX_LEVELS], f32_off[TM_MAX_LEVELS], grd_off[TM_MAX_LEVELS];
     const bool gradient = pp->source == TM_PYR_GRADIENT;
+    bool has_field[TM_MAX_LEVELS];
     for (int l = 0; l < p->L; ++l) {
         img_off[l] = total;
         total = align_up(total + (size_t)ws[l] * hs[l], 256);
         fld_off[l] = total;
-        total = align_up(total + (size_t)ws[l] * hs[l] * fsz, 256);
+        has_field[l] = !(fp16 && top_only_fp16 && l < p->L - 1);
+        if (has_field[l]) total = align_up(total + (size_t)ws[l] * hs[l] * fsz, 256);
         f32_off[l] = fp16 ? total : fld_off[l];
         if (fp16) total = align_up(total + (size_t)ws[l] * hs[l] * 8, 256);
         grd_off[l] = total;
@@ -560,7 +566,7 @@ tm_status alloc_pyramid(int w, int h, const tm_pyr_params* pp, hipStream_t s, tm
         p->lv[l].w = ws[l];
         p->lv[l].h = hs[l];
         p->lv[l].img = reinterpret_cast<uint8_t*>(p->block) + img_off[l];
-        p->lv[l].field = reinterpret_cast<uint8_t*>(p->block) + fld_off[l];
+        p->lv[l].field = has_field[l] ? reinterpret_cast<uint8_t*>(p->block) + fld_off[l] : nullptr;
         p->lv[l].field32 = reinterpret_cast<uint8_t*>(p->block) + f32_off[l];
         p->lv[l].grad = gradient ? reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(p->block) + grd_off[l])
                                  : nullptr;
@@ -802,6 +808,9 @@ TM_EXPORT tm_status tm_pyramid_read(const tm_pyramid* p, int32_t level, uint8_t*
     if (!p) return fail(TM_EINVAL, "tm_pyramid_read: null pyramid");
     if (level < 0 || level >= p->L) return fail(TM_EINVAL, "tm_pyramid_read: bad level %d", level);
     const size_t np = (size_t)p->lv[level].w * p->lv[level].h;
+    if (field && !p->lv[level].field)
+        return fail(TM_EINVAL, "tm_pyramid_read: level %d keeps no field in the pyramid's precision "
+                               "(a batch's FP16 pyramid keeps FP16 directions at its top level only)", level);
     if (img) HIP_TRY(hipMemcpyAsync(img, p->lv[level].img, np, hipMemcpyDeviceToDevice, S(stream)));
     if (field)
         HIP_TRY(hipMemcpyAsync(field, p->lv[level].field, np * (p->precision == TM_FP16 ? 4 : 8),
@@ -820,6 +829,8 @@ TM_EXPORT tm_status tm_score_poses(const tm_model* m, const tm_pyramid* p, int32
         return fail(TM_EINVAL, "tm_score_poses: vote must be TM_VOTE_ALL or TM_VOTE_EDGE");
     if (n < 0) return fail(TM_EINVAL, "tm_score_poses: n < 0");
     if (n > 0 && (!poses || !scores)) return fail(TM_EINVAL, "tm_score_poses: null buffer");
+    if (!p->lv[level].field)
+        return fail(TM_EINVAL, "tm_score_poses: level %d keeps no field in the pyramid's precision", level);
     HIP_TRY(tmk::launch_sparse(p->lv[level].field, p->lv[level].w, p->lv[level].h, p->precision, m->lv[level].pts,
                               m->lv[level].n, win, vote, poses, n, scores, S(stream)));
     return TM_OK;
@@ -833,6 +844,8 @@ TM_EXPORT tm_status tm_score_map(const tm_model* m, tm_pyramid* p, int32_t level
     st = check_search(sp, "tm_score_map");
     if (st != TM_OK) return st;
     if (level < 0 || level >= p->L) return fail(TM_EINVAL, "tm_score_map: bad level %d", level);
+    if (!p->lv[level].field)
+        return fail(TM_EINVAL, "tm_score_map: level %d keeps no field in the pyramid's precision", level);
     if (!sw || !s1 || !k) return fail(TM_EINVAL, "tm_score_map: null output");
     Grid g;
     st = make_grid(sp, p->L, &g);
@@ -1142,6 +1155,7 @@ tm_status cont_prepare(const tm_model* m, tm_pyramid* p, int level, size_t extra
     tm_status st = check_pair(m, p, what);
     if (st != TM_OK) return st;
     if (level < 0 || level >= p->L) return fail(TM_EINVAL, "%s: bad level %d", what, level);
+    if (!p->lv[level].field) return fail(TM_EINVAL, "%s: level %d keeps no field in the pyramid's precision", what, level);
     st = ensure_ws(p, kDescBytes + extra, s);
     if (st != TM_OK) return st;
     tmk::PairDesc d;
@@ -1306,7 +1320,7 @@ TM_EXPORT tm_status tm_batch_create(const tm_model* const* models, int32_t n_mod
     b->models.assign(models, models + n_models);
     for (int i = 0; i < n_images; ++i) {
         tm_pyramid* p = nullptr;
-        st = alloc_pyramid(widths[i], heights[i], pp, s, &p);
+        st = alloc_pyramid(widths[i], heights[i], pp, s, &p, true);
         if (st != TM_OK) {
             tm_batch_free(b);
             return st;

@@ -187,6 +187,23 @@ __device__ __forceinline__ bool key_better(float aw, float a1, int ax, int ay, i
     return ak < bk;
 }
 
+// The workgroup's place in a grid renumbered so that each XCD takes one
+// contiguous run of it: workgroups go to the 8 XCDs in turn by their linear
+// index (x fastest, then y, then z), so without this neighbouring blocks sit
+// in different L2s and fetch their shared rows once per XCD.  A bijection of
+// the grid (XCD k runs the k-th run, of q or q + 1 blocks).
+constexpr unsigned kXcds = 8;
+__device__ __forceinline__ uint3 xcd_block()
+{
+    const unsigned nx = gridDim.x, ny = gridDim.y;
+    const unsigned total = nx * ny * gridDim.z;
+    const unsigned lin = blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z);
+    const unsigned q = total / kXcds, r = total % kXcds;
+    const unsigned x = lin % kXcds, local = lin / kXcds;
+    const unsigned m = x < r ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
+    return make_uint3(m % nx, m / nx % ny, m / (nx * ny));
+}
+
 // Best of the 27 poses around (x, y, k) (a pose of level l+1) at level l, from
 // the per-wave sums part[g][w][m] (m < 9: S_w of translation m, m >= 9: S_1),
 // the waves added in order.  Runs on one wave; every lane returns the result.

@@ -161,3 +161,46 @@ def test_tables_cached_per_grid():
     got0 = P.poses_to_numpy(outs[0], int(ns[0].item()))
     got1 = P.poses_to_numpy(outs[1], int(ns[1].item()))
     assert got0.tobytes() == ref[1].tobytes() and got1.tobytes() == ref[0].tobytes()
+
+
+def test_fp16_batch_pyramid_keeps_fp16_at_the_top_only():
+    """An FP16 batch stores FP16 directions at its searched level only: the
+    top level's field equals a single FP16 pyramid's bit for bit, the lower
+    levels have none (null in tm_pyramid_level, TM_EINVAL on a field read),
+    and their uint8 images are still there."""
+    import ctypes
+
+    P, sc, cfg, L = _c2(3)
+    case("FP16 batch pyramid levels")
+    img = torch.from_numpy(sc.image).cuda()
+    model = P.Model(sc.model, L, cfg["tau_m"])
+    b = P.Batch([model], [img], L, cfg["tau_s"], P.SearchParams(theta_step_top=cfg["theta_step_top"]),
+                precision=P.TM_FP16)
+    b.run()
+    single = P.Pyramid(img, L, cfg["tau_s"], precision=P.TM_FP16)
+    torch.cuda.synchronize()
+    h = ctypes.c_void_p()
+    assert P.lib().tm_batch_pyramid(b._h, 0, ctypes.byref(h)) == 0
+    pyr = P.Pyramid.__new__(P.Pyramid)
+    pyr._h, pyr.levels, pyr.precision = h, L, P.TM_FP16
+    try:
+        gi, gf = pyr.read(L - 1)
+        si, sf = single.read(L - 1)
+        torch.cuda.synchronize()
+        assert torch.equal(gi, si) and gf.view(torch.int16).equal(sf.view(torch.int16))
+        for l in range(L - 1):
+            w, hh, prec = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+            a, f = ctypes.c_void_p(), ctypes.c_void_p(1)
+            assert P.lib().tm_pyramid_level(h, l, ctypes.byref(w), ctypes.byref(hh), ctypes.byref(a), ctypes.byref(f),
+                                            ctypes.byref(prec)) == 0
+            assert a.value and not f.value
+            with pytest.raises(P.TMError) as e:
+                pyr.read(l)
+            assert e.value.status == P.tm.TM_EINVAL
+            im = torch.empty((hh.value, w.value), dtype=torch.uint8, device="cuda")
+            assert P.lib().tm_pyramid_read(h, l, ctypes.c_void_p(im.data_ptr()), None, None) == 0
+            torch.cuda.synchronize()
+            assert torch.equal(im, single.read(l)[0])
+    finally:
+        pyr._h = ctypes.c_void_p()  # owned by the batch
+        single.free()
