@@ -219,7 +219,9 @@ def cpu_baseline(scenes, cfg, budget_s, paper=False):
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
+    n_top = len(model.levels[L - 1].t)
     res = {"value": poses / dt, "unit": "pose-evals/s", "cores": threads, "kind": "oracle",
+           "taps_per_sec": poses * n_top * 9 / dt,
            "sample": f"{len(dets)} full detections of distinct 640x480 images (4 levels, 360 top angles), "
                      f"{dt:.1f} s",
            "cpu": _cpu_model()}
@@ -385,7 +387,17 @@ def c4_legs(P, torch, steps, warmup, oracle_threads=0):
                 n_o += poses_o
                 r = top1_one(res[i * nm + k], ref, f0, om, cfg, L)
                 top1[r] = top1.get(r, 0) + 1
+        # linear extrapolation to the whole batch by top-level work (translations x angles x points)
+        def work(i, k):
+            return (scenes[i].image.shape[0] >> (L - 1)) * (scenes[i].image.shape[1] >> (L - 1)) * \
+                models[k].level_info(L - 1)[2]
+
+        scale = sum(work(i, k) for i in range(len(scenes)) for k in range(nm)) / sum(
+            work(i, k) for i in range(2) for k in range(nm))
         c4["cpu_oracle"] = {"ms_per_detection": secs / (2 * nm) * 1e3, "pose_evals_per_sec": n_o / secs,
+                            "extrapolated_batch_s": secs * scale,
+                            "extrapolation": "linear in top-level translations x points over the 512 pairs "
+                                             "(not measured)",
                             "cores": oracle_threads,
                             "sample": f"images 0-1 ({scenes[0].image.shape[1]}x{scenes[0].image.shape[0]}, "
                                       f"{scenes[1].image.shape[1]}x{scenes[1].image.shape[0]}) x {nm} models, "
