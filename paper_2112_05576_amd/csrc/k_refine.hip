@@ -69,7 +69,11 @@ struct Raw<TM_FP32> {
 // field values around its projection (taps outside the image vote 0).  VOTE
 // 1: the edge-taps-only window (off-edge and outside taps enter the maxima as
 // kOffEdge, each maximum is finished by vote_finish); centre votes as in 0.
-template <int PREC, int VOTE>
+// ZEROS: the block already holds (+0, +0) outside the image (a staged tile),
+// so no tap needs its position tested: such a tap's product is a zero of
+// either sign, which changes no maximum but a zero's sign and no sum at all
+// (every sum starts at +0, and x + (-0) = x), and it is off the edge set.
+template <int PREC, int VOTE, bool ZEROS = false>
 __device__ __forceinline__ void votes5x5(const typename Raw<PREC>::T (&gv)[5][5], const bool (&rin)[5],
                                          const bool (&cin)[5], typename Raw<PREC>::R r, float (&aw)[9], float (&a1)[9])
 {
@@ -79,9 +83,10 @@ __device__ __forceinline__ void votes5x5(const typename Raw<PREC>::T (&gv)[5][5]
 #pragma unroll
         for (int u = 0; u < 5; ++u) {
             const float d = Raw<PREC>::dot(r, gv[v][u]);
-            D[v][u] = (rin[v] && cin[u]) ? d : 0.0f;
+            const bool in = ZEROS || (rin[v] && cin[u]);
+            D[v][u] = in ? d : 0.0f;
             if constexpr (VOTE == 1)
-                E[v][u] = (rin[v] && cin[u] && Raw<PREC>::edge(gv[v][u])) ? d : kOffEdge;
+                E[v][u] = (in && Raw<PREC>::edge(gv[v][u])) ? d : kOffEdge;
             else
                 E[v][u] = D[v][u];
         }
@@ -294,10 +299,13 @@ __global__ __launch_bounds__(kThreads * kTileGroups) void k_refine_tile(LevelArg
     using T = typename Raw<PREC>::T;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int cur[4];
-    const PairDesc& P = pairs[blockIdx.y];
+    // an image's candidates run on one XCD, whose L2 then serves their
+    // overlapping blocks
+    const uint3 B = xcd_block();  // (candidate, pair)
+    const PairDesc& P = pairs[B.y];
     const int l = a.level;
     if (!P.rtile[l]) return;
-    const int c = blockIdx.x;
+    const int c = B.x;
     int count = a.max_cand;
     if (P.ncand) count = min(count, *P.ncand);
     if (c >= count) return;
@@ -353,18 +361,14 @@ __global__ __launch_bounds__(kThreads * kTileGroups) void k_refine_tile(LevelArg
             const int px = 2 * x + qx, py = 2 * y + qy;
             // |q| < rad per component, so the block covers px - 2 .. px + 2
             const T* b = tile + (size_t)(py - 2 - oy) * S + (px - 2 - ox);
-            bool cin[5], rin[5];
+            // the staged block is zero outside the image: no tap is tested
+            const bool none[5] = {};
             T gv[5][5];
-#pragma unroll
-            for (int u = 0; u < 5; ++u) {
-                cin[u] = (unsigned)(px - 2 + u) < (unsigned)W;
-                rin[u] = (unsigned)(py - 2 + u) < (unsigned)H;
-            }
 #pragma unroll
             for (int v = 0; v < 5; ++v)
 #pragma unroll
                 for (int u = 0; u < 5; ++u) gv[v][u] = b[v * S + u];
-            votes5x5<PREC, VOTE>(gv, rin, cin, Raw<PREC>::dir(rx, ry), aw, a1);
+            votes5x5<PREC, VOTE, true>(gv, none, none, Raw<PREC>::dir(rx, ry), aw, a1);
         }
         wave_sum18(aw, a1, P.part[l] + (size_t)c * kPartPerCand + (g * kWaves + (t >> 6)) * 18);
     }
