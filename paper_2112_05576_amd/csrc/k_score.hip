@@ -1025,10 +1025,12 @@ __device__ __forceinline__ void score_fp32(const TabEntry* __restrict__ Tb, int 
     *s1 = t1 / n_f;
 }
 
-// The queued translations: one workgroup per translation (looping over the
-// queue), the FP32 field block around it staged in LDS when it fits, one
-// thread per angle to score, the best by the key (S_w desc, S_1 desc, angle
-// asc) written to the map.
+// The queued translations, the best by the key (S_w desc, S_1 desc, angle
+// asc) written to the map: an entry naming one or two angles is scored by one
+// wave (its lanes taking the points, the angles in turn, taps read from
+// memory); an entry of open chunks by a whole workgroup (looping over those
+// entries), the FP32 field block around it staged in LDS when it fits, one
+// thread per angle.
 template <int VOTE, int HW>
 __global__ __launch_bounds__(256) void k_rescore(CertArgs a, const PairDesc* __restrict__ pairs)
 {
@@ -1039,10 +1041,50 @@ __global__ __launch_bounds__(256) void k_rescore(CertArgs a, const PairDesc* __r
     __shared__ int ch_lo[64], ch_n[64], n_ang;
     const int count = a.cb.count[0];
     const int h = (a.win - 1) / 2;
+    // entries with one or two explicit angles: one wave each, the angles in
+    // turn, the taps read from memory (the values a staged block gives:
+    // zero outside the image)
+    {
+        const int nw = blockDim.x >> 6;
+        for (int e = blockIdx.x * nw + (threadIdx.x >> 6); e < count; e += gridDim.x * nw) {
+            const int4 en = a.cb.list[e];
+            if (en.x < 0) continue;  // open chunks: below, by the whole workgroup
+            const PairDesc& P = pairs[en.x];
+            const int p = en.y;
+            const int x = (p % P.gw) * a.sx, y = (p / P.gw) * a.sy;
+            const int W = P.W[a.level], H = P.H[a.level];
+            const float2* __restrict__ f32 = reinterpret_cast<const float2*>(P.field[a.level]);
+            auto gathered_at = [&](int qx, int qy) {
+                const int gx = x + qx, gy = y + qy;
+                return ((unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H) ? f32[(size_t)gy * W + gx]
+                                                                                  : make_float2(0.f, 0.f);
+            };
+            const float n_f = (float)P.n[a.level];
+            float kw = -INFINITY, k1 = -INFINITY;
+            int kk = 0x7fffffff;
+            for (int t = 0; t < 2; ++t) {
+                const int k = t == 0 ? en.z : en.w;
+                if (k < 0) break;
+                float sw, s1;
+                score_fp32_wave<VOTE, HW>(P.tab + (size_t)k * P.n_pad, P.n_pad, n_f, h, gathered_at, &sw, &s1);
+                if (key_better(sw, s1, 0, 0, k, kw, k1, 0, 0, kk)) {
+                    kw = sw;
+                    k1 = s1;
+                    kk = k;
+                }
+            }
+            if ((threadIdx.x & 63) == 0) {
+                P.mw[p] = kw;
+                P.m1[p] = k1;
+                P.mk[p] = kk;
+            }
+        }
+    }
     for (int e = blockIdx.x; e < count; e += gridDim.x) {
         const int4 en = a.cb.list[e];
         const bool chunks = en.x < 0;
-        const PairDesc& P = pairs[chunks ? -1 - en.x : en.x];
+        if (!chunks) continue;  // taken above (the test is the same for the whole workgroup)
+        const PairDesc& P = pairs[-1 - en.x];
         const int p = en.y;
         const int x = (p % P.gw) * a.sx, y = (p / P.gw) * a.sy;
         const int W = P.W[a.level], H = P.H[a.level];
@@ -1051,18 +1093,7 @@ __global__ __launch_bounds__(256) void k_rescore(CertArgs a, const PairDesc* __r
         const bool staged = (long long)S * S * 8 <= a.lds_bytes;
         if (threadIdx.x == 0) {
             int m = 0, t = 0;
-            if (!chunks) {
-                ch_lo[0] = en.z;
-                ch_n[0] = 1;
-                m = 1;
-                t = 1;
-                if (en.w >= 0) {
-                    ch_lo[1] = en.w;
-                    ch_n[1] = 1;
-                    m = 2;
-                    t = 2;
-                }
-            } else if (a.C > 64) {  // every angle as one range
+            if (a.C > 64) {  // every angle as one range
                 ch_lo[0] = 0;
                 ch_n[0] = a.K;
                 t = a.K;
@@ -1096,24 +1127,7 @@ __global__ __launch_bounds__(256) void k_rescore(CertArgs a, const PairDesc* __r
             return ((unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H) ? f32[(size_t)gy * W + gx]
                                                                               : make_float2(0.f, 0.f);
         };
-        if (!chunks) {
-            // one or two angles: a wave each, its lanes taking the points
-            const int wv = threadIdx.x >> 6;
-            if (wv < n_ang) {
-                const int k = ch_lo[wv];
-                const TabEntry* Tb = P.tab + (size_t)k * P.n_pad;
-                float sw, s1;
-                if (staged)
-                    score_fp32_wave<VOTE, HW>(Tb, P.n_pad, n_f, h, staged_at, &sw, &s1);
-                else
-                    score_fp32_wave<VOTE, HW>(Tb, P.n_pad, n_f, h, gathered_at, &sw, &s1);
-                if ((threadIdx.x & 63) == 0) {
-                    kw = sw;
-                    k1 = s1;
-                    kk = k;
-                }
-            }
-        } else {
+        {
             // open chunks: a thread per angle, its points in order
             for (int j = threadIdx.x; j < n_ang; j += blockDim.x) {
                 int c = 0, r = j;
@@ -1165,7 +1179,7 @@ __global__ __launch_bounds__(256) void k_rescore(CertArgs a, const PairDesc* __r
     }
 }
 
-constexpr int kCertLds = 64 * 1024;  // largest staged block of k_rescore_multi
+constexpr int kCertLds = 64 * 1024;  // largest staged block of k_rescore
 
 // ---------------------------------------------------------------- planning
 constexpr int kLC[] = {64, 96, 128, 192, 256};
