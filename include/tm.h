@@ -266,7 +266,7 @@ tm_status tm_detect_static(const tm_model* model, const tm_pyramid* pyr, const t
 
 /* Coarse-to-fine refinement of n poses of level `from_level` (x, y, k on
  * that level's grid) down to level 0, in place (Sec. II para. 2: the search
- * starts with the pyramid's top image and is carried down to the full image;
+ * begins at the top image of the pyramid and is carried down to the full image;
  * the paper gives no neighbourhood for the step, this uses the 3 x 3 x 3 one
  * around the doubled pose): at each level below, the pose is replaced by the
  * best (by the selection key) of the 27 poses (2x+a, 2y+b, 2k+c),
