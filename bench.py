@@ -7,32 +7,41 @@ translations x 360 angles, candidate selection, refinement through 3 levels,
 final selection.  Images are synthetic, seeded, and resident in device memory
 before timing starts.
 
-Two legs, as the metric asks: FP32 plain (one detection per call, timed as
-a side measurement) and the batched path (the timed steps): a step is one
-graph launch of all --batch images (FP16 direction storage with FP32
-accumulation by default); by default two such batches are in flight on two
-streams, the steps alternating between them (--streams 1: one at a time).  Prints one JSON line; `value` is pose evaluations
-per second of the batched leg (exhaustive top-level poses; refinement adds 27
-x candidates x 3 per detection and is not counted); the plain leg,
-detections/s, taps/s and the agreement of top-1 poses between the legs are
-given beside it.  The search kernel's own duration (for the roofline entry)
-comes from HIP events around its launches in a few eager batched steps after
-the timed region, on the same stream.  The search-kernel form is the
-autotuner's, or the default one if that gives the faster pipelined step
-(both give the same detections).
+The headline leg (the timed steps): a step is one graph launch of all
+--batch images, FP16 direction storage with FP32 accumulation and a certified
+search by default; two such batches are in flight on two streams, the steps
+alternating between them (--streams 1: one at a time).  The search schedule
+is the autotuner's, chosen on that pipelined step.  Beside it: the batched
+leg in the other precision, and the FP32 plain leg (one detection per call),
+the bit-for-bit agreement of the legs' detections, top-1 against the oracle
+per leg and ground-truth hits.  Prints one JSON line; `value` is pose
+evaluations per second of the headline leg (exhaustive top-level poses;
+refinement adds 27 x candidates x 3 per detection and is not counted);
+detections/s and taps/s are given beside it.
+
+`roofline`: the batched search kernel, its duration from HIP events around
+its launches in eager steps after the timed region, on the stream it runs on;
+bound by VALU issue: its executed VALU instructions per second (counted by
+rocprofv3 for the schedule in use, profiles/dense_c2_valu.json) against the
+issue peak of its inner loop's instruction mix (profiles/dense_c2_loop_mix.json),
+with its HBM bytes per launch (profiles/dense_c2_traffic.json) and the
+measured ceilings of the tm_probe kernels; the FLOP and tap figures beside.
+`cpu_baseline`: the FP64 oracle on the host cores over a bounded sample.
 
 --c4 adds the mixed batch (64 images of 640x480 to 2448x2048 against 8 models,
 one graph launch per step) and the continuous refinement of 4096 poses over
-its pairs (10 ascent steps).  --paper times the search of the paper's own
-experiment shape (812x617, 3 px / 3 px / 3 deg steps over 90 deg, one level);
---similarity the similarity pose (angles x scales); --readings the four
-combinations of pyramid source (grey image or gradient maps) and window vote
-(all taps or edge taps only), with their ground-truth matches.  --copy-probe
-ends the run with one 256 MiB
-elementwise copy, the calibration of the HBM byte counters; --traffic-from
-turns two rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE) into the committed
-per-launch traffic figure of the search kernel; --trace-summary prints a
-rocprofv3 kernel trace as a table with one row per kernel and launch shape.
+its pairs (10 ascent steps); --c3 the 2048x2048 frames in FP16 and FP32;
+--paper the search of the paper's own experiment shape (812x617, 3 px / 3 px /
+3 deg steps over 90 deg, one level); --similarity the similarity pose (angles
+x scales); --readings the four combinations of pyramid source (grey image or
+gradient maps) and window vote (all taps or edge taps only), with their
+ground-truth matches.  With the oracle on (no --no-cpu-baseline) the --c3 and
+--c4 legs also time the oracle on their workloads.  --plain-only times the
+plain leg alone.  --copy-probe ends the run with one 256 MiB elementwise copy,
+the calibration of the HBM byte counters; --traffic-from, --valu-from and
+--loop-mix-from turn rocprofv3 counter runs and the kernel's assembly into the
+committed records; --trace-summary prints a rocprofv3 kernel trace as a table
+with one row per kernel and launch shape.
 """
 from __future__ import annotations
 
