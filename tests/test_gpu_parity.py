@@ -693,6 +693,11 @@ def test_batch_tune_keeps_results():
                 assert 360 // chunk > 12
                 continue
             assert b.search_form()["chunk_angles"] == chunk
+            # the launch shape follows the schedule: a wave per 64 threads sharing a chunk, and at least
+            # one workgroup per (tile, chunk) of every pair (the work list may pad its XCD bins)
+            shape = b.search_launch()
+            assert shape["threads"] == 64 * planned["waves_per_chunk"]
+            assert shape["workgroups"] >= -(-360 // chunk) * len(images)
             b.run(graph=True)
             assert all(_poses_equal(a, c) for a, c in zip(b.results(), ref)), chunk
         # tuned on the pipelined step with a partner of the same shape: both keep the choice
