@@ -100,6 +100,34 @@ __device__ void bucket_sort(const Keys& in, const Keys& out, int N, int* cnt, in
     __syncthreads();
 }
 
+// Sort in[0..N) best first into out[0..N) by counting, for N <= 1024 (1024
+// threads): G lanes of one wave share a pose i (G the largest power of two
+// up to 64 with G N <= 1024), each counts the poses better than i among every
+// G-th one, and the G counts are added across the lanes.  With ties (equal
+// keys), the earlier one in `in` goes first.
+template <bool TIES>
+__device__ void rank_sort(const Keys& in, const Keys& out, int N)
+{
+    int G = 64;
+    while (G > 1 && G * N > (int)blockDim.x) G >>= 1;
+    const int i = threadIdx.x / G, r = threadIdx.x & (G - 1);
+    int c = 0;
+    if (i < N) {
+        const float w = in.sw[i], s = in.s1[i];
+        const int x = in.x[i], y = in.y[i], k = in.k[i];
+        for (int j = r; j < N; j += G) {
+            const float jw = in.sw[j], js = in.s1[j];
+            const int jx = in.x[j], jy = in.y[j], jk = in.k[j];
+            bool b = key_better(jw, js, jx, jy, jk, w, s, x, y, k);
+            if (TIES) b = b || (j < i && !key_better(w, s, x, y, k, jw, js, jx, jy, jk));
+            c += b ? 1 : 0;
+        }
+    }
+    for (int o = 1; o < G; o <<= 1) c += __shfl_xor(c, o, 64);
+    if (i < N && r == 0) kcopy(out, c, in, i);
+    __syncthreads();
+}
+
 // The squared distance d2 (scaled by 4^level) is an integer below 2^53 for
 // any image this library accepts, so d2 < dmin2 exactly when d2 < lim with
 // lim = ceil(dmin2) (dmin2 = dmin^2 is exact in FP64): the test runs in
@@ -109,63 +137,255 @@ __device__ __forceinline__ long long dist_limit(double dmin2)
     return dmin2 >= 9.0e18 ? 0x7fffffffffffffffLL : (long long)ceil(dmin2);
 }
 
-__device__ __forceinline__ bool too_close(int x, int y, int ax, int ay, int level, long long lim)
+// Coordinates in [0, 2^15): d2 = dx^2 + dy^2 < 2^31 in 32-bit integers (the
+// products in the 24-bit multiplier), tested against the limit divided by
+// 4^level and rounded up: for an integer d2, d2 4^level < lim exactly when
+// d2 < ceil(lim / 4^level).  Otherwise in 64 bits.
+constexpr int kSmallCoord = 1 << 15;
+
+__device__ __forceinline__ unsigned small_limit(long long lim, int level)
 {
+    const int s = 2 * level;
+    const long long q = (lim >> s) + ((lim & ((1LL << s) - 1)) != 0 ? 1 : 0);
+    return q > 0xffffffffLL ? 0xffffffffu : (unsigned)q;
+}
+
+template <bool SMALL>
+__device__ __forceinline__ bool too_close(int x, int y, int ax, int ay, int level, long long lim, unsigned lim32)
+{
+    if (SMALL) {
+        const int dx = x - ax, dy = y - ay;
+        return (unsigned)(__mul24(dx, dx) + __mul24(dy, dy)) < lim32;
+    }
     const long long dx = (long long)x - ax, dy = (long long)y - ay;
     const long long d2 = (dx * dx + dy * dy) << (2 * level);
     return d2 < lim;
 }
 
-// Greedy suppression over `a` sorted best first (N entries), run by wave 0:
-// a pose is accepted iff its squared distance (scaled by 4^level) to every
-// accepted pose is >= dmin2.  The distance test is exact (integers against
-// dist_limit(dmin2)).  The wave takes 64
-// candidates at a time: each lane tests its candidate against the poses
-// accepted so far, then the survivors are accepted in key order, each one
-// removing the later lanes it is too close to.
-__device__ int greedy_wave0(const Keys& a, int N, int level, double dmin2, int cap, int* ax, int* ay, int* aidx)
+// One chunk of up to 64 candidates at a time: every wave builds rows of the
+// chunk's closeness matrix (row j: the lanes within the distance of lane j's
+// pose, one ballot), wave 0 drops the lanes close to a pose accepted in an
+// earlier chunk, then accepts the rest in rounds and writes the accepted
+// poses in parallel.  A round accepts every live lane with no live lane
+// before it in its row: the lanes before it that left the live set were each
+// close to an accepted lane, so none of them is accepted, and the greedy pass
+// in key order accepts it too; the accepted lanes and the lanes in their rows
+// then leave the live set.  The first live lane is accepted in every round,
+// so the rounds end, and they accept what the pass in key order accepts.  At
+// most cap poses: the first ones of the accepted lanes, in lane order.
+template <bool SMALL>
+__device__ int greedy_run(const Keys& a, int N, int level, long long lim, int cap, int* ax, int* ay, int* aidx,
+                          unsigned* rows, int* n_acc)
 {
-    const int lane = threadIdx.x & 63;
-    if (!(dmin2 > 0.0)) {
-        // no squared distance is below a bound <= 0: the first poses are
-        // accepted as they come
-        const int m = N < cap ? N : cap;
-        for (int c = lane; c < m; c += 64) {
-            ax[c] = a.x[c];
-            ay[c] = a.y[c];
-            aidx[c] = c;
-        }
-        __threadfence_block();
-        return m;
-    }
-    const long long lim = dist_limit(dmin2);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+    const unsigned lim32 = SMALL ? small_limit(lim, level) : 0u;
     int acc = 0;
     for (int c0 = 0; c0 < N && acc < cap; c0 += 64) {
-        const int c = c0 + lane;
-        const bool valid = c < N;
-        const int x = valid ? a.x[c] : 0, y = valid ? a.y[c] : 0;
-        bool sup = !valid;
-        for (int q = 0; q < acc; ++q) sup |= too_close(x, y, ax[q], ay[q], level, lim);
-        unsigned long long live = __ballot(!sup);
-        while (live != 0ull && acc < cap) {
-            const int j = __builtin_ctzll(live);  // wave-uniform: read the lane directly
-            const int xj = __builtin_amdgcn_readlane(x, j), yj = __builtin_amdgcn_readlane(y, j);
+        const int nch = N - c0 < 64 ? N - c0 : 64;
+        const bool valid = lane < nch;
+        const int x = valid ? a.x[c0 + lane] : 0, y = valid ? a.y[c0 + lane] : 0;
+        for (int j = wv; j < nch; j += nwv) {
+            const int xj = a.x[c0 + j], yj = a.y[c0 + j];
+            const unsigned long long m = __ballot(valid && too_close<SMALL>(x, y, xj, yj, level, lim, lim32));
             if (lane == 0) {
-                ax[acc] = xj;
-                ay[acc] = yj;
-                aidx[acc] = c0 + j;
+                rows[2 * j] = (unsigned)m;
+                rows[2 * j + 1] = (unsigned)(m >> 32);
             }
-            ++acc;
-            live &= ~__ballot(too_close(x, y, xj, yj, level, lim));
-            live &= (j == 63) ? 0ull : ~((2ull << j) - 1ull);
         }
-        __threadfence_block();
+        bool sup = !valid;
+        if (wv == 0)
+            for (int q = 0; q < acc; ++q) sup |= too_close<SMALL>(x, y, ax[q], ay[q], level, lim, lim32);
+        __syncthreads();
+        if (wv == 0) {
+            // a lane past the chunk is never live, so its stale row plays no part
+            const unsigned long long row = ((unsigned long long)rows[2 * lane + 1] << 32) | rows[2 * lane];
+            const unsigned long long before = (1ull << lane) - 1ull;
+            unsigned long long live = __ballot(!sup), accm = 0ull;
+            while (live != 0ull) {
+                const unsigned long long f = __ballot(((live >> lane) & 1ull) && (row & live & before) == 0ull);
+                accm |= f;
+                live &= ~(f | __ballot((row & f) != 0ull));
+            }
+            const int room = cap - acc;
+            const int pos = __popcll(accm & before);
+            if (((accm >> lane) & 1ull) && pos < room) {
+                ax[acc + pos] = x;
+                ay[acc + pos] = y;
+                aidx[acc + pos] = c0 + lane;
+            }
+            if (lane == 0) *n_acc = acc + min(__popcll(accm), room);
+        }
+        __syncthreads();
+        acc = *n_acc;
     }
     return acc;
 }
 
+// Greedy suppression over `a` sorted best first (N entries), by the whole
+// workgroup: a pose is accepted iff its squared distance (scaled by 4^level)
+// to every accepted pose is >= dmin2, at most cap poses.  The distance test
+// is exact (integers against dist_limit(dmin2)); `small`: every coordinate in
+// [0, kSmallCoord).  Returns the count to every thread, with ax, ay (the
+// accepted coordinates) and aidx (their places in `a`) written and visible.
+// rows: 128 words of LDS; n_acc: one.
+__device__ int greedy(const Keys& a, int N, int level, double dmin2, int cap, bool small, int* ax, int* ay,
+                      int* aidx, unsigned* rows, int* n_acc)
+{
+    if (!(dmin2 > 0.0)) {
+        // no squared distance is below a bound <= 0: the first poses are
+        // accepted as they come
+        const int m = N < cap ? N : cap;
+        for (int c = threadIdx.x; c < m; c += blockDim.x) {
+            ax[c] = a.x[c];
+            ay[c] = a.y[c];
+            aidx[c] = c;
+        }
+        __syncthreads();
+        return m;
+    }
+    const long long lim = dist_limit(dmin2);
+    return small ? greedy_run<true>(a, N, level, lim, cap, ax, ay, aidx, rows, n_acc)
+                 : greedy_run<false>(a, N, level, lim, cap, ax, ay, aidx, rows, n_acc);
+}
+
 constexpr int kSelCap = 1024;   // candidates sorted into LDS by k_select (more go through global scratch)
 constexpr int kFinCap = 1024;   // candidates handled by k_final
+constexpr int kMapCap = 8192;   // bordered map cells whose S_w and S_1 k_select stages in LDS for the scan
+constexpr int kRankMax = 128;   // k_select sorts up to this many candidates by counting, more by buckets
+
+// The strict local maxima of the key over the 8 neighbours on the translation
+// grid, at or above the floor, in any order: appended to g and (the first
+// kSelCap) to u.  W, S1: the best-angle S_w and S_1 maps (in LDS or global).
+__device__ __forceinline__ void scan_maxima(const float* W, const float* S1, const int32_t* __restrict__ mk, int gw,
+                                            int gh, int sx, int sy, float min_score, const Keys& g, const Keys& u,
+                                            int* count)
+{
+    const int np = gw * gh;
+    for (int p = threadIdx.x; p < np; p += blockDim.x) {
+        const float w = W[p];
+        if (!(w >= min_score)) continue;  // most translations: below the floor, one load
+        const int j = p / gw, i = p - j * gw;
+        const float s = S1[p];
+        // the 8 neighbours' S_w loaded at clamped addresses, then compared;
+        // a neighbour's S_1 only decides (and is only read) on an equal S_w
+        float nw[8];
+        int nq[8];
+        bool nin[8];
+        int c = 0;
+#pragma unroll
+        for (int b = -1; b <= 1; ++b) {
+#pragma unroll
+            for (int a = -1; a <= 1; ++a) {
+                if (a == 0 && b == 0) continue;
+                const int ii = i + a, jj = j + b;
+                nin[c] = (unsigned)ii < (unsigned)gw && (unsigned)jj < (unsigned)gh;
+                nq[c] = min(max(jj, 0), gh - 1) * gw + min(max(ii, 0), gw - 1);
+                nw[c] = W[nq[c]];
+                ++c;
+            }
+        }
+        bool is_max = true;
+        c = 0;
+#pragma unroll
+        for (int b = -1; b <= 1; ++b) {
+#pragma unroll
+            for (int a = -1; a <= 1; ++a) {
+                if (a == 0 && b == 0) continue;
+                if (nin[c] && !(nw[c] < w)) {  // otherwise this pose is strictly better
+                    const float n1 = nw[c] == w ? S1[nq[c]] : 0.0f;
+                    is_max = is_max && key_better(w, s, i, j, 0, nw[c], n1, i + a, j + b, 0);
+                }
+                ++c;
+            }
+        }
+        if (is_max) {
+            const int idx = atomicAdd(count, 1);
+            const int x = i * sx, y = j * sy, k = mk[p];
+            g.sw[idx] = w;
+            g.s1[idx] = s;
+            g.x[idx] = x;
+            g.y[idx] = y;
+            g.k[idx] = k;
+            if (idx < kSelCap) {
+                u.sw[idx] = w;
+                u.s1[idx] = s;
+                u.x[idx] = x;
+                u.y[idx] = y;
+                u.k[idx] = k;
+            }
+        }
+    }
+}
+
+// The same maxima from maps staged in LDS with a border of one cell (row
+// pitch gw + 2, border S_w = -inf), one pass over the translations in steps of
+// the workgroup size (row and column carried, no division).  Of the eight
+// stored neighbours: one strictly above the pose makes it no maximum (it lies
+// inside the grid, the border being -inf); all strictly below make it one
+// (every neighbour inside the grid is below it, and only those count); any
+// other pose (an equal S_w, a NaN) takes the tie rules above.
+__device__ __forceinline__ void scan_maxima_staged(const float* W, const float* S1, const int32_t* __restrict__ mk,
+                                                   int gw, int gh, int sx, int sy, float min_score, const Keys& g,
+                                                   const Keys& u, int* count)
+{
+    const int np = gw * gh, pw = gw + 2, step = blockDim.x, dj = step / gw, di = step - dj * gw;
+    int j = threadIdx.x / gw, i = threadIdx.x - j * gw;
+    for (int p = threadIdx.x; p < np; p += step) {
+        const int q = (j + 1) * pw + i + 1;
+        const float w = W[q];
+        if (w >= min_score) {
+            const float nw[8] = {W[q - pw - 1], W[q - pw], W[q - pw + 1], W[q - 1],
+                                 W[q + 1],      W[q + pw - 1], W[q + pw], W[q + pw + 1]};
+            bool lower = true, higher = false;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                lower = lower && nw[c] < w;
+                higher = higher || nw[c] > w;
+            }
+            bool is_max = !higher;
+            if (!higher && !lower) {
+                const float s = S1[q];
+                int c = 0;
+#pragma unroll
+                for (int b = -1; b <= 1; ++b) {
+#pragma unroll
+                    for (int a = -1; a <= 1; ++a) {
+                        if (a == 0 && b == 0) continue;
+                        const bool nin = (unsigned)(i + a) < (unsigned)gw && (unsigned)(j + b) < (unsigned)gh;
+                        if (nin && !(nw[c] < w)) {
+                            const float n1 = nw[c] == w ? S1[q + b * pw + a] : 0.0f;
+                            is_max = is_max && key_better(w, s, i, j, 0, nw[c], n1, i + a, j + b, 0);
+                        }
+                        ++c;
+                    }
+                }
+            }
+            if (is_max) {
+                const int idx = atomicAdd(count, 1);
+                const float s = S1[q];
+                const int x = i * sx, y = j * sy, k = mk[p];
+                g.sw[idx] = w;
+                g.s1[idx] = s;
+                g.x[idx] = x;
+                g.y[idx] = y;
+                g.k[idx] = k;
+                if (idx < kSelCap) {
+                    u.sw[idx] = w;
+                    u.s1[idx] = s;
+                    u.x[idx] = x;
+                    u.y[idx] = y;
+                    u.k[idx] = k;
+                }
+            }
+        }
+        i += di;
+        j += dj;
+        if (i >= gw) {
+            i -= gw;
+            ++j;
+        }
+    }
+}
 
 struct SelectArgs {
     int sx, sy, level, cap;
@@ -193,77 +413,85 @@ __global__ __launch_bounds__(1024) void k_select(SelectArgs sa, const PairDesc* 
     Keys gs{P.sel + 5 * npg, P.sel + 6 * npg, reinterpret_cast<int*>(P.sel + 7 * npg),
             reinterpret_cast<int*>(P.sel + 8 * npg), reinterpret_cast<int*>(P.sel + 9 * npg)};
     int* gidx = reinterpret_cast<int*>(P.sel + 10 * npg);
-    __shared__ float l_sw[kSelCap], l_s1[kSelCap];
-    __shared__ int l_x[kSelCap], l_y[kSelCap], l_k[kSelCap];
+    // the maps staged for the scan; after it, the sorted keys and the bucket counters
+    __shared__ int stage[2 * kMapCap];
+    static_assert(5 * kSelCap + 2 * kBuckets + 128 <= 2 * kMapCap, "sort buffers exceed the map stage");
+    __shared__ float u_sw[kSelCap], u_s1[kSelCap];
+    __shared__ int u_x[kSelCap], u_y[kSelCap], u_k[kSelCap];
     __shared__ int acc_x[kFinCap], acc_y[kFinCap], acc_i[kFinCap];
-    __shared__ int cnt[kBuckets], off[kBuckets], wsum[16];
+    __shared__ int wsum[16];
     __shared__ int count, n_acc;
     if (threadIdx.x == 0) count = 0;
-    __syncthreads();
     const int np = gw * gh;
-    for (int p = threadIdx.x; p < np; p += blockDim.x) {
-        const float w = mw[p];
-        if (!(w >= min_score)) continue;  // most translations: below the floor, one load
-        const int j = p / gw, i = p - j * gw;
-        const float s = m1[p];
-        // the 8 neighbours' S_w loaded at clamped addresses, then compared;
-        // a neighbour's S_1 only decides (and is only read) on an equal S_w
-        float nw[8];
-        int nq[8];
-        bool nin[8];
-        int c = 0;
-#pragma unroll
-        for (int b = -1; b <= 1; ++b) {
-#pragma unroll
-            for (int a = -1; a <= 1; ++a) {
-                if (a == 0 && b == 0) continue;
-                const int ii = i + a, jj = j + b;
-                nin[c] = (unsigned)ii < (unsigned)gw && (unsigned)jj < (unsigned)gh;
-                nq[c] = min(max(jj, 0), gh - 1) * gw + min(max(ii, 0), gw - 1);
-                nw[c] = mw[nq[c]];
-                ++c;
-            }
+    const Keys u{u_sw, u_s1, u_x, u_y, u_k};
+    const int pw = gw + 2;
+    if ((long long)pw * (gh + 2) <= kMapCap) {
+        // the maps into LDS with their border (four loads of each in flight
+        // per thread), then the scan from LDS
+        float* s_w = reinterpret_cast<float*>(stage);
+        float* s_1 = s_w + kMapCap;
+        for (int e = threadIdx.x; e < 2 * pw + 2 * gh; e += blockDim.x) {
+            const int cell = e < pw ? e
+                             : e < 2 * pw ? (gh + 1) * pw + (e - pw)
+                             : e < 2 * pw + gh ? (e - 2 * pw + 1) * pw
+                                               : (e - 2 * pw - gh + 1) * pw + pw - 1;
+            s_w[cell] = -INFINITY;
+            s_1[cell] = -INFINITY;
         }
-        bool is_max = true;
-        c = 0;
+        const int step = blockDim.x, dj = step / gw, di = step - dj * gw;
+        int j = threadIdx.x / gw, i = threadIdx.x - j * gw;
+        for (int p0 = 0; p0 < np; p0 += 4 * step) {
+            float vw[4], v1[4];
+            int dst[4];
 #pragma unroll
-        for (int b = -1; b <= 1; ++b) {
-#pragma unroll
-            for (int a = -1; a <= 1; ++a) {
-                if (a == 0 && b == 0) continue;
-                if (nin[c] && !(nw[c] < w)) {  // otherwise this pose is strictly better
-                    const float n1 = nw[c] == w ? m1[nq[c]] : 0.0f;
-                    is_max = is_max && key_better(w, s, i, j, 0, nw[c], n1, i + a, j + b, 0);
+            for (int q = 0; q < 4; ++q) {
+                const int p = p0 + q * step + (int)threadIdx.x;
+                vw[q] = p < np ? mw[p] : 0.0f;
+                v1[q] = p < np ? m1[p] : 0.0f;
+                dst[q] = (j + 1) * pw + i + 1;
+                i += di;
+                j += dj;
+                if (i >= gw) {
+                    i -= gw;
+                    ++j;
                 }
-                ++c;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int p = p0 + q * step + (int)threadIdx.x;
+                if (p < np) {
+                    s_w[dst[q]] = vw[q];
+                    s_1[dst[q]] = v1[q];
+                }
             }
         }
-        if (is_max) {
-            const int idx = atomicAdd(&count, 1);
-            g.sw[idx] = w;
-            g.s1[idx] = s;
-            g.x[idx] = i * sx;
-            g.y[idx] = j * sy;
-            g.k[idx] = mk[p];
-        }
+        __syncthreads();
+        scan_maxima_staged(s_w, s_1, mk, gw, gh, sx, sy, min_score, g, u, &count);
+    } else {
+        __syncthreads();
+        scan_maxima(mw, m1, mk, gw, gh, sx, sy, min_score, g, u, &count);
     }
     __syncthreads();
     const int N = count;
+    int* cnt = stage + 5 * kSelCap;
+    int* off = cnt + kBuckets;
     Keys a;
     if (N <= kSelCap) {
-        a = Keys{l_sw, l_s1, l_x, l_y, l_k};
-        bucket_sort(g, a, N, cnt, off, acc_i, wsum);  // acc_i doubles as the index buffer
+        a = Keys{reinterpret_cast<float*>(stage), reinterpret_cast<float*>(stage) + kSelCap, stage + 2 * kSelCap,
+                 stage + 3 * kSelCap, stage + 4 * kSelCap};
+        if (N <= kRankMax)
+            rank_sort<false>(u, a, N);  // keys are distinct: (x, y) differ
+        else
+            bucket_sort(u, a, N, cnt, off, acc_i, wsum);  // acc_i doubles as the index buffer
     } else {
         a = gs;
         bucket_sort(g, a, N, cnt, off, gidx, wsum);
     }
     const int capc = cap < kFinCap ? cap : kFinCap;
-    if (threadIdx.x < 64) {
-        const int m = greedy_wave0(a, N, level, dmin2, capc, acc_x, acc_y, acc_i);
-        if (threadIdx.x == 0) n_acc = m;
-    }
-    __syncthreads();
-    const int m = n_acc;
+    // x < gw sx and y < gh sy
+    const bool small = (long long)gw * sx <= kSmallCoord && (long long)gh * sy <= kSmallCoord;
+    const int m = greedy(a, N, level, dmin2, capc, small, acc_x, acc_y, acc_i,
+                         reinterpret_cast<unsigned*>(off + kBuckets), &n_acc);
     for (int t = threadIdx.x; t < m; t += blockDim.x) {
         const int c = acc_i[t];
         tm_pose o;
@@ -315,22 +543,27 @@ __global__ __launch_bounds__(1024) void k_final(FinalArgs fa, const PairDesc* __
     __shared__ float l_sw[kFinCap], l_s1[kFinCap];
     __shared__ int l_x[kFinCap], l_y[kFinCap], l_k[kFinCap];
     __shared__ int acc_x[kFinCap], acc_y[kFinCap], acc_i[kFinCap];
-    __shared__ int count, n_acc;
-    if (threadIdx.x == 0) count = 0;
+    __shared__ unsigned rows[128];
+    __shared__ int count, n_acc, large;
+    if (threadIdx.x == 0) {
+        count = 0;
+        large = 0;
+    }
     __syncthreads();
     int nc = n_cand ? *n_cand : max_cand;
     nc = nc < max_cand ? nc : max_cand;
     nc = nc < kFinCap ? nc : kFinCap;
     if (fa.pick >= 0) {
-        // one wave per candidate: the best of the 27 poses around its centre
-        const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-        for (int i = wv; i < nc; i += nw) {
+        // half a wave per candidate: the best of the 27 poses around its centre
+        const int h = threadIdx.x >> 5, nh = blockDim.x >> 5;
+        for (int i0 = h & ~1; i0 < nc; i0 += nh) {  // both halves of a wave take the shuffles
+            const int i = (i0 | (h & 1)) < nc ? (i0 | (h & 1)) : i0;
             const tm_pose ctr = P.ctr[fa.pick][i];
             float sw, s1;
             int x, y, k;
-            pick27(P.part[0] + (size_t)i * kPartPerCand, ctr.x, ctr.y, ctr.k, P.W[0], P.H[0], P.n[0], fa.K0, fa.full, &sw, &s1,
-                   &x, &y, &k);
-            if ((threadIdx.x & 63) == 0 && sw >= min_score) {
+            pick27<32>(P.part[0] + (size_t)i * kPartPerCand, ctr.x, ctr.y, ctr.k, P.W[0], P.H[0], P.n[0], fa.K0, fa.full,
+                       &sw, &s1, &x, &y, &k);
+            if ((threadIdx.x & 31) == 0 && i == (i0 | (h & 1)) && sw >= min_score) {
                 const int idx = atomicAdd(&count, 1);
                 u_sw[idx] = sw;
                 u_s1[idx] = s1;
@@ -355,19 +588,10 @@ __global__ __launch_bounds__(1024) void k_final(FinalArgs fa, const PairDesc* __
     const int N = count;
     Keys u{u_sw, u_s1, u_x, u_y, u_k};
     Keys a{l_sw, l_s1, l_x, l_y, l_k};
-    // duplicates (equal keys) keep their relative order by arrival index
-    for (int i = threadIdx.x; i < N; i += blockDim.x) {
-        int rank = 0;
-        for (int j = 0; j < N; ++j) rank += (kb(u, j, i) || (j < i && !kb(u, i, j))) ? 1 : 0;
-        kcopy(a, rank, u, i);
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        const int m = greedy_wave0(a, N, 0, dmin2, cap < kFinCap ? cap : kFinCap, acc_x, acc_y, acc_i);
-        if (threadIdx.x == 0) n_acc = m;
-    }
-    __syncthreads();
-    const int m = n_acc;
+    for (int i = threadIdx.x; i < N; i += blockDim.x)
+        if ((unsigned)u_x[i] >= (unsigned)kSmallCoord || (unsigned)u_y[i] >= (unsigned)kSmallCoord) large = 1;
+    rank_sort<true>(u, a, N);  // duplicates (equal keys) keep their relative order by arrival index
+    const int m = greedy(a, N, 0, dmin2, cap < kFinCap ? cap : kFinCap, large == 0, acc_x, acc_y, acc_i, rows, &n_acc);
     const int mw = m < fa.buf ? m : fa.buf;  // written: the best by key first
     for (int t = threadIdx.x; t < mw; t += blockDim.x) {
         const int c = acc_i[t];

@@ -206,11 +206,14 @@ __device__ __forceinline__ uint3 xcd_block()
 
 // Best of the 27 poses around (x, y, k) (a pose of level l+1) at level l, from
 // the per-wave sums part[g][w][m] (m < 9: S_w of translation m, m >= 9: S_1),
-// the waves added in order.  Runs on one wave; every lane returns the result.
+// the waves added in order.  Runs on LANES (64 or 32) aligned lanes of one
+// wave; every one of them returns the result.
+template <int LANES = 64>
 __device__ __forceinline__ void pick27(const float* __restrict__ part, int x, int y, int k, int W, int H, int n, int K, int full,
                        float* bw, float* b1, int* bx, int* by, int* bk)
 {
-    const int lane = threadIdx.x & 63;
+    static_assert(LANES == 64 || LANES == 32, "a wave or half a wave");
+    const int lane = threadIdx.x & (LANES - 1);
     const int m = lane < 27 ? lane : 26;
     const int g = m / 9, t = m % 9, b = t / 3, u = t % 3;
     const int kg = angle_index(2 * k + g - 1, K, full);
@@ -227,7 +230,7 @@ __device__ __forceinline__ void pick27(const float* __restrict__ part, int x, in
     float kw = ok ? sw : -INFINITY, k1 = ok ? s1 : -INFINITY;
     int kx = ok ? xx : 0x7fffffff, ky = ok ? yy : 0x7fffffff, kk = ok ? kg : 0x7fffffff;
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
+    for (int off = LANES / 2; off >= 1; off >>= 1) {
         const float ow = __shfl_xor(kw, off, 64), o1 = __shfl_xor(k1, off, 64);
         const int ox = __shfl_xor(kx, off, 64), oy = __shfl_xor(ky, off, 64), okk = __shfl_xor(kk, off, 64);
         if (key_better(ow, o1, ox, oy, okk, kw, k1, kx, ky, kk)) {
