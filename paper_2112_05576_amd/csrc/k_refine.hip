@@ -104,33 +104,63 @@ __device__ __forceinline__ void votes5x5(const typename Raw<PREC>::T (&gv)[5][5]
         }
 }
 
-// The 18 sums of one wave (a fixed butterfly), written to out[0..17] by its
-// first lane.
+// One step of the reduce-scatter below: N slots (values base .. base + n - 1
+// of the 18, n <= N, the rest padding) to H = (N + 1) / 2 slots.  The lane
+// with the offset's bit clear keeps the first H slots and the other lane the
+// rest; each kept slot adds the partner's slot of the same value.
+template <int N>
+__device__ __forceinline__ void rs_step(float (&v)[N], float (&k)[(N + 1) / 2], int off, int& base, int& n)
+{
+    constexpr int H = (N + 1) / 2;
+    const bool hi = (threadIdx.x & off) != 0;
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+        const float lo_v = v[j], hi_v = H + j < N ? v[H + j] : 0.0f;
+        const float keep = hi ? hi_v : lo_v, send = hi ? lo_v : hi_v;
+        k[j] = keep + __shfl_xor(send, off, 64);
+    }
+    if (hi) {
+        base += H;
+        n -= H;
+    } else if (n > H) {
+        n = H;
+    }
+}
+
+// The 18 sums of one wave, written to out[0..17].  The pairs added are those
+// of the butterfly over lane offsets 32, 16, .., 1 (each partial is the sum
+// of the same two operands, and addition commutes), so every sum has the
+// bits of that butterfly's; the values are split between the lanes as they
+// go (9, 5, 3, 2, 1 slots, then one pair), 21 shuffles instead of 108, and
+// the lane that ends with a value writes it.
 __device__ __forceinline__ void wave_sum18(float (&aw)[9], float (&a1)[9], float* out)
 {
+    float v18[18];
 #pragma unroll
     for (int m = 0; m < 9; ++m) {
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            aw[m] += __shfl_xor(aw[m], off, 64);
-            a1[m] += __shfl_xor(a1[m], off, 64);
-        }
+        v18[m] = aw[m];
+        v18[9 + m] = a1[m];
     }
-    if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-        for (int m = 0; m < 9; ++m) {
-            out[m] = aw[m];
-            out[9 + m] = a1[m];
-        }
-    }
+    int base = 0, n = 18;
+    float v9[9], v5[5], v3[3], v2[2], v1[1];
+    rs_step<18>(v18, v9, 32, base, n);
+    rs_step<9>(v9, v5, 16, base, n);
+    rs_step<5>(v5, v3, 8, base, n);
+    rs_step<3>(v3, v2, 4, base, n);
+    rs_step<2>(v2, v1, 2, base, n);
+    const float s = v1[0] + __shfl_xor(v1[0], 1, 64);
+    if ((threadIdx.x & 1) == 0 && n > 0) out[base] = s;
 }
 
 // The candidate's pose at the level above: picked by the first wave from that
 // level's sums (or the candidate itself on the first refined level),
 // published in cur[0..3] (x, y, angle index, scale index); `writer` also
 // records it as the centre.  The 27 poses of a pick share the scale, so the
-// key's last component (the pose index j K + k) orders them as k does.
-__device__ void take_centre(const LevelArgs& a, const PairDesc& P, int c, bool writer, int* cur)
+// key's last component (the pose index j K + k) orders them as k does.  c <
+// max_cand, whose slots every buffer holds, so the reads are taken before the
+// candidate count is known (their latencies overlap) and only `live` (c below
+// the count) lets the results out.
+__device__ void take_centre(const LevelArgs& a, const PairDesc& P, int c, bool writer, bool live, int* cur)
 {
     const int l = a.level;
     const int lane = threadIdx.x & 63;
@@ -153,7 +183,7 @@ __device__ void take_centre(const LevelArgs& a, const PairDesc& P, int c, bool w
             s1 = p.score_1;
         }
         j = min(max(j, 0), a.S - 1);  // poses given by a caller may name any scale
-        if (lane == 0) {
+        if (lane == 0 && live) {
             cur[0] = x;
             cur[1] = y;
             cur[2] = k;
@@ -266,10 +296,9 @@ __global__ __launch_bounds__(64) void k_refine_level(LevelArgs a, const PairDesc
     if (a.staged && P.rtile[l]) return;  // this pair's level is refined by k_refine_tile
     const int c = blockIdx.x / (3 * kWaves);
     const int g = blockIdx.x / kWaves % 3, w = blockIdx.x % kWaves;
-    int count = a.max_cand;
-    if (P.ncand) count = min(count, *P.ncand);
+    const int count = P.ncand ? min(a.max_cand, *P.ncand) : a.max_cand;
+    take_centre(a, P, c, g == 0 && w == 0, c < count, cur);
     if (c >= count) return;
-    take_centre(a, P, c, g == 0 && w == 0, cur);
     __syncthreads();
     const int x = cur[0], y = cur[1], k = cur[2];
     const double sigma = scale_of(a.sigma_min, a.sigma_step, cur[3]);
@@ -306,10 +335,9 @@ __global__ __launch_bounds__(kThreads * kTileGroups) void k_refine_tile(LevelArg
     const int l = a.level;
     if (!P.rtile[l]) return;
     const int c = B.x;
-    int count = a.max_cand;
-    if (P.ncand) count = min(count, *P.ncand);
+    const int count = P.ncand ? min(a.max_cand, *P.ncand) : a.max_cand;
+    take_centre(a, P, c, true, c < count, cur);
     if (c >= count) return;
-    take_centre(a, P, c, true, cur);
     __syncthreads();
     const int x = cur[0], y = cur[1], k = cur[2];
     const double sigma = scale_of(a.sigma_min, a.sigma_step, cur[3]);
