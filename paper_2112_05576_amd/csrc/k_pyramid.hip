@@ -185,11 +185,32 @@ __global__ __launch_bounds__(256) void k_grad_level(FieldsArg one, const FieldsA
     a.grad[l][idx] = pack_grad(gx, gy);
 }
 
-// Unit gradient direction of every pixel of every level: (gx, gy)/|g| formed
-// in FP64 and rounded once to the storage precision where gx^2 + gy^2 > T2,
-// (0, 0) elsewhere (an FP16 pyramid also gets the FP32 rounding, its twin).  Each thread covers 4 consecutive pixels of a row; their
-// 3 x 6 neighbourhood (or their 4 gradient pairs) is loaded at once, before
-// any of the four is computed, so a thread waits for memory once.
+// (gx, gy)/|g| rounded to FP32, for |gx|, |gy| <= 1020 (the Sobel range, which
+// the gradient-map levels keep) and m2 = gx^2 + gy^2 > 0.  1/|g| is the FP32
+// reciprocal square root (relative error within 2^-22) refined by two Newton
+// steps in FP64, each of which squares the error (it ends below 2^-50); the
+// products gx/|g|, gy/|g| are formed in FP64 and rounded once.  Over that
+// range every quotient lies at least 2^-43.9 (relative) from the midpoint of
+// two FP32 neighbours (found by enumerating all pairs), so the result is the
+// FP32 rounding of the exact quotient: the bits FP64 square root and division
+// give, with no FP64 division and no FP64 square root.
+__device__ __forceinline__ void unit_dir(int gx, int gy, int m2, float* fx, float* fy)
+{
+    const double md = (double)m2;
+    double r = (double)__builtin_amdgcn_rsqf((float)m2);  // m2 <= 2 * 1020^2 is exact in FP32
+    r = fma(0.5 * r, fma(-md * r, r, 1.0), r);
+    r = fma(0.5 * r, fma(-md * r, r, 1.0), r);
+    *fx = (float)((double)gx * r);
+    *fy = (float)((double)gy * r);
+}
+
+// Unit gradient direction of every pixel of every level: (gx, gy)/|g| rounded
+// once to the storage precision where gx^2 + gy^2 > T2, (0, 0) elsewhere (an
+// FP16 pyramid also gets the FP32 rounding, its twin).  Each thread covers 4
+// consecutive pixels of a row; their 3 x 6 neighbourhood (three aligned words
+// per row where rows start on a word, else bytes; or their 4 gradient pairs)
+// is loaded at once, before any of the four is computed, so a thread waits
+// for memory once.
 template <bool BATCH>
 __global__ __launch_bounds__(256) void k_sobel_fields(FieldsArg one, const FieldsArg* __restrict__ many)
 {
@@ -219,11 +240,27 @@ __global__ __launch_bounds__(256) void k_sobel_fields(FieldsArg one, const Field
         // clamped value only ever feeds a pixel of the one-pixel frame,
         // whose gradient is 0
         int p[3][6];
+        if ((W & 3) == 0 && (reinterpret_cast<uintptr_t>(img) & 3) == 0) {
+            // words x0/4 - 1 .. x0/4 + 1 of each row, clamped to the row (a
+            // clamped word only feeds the frame as above)
+            const int q = x0 >> 2, nq = W >> 2;
 #pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            const size_t row = (size_t)min(max(y - 1 + r, 0), H - 1) * W;
+            for (int r = 0; r < 3; ++r) {
+                const uint32_t* rw =
+                    reinterpret_cast<const uint32_t*>(img + (size_t)min(max(y - 1 + r, 0), H - 1) * W);
+                const uint32_t wl = rw[max(q - 1, 0)], wc = rw[q], wr = rw[min(q + 1, nq - 1)];
+                p[r][0] = (int)(wl >> 24);
 #pragma unroll
-            for (int c = 0; c < 6; ++c) p[r][c] = img[row + min(max(x0 - 1 + c, 0), W - 1)];
+                for (int c = 0; c < 4; ++c) p[r][1 + c] = (int)((wc >> (8 * c)) & 0xFFu);
+                p[r][5] = (int)(wr & 0xFFu);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const size_t row = (size_t)min(max(y - 1 + r, 0), H - 1) * W;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) p[r][c] = img[row + min(max(x0 - 1 + c, 0), W - 1)];
+            }
         }
         const bool row_in = y >= 1 && y <= H - 2;
 #pragma unroll
@@ -241,14 +278,9 @@ __global__ __launch_bounds__(256) void k_sobel_fields(FieldsArg one, const Field
     for (int i = 0; i < 4; ++i) {
         const int gx = gxv[i], gy = gyv[i];
         const long long m2 = (long long)gx * gx + (long long)gy * gy;
-        double dx = 0.0, dy = 0.0;
-        if (m2 > T2) {
-            double m = sqrt((double)m2);
-            dx = (double)gx / m;
-            dy = (double)gy / m;
-        }
-        fx[i] = (float)dx;
-        fy[i] = (float)dy;
+        fx[i] = 0.0f;
+        fy[i] = 0.0f;
+        if (m2 > T2 && m2 > 0) unit_dir(gx, gy, (int)m2, &fx[i], &fy[i]);
     }
     const size_t o = (size_t)y * W + x0;
     // FP32 pairs: two pixels per 16-byte store where the four are whole and

@@ -172,13 +172,49 @@ def test_integer_distance_test_equals_the_fp64_one():
     dmin2 = dmin.astype(np.float64) ** 2
     lim = np.ceil(dmin2).astype(np.int64)
     for level in (0, 1, 3, 5):
+        # the 32-bit form for coordinates below 2^15: the unscaled distance
+        # against ceil(lim / 4^level), capped at 2^32 - 1
+        s = 2 * level
+        lim32 = np.minimum((lim >> s) + ((lim & ((1 << s) - 1)) != 0), 0xFFFFFFFF)
         for dx in range(-20, 21):
             for dy in (0, 1, 7, 19):
                 d2 = (dx * dx + dy * dy) << (2 * level)
                 assert np.array_equal(float(d2) < dmin2, d2 < lim), (level, dx, dy)
+                assert np.array_equal(d2 < lim, (dx * dx + dy * dy) < lim32), (level, dx, dy)
     # exact squares land on the boundary: not too close in either form
     d = np.float32(5.0)
     assert not (25.0 < float(d) ** 2) and not (25 < int(np.ceil(float(d) ** 2)))
+
+
+def test_unit_direction_rounds_as_fp64_sqrt_and_division():
+    """The edge field's (gx, gy)/|g| in FP32: over the Sobel range |gx|, |gy| <=
+    1020 every quotient lies at least 2^-44 (relative) from the midpoint of
+    two FP32 neighbours, and two Newton steps in FP64 from an FP32 estimate
+    of 1/|g| (even one 2^-15 off; the hardware's is within 2^-22) reach 2^-50,
+    so the products round as FP64 square root and division do, for every
+    pair."""
+    g = np.arange(-1020, 1021, dtype=np.int64)
+    gx, gy = (a.ravel() for a in np.meshgrid(g, g, indexing="ij"))
+    m2 = gx * gx + gy * gy
+    gx, gy, m2 = gx[m2 > 0], gy[m2 > 0], m2[m2 > 0]
+    md = m2.astype(np.float64)
+    m = np.sqrt(md)
+    ref_x, ref_y = (gx / m).astype(np.float32), (gy / m).astype(np.float32)
+    # distance of each positive quotient to the nearest FP32 midpoint (the
+    # FP64 quotient is within 2^-52 of the exact one)
+    q = (gx / m)[gx > 0]
+    f = q.astype(np.float32)
+    lo = np.where(f.astype(np.float64) <= q, f, np.nextafter(f, np.float32(-1)))
+    mid = (lo.astype(np.float64) + np.nextafter(lo, np.float32(2)).astype(np.float64)) / 2
+    assert np.min(np.abs(q - mid) / q) > 2.0 ** -44
+    exact = 1.0 / m
+    for rel in (2.0 ** -22, -(2.0 ** -22), 2.0 ** -15):
+        r = (exact * (1 + rel)).astype(np.float32).astype(np.float64)
+        for _ in range(2):
+            r = (0.5 * r) * (1.0 - (md * r) * r) + r
+        assert np.max(np.abs(r - exact) / exact) < 2.0 ** -50
+        assert np.array_equal((gx * r).astype(np.float32), ref_x)
+        assert np.array_equal((gy * r).astype(np.float32), ref_y)
 
 
 def test_valu_counts_per_form(tmp_path, monkeypatch):
