@@ -968,30 +968,42 @@ __device__ __forceinline__ void vote_fp32(const TabEntry& e, int h, Fetch g, flo
     *centre = c;
 }
 
+constexpr int kWaveSeg = 512;  // points whose votes score_fp32_wave keeps in LDS at a time
+
 // One pose scored by a whole wave, lane t taking points t, t + 64, ...: the
-// votes are computed side by side and then added in point order (blocks of
-// 32, block sums in order) by reading them lane by lane, so the sums are
-// those of score_fp32 bit for bit.  Every lane returns the result.
+// votes of kWaveSeg points at a time go to the wave's LDS buffers vb, cb
+// (kWaveSeg floats each), lane b then adds block b of 32 of them in point
+// order, and the block sums are added in order, so the sums are those of
+// score_fp32 bit for bit.  Every lane returns the result.
 template <int VOTE, int HW, class Fetch>
 __device__ __forceinline__ void score_fp32_wave(const TabEntry* __restrict__ Tb, int n_pad, float n_f, int h, Fetch g,
-                                                float* sw, float* s1)
+                                                float* vb, float* cb, float* sw, float* s1)
 {
     const int lane = threadIdx.x & 63;
-    float tw = 0.f, t1 = 0.f, pw = 0.f, p1 = 0.f;
-    for (int i0 = 0; i0 < n_pad; i0 += 64) {
-        float v = 0.f, c = 0.f;
-        if (i0 + lane < n_pad) vote_fp32<VOTE, HW>(Tb[i0 + lane], h, g, &v, &c);
-        const int m = min(64, n_pad - i0);  // a multiple of 8, so block ends fall on lanes 31 and 63
-        for (int j = 0; j < m; ++j) {
-            pw += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
-            p1 += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(c), j));
-            if (((i0 + j) & (kBlock - 1)) == kBlock - 1 || i0 + j == n_pad - 1) {
-                tw += pw;
-                t1 += p1;
-                pw = 0.f;
-                p1 = 0.f;
+    float tw = 0.f, t1 = 0.f;
+    for (int s0 = 0; s0 < n_pad; s0 += kWaveSeg) {
+        const int sn = min(kWaveSeg, n_pad - s0);
+        for (int i = lane; i < sn; i += 64) {
+            float v, c;
+            vote_fp32<VOTE, HW>(Tb[s0 + i], h, g, &v, &c);
+            vb[i] = v;
+            cb[i] = c;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // the votes written before any lane reads them
+        const int nbk = (sn + kBlock - 1) / kBlock;
+        float pw = 0.f, p1 = 0.f;
+        if (lane < nbk) {
+            const int i1 = min(sn, (lane + 1) * kBlock);
+            for (int i = lane * kBlock; i < i1; ++i) {
+                pw += vb[i];
+                p1 += cb[i];
             }
         }
+        for (int b = 0; b < nbk; ++b) {
+            tw += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(pw), b));
+            t1 += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p1), b));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  // read before the next segment overwrites
     }
     *sw = tw / n_f;
     *s1 = t1 / n_f;
@@ -1025,12 +1037,19 @@ __device__ __forceinline__ void score_fp32(const TabEntry* __restrict__ Tb, int 
     *s1 = t1 / n_f;
 }
 
+constexpr int kRescoreSums = 2048;  // (angle, block) sums k_rescore keeps in LDS at a time
+static_assert(kRescoreSums >= 4 * kWaveSeg, "each of the four waves' vote buffers lies in the sums' space");
+
 // The queued translations, the best by the key (S_w desc, S_1 desc, angle
 // asc) written to the map: an entry naming one or two angles is scored by one
 // wave (its lanes taking the points, the angles in turn, taps read from
-// memory); an entry of open chunks by a whole workgroup (looping over those
-// entries), the FP32 field block around it staged in LDS when it fits, one
-// thread per angle.
+// memory); an entry of open chunks by a whole workgroup, the FP32 field
+// block around it staged in LDS when it fits, a thread per (angle, block of
+// 32 points) forming that block's sum in point order, then a thread per
+// angle adding its block sums in order (the sums of score_fp32, bit for
+// bit).  Entry e goes to workgroup e mod the grid (an explicit one to its
+// wave e / grid mod 4), so that no workgroup takes both kinds while others
+// idle.
 template <int VOTE, int HW>
 __global__ __launch_bounds__(256) void k_rescore(CertArgs a, const PairDesc* __restrict__ pairs)
 {
@@ -1039,14 +1058,17 @@ __global__ __launch_bounds__(256) void k_rescore(CertArgs a, const PairDesc* __r
     __shared__ float rw[4], r1[4];
     __shared__ int rk[4];
     __shared__ int ch_lo[64], ch_n[64], n_ang;
+    __shared__ float bs_w[kRescoreSums], bs_1[kRescoreSums];
     const int count = a.cb.count[0];
     const int h = (a.win - 1) / 2;
     // entries with one or two explicit angles: one wave each, the angles in
     // turn, the taps read from memory (the values a staged block gives:
-    // zero outside the image)
+    // zero outside the image); each wave's votes pass through its quarter of
+    // bs_w / bs_1, which the open-chunk entries below reuse only after a
+    // barrier every wave reaches once done here
     {
         const int nw = blockDim.x >> 6;
-        for (int e = blockIdx.x * nw + (threadIdx.x >> 6); e < count; e += gridDim.x * nw) {
+        for (int e = blockIdx.x + gridDim.x * (threadIdx.x >> 6); e < count; e += gridDim.x * nw) {
             const int4 en = a.cb.list[e];
             if (en.x < 0) continue;  // open chunks: below, by the whole workgroup
             const PairDesc& P = pairs[en.x];
@@ -1066,7 +1088,9 @@ __global__ __launch_bounds__(256) void k_rescore(CertArgs a, const PairDesc* __r
                 const int k = t == 0 ? en.z : en.w;
                 if (k < 0) break;
                 float sw, s1;
-                score_fp32_wave<VOTE, HW>(P.tab + (size_t)k * P.n_pad, P.n_pad, n_f, h, gathered_at, &sw, &s1);
+                score_fp32_wave<VOTE, HW>(P.tab + (size_t)k * P.n_pad, P.n_pad, n_f, h, gathered_at,
+                                          bs_w + kWaveSeg * (threadIdx.x >> 6), bs_1 + kWaveSeg * (threadIdx.x >> 6),
+                                          &sw, &s1);
                 if (key_better(sw, s1, 0, 0, k, kw, k1, 0, 0, kk)) {
                     kw = sw;
                     k1 = s1;
@@ -1128,22 +1152,56 @@ __global__ __launch_bounds__(256) void k_rescore(CertArgs a, const PairDesc* __r
                                                                               : make_float2(0.f, 0.f);
         };
         {
-            // open chunks: a thread per angle, its points in order
-            for (int j = threadIdx.x; j < n_ang; j += blockDim.x) {
+            // open chunks, kRescoreSums / nb angles at a time: the block sums of
+            // every (angle, block) pair, each a thread's, then each angle's total
+            const int n_pad = P.n_pad, nb = (n_pad + kBlock - 1) / kBlock, per = kRescoreSums / nb;
+            auto angle_of = [&](int j) {
                 int c = 0, r = j;
                 while (r >= ch_n[c]) r -= ch_n[c++];
-                const int k = ch_lo[c] + r;
-                const TabEntry* Tb = P.tab + (size_t)k * P.n_pad;
-                float sw, s1;
-                if (staged)
-                    score_fp32<VOTE, HW>(Tb, P.n_pad, n_f, h, staged_at, &sw, &s1);
-                else
-                    score_fp32<VOTE, HW>(Tb, P.n_pad, n_f, h, gathered_at, &sw, &s1);
-                if (key_better(sw, s1, 0, 0, k, kw, k1, 0, 0, kk)) {
-                    kw = sw;
-                    k1 = s1;
-                    kk = k;
+                return ch_lo[c] + r;
+            };
+            for (int j0 = 0; j0 < n_ang; j0 += per) {
+                const int na = min(per, n_ang - j0);
+                for (int q = threadIdx.x; q < na * nb; q += blockDim.x) {
+                    const int j = q / nb, b = q - j * nb;
+                    const TabEntry* Tb = P.tab + (size_t)angle_of(j0 + j) * n_pad + b * kBlock;
+                    const int m = min(kBlock, n_pad - b * kBlock);
+                    float pw = 0.f, p1 = 0.f;
+                    if (staged) {
+#pragma unroll 4
+                        for (int i = 0; i < m; ++i) {
+                            float v, c;
+                            vote_fp32<VOTE, HW>(Tb[i], h, staged_at, &v, &c);
+                            pw += v;
+                            p1 += c;
+                        }
+                    } else {
+                        for (int i = 0; i < m; ++i) {
+                            float v, c;
+                            vote_fp32<VOTE, HW>(Tb[i], h, gathered_at, &v, &c);
+                            pw += v;
+                            p1 += c;
+                        }
+                    }
+                    bs_w[q] = pw;
+                    bs_1[q] = p1;
                 }
+                __syncthreads();
+                for (int j = threadIdx.x; j < na; j += blockDim.x) {
+                    float tw = 0.f, t1 = 0.f;
+                    for (int b = 0; b < nb; ++b) {
+                        tw += bs_w[j * nb + b];
+                        t1 += bs_1[j * nb + b];
+                    }
+                    const float sw = tw / n_f, s1 = t1 / n_f;
+                    const int k = angle_of(j0 + j);
+                    if (key_better(sw, s1, 0, 0, k, kw, k1, 0, 0, kk)) {
+                        kw = sw;
+                        k1 = s1;
+                        kk = k;
+                    }
+                }
+                __syncthreads();  // before the next angles' block sums
             }
         }
         // the best of the workgroup by the key (a total order: any merge order gives it)
