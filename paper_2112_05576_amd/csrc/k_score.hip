@@ -876,19 +876,10 @@ __global__ __launch_bounds__(64) void k_cert_zero(int* count)
     if (threadIdx.x == 0) count[0] = 0;
 }
 
-// One thread per translation of every pair: the translations whose FP32
-// values the selection needs, queued with the angles to score.  Entry
-// (pair, translation, a, b): the angles a and b (b < 0: none) when every
-// other angle is below M - 2E (the map's runner-up and rest's best say so);
-// otherwise (-1 - pair, translation, mask low, mask high): the angle chunks
-// whose FP16 best reaches M - 2E.
-__global__ __launch_bounds__(256) void k_certify(CertArgs a, const PairDesc* __restrict__ pairs)
+// Whether translation p of pair pr must be re-scored in FP32, and its entry.
+__device__ __forceinline__ bool certify_entry(const CertArgs& a, const PairDesc& P, int pr, int p, int gw, int gh,
+                                              int np, int4* out)
 {
-    const int pr = blockIdx.y;
-    const PairDesc& P = pairs[pr];
-    const int gw = P.gw, gh = P.gh, np = gw * gh;
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= np) return;
     const int x = p % gw, y = p / gw;
     const double E = cert_eps(P.n[a.level]);
     double M[5][5];
@@ -921,9 +912,9 @@ __global__ __launch_bounds__(256) void k_certify(CertArgs a, const PairDesc* __r
 #pragma unroll
         for (int u = -1; u <= 1; ++u)
             if ((u || v) && !need && possible(2 + v, 2 + u) && hi_u >= M[2 + v][2 + u] - E) need = true;
-    if (!need) return;
+    if (!need) return false;
     const double lim = M[2][2] - 2.0 * E;
-    int4 en;
+    int4& en = *out;
     if ((double)P.m3[p] < lim) {
         // the FP32 best is the FP16 best angle, or the runner-up if it reaches M - 2E
         en = make_int4(pr, p, P.mk[p], (double)P.m2[p] >= lim ? P.mk2[p] : -1);
@@ -934,7 +925,32 @@ __global__ __launch_bounds__(256) void k_certify(CertArgs a, const PairDesc* __r
         if (a.C > 64) mask = ~0ull;  // all angles
         en = make_int4(-1 - pr, p, (int)(unsigned)(mask & 0xffffffffull), (int)(unsigned)(mask >> 32));
     }
-    a.cb.list[atomicAdd(&a.cb.count[0], 1)] = en;
+    return true;
+}
+
+// One thread per translation of every pair: the translations whose FP32
+// values the selection needs, queued with the angles to score.  Entry
+// (pair, translation, a, b): the angles a and b (b < 0: none) when every
+// other angle is below M - 2E (the map's runner-up and rest's best say so);
+// otherwise (-1 - pair, translation, mask low, mask high): the angle chunks
+// whose FP16 best reaches M - 2E.  A workgroup's entries take their places
+// in the list with one atomic (its count, in LDS first), not one each.
+__global__ __launch_bounds__(256) void k_certify(CertArgs a, const PairDesc* __restrict__ pairs)
+{
+    __shared__ int wg_count, wg_base;
+    if (threadIdx.x == 0) wg_count = 0;
+    __syncthreads();
+    const int pr = blockIdx.y;
+    const PairDesc& P = pairs[pr];
+    const int gw = P.gw, gh = P.gh, np = gw * gh;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    int4 en = make_int4(0, 0, 0, 0);
+    const bool listed = p < np && certify_entry(a, P, pr, p, gw, gh, np, &en);
+    const int slot = listed ? atomicAdd(&wg_count, 1) : 0;
+    __syncthreads();
+    if (threadIdx.x == 0 && wg_count > 0) wg_base = atomicAdd(&a.cb.count[0], wg_count);
+    __syncthreads();
+    if (listed) a.cb.list[wg_base + slot] = en;
 }
 
 // One model point's windowed vote (the maximum of its window's products,
