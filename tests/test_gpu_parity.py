@@ -275,6 +275,37 @@ def test_select_large_candidate_count():
     assert np.array_equal(got["x"], ref.x) and np.array_equal(got["y"], ref.y) and np.array_equal(got["k"], ref.k)
 
 
+@pytest.mark.parametrize("name,gh,gw,sx,levels_q,level,dmin,cap", [
+    ("several hundred maxima from staged maps (bucket sort in LDS)", 60, 80, 1, 0, 1, 3.0, 1024),
+    ("equal scores everywhere (tie rules of the staged scan)", 60, 80, 1, 8, 0, 2.0, 1024),
+    ("coordinates beyond 2^15 (64-bit distance test)", 50, 70, 600, 0, 0, 700.0, 1024),
+    ("coordinates beyond 2^15, few accepted", 50, 70, 600, 4, 2, 1000.0, 7),
+])
+def test_select_paths(name, gh, gw, sx, levels_q, level, dmin, cap):
+    """Random maps through each path of the selection, against the oracle's
+    list: the scan from maps staged in LDS (np <= 8192), the bucket sort
+    (129..1024 maxima), many equal S_w and S_1 (levels_q > 0 quantises both),
+    and the suppression's distance test in 64 bits (x = i sx beyond 2^15)."""
+    P = _P()
+    case(f"select: {name}")
+    rng = np.random.default_rng(gh * 1000 + gw + sx + levels_q)
+    mw = rng.random((gh, gw))
+    m1 = rng.random((gh, gw))
+    if levels_q:
+        mw = np.floor(mw * levels_q) / levels_q
+        m1 = np.floor(m1 * 2) / 2
+    mw, m1 = mw.astype(np.float32), m1.astype(np.float32)
+    mk = rng.integers(0, 90, (gh, gw)).astype(np.int32)
+    ref = O.select(mw.astype(np.float64), m1.astype(np.float64), mk, sx, sx, level, 0.0, dmin, cap)
+    out, n = P.select(torch.from_numpy(mw).cuda(), torch.from_numpy(m1).cuda(), torch.from_numpy(mk).cuda(), sx, sx,
+                      level, 0.0, dmin, cap)
+    got = P.poses_to_numpy(out, int(n.item()))
+    print(f"{len(ref)} candidates")
+    assert len(got) == len(ref) and len(ref) > 0
+    assert np.array_equal(got["x"], ref.x) and np.array_equal(got["y"], ref.y) and np.array_equal(got["k"], ref.k)
+    assert np.array_equal(got["sw"], ref.sw.astype(np.float32)) and np.array_equal(got["s1"], ref.s1.astype(np.float32))
+
+
 # ------------------------------------------------------------ refine, detect
 def _oracle_key(fields, om, sp, L, x, y, k, level=0):
     st = O.level_step(sp, L, level)
