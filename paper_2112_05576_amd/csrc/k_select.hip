@@ -250,7 +250,10 @@ __device__ int greedy(const Keys& a, int N, int level, double dmin2, int cap, bo
 
 constexpr int kSelCap = 1024;   // candidates sorted into LDS by k_select (more go through global scratch)
 constexpr int kFinCap = 1024;   // candidates handled by k_final
-constexpr int kMapCap = 8192;   // bordered map cells whose S_w and S_1 k_select stages in LDS for the scan
+// bordered map cells whose S_w and S_1 k_select stages in LDS for the scan
+// (an 80x60 grid takes 82x62 = 5084); with it the kernel holds about 73 KB of
+// LDS, so two workgroups (pairs) share a CU
+constexpr int kMapCap = 5120;
 constexpr int kRankMax = 128;   // k_select sorts up to this many candidates by counting, more by buckets
 
 // The strict local maxima of the key over the 8 neighbours on the translation

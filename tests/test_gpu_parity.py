@@ -283,7 +283,7 @@ def test_select_large_candidate_count():
 ])
 def test_select_paths(name, gh, gw, sx, levels_q, level, dmin, cap):
     """Random maps through each path of the selection, against the oracle's
-    list: the scan from maps staged in LDS (np <= 8192), the bucket sort
+    list: the scan from maps staged in LDS (bordered grid of at most 5120 cells), the bucket sort
     (129..1024 maxima), many equal S_w and S_1 (levels_q > 0 quantises both),
     and the suppression's distance test in 64 bits (x = i sx beyond 2^15)."""
     P = _P()
