@@ -1425,6 +1425,9 @@ DensePlan plan_dense(const SearchDesc& s, const PairGeom* g, int npairs)
         p.max_blocks = max_tiles * p.C;
         int wa = knob("TM_DENSE_WA", small ? 16 : 4, 1, 16);
         if (p.WY * wa > 16) wa = 16 / p.WY;
+        // a small FP32 launch fetches 8 entries per step too (one 640x480
+        // detection: 125.0 against 126.7 us with 4)
+        if (small && !p.vote && s.precision == TM_FP32) p.variant = knob("TM_DENSE_ASM", 4, 0, 5);
         if (!retune_dense(p, p.variant, wa)) retune_dense(p, p.variant, 4);
     } else {
         // the generic search reads a copy of the field with a zero border of
