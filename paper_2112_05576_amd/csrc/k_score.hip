@@ -764,9 +764,11 @@ __global__ __launch_bounds__(256) void k_reduce_chunks(int C, const PairDesc* __
 
 // Per translation of a certified search: the chunks' Top3 summaries merged
 // (the key is a total order, so the merge order does not matter), written to
-// the map with the runner-up and the rest's best.
-__global__ __launch_bounds__(256) void k_reduce_screen(int C, const PairDesc* __restrict__ pairs)
+// the map with the runner-up and the rest's best.  clear (optional): the
+// certification's list counter, set to 0 here for the launches that follow.
+__global__ __launch_bounds__(256) void k_reduce_screen(int C, const PairDesc* __restrict__ pairs, int* clear)
 {
+    if (clear && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *clear = 0;
     const PairDesc& P = pairs[blockIdx.y];
     const int np = P.gw * P.gh;
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1559,7 +1561,7 @@ hipError_t prepare_dense(const SearchDesc& s, const DensePlan& p)
 }
 
 hipError_t launch_dense(const SearchDesc& s, const DensePlan& p, const PairDesc* d, int npairs, hipStream_t st,
-                        hipEvent_t ev0, hipEvent_t ev1)
+                        hipEvent_t ev0, hipEvent_t ev1, int* cert_count)
 {
     hipError_t e;
     if (ev0) {
@@ -1618,7 +1620,8 @@ hipError_t launch_dense(const SearchDesc& s, const DensePlan& p, const PairDesc*
         if (e != hipSuccess) return e;
     }
     if (p.screen)
-        hipLaunchKernelGGL(k_reduce_screen, dim3((p.max_np + 255) / 256, npairs), dim3(256), 0, st, p.C, d);
+        hipLaunchKernelGGL(k_reduce_screen, dim3((p.max_np + 255) / 256, npairs), dim3(256), 0, st, p.C, d,
+                           cert_count);
     else
         hipLaunchKernelGGL(k_reduce_chunks, dim3((p.max_np + kRedPos - 1) / kRedPos, npairs),
                            dim3(kRedPos * kRedLanes), 0, st, p.C, d);
@@ -1673,7 +1676,7 @@ hipError_t rescore_attr()
 }  // namespace
 
 hipError_t launch_certify(const SearchDesc& s, const DensePlan& p, const PairDesc* d, int npairs, const CertBufs& cb,
-                          hipStream_t st)
+                          hipStream_t st, bool count_cleared)
 {
     static bool attr_set = false;
     if (!attr_set) {
@@ -1698,7 +1701,7 @@ hipError_t launch_certify(const SearchDesc& s, const DensePlan& p, const PairDes
     // pairs whose block fits are staged, larger ones gather from memory
     const int B = p.max_rad + (s.win - 1) / 2, S = 2 * B + 1;
     a.lds_bytes = (long long)S * S * 8 <= kCertLds ? S * S * 8 : kCertLds;
-    hipLaunchKernelGGL(k_cert_zero, dim3(1), dim3(64), 0, st, cb.count);
+    if (!count_cleared) hipLaunchKernelGGL(k_cert_zero, dim3(1), dim3(64), 0, st, cb.count);
     hipLaunchKernelGGL(k_certify, dim3((p.max_np + 255) / 256, npairs), dim3(256), 0, st, a, d);
     const dim3 grid(min(cb.cap, 4096)), block(256);
     if (s.win == 3) {

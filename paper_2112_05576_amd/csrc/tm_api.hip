@@ -969,12 +969,10 @@ TM_EXPORT tm_status tm_detect(const tm_model* m, tm_pyramid* p, const tm_search_
     hipEvent_t ev0, ev1;
     st = timing_pair(&ev0, &ev1);
     if (st != TM_OK) return st;
-    HIP_TRY(tmk::launch_dense(sd, plan, dd, 1, s, ev0, ev1));
-    if (certify)
-        HIP_TRY(tmk::launch_certify(sd, plan, dd, 1,
-                                    tmk::cert_bufs(reinterpret_cast<uint8_t*>(p->ws.ptr) + kDescBytes + pair_bytes,
-                                                   pg.gw * pg.gh),
-                                    s));
+    const tmk::CertBufs cb =
+        tmk::cert_bufs(reinterpret_cast<uint8_t*>(p->ws.ptr) + kDescBytes + pair_bytes, pg.gw * pg.gh);
+    HIP_TRY(tmk::launch_dense(sd, plan, dd, 1, s, ev0, ev1, certify ? cb.count : nullptr));
+    if (certify) HIP_TRY(tmk::launch_certify(sd, plan, dd, 1, cb, s, true));
     HIP_TRY(tmk::launch_select(sd, dd, 1, pg.gw * pg.gh, s));
     if (refine) {
         const tmk::RefinePlan rp =
@@ -1058,10 +1056,9 @@ TM_EXPORT tm_status tm_detect_static(const tm_model* m, const tm_pyramid* p, con
     tmk::PairDesc* dd = reinterpret_cast<tmk::PairDesc*>(b);
     hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, d, dd);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(tmk::launch_dense(sd, plan, dd, 1, s));
-    if (certify)
-        HIP_TRY(tmk::launch_certify(sd, plan, dd, 1,
-                                    tmk::cert_bufs(b + kDescBytes + tab_bytes + pair_bytes, pg.gw * pg.gh), s));
+    const tmk::CertBufs cb = tmk::cert_bufs(b + kDescBytes + tab_bytes + pair_bytes, pg.gw * pg.gh);
+    HIP_TRY(tmk::launch_dense(sd, plan, dd, 1, s, nullptr, nullptr, certify ? cb.count : nullptr));
+    if (certify) HIP_TRY(tmk::launch_certify(sd, plan, dd, 1, cb, s, true));
     HIP_TRY(tmk::launch_select(sd, dd, 1, pg.gw * pg.gh, s));
     if (refine) {
         const tmk::RefinePlan rp =
@@ -1520,8 +1517,9 @@ tm_status batch_enqueue(tm_batch* b, hipStream_t s, bool timed)
         tm_status st = timing_pair(&ev0, &ev1);
         if (st != TM_OK) return st;
     }
-    HIP_TRY(tmk::launch_dense(b->sd, b->plan, b->d_pairs, b->npairs, s, ev0, ev1));
-    if (b->certify) HIP_TRY(tmk::launch_certify(b->sd, b->plan, b->d_pairs, b->npairs, b->cert, s));
+    HIP_TRY(tmk::launch_dense(b->sd, b->plan, b->d_pairs, b->npairs, s, ev0, ev1,
+                              b->certify ? b->cert.count : nullptr));
+    if (b->certify) HIP_TRY(tmk::launch_certify(b->sd, b->plan, b->d_pairs, b->npairs, b->cert, s, true));
     HIP_TRY(tmk::launch_select(b->sd, b->d_pairs, b->npairs, b->max_np, s));
     if (b->L > 1) HIP_TRY(tmk::launch_refine(b->sd, b->d_pairs, b->npairs, top, b->rplan, s, false));
     HIP_TRY(tmk::launch_final(b->sd, b->d_pairs, b->npairs, s, nullptr, nullptr, b->L > 1 ? top % 2 : -1));

@@ -295,9 +295,11 @@ bool refine_tile_fits(int rad, int precision, int win);
 // Kernel attributes of the plan's search kernel (call before capturing it).
 hipError_t prepare_dense(const SearchDesc& s, const DensePlan& p);
 // Exhaustive search of s.level for every pair: pair.mw/m1/mk.  ev0 / ev1
-// (optional) are recorded around the search kernel only.
+// (optional) are recorded around the search kernel only.  cert_count
+// (optional, a certified search): the certification's list counter, cleared
+// by the search's last kernel so that launch_certify needs no kernel for it.
 hipError_t launch_dense(const SearchDesc& s, const DensePlan& p, const PairDesc* d, int npairs, hipStream_t st,
-                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr, int* cert_count = nullptr);
 // Certification of an FP16 search (see k_score.hip): translations whose
 // FP32 scores could decide the candidate selection are re-scored in FP32 from
 // the FP32 twin, with the FP32 search's arithmetic, over the angles their FP16
@@ -311,10 +313,11 @@ struct CertBufs {
 };
 size_t cert_bytes(int total_np);
 CertBufs cert_bufs(void* base, int total_np);
-// Enqueues: the counter cleared (a kernel, not a memset), the flagging of
-// the translations, and the re-scoring kernel.
+// Enqueues: the counter cleared (a kernel, not a memset) unless the search
+// before it cleared it (count_cleared: launch_dense had cb.count), the
+// flagging of the translations, and the re-scoring kernel.
 hipError_t launch_certify(const SearchDesc& s, const DensePlan& p, const PairDesc* d, int npairs, const CertBufs& cb,
-                          hipStream_t st);
+                          hipStream_t st, bool count_cleared = false);
 
 // Candidates of every pair from its map: pair.cand / ncand (<= s.max_cand).
 hipError_t launch_select(const SearchDesc& s, const PairDesc* d, int npairs, int max_np, hipStream_t st);
